@@ -1,0 +1,231 @@
+"""Langevin integrators (oracle, float64 numpy).
+
+Units: Angstrom, fs, amu, kcal/mol, K.  Accelerations are ACC * F / m with
+ACC = 4.184e-4 (kcal/mol/A/amu -> A/fs^2); kinetic energies are
+0.5 sum m v^2 / ACC; k_B = 8.31446261815324 / 4184 kcal/mol/K.  Frictions
+are given in ps^-1 and used as 1e-3 fs^-1.
+
+* BAOAB (paper, Methods "Multi-time-step integrator", the Strang splitting
+  e^{tL} ~ B A O A B): half kick, half drift, Ornstein-Uhlenbeck step, half
+  drift, force evaluation, half kick.
+* DMTS-NC (Algorithm 1): with a cached pair (F, F_NC),
+      v += (D/2) M^-1 (F - F_NC)
+      n times: v += (d/2) M^-1 F_NC; x += (d/2) v; v <- O(v, d);
+               x += (d/2) v; F_NC <- NC(x); v += (d/2) M^-1 F_NC
+      F <- CONS(x); v += (D/2) M^-1 (F - F_NC)
+  with d = D / n.  The sign of the outer kick is "+" as in Algorithm 1 (the
+  enumerated list before it writes "-", but F_L = -grad U - F_S is a force).
+  The thermostat of Algorithm 1 is the Ornstein-Uhlenbeck step
+      v <- c1 v + sqrt((1 - c1^2) k_B T ACC / m) G,  c1 = exp(-gamma d)
+  (the inner expression of the Fast-Forward Langevin update of the paper).
+* The Fast-Forward Langevin variant replaces that step by
+      v <- |c1 v + sigma G| v / |v|   per atom (3-vector norm).
+* Hydrogen mass repartitioning: each hydrogen's mass is raised (set to a
+  value, or increased by an amount) and the difference is removed from the
+  heavy atom it is bonded to, so each molecule keeps its mass.
+* High hydrogen friction: a per-species friction table (diagonal Gamma).
+
+Random numbers: Philox-4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) with key
+(seed, stream) and counter (atom, step, 0, 0); the four 64-bit words give
+uniforms u = ((w >> 11) + 0.5) 2^-53 and Box-Muller normals
+    g0 = sqrt(-2 ln u0) cos(2 pi u1), g1 = sqrt(-2 ln u0) sin(2 pi u1),
+    g2 = sqrt(-2 ln u2) cos(2 pi u3)
+for the x, y, z noise of that atom at that O-step.  ``step`` counts O-steps
+from the start of the trajectory.
+
+Pins (tests/test_oracle_integrator.py): Philox known-answer vectors and
+numpy's Philox bit generator; Box-Muller at chosen uniforms; RESPA with n = 1
+equal to BAOAB; RESPA with NC equal to the conservative force equal to n
+BAOAB steps of size d; BAOAB on harmonic oscillators giving <x^2> = kT/k;
+temperatures following (T/d) chi^2(d); molecule masses kept by HMR.
+"""
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+ACC = 4.184e-4
+KB = 8.31446261815324 / 4184.0
+
+_M0 = 0xD2E7470EE14C6C93
+_M1 = 0xCA5A826395121157
+_W0 = 0x9E3779B97F4A7C15
+_W1 = 0xBB67AE8584CAA73B
+_MASK = (1 << 64) - 1
+
+
+# ------------------------------------------------------------------ Philox --
+
+def philox4x64_scalar(counter, key, rounds=10):
+    """One Philox-4x64 block with Python integers (reference form)."""
+    c0, c1, c2, c3 = (int(x) & _MASK for x in counter)
+    k0, k1 = (int(x) & _MASK for x in key)
+    for _ in range(rounds):
+        p0 = _M0 * c0
+        p1 = _M1 * c2
+        c0, c1, c2, c3 = ((p1 >> 64) ^ c1 ^ k0) & _MASK, p1 & _MASK, ((p0 >> 64) ^ c3 ^ k1) & _MASK, p0 & _MASK
+        k0 = (k0 + _W0) & _MASK
+        k1 = (k1 + _W1) & _MASK
+    return [c0, c1, c2, c3]
+
+
+def _mulhilo(a, b):
+    """64x64 -> (hi, lo) on uint64 numpy arrays via 32-bit halves."""
+    lo32 = np.uint64(0xFFFFFFFF)
+    s32 = np.uint64(32)
+    a_lo, a_hi = a & lo32, a >> s32
+    b_lo, b_hi = b & lo32, b >> s32
+    ll = a_lo * b_lo
+    hl = a_hi * b_lo
+    lh = a_lo * b_hi
+    hh = a_hi * b_hi
+    cross = (ll >> s32) + (hl & lo32) + (lh & lo32)
+    hi = hh + (hl >> s32) + (lh >> s32) + (cross >> s32)
+    lo = a * b
+    return hi, lo
+
+
+def philox4x64(c0, c1, c2, c3, k0, k1, rounds=10):
+    """Vectorised Philox-4x64 over uint64 arrays (broadcast)."""
+    with np.errstate(over="ignore"):
+        c0, c1, c2, c3 = (np.asarray(x, dtype=np.uint64) for x in (c0, c1, c2, c3))
+        c0, c1, c2, c3 = np.broadcast_arrays(c0, c1, c2, c3)
+        c0, c1, c2, c3 = c0.copy(), c1.copy(), c2.copy(), c3.copy()
+        k0 = np.uint64(k0)
+        k1 = np.uint64(k1)
+        m0, m1 = np.uint64(_M0), np.uint64(_M1)
+        w0, w1 = np.uint64(_W0), np.uint64(_W1)
+        for _ in range(rounds):
+            hi0, lo0 = _mulhilo(m0, c0)
+            hi1, lo1 = _mulhilo(m1, c2)
+            c0, c1, c2, c3 = hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0
+            k0 = k0 + w0
+            k1 = k1 + w1
+    return c0, c1, c2, c3
+
+
+def uniforms_from_bits(w):
+    return ((np.asarray(w, dtype=np.uint64) >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53
+
+
+def langevin_normals(seed, stream, step, n_atoms):
+    """(N, 3) standard normals for O-step ``step`` of stream ``stream``."""
+    atoms = np.arange(n_atoms, dtype=np.uint64)
+    w = philox4x64(atoms, np.uint64(step), 0, 0, seed, stream)
+    u0, u1, u2, u3 = (uniforms_from_bits(x) for x in w)
+    r0 = np.sqrt(-2.0 * np.log(u0))
+    r1 = np.sqrt(-2.0 * np.log(u2))
+    return np.stack([r0 * np.cos(2.0 * math.pi * u1),
+                     r0 * np.sin(2.0 * math.pi * u1),
+                     r1 * np.cos(2.0 * math.pi * u3)], axis=1)
+
+
+# ----------------------------------------------------- masses and friction --
+
+def hmr_masses(species, bonded_heavy, masses, h_mass=3.0, mode="set"):
+    """Hydrogen mass repartitioning: hydrogens get ``h_mass`` ('set') or
+    their mass plus ``h_mass`` ('add'); the bonded heavy atom loses the
+    difference."""
+    m = np.array(masses, dtype=np.float64, copy=True)
+    for a in range(m.shape[0]):
+        h = int(bonded_heavy[a])
+        if h < 0:
+            continue
+        new = h_mass if mode == "set" else masses[a] + h_mass
+        delta = new - masses[a]
+        m[a] = new
+        m[h] = m[h] - delta
+    return m
+
+
+def friction_per_atom(species, gamma_per_species_ps):
+    return np.asarray(gamma_per_species_ps, dtype=np.float64)[np.asarray(species)]
+
+
+# -------------------------------------------------------------- integrators --
+
+@dataclass
+class LangevinParams:
+    dt_outer: float          # fs (Delta); for BAOAB the step size
+    n_inner: int             # n (1 for BAOAB)
+    temperature: float       # K
+    gamma_ps: np.ndarray     # (N,) ps^-1
+    seed: int
+    stream: int = 0
+    thermostat: str = "langevin"   # or "ffl"
+
+
+@dataclass
+class State:
+    x: np.ndarray            # (N, 3)
+    v: np.ndarray            # (N, 3)
+    m: np.ndarray            # (N,)
+    f: np.ndarray = None     # cached conservative force
+    f_nc: np.ndarray = None  # cached fast force
+    step: int = 0            # O-steps done
+    first_step: bool = True
+
+
+def kinetic_energy(v, m):
+    return 0.5 * float(np.sum(m[:, None] * v * v)) / ACC
+
+
+def temperature(v, m):
+    return 2.0 * kinetic_energy(v, m) / (3 * v.shape[0] * KB)
+
+
+def _o_step(st, prm, dt):
+    g = np.asarray(prm.gamma_ps, dtype=np.float64) * 1e-3
+    c1 = np.exp(-g * dt)
+    sigma = np.sqrt((1.0 - c1 * c1) * KB * prm.temperature * ACC / st.m)
+    G = langevin_normals(prm.seed, prm.stream, st.step, st.x.shape[0])
+    new = c1[:, None] * st.v + sigma[:, None] * G
+    if prm.thermostat == "ffl":
+        nv = np.linalg.norm(st.v, axis=1)
+        nn = np.linalg.norm(new, axis=1)
+        scale = np.where(nv > 0, nn / np.where(nv > 0, nv, 1.0), 0.0)
+        new = np.where(nv[:, None] > 0, st.v * scale[:, None], new)
+    st.v = new
+    st.step += 1
+
+
+def _kick(st, f, dt):
+    st.v = st.v + (0.5 * dt) * ACC * f / st.m[:, None]
+
+
+def baoab_step(st, force_fn, prm):
+    """One BAOAB step of size prm.dt_outer with force ``force_fn(x)``."""
+    dt = prm.dt_outer
+    if st.first_step or st.f is None:
+        st.f = force_fn(st.x)
+        st.first_step = False
+    _kick(st, st.f, dt)
+    st.x = st.x + 0.5 * dt * st.v
+    _o_step(st, prm, dt)
+    st.x = st.x + 0.5 * dt * st.v
+    st.f = force_fn(st.x)
+    _kick(st, st.f, dt)
+    return st
+
+
+def dmts_nc_step(st, cons_fn, nc_fn, prm):
+    """One outer step of Algorithm 1 (BAOAB-RESPA with F_S = F_NC and
+    F_L = F - F_NC)."""
+    D, n = prm.dt_outer, prm.n_inner
+    d = D / n
+    if st.first_step or st.f is None or st.f_nc is None:
+        st.f_nc = nc_fn(st.x)
+        st.f = cons_fn(st.x)
+        st.first_step = False
+    st.v = st.v + (0.5 * D) * ACC * (st.f - st.f_nc) / st.m[:, None]
+    for _ in range(n):
+        _kick(st, st.f_nc, d)
+        st.x = st.x + 0.5 * d * st.v
+        _o_step(st, prm, d)
+        st.x = st.x + 0.5 * d * st.v
+        st.f_nc = nc_fn(st.x)
+        _kick(st, st.f_nc, d)
+    st.f = cons_fn(st.x)
+    st.v = st.v + (0.5 * D) * ACC * (st.f - st.f_nc) / st.m[:, None]
+    return st

@@ -1,0 +1,189 @@
+"""Pins for the oracle's random numbers, integrators, HMR and observables."""
+
+import copy
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import synth
+from oracle import analysis as oa
+from oracle import integrator as oi
+
+
+# ------------------------------------------------------------------ Philox --
+
+def test_philox_known_answer():
+    # Random123 known-answer vector for philox4x64-10 with zero counter and key.
+    assert oi.philox4x64_scalar([0, 0, 0, 0], [0, 0]) == [
+        0x16554D9ECA36314C, 0xDB20FE9D672D0FDC, 0xD7E772CEE186176B, 0x7E68B68AEC7BA23B]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_philox_matches_numpy_bit_generator(seed):
+    rng = np.random.default_rng(seed)
+    for _ in range(5):
+        key = [int(x) for x in rng.integers(0, 2 ** 63, size=2, dtype=np.uint64)]
+        ctr = [int(x) for x in rng.integers(1, 2 ** 63, size=4, dtype=np.uint64)]
+        # numpy's Philox increments its counter before producing a block.
+        start = np.array([ctr[0] - 1, ctr[1], ctr[2], ctr[3]], dtype=np.uint64)
+        bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=start)
+        assert [int(x) for x in bg.random_raw(4)] == oi.philox4x64_scalar(ctr, key)
+
+
+def test_philox_vectorised_equals_scalar():
+    atoms = np.arange(50, dtype=np.uint64)
+    w = oi.philox4x64(atoms, np.uint64(123456789), 0, 0, 42, 7)
+    for a in (0, 1, 17, 49):
+        assert [int(x[a]) for x in w] == oi.philox4x64_scalar([a, 123456789, 0, 0], [42, 7])
+
+
+def test_normals_are_standard_gaussian():
+    g = np.concatenate([oi.langevin_normals(5, 3, step, 20000) for step in range(10)])
+    for c in range(3):
+        assert stats.kstest(g[:, c], "norm").pvalue > 1e-4
+    assert abs(g.mean()) < 5 / np.sqrt(g.size)
+    assert abs(g.var() - 1) < 0.01
+    # distinct steps and streams decorrelate
+    a = oi.langevin_normals(5, 3, 0, 20000)[:, 0]
+    b = oi.langevin_normals(5, 4, 0, 20000)[:, 0]
+    assert abs(np.corrcoef(a, b)[0, 1]) < 0.03
+
+
+def test_uniform_mapping_endpoints():
+    u = oi.uniforms_from_bits(np.array([0, 2 ** 64 - 1], dtype=np.uint64))
+    assert u[0] == 0.5 * 2.0 ** -53 and u[1] == 1.0 - 0.5 * 2.0 ** -53
+
+
+# ------------------------------------------------------------ integrators --
+
+def _harmonic(k):
+    return lambda x: -k * x
+
+
+def _state(n, seed, m=1.0):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(scale=0.1, size=(n, 3))
+    mass = np.full(n, m)
+    v = synth.maxwell_boltzmann(mass, 300.0, seed + 1)
+    return oi.State(x, v, mass)
+
+
+def test_respa_one_inner_step_is_baoab():
+    k = 50.0
+    fs = _harmonic(k)
+    fnc = lambda x: -0.3 * k * x + 0.01 * np.sin(x)  # any fast force
+    st_a = _state(30, 1)
+    st_b = copy.deepcopy(st_a)
+    prm = oi.LangevinParams(1.0, 1, 300.0, np.full(30, 5.0), seed=9, stream=2)
+    for _ in range(100):
+        oi.dmts_nc_step(st_a, fs, fnc, prm)
+        oi.baoab_step(st_b, fs, prm)
+    assert np.max(np.abs(st_a.x - st_b.x)) <= 1e-12 * np.max(np.abs(st_b.x))
+    assert np.max(np.abs(st_a.v - st_b.v)) <= 1e-12 * np.max(np.abs(st_b.v))
+
+
+def test_respa_with_equal_models_is_n_baoab_steps():
+    fs = _harmonic(80.0)
+    st_a = _state(25, 2)
+    st_b = copy.deepcopy(st_a)
+    prm_a = oi.LangevinParams(4.0, 4, 300.0, np.full(25, 2.0), seed=3)
+    prm_b = oi.LangevinParams(1.0, 1, 300.0, np.full(25, 2.0), seed=3)
+    for _ in range(20):
+        oi.dmts_nc_step(st_a, fs, fs, prm_a)
+    for _ in range(80):
+        oi.baoab_step(st_b, fs, prm_b)
+    assert np.array_equal(st_a.x, st_b.x) and np.array_equal(st_a.v, st_b.v)
+    assert st_a.step == st_b.step == 80
+
+
+def test_baoab_harmonic_configurational_variance():
+    """BAOAB samples the exact configurational law of a harmonic oscillator
+    for any stable step: <x^2> = k_B T / k per component."""
+    n, k, T = 4000, 215.0, 300.0
+    st = _state(n, 3)
+    st.x = np.zeros((n, 3))
+    prm = oi.LangevinParams(2.0, 1, T, np.full(n, 50.0), seed=4)
+    fs = _harmonic(k)
+    for _ in range(150):
+        oi.baoab_step(st, fs, prm)
+    acc = []
+    for _ in range(200):
+        oi.baoab_step(st, fs, prm)
+        acc.append(np.mean(st.x ** 2))
+    assert abs(np.mean(acc) / (oi.KB * T / k) - 1) < 0.02
+
+
+def test_temperature_follows_chi_square():
+    n, T = 64, 300.0
+    st = _state(n, 5)
+    st.x = np.zeros((n, 3))
+    prm = oi.LangevinParams(2.0, 1, T, np.full(n, 200.0), seed=6)
+    zero = lambda x: np.zeros_like(x)
+    temps = []
+    for step in range(3000):
+        oi.baoab_step(st, zero, prm)
+        if step >= 100 and step % 3 == 0:
+            temps.append(oi.temperature(st.v, st.m))
+    mean, sd = oa.chi2_temperature_moments(T, n)
+    assert abs(np.mean(temps) - mean) < 0.02 * mean
+    assert abs(np.std(temps) / sd - 1) < 0.1
+
+
+def test_ffl_keeps_direction():
+    st = _state(10, 7)
+    v0 = st.v.copy()
+    prm = oi.LangevinParams(1.0, 1, 300.0, np.full(10, 10.0), seed=1, thermostat="ffl")
+    oi._o_step(st, prm, 1.0)
+    cos = np.sum(st.v * v0, 1) / np.linalg.norm(st.v, axis=1) / np.linalg.norm(v0, axis=1)
+    np.testing.assert_allclose(cos, 1.0, atol=1e-12)
+
+
+# -------------------------------------------------------------- HMR/friction --
+
+def test_hmr_keeps_molecule_mass():
+    s = synth.solvated_chain(30, 50, seed=5)
+    m0 = s.standard_masses()
+    m = oi.hmr_masses(s.species, s.bonded_heavy, m0, 3.0, "set")
+    for mol in np.unique(s.molecule):
+        sel = s.molecule == mol
+        assert abs(m[sel].sum() - m0[sel].sum()) < 1e-12
+    assert np.all(m[s.species == 0] == 3.0)
+    w = synth.water_config(0)
+    mw = oi.hmr_masses(w.species, w.bonded_heavy, w.standard_masses(), 3.0, "set")
+    np.testing.assert_allclose(mw[w.species == 3], 15.999 - 2 * (3.0 - 1.008), rtol=0, atol=1e-12)
+    ma = oi.hmr_masses(w.species, w.bonded_heavy, w.standard_masses(), 3.0, "add")
+    np.testing.assert_allclose(ma[w.species == 0], 4.008, atol=1e-12)
+
+
+def test_friction_table():
+    g = oi.friction_per_atom(np.array([0, 3, 1, 0]), [100.0, 1.0, 1.0, 1.0])
+    assert list(g) == [100.0, 1.0, 1.0, 100.0]
+
+
+# ------------------------------------------------------------------- RDF ----
+
+def test_rdf_ideal_gas_is_one():
+    rng = np.random.default_rng(0)
+    box = 20.0
+    pos = rng.uniform(0, box, size=(3000, 3))
+    r, g = oa.rdf(pos, box, np.ones(3000, bool), dr=0.5)
+    sel = r > 2.0
+    assert abs(g[sel].mean() - 1) < 0.01
+    assert np.all(np.abs(g[sel] - 1) < 0.1)
+
+
+def test_rdf_simple_cubic_first_shell():
+    a, m = 3.0, 6
+    idx = np.arange(m)
+    gx, gy, gz = np.meshgrid(idx, idx, idx, indexing="ij")
+    pos = a * np.stack([gx.ravel(), gy.ravel(), gz.ravel()], 1).astype(float)
+    box = a * m
+    n = pos.shape[0]
+    dr = 0.05
+    r, g = oa.rdf(pos, box, np.ones(n, bool), dr=dr)
+    shell = np.abs(r - a) < dr
+    edges_lo = r[shell] - dr / 2
+    edges_hi = r[shell] + dr / 2
+    count = g[shell] * (n - 1) / box ** 3 * 4 / 3 * np.pi * (edges_hi ** 3 - edges_lo ** 3)
+    assert abs(count.sum() - 6.0) < 1e-9
