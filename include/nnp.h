@@ -1,0 +1,321 @@
+/*
+ * nnp.h -- C interface of libnnp, the MI355X (gfx950) hot path of DMTS-NC:
+ * distilled multi-time-stepping with non-conservative forces
+ * (Gouraud, Cattin, Ple, Adjoua, Lagardere, Piquemal; arXiv 2602.14975).
+ *
+ * Units: Angstrom, fs, amu, kcal/mol, K; frictions in ps^-1.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Device arrays are HIP device pointers owned by the caller (for example
+ *    torch tensors); the library never frees or reallocates them.  Host
+ *    arrays are read during the call only.
+ *  - Per-atom vectors are structure-of-arrays: x row, then y row, then z row
+ *    ([3][n], row stride n).  Positions and velocities are float64; forces
+ *    float32.  Positions are kept unwrapped; only the pair rule wraps.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls enqueue work on it and return without waiting unless stated.
+ *  - A call returns NNP_OK or a negative status and never throws;
+ *    nnp_last_error() then describes the failure (thread-local string, valid
+ *    until the next call from the same thread).
+ *  - Workspaces are caller-owned device buffers of at least the size
+ *    reported by nnp_workspace_size(); their contents are scratch.
+ *
+ * Pair rule (paper, Methods "Model architecture": N(i) is every j != i
+ * within the cutoff): in float64, per component d = x_j - x_i,
+ * d = d - L * rint(d * (1/L)) with rint rounding half to even, then
+ * r2 = (dx*dx + dy*dy) + dz*dz without fused multiply-add, and j is a
+ * neighbour of i iff r2 < rc*rc.  The relation is symmetric.  It requires
+ * rc < L/2 for every box.
+ */
+#ifndef NNP_H
+#define NNP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nnp_status;
+enum {
+    NNP_OK = 0,
+    NNP_EINVAL = -1,     /* bad argument, descriptor, size or geometry */
+    NNP_ENOMEM = -2,     /* device allocation failed or budget exceeded */
+    NNP_ECAPACITY = -3,  /* a neighbour list did not fit its buffer */
+    NNP_EDEVICE = -4,    /* a HIP runtime call failed */
+    NNP_EUNSTABLE = -5,  /* non-finite positions or velocities detected */
+    NNP_ENOTFOUND = -6   /* unknown ticket */
+};
+
+const char* nnp_last_error(void);
+/* Interface version (increments on incompatible change). */
+int32_t nnp_abi_version(void);
+
+/* ------------------------------------------------------------------ models
+ * Two model kinds share one embedding block.
+ *
+ * NNP_MODEL_CONS, the conservative potential U at the outer step (paper,
+ * Methods "Model architecture", first paragraph; a synthetic equivariant
+ * message-passing stand-in for FeNNix-Bio1, whose weights are unavailable):
+ *   s_i = emb[t_i], v_i = 0; then n_layers times, with
+ *   phi_j = W2 silu(W1 s_j + b1) + b2, w_ij = (Wr e(r_ij) + br) fcos(r_ij),
+ *   [a|b|c]_ij = phi_j * w_ij:
+ *     s_i += sum_j a_ij;  v_i[alpha] += sum_j (b_ij v_j[alpha] + u_ij[alpha] c_ij)
+ *   followed by the update block
+ *     Uv = U v, Vv = V v, n = sqrt(sum_alpha Vv^2 + 1e-8),
+ *     [p|q|o] = M2 silu(M1 [s; n] + m1) + m2,
+ *     s += p + q * sum_alpha Uv Vv,  v += o * Uv;
+ *   E_i = wo . silu(Wo s_i + bo) + beta[t_i], E = sum_i E_i; forces -dE/dx.
+ *   e_k(r) = sqrt(2/rc) sin(k pi r/rc)/r (k = 1..n_rbf);
+ *   fcos(r) = (cos(pi r/rc) + 1)/2.
+ *
+ * NNP_MODEL_NC, the distilled non-conservative force model (paper, Methods:
+ * equations for q_ih, k_ih, c_ijh, F_ij and F_i): one embedding layer with
+ * the polynomial envelope u(d) = 1 - (p+1)(p+2)/2 d^p + p(p+2) d^(p+1)
+ *   - p(p+1)/2 d^(p+2), d = r/rc, in place of fcos; then
+ *   q_ih = Wq[h] s_i, k_ih = Wk[h] s_i (n_c each, h < n_s + n_l),
+ *   V_ih = sum_f WV[h][f] v_i[:, f] (h < n_l),
+ *   c_ijh = q_ih . k_jh / sqrt(n_c),
+ *   F_ij = (sum_{h<n_s} c_ijh B_h(r)) (u_ij + sum_{h<n_l} c_ij(n_s+h) V_ih) u(r/rc),
+ *   F_i = sum_{j in N(i)} (F_ij - F_ji), with B_h the same Bessel basis.
+ *   The screened nuclear repulsion term of the paper is not included.
+ *
+ * Weight manifest: `weights` is one flat float64 host vector holding, in
+ * order, row-major [out][in] matrices and vectors (F = width, K = n_rbf,
+ * S = n_species, H = n_s + n_l):
+ *   emb[S][F];
+ *   per layer (CONS: n_layers of them, NC: exactly one):
+ *     W1[F][F] b1[F] W2[3F][F] b2[3F] Wr[3F][K] br[3F] U[F][F] V[F][F]
+ *     M1[F][2F] m1[F] M2[3F][F] m2[3F];
+ *   CONS: Wo[F][F] bo[F] wo[F] beta[S];
+ *   NC:   Wq[H][n_c][F] Wk[H][n_c][F] WV[n_l][F].
+ * Supported sizes: width in {16, 32, 64, 128}; n_rbf in {8, 16};
+ * NC: n_s = 8, n_l = 2, n_c = 8, poly_p = 5.
+ */
+enum { NNP_MODEL_CONS = 0, NNP_MODEL_NC = 1 };
+enum { NNP_FP32 = 0, NNP_BF16 = 1 };  /* arithmetic of the perceptrons and filters */
+
+typedef struct {
+    int32_t kind;        /* NNP_MODEL_CONS or NNP_MODEL_NC */
+    int32_t n_species;   /* 1..8 */
+    int32_t width;       /* F */
+    int32_t n_layers;    /* CONS: >= 1; NC: 1 */
+    int32_t n_rbf;       /* K */
+    int32_t poly_p;      /* NC envelope order */
+    int32_t n_s, n_l, n_c;
+    int32_t precision;   /* NNP_FP32 or NNP_BF16 */
+    double cutoff;       /* rc, Angstrom */
+    const double* weights;  /* host, manifest order */
+    int64_t n_weights;
+} nnp_model_desc;
+
+typedef struct nnp_model nnp_model;
+
+/* Copies the weights to the device (the only allocation of a model).
+ * NNP_EINVAL if the descriptor is unsupported or n_weights does not match
+ * the manifest. */
+nnp_status nnp_model_create(const nnp_model_desc* desc, nnp_model** out);
+void nnp_model_destroy(nnp_model* model);
+int64_t nnp_model_n_weights(const nnp_model* model);
+/* Replaces the weights from a device float32 vector in manifest order
+ * (used by distillation after an optimiser step).  Enqueued on `stream`. */
+nnp_status nnp_model_set_weights_f32(nnp_model* model, const float* weights_dev,
+                                     int64_t n_weights, void* stream);
+
+/* ----------------------------------------------------------------- systems
+ * A system is one or more independent replicas packed contiguously: replica
+ * r owns atoms [rep_start[r], rep_start[r+1]) and has cubic box box[r].
+ * Neighbour lists never cross replicas. */
+typedef struct {
+    int64_t n_atoms;
+    int32_t n_rep;               /* >= 1 */
+    const double* pos;           /* device [3][n_atoms] */
+    const int32_t* species;      /* device [n_atoms] */
+    const int32_t* rep_of_atom;  /* device [n_atoms]; may be NULL if n_rep == 1 */
+    const double* box_dev;       /* device [n_rep]; may be NULL if n_rep == 1 */
+    const int64_t* rep_start;    /* host [n_rep + 1] */
+    const double* box;           /* host [n_rep] */
+} nnp_system;
+
+/* Neighbour list in CSR form: row i lists its neighbours j in ascending
+ * order in nbr[offsets[i] .. offsets[i+1]).  Buffers are caller-owned. */
+typedef struct {
+    int64_t n_atoms;    /* rows */
+    int64_t capacity;   /* entries nbr can hold */
+    int64_t n_edges;    /* out: entries written, or required on NNP_ECAPACITY */
+    int32_t* offsets;   /* device [n_atoms + 1] */
+    int32_t* nbr;       /* device [capacity] */
+    int32_t* rev;       /* device [capacity] or NULL: rev[e] = index of the
+                           reverse pair (j, i) of entry e = (i, j) */
+    double cutoff;      /* radius of the pair rule used to build the list */
+} nnp_nlist;
+
+/* Workspace bytes sufficient for every call below on systems of at most
+ * n_atoms atoms, n_rep replicas and max_edges list entries per list.
+ * Either model may be NULL. */
+nnp_status nnp_workspace_size(const nnp_model* cons, const nnp_model* nc, int64_t n_atoms,
+                              int32_t n_rep, int64_t max_edges, size_t* bytes);
+
+/* Builds the list of all pairs under the pair rule at nl->cutoff (a cell
+ * list with a 27-cell stencil where a replica has >= 3 cells per side, all
+ * atoms of the replica otherwise).  Synchronises `stream` to learn the edge
+ * count.  NNP_ECAPACITY: nl->n_edges holds the required capacity and the
+ * buffers are unchanged; NNP_EINVAL: cutoff >= L/2 or bad sizes. */
+nnp_status nnp_neighbors(const nnp_system* sys, nnp_nlist* nl, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* Conservative energy and forces F = -dE/dx by a hand-written reverse pass
+ * (the outer-step force of Algorithm 1).  `nl` may be built at any radius
+ * >= the model cutoff (a Verlet list); pairs are filtered with the pair rule
+ * at the model cutoff, so the result does not depend on the list radius.
+ * energy: device float64 [n_rep] (per replica); forces: device float32
+ * [3][n_atoms]. */
+nnp_status nnp_cons_energy_forces(const nnp_model* cons, const nnp_system* sys,
+                                  const nnp_nlist* nl, void* ws, size_t ws_bytes,
+                                  double* energy, float* forces, void* stream);
+
+/* Non-conservative forces F_NC (the inner-step force of Algorithm 1);
+ * forces: device float32 [3][n_atoms].  Same list rules as above. */
+nnp_status nnp_nc_forces(const nnp_model* nc, const nnp_system* sys, const nnp_nlist* nl,
+                         void* ws, size_t ws_bytes, float* forces, void* stream);
+
+/* Weight gradient of the NC model: given dl_df = dL/dF_NC (device float32
+ * [3][n_atoms]) writes dL/dtheta (device float32 [n_weights], manifest
+ * order), the vector-Jacobian product used to distil the NC model onto
+ * conservative forces.  Deterministic (fixed reduction order). */
+nnp_status nnp_nc_weight_grad(const nnp_model* nc, const nnp_system* sys, const nnp_nlist* nl,
+                              const float* dl_df, float* dl_dtheta, void* ws, size_t ws_bytes,
+                              void* stream);
+
+/* One Adam step on a device float32 parameter vector (in place):
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; with bias corrections for
+ * step t (>= 1): p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
+nnp_status nnp_adam_step(float* param, const float* grad, float* m, float* v, int64_t n,
+                         int64_t t, double lr, double beta1, double beta2, double eps,
+                         void* stream);
+
+/* --------------------------------------------------------------- integrator
+ * Hydrogen mass repartitioning (paper, Methods "Hydrogen Mass
+ * Repartitioning"): for each atom a with bonded_heavy[a] = h >= 0 (a
+ * hydrogen bonded to heavy atom h) the new mass is h_mass (mode 0, "set") or
+ * mass[a] + h_mass (mode 1, "add"); h loses the difference, so every
+ * molecule keeps its mass.  Host arrays, n entries; writes out_mass. */
+nnp_status nnp_hmr_masses(int64_t n, const int32_t* bonded_heavy, const double* mass,
+                          double h_mass, int32_t mode, double* out_mass);
+
+enum { NNP_MODE_DMTS_NC = 0, NNP_MODE_STS = 1 };
+enum { NNP_THERMO_LANGEVIN = 0, NNP_THERMO_FFL = 1 };
+
+typedef struct {
+    double dt_outer_fs;     /* Delta (STS: the step) */
+    int32_t n_inner;        /* n; delta = Delta / n (STS: ignored, 1) */
+    int32_t mode;           /* NNP_MODE_DMTS_NC or NNP_MODE_STS */
+    int32_t thermostat;     /* NNP_THERMO_LANGEVIN or NNP_THERMO_FFL */
+    int32_t check_every;    /* outer steps between finiteness checks (>= 1) */
+    double temperature_K;
+    uint64_t seed;          /* Philox key word 0 */
+    uint64_t stream_id;     /* Philox key word 1 for replica 0; replica r uses stream_id + r */
+    double skin;            /* Verlet skin (A) of both lists; lists are rebuilt when an
+                               atom has moved more than skin/2 since the last build */
+} respa_params;
+
+/* Device-resident trajectory state.  All pointers are caller-owned device
+ * buffers.  The neighbour lists are built at (model cutoff + skin). */
+typedef struct {
+    nnp_system sys;        /* sys.pos aliases pos */
+    double* pos;           /* [3][n] read/write */
+    double* vel;           /* [3][n] read/write */
+    const double* mass;    /* [n] amu (HMR applied by the caller if wanted) */
+    const double* gamma;   /* [n] friction, ps^-1 (per-species table expanded) */
+    float* f_cons;         /* [3][n] cached conservative force F */
+    float* f_nc;           /* [3][n] cached fast force F_NC (DMTS-NC) */
+    double* energy;        /* [n_rep] conservative energy at the last evaluation */
+    double* pos_ref;       /* [3][n] positions at the last list build */
+    nnp_nlist nl_cons;     /* conservative list (cutoff + skin) */
+    nnp_nlist nl_nc;       /* NC list (NC cutoff + skin); unused in STS mode */
+    uint64_t step;         /* O-steps done so far (advanced by the call) */
+    int32_t first_step;    /* 1: evaluate F and F_NC before the first kick */
+    int32_t lists_valid;   /* 0: build both lists before the first use */
+    double* ke;            /* [n_outer][n_rep] kinetic energy after each outer
+                              step (kcal/mol), or NULL */
+    int64_t n_rebuilds;    /* out: list rebuilds performed (accumulates) */
+} respa_state;
+
+/* Advances the state by n_outer outer steps of Algorithm 1 (DMTS-NC:
+ * v += (D/2) M^-1 (F - F_NC); n x [B(d/2), A(d/2), O(d), A(d/2), F_NC, B(d/2)];
+ * F; v += (D/2) M^-1 (F - F_NC)), or of BAOAB with the conservative force
+ * (STS).  The O step is v <- c v + sqrt((1 - c^2) kT/m) G, c = exp(-gamma d),
+ * G from Philox-4x64-10 with key (seed, stream_id + r) and counter
+ * (atom index within its replica, O-step index, 0, 0), Box-Muller on the four
+ * uniforms ((w >> 11) + 0.5) 2^-53; FFL keeps each atom's velocity direction.
+ * Every `check_every` outer steps the call synchronises and checks list
+ * capacity and finiteness; on NNP_ECAPACITY the state is restored to the
+ * start of the failing outer step (grow the list buffers and call again);
+ * on NNP_EUNSTABLE it is left at the last checked good step.  The sizes of
+ * completed steps are reflected in state->step. */
+nnp_status respa_step(const nnp_model* cons, const nnp_model* nc, respa_state* state,
+                      const respa_params* params, int32_t n_outer, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* ------------------------------------------------------------------ serving
+ * Continuous batching of independent replicas.  Replicas are submitted at
+ * any time, admitted at outer-step boundaries when a slot is free and their
+ * device footprint fits the HBM budget, advanced together in fused launches
+ * (one packed system, block-diagonal neighbour lists, per-replica boxes,
+ * Philox keys and step counters), and retired when they reach their step
+ * count.  All their state stays on the device while resident.  Results do
+ * not depend on which other replicas share the launches. */
+typedef struct nnp_server nnp_server;
+
+nnp_status nnp_server_create(const nnp_model* cons, const nnp_model* nc,
+                             const respa_params* params, size_t hbm_budget_bytes,
+                             int32_t max_slots, nnp_server** out);
+void nnp_server_destroy(nnp_server* server);
+
+typedef struct {
+    int64_t n;                 /* atoms */
+    const double* pos;         /* host [n][3] */
+    const double* vel;         /* host [n][3] */
+    const double* mass;        /* host [n] */
+    const double* gamma;       /* host [n] ps^-1 */
+    const int32_t* species;    /* host [n] */
+    double box;
+    uint64_t seed;             /* Philox key word 0 for this replica */
+    uint64_t stream_id;        /* Philox key word 1 */
+    int32_t n_outer_steps;
+} replica_desc;
+
+enum { NNP_REPLICA_QUEUED = 0, NNP_REPLICA_RUNNING = 1, NNP_REPLICA_DONE = 2,
+       NNP_REPLICA_FAILED = 3 };
+
+typedef struct {
+    int32_t state;
+    int32_t steps_done;
+    nnp_status error;
+    double t_submit, t_admit, t_done;   /* seconds on the server clock */
+} replica_status;
+
+/* Copies the replica into the host queue and returns a ticket; never blocks
+ * on the device.  NNP_EINVAL for bad geometry, NNP_ENOMEM if it can never fit
+ * the budget. */
+nnp_status replica_submit(nnp_server* server, const replica_desc* desc, uint64_t* ticket);
+/* Status of a ticket; for DONE replicas, pos_out/vel_out (host [n][3], or
+ * NULL) receive the final state. */
+nnp_status replica_poll(nnp_server* server, uint64_t ticket, replica_status* out,
+                        double* pos_out, double* vel_out);
+/* Runs up to max_outer_steps fused outer steps, admitting and retiring at
+ * each boundary; returns after the first step boundary at which nothing is
+ * resident or queued.  *n_resident receives the resident count. */
+nnp_status nnp_server_progress(nnp_server* server, int32_t max_outer_steps, int32_t* n_resident);
+/* Copies up to cap per-replica step latencies (seconds between consecutive
+ * outer-step completions of a replica; the first from its admission). */
+nnp_status nnp_server_step_latencies(nnp_server* server, double* out, int64_t cap, int64_t* n_out);
+/* Server clock now (seconds). */
+double nnp_server_clock(const nnp_server* server);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NNP_H */

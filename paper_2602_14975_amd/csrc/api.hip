@@ -1,0 +1,855 @@
+// C entry points of libnnp (see include/nnp.h) and the host-side drivers that
+// sequence the kernels of one force evaluation or one integration call.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <mutex>
+
+#include "common.h"
+#include "kernels.h"
+#include "model.h"
+
+namespace nnp {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+}  // namespace nnp
+
+using namespace nnp;
+
+#define NNP_API_BEGIN try {
+#define NNP_API_END                                                        \
+    }                                                                      \
+    catch (const Fail& f) {                                                \
+        return f.code;                                                     \
+    }                                                                      \
+    catch (const std::exception& e) {                                      \
+        set_error(std::string("internal error: ") + e.what());             \
+        return NNP_EINVAL;                                                 \
+    }                                                                      \
+    return NNP_OK;
+
+extern "C" const char* nnp_last_error(void) { return g_err.c_str(); }
+extern "C" int32_t nnp_abi_version(void) { return 1; }
+
+// ===================================================================== model
+namespace nnp {
+
+static int64_t manifest_count(const nnp_model_desc& d) {
+    const int64_t F = d.width, K = d.n_rbf, S = d.n_species;
+    const int64_t block = F * F + F + 3 * F * F + 3 * F + 3 * F * K + 3 * F + 2 * F * F + 2 * F * F + F +
+                          3 * F * F + 3 * F;
+    int64_t n = S * F;
+    if (d.kind == NNP_MODEL_CONS) {
+        n += d.n_layers * block + F * F + F + F + S;
+    } else {
+        const int64_t H = d.n_s + d.n_l;
+        n += block + 2 * H * d.n_c * F + d.n_l * F;
+    }
+    return n;
+}
+
+void Model::layout() {
+    const int64_t F = desc.width, K = desc.n_rbf, S = desc.n_species;
+    int64_t o = 0;
+    auto take = [&](int64_t count) { int64_t at = o; o += count; return at; };
+    off_emb = take(S * F);
+    const int L = desc.kind == NNP_MODEL_CONS ? desc.n_layers : 1;
+    for (int l = 0; l < L; ++l) {
+        LayerOff& lo = loff[l];
+        lo.W1 = take(F * F); lo.b1 = take(F);
+        lo.W2 = take(3 * F * F); lo.b2 = take(3 * F);
+        lo.Wr = take(3 * F * K); lo.br = take(3 * F);
+        lo.U = take(F * F); lo.V = take(F * F);
+        lo.M1 = take(2 * F * F); lo.m1 = take(F);
+        lo.M2 = take(3 * F * F); lo.m2 = take(3 * F);
+    }
+    if (desc.kind == NNP_MODEL_CONS) {
+        off_Wo = take(F * F); off_bo = take(F); off_wo = take(F); off_beta = take(S);
+    } else {
+        const int64_t H = desc.n_s + desc.n_l;
+        off_Wq = take(H * desc.n_c * F); off_Wk = take(H * desc.n_c * F); off_WV = take(desc.n_l * F);
+    }
+    n_weights = o;
+}
+
+}  // namespace nnp
+
+extern "C" nnp_status nnp_model_create(const nnp_model_desc* desc, nnp_model** out) {
+    NNP_API_BEGIN
+    NNP_REQUIRE(desc && out, NNP_EINVAL, "null argument");
+    *out = nullptr;
+    const nnp_model_desc& d = *desc;
+    NNP_REQUIRE(d.kind == NNP_MODEL_CONS || d.kind == NNP_MODEL_NC, NNP_EINVAL, "unknown model kind");
+    NNP_REQUIRE(d.width == 8 || d.width == 16 || d.width == 32 || d.width == 64 || d.width == 128, NNP_EINVAL,
+                "width must be 8, 16, 32, 64 or 128");
+    NNP_REQUIRE(d.n_species >= 1 && d.n_species <= 8, NNP_EINVAL, "n_species must be in 1..8");
+    NNP_REQUIRE(d.cutoff > 0, NNP_EINVAL, "cutoff must be positive");
+    NNP_REQUIRE(d.precision == NNP_FP32 || d.precision == NNP_BF16, NNP_EINVAL, "unknown precision");
+    if (d.kind == NNP_MODEL_CONS) {
+        NNP_REQUIRE(d.n_rbf == 16, NNP_EINVAL, "conservative model needs n_rbf = 16");
+        NNP_REQUIRE(d.n_layers >= 1 && d.n_layers <= kMaxLayers, NNP_EINVAL, "n_layers must be in 1..4");
+    } else {
+        NNP_REQUIRE(d.n_rbf == 8 && d.n_s == 8 && d.n_l == 2 && d.n_c == 8 && d.poly_p == 5 && d.n_layers == 1,
+                    NNP_EINVAL, "NC model needs n_rbf = n_s = n_c = 8, n_l = 2, poly_p = 5, one layer");
+        NNP_REQUIRE(d.width <= 64, NNP_EINVAL, "NC width must be <= 64");
+    }
+    NNP_REQUIRE(d.weights != nullptr, NNP_EINVAL, "weights are required");
+    const int64_t need = manifest_count(d);
+    NNP_REQUIRE(d.n_weights == need, NNP_EINVAL,
+                "weight vector has " + std::to_string(d.n_weights) + " entries, manifest needs " +
+                    std::to_string(need));
+    Model* m = new Model();
+    m->desc = d;
+    m->desc.weights = nullptr;
+    m->layout();
+    std::vector<float> w32(size_t(m->n_weights));
+    for (int64_t k = 0; k < m->n_weights; ++k) w32[k] = float(d.weights[k]);
+    hipError_t e = hipMalloc(&m->w, sizeof(float) * m->n_weights);
+    if (e != hipSuccess) {
+        delete m;
+        set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+        return NNP_ENOMEM;
+    }
+    e = hipMemcpy(m->w, w32.data(), sizeof(float) * m->n_weights, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(m->w);
+        delete m;
+        set_error(std::string("hipMemcpy: ") + hipGetErrorString(e));
+        return NNP_EDEVICE;
+    }
+    *out = reinterpret_cast<nnp_model*>(m);
+    NNP_API_END
+}
+
+extern "C" void nnp_model_destroy(nnp_model* model) {
+    if (!model) return;
+    Model* m = reinterpret_cast<Model*>(model);
+    if (m->w) (void)hipFree(m->w);
+    delete m;
+}
+
+extern "C" int64_t nnp_model_n_weights(const nnp_model* model) {
+    return model ? reinterpret_cast<const Model*>(model)->n_weights : -1;
+}
+
+extern "C" nnp_status nnp_model_set_weights_f32(nnp_model* model, const float* weights_dev, int64_t n_weights,
+                                                void* stream) {
+    NNP_API_BEGIN
+    NNP_REQUIRE(model && weights_dev, NNP_EINVAL, "null argument");
+    Model* m = reinterpret_cast<Model*>(model);
+    NNP_REQUIRE(n_weights == m->n_weights, NNP_EINVAL, "weight count does not match the model");
+    NNP_HIP(hipMemcpyAsync(m->w, weights_dev, sizeof(float) * n_weights, hipMemcpyDeviceToDevice,
+                           static_cast<hipStream_t>(stream)));
+    NNP_API_END
+}
+
+// ============================================================ system tables
+namespace nnp {
+
+void check_system(const nnp_system* sys) {
+    NNP_REQUIRE(sys && sys->pos && sys->species && sys->rep_start && sys->box, NNP_EINVAL, "incomplete system");
+    NNP_REQUIRE(sys->n_atoms >= 1 && sys->n_atoms < (int64_t(1) << 31), NNP_EINVAL, "n_atoms out of range");
+    NNP_REQUIRE(sys->n_rep >= 1, NNP_EINVAL, "n_rep must be >= 1");
+    NNP_REQUIRE(sys->n_rep == 1 || (sys->rep_of_atom && sys->box_dev), NNP_EINVAL,
+                "multi-replica systems need rep_of_atom and box_dev");
+    NNP_REQUIRE(sys->rep_start[0] == 0 && sys->rep_start[sys->n_rep] == sys->n_atoms, NNP_EINVAL,
+                "rep_start must run from 0 to n_atoms");
+    for (int r = 0; r < sys->n_rep; ++r) {
+        NNP_REQUIRE(sys->rep_start[r + 1] >= sys->rep_start[r], NNP_EINVAL, "rep_start must be non-decreasing");
+        NNP_REQUIRE(sys->box[r] > 0 && std::isfinite(sys->box[r]), NNP_EINVAL, "box edges must be positive");
+    }
+}
+
+void carve_tables(Arena& a, int32_t n_rep, SysTables& t) {
+    t.rep_start = a.take<int64_t>(n_rep + 1);
+    t.box = a.take<double>(n_rep);
+    t.inv_box = a.take<double>(n_rep);
+    t.seed = a.take<uint64_t>(n_rep);
+    t.stream = a.take<uint64_t>(n_rep);
+    t.step_base = a.take<uint64_t>(n_rep);
+    t.flags = a.take<int>(16);
+    t.rep_bad = a.take<int>(n_rep);
+    t.rebuilds = a.take<long long>(1);
+}
+
+// Uploads the replica tables of `sys` (pageable copies are staged by the
+// runtime before hipMemcpyAsync returns).
+RepGeom upload_tables(const nnp_system& sys, SysTables& t, hipStream_t s, std::vector<double>& host_scratch) {
+    const int R = sys.n_rep;
+    host_scratch.assign(size_t(2 * R), 0.0);
+    for (int r = 0; r < R; ++r) {
+        host_scratch[r] = sys.box[r];
+        host_scratch[R + r] = 1.0 / sys.box[r];
+    }
+    NNP_HIP(hipMemcpyAsync(t.rep_start, sys.rep_start, sizeof(int64_t) * (R + 1), hipMemcpyHostToDevice, s));
+    NNP_HIP(hipMemcpyAsync(t.box, host_scratch.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+    NNP_HIP(hipMemcpyAsync(t.inv_box, host_scratch.data() + R, sizeof(double) * R, hipMemcpyHostToDevice, s));
+    RepGeom g{};
+    g.rep_of_atom = R > 1 ? sys.rep_of_atom : nullptr;
+    g.box = t.box;
+    g.inv_box = t.inv_box;
+    g.rep_start = t.rep_start;
+    g.box0 = sys.box[0];
+    g.inv0 = 1.0 / sys.box[0];
+    return g;
+}
+
+// ========================================================= model scratch
+void carve_model(Arena& a, const Model* m, int64_t n, int64_t E, bool for_wgrad, ModelBuf& b) {
+    const int64_t F = m->desc.width;
+    const int L = m->n_layers();
+    for (int l = 0; l <= L; ++l) {
+        b.s[l] = a.take<float>(n * F);
+        b.v[l] = a.take<float>(n * 3 * F);
+    }
+    for (int l = 0; l < L; ++l) {
+        LayerBuf& lb = b.layer[l];
+        lb.h1 = a.take<float>(n * F);
+        lb.zphi = a.take<float>(n * F);
+        lb.phi = a.take<float>(n * 3 * F);
+        lb.smid = a.take<float>(n * F);
+        lb.vmid = a.take<float>(n * 3 * F);
+        lb.UV = a.take<float>(n * 6 * F);
+        lb.X = a.take<float>(n * 2 * F);
+        lb.a1 = a.take<float>(n * F);
+        lb.z = a.take<float>(n * F);
+        lb.pqo = a.take<float>(n * 3 * F);
+    }
+    if (m->desc.kind == NNP_MODEL_CONS) {
+        b.ao = a.take<float>(n * F);
+        b.zo = a.take<float>(n * F);
+        b.Ei = a.take<float>(n);
+        b.gs = a.take<float>(n * F);
+        b.gs2 = a.take<float>(n * F);
+        b.gv = a.take<float>(n * 3 * F);
+        b.gv2 = a.take<float>(n * 3 * F);
+        b.gpqo = a.take<float>(n * 3 * F);
+        b.ga1 = a.take<float>(n * F);
+        b.gX = a.take<float>(n * 2 * F);
+        b.gUV = a.take<float>(n * 6 * F);
+        b.gphi = a.take<float>(n * 3 * F);
+        b.gh1 = a.take<float>(n * F);
+        b.edge_g = a.take<float>(E * 3);
+        b.rev = a.take<int>(E);
+    } else {
+        const int64_t HC = 2 * int64_t(m->desc.n_s + m->desc.n_l) * m->desc.n_c;
+        b.QK = a.take<float>(n * HC);
+        b.Vh = a.take<float>(n * 3 * m->desc.n_l);
+        if (for_wgrad) {
+            b.gQK = a.take<float>(n * HC);
+            b.gVh = a.take<float>(n * 3 * m->desc.n_l);
+            b.gs = a.take<float>(n * F);
+            b.gs2 = a.take<float>(n * F);
+            b.gv = a.take<float>(n * 3 * F);
+            b.gv2 = a.take<float>(n * 3 * F);
+            b.gpqo = a.take<float>(n * 3 * F);
+            b.ga1 = a.take<float>(n * F);
+            b.gX = a.take<float>(n * 2 * F);
+            b.gUV = a.take<float>(n * 6 * F);
+            b.gphi = a.take<float>(n * 3 * F);
+            b.gh1 = a.take<float>(n * F);
+            const int64_t maxNK = std::max<int64_t>({3 * F * F, HC * F, 2 * F * F});
+            b.chunk_part = a.take<float>(int64_t(cdiv(3 * n, kChunk) + 1) * maxNK);
+            b.mp_part = a.take<float>(int64_t(mp_blocks(int(n), int(F))) * 3 * F * (m->desc.n_rbf + 1));
+            b.filt_sum = a.take<float>(3 * F * (m->desc.n_rbf + 1));
+        }
+    }
+}
+
+// Embedding forward: species embedding, then each layer's perceptron,
+// message and update block.  Every intermediate needed by the reverse pass
+// stays in `b`.
+void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, ModelBuf& b, hipStream_t s) {
+    const int n = int(sys.n_atoms);
+    const int F = m->desc.width, K = m->desc.n_rbf;
+    const int cut = m->desc.kind == NNP_MODEL_CONS ? 0 : 1;
+    launch_embed(n, F, m->desc.n_species, sys.species, m->p(m->off_emb), b.s[0], b.v[0], s);
+    for (int l = 0; l < m->n_layers(); ++l) {
+        const LayerOff& lo = m->loff[l];
+        LayerBuf& lb = b.layer[l];
+        gemm_xwt(n, F, F, b.s[l], F, m->p(lo.W1), m->p(lo.b1), lb.zphi, F, EPI_SILU, lb.h1, F, false, s);
+        gemm_xwt(n, 3 * F, F, lb.zphi, F, m->p(lo.W2), m->p(lo.b2), lb.phi, 3 * F, EPI_NONE, nullptr, 0, false, s);
+        MpFwd a{b.s[l], b.v[l], lb.phi, m->p(lo.Wr), m->p(lo.br), lb.smid, lb.vmid};
+        launch_message_fwd(F, K, cut, mg, a, s);
+        gemm_xwt(3 * n, 2 * F, F, lb.vmid, F, m->p(lo.U), nullptr, lb.UV, 2 * F, EPI_NONE, nullptr, 0, false, s);
+        launch_build_x(n, F, lb.smid, lb.UV, lb.X, s);
+        gemm_xwt(n, F, 2 * F, lb.X, 2 * F, m->p(lo.M1), m->p(lo.m1), lb.z, F, EPI_SILU, lb.a1, F, false, s);
+        gemm_xwt(n, 3 * F, F, lb.z, F, m->p(lo.M2), m->p(lo.m2), lb.pqo, 3 * F, EPI_NONE, nullptr, 0, false, s);
+        launch_update_combine(n, F, lb.smid, lb.vmid, lb.UV, lb.pqo, b.s[l + 1], b.v[l + 1], s);
+    }
+}
+
+// Reverse of one embedding layer.  In: gs, gv = adjoints of the layer
+// output.  Out: gs, gv = adjoints of the layer input (buffers swapped).
+// With `dtheta`, the weight adjoints of the layer are written too.
+void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float* edge_g, float* dtheta,
+                    hipStream_t s) {
+    const int n = mg.n;
+    const int F = m->desc.width, K = m->desc.n_rbf;
+    const int cut = m->desc.kind == NNP_MODEL_CONS ? 0 : 1;
+    const LayerOff& lo = m->loff[l];
+    LayerBuf& lb = b.layer[l];
+    const bool wg = dtheta != nullptr;
+    launch_update_combine_bwd(n, F, lb.UV, lb.pqo, b.gs, b.gv, b.gpqo, b.gUV, s);
+    if (wg) {
+        gemm_wgrad(n, 3 * F, F, b.gpqo, 3 * F, lb.z, F, dtheta + lo.M2, b.chunk_part, kChunk, false, s);
+        colsum(n, 3 * F, b.gpqo, 3 * F, dtheta + lo.m2, b.chunk_part, kChunk, false, s);
+    }
+    gemm_gw(n, 3 * F, F, b.gpqo, 3 * F, m->p(lo.M2), b.ga1, F, EPI_DSILU, lb.a1, F, false, s);
+    if (wg) {
+        gemm_wgrad(n, F, 2 * F, b.ga1, F, lb.X, 2 * F, dtheta + lo.M1, b.chunk_part, kChunk, false, s);
+        colsum(n, F, b.ga1, F, dtheta + lo.m1, b.chunk_part, kChunk, false, s);
+    }
+    gemm_gw(n, F, 2 * F, b.ga1, F, m->p(lo.M1), b.gX, 2 * F, EPI_NONE, nullptr, 0, false, s);
+    launch_norm_bwd(n, F, b.gs, b.gX, lb.X, lb.UV, b.gs2, b.gUV, s);  // gs2 = g_smid
+    if (wg) gemm_wgrad(3 * n, 2 * F, F, b.gUV, 2 * F, lb.vmid, F, dtheta + lo.U, b.chunk_part, kChunk, false, s);
+    gemm_gw(3 * n, 2 * F, F, b.gUV, 2 * F, m->p(lo.U), b.gv, F, EPI_NONE, nullptr, 0, true, s);  // gv = g_vmid
+    MpBwd a{};
+    a.v_in = b.v[l];
+    a.phi = lb.phi;
+    a.gsm = b.gs2;
+    a.gvm = b.gv;
+    a.Wr = m->p(lo.Wr);
+    a.br = m->p(lo.br);
+    a.gphi = b.gphi;
+    a.gv_in = b.gv2;
+    a.edge_g = edge_g;
+    a.wgrad_part = wg ? b.mp_part : nullptr;
+    launch_message_bwd(F, K, cut, mg, a, edge_g != nullptr, wg, s);
+    if (wg) {
+        const int nb = mp_blocks(n, F);
+        const int64_t cnt = int64_t(3) * F * (K + 1);
+        launch_reduce_chunks(cnt, nb, b.mp_part, cnt, b.filt_sum, false, s);
+        launch_split_filter_grad(3 * F, K, b.filt_sum, dtheta + lo.Wr, dtheta + lo.br, s);
+        gemm_wgrad(n, 3 * F, F, b.gphi, 3 * F, lb.zphi, F, dtheta + lo.W2, b.chunk_part, kChunk, false, s);
+        colsum(n, 3 * F, b.gphi, 3 * F, dtheta + lo.b2, b.chunk_part, kChunk, false, s);
+    }
+    gemm_gw(n, 3 * F, F, b.gphi, 3 * F, m->p(lo.W2), b.gh1, F, EPI_DSILU, lb.h1, F, false, s);
+    if (wg) {
+        gemm_wgrad(n, F, F, b.gh1, F, b.s[l], F, dtheta + lo.W1, b.chunk_part, kChunk, false, s);
+        colsum(n, F, b.gh1, F, dtheta + lo.b1, b.chunk_part, kChunk, false, s);
+    }
+    gemm_gw(n, F, F, b.gh1, F, m->p(lo.W1), b.gs2, F, EPI_NONE, nullptr, 0, true, s);  // gs2 = g_s_in
+    std::swap(b.gs, b.gs2);
+    std::swap(b.gv, b.gv2);
+}
+
+MpGeom make_geom(const Model* m, const nnp_system& sys, const RepGeom& geom, const nnp_nlist& nl) {
+    MpGeom mg{};
+    mg.n = int(sys.n_atoms);
+    mg.pos = sys.pos;
+    mg.geom = geom;
+    mg.off = nl.offsets;
+    mg.nbr = nl.nbr;
+    mg.rc = m->desc.cutoff;
+    mg.rc2 = m->desc.cutoff * m->desc.cutoff;
+    mg.bessel_norm = std::sqrt(2.0 / m->desc.cutoff);
+    return mg;
+}
+
+void cons_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const SysTables& t, const nnp_nlist& nl,
+               const int* rev, ModelBuf& b, double* energy, float* forces, hipStream_t s) {
+    const int n = int(sys.n_atoms);
+    const int F = m->desc.width;
+    MpGeom mg = make_geom(m, sys, geom, nl);
+    embed_forward(m, sys, mg, b, s);
+    const int L = m->n_layers();
+    gemm_xwt(n, F, F, b.s[L], F, m->p(m->off_Wo), m->p(m->off_bo), b.zo, F, EPI_SILU, b.ao, F, false, s);
+    launch_readout(n, F, m->desc.n_species, b.zo, m->p(m->off_wo), m->p(m->off_beta), sys.species, b.Ei, s);
+    if (energy) launch_rep_sum(sys.n_rep, t.rep_start, b.Ei, energy, s);
+    if (!forces) return;
+    launch_readout_bwd(n, F, b.ao, m->p(m->off_wo), b.gs2, s);
+    gemm_gw(n, F, F, b.gs2, F, m->p(m->off_Wo), b.gs, F, EPI_NONE, nullptr, 0, false, s);
+    NNP_HIP(hipMemsetAsync(b.gv, 0, sizeof(float) * size_t(n) * 3 * F, s));
+    const int64_t E = nl.capacity;
+    NNP_HIP(hipMemsetAsync(b.edge_g, 0, sizeof(float) * size_t(E) * 3, s));
+    for (int l = L - 1; l >= 0; --l) layer_backward(m, l, mg, b, b.edge_g, nullptr, s);
+    launch_assemble_forces(n, nl.offsets, rev, b.edge_g, forces, false, s);
+}
+
+void nc_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const nnp_nlist& nl, ModelBuf& b,
+             float* forces, hipStream_t s) {
+    const int n = int(sys.n_atoms);
+    const int F = m->desc.width;
+    const int HC = 2 * (m->desc.n_s + m->desc.n_l) * m->desc.n_c;
+    MpGeom mg = make_geom(m, sys, geom, nl);
+    embed_forward(m, sys, mg, b, s);
+    gemm_xwt(n, HC, F, b.s[1], F, m->p(m->off_Wq), nullptr, b.QK, HC, EPI_NONE, nullptr, 0, false, s);
+    gemm_xwt(3 * n, m->desc.n_l, F, b.v[1], F, m->p(m->off_WV), nullptr, b.Vh, m->desc.n_l, EPI_NONE, nullptr, 0,
+             false, s);
+    launch_head_fwd(mg, b.QK, b.Vh, forces, false, s);
+}
+
+void nc_wgrad(const Model* m, const nnp_system& sys, const RepGeom& geom, const nnp_nlist& nl, ModelBuf& b,
+              const float* dl_df, float* dtheta, hipStream_t s) {
+    const int n = int(sys.n_atoms);
+    const int F = m->desc.width;
+    const int nl_ = m->desc.n_l;
+    const int HC = 2 * (m->desc.n_s + m->desc.n_l) * m->desc.n_c;
+    MpGeom mg = make_geom(m, sys, geom, nl);
+    embed_forward(m, sys, mg, b, s);
+    gemm_xwt(n, HC, F, b.s[1], F, m->p(m->off_Wq), nullptr, b.QK, HC, EPI_NONE, nullptr, 0, false, s);
+    gemm_xwt(3 * n, nl_, F, b.v[1], F, m->p(m->off_WV), nullptr, b.Vh, nl_, EPI_NONE, nullptr, 0, false, s);
+    launch_head_bwd(mg, b.QK, b.Vh, dl_df, b.gQK, b.gVh, s);
+    gemm_wgrad(n, HC, F, b.gQK, HC, b.s[1], F, dtheta + m->off_Wq, b.chunk_part, kChunk, false, s);
+    gemm_gw(n, HC, F, b.gQK, HC, m->p(m->off_Wq), b.gs, F, EPI_NONE, nullptr, 0, false, s);
+    gemm_wgrad(3 * n, nl_, F, b.gVh, nl_, b.v[1], F, dtheta + m->off_WV, b.chunk_part, kChunk, false, s);
+    gemm_gw(3 * n, nl_, F, b.gVh, nl_, m->p(m->off_WV), b.gv, F, EPI_NONE, nullptr, 0, false, s);
+    layer_backward(m, 0, mg, b, nullptr, dtheta, s);
+    launch_emb_grad(n, F, m->desc.n_species, sys.species, b.gs, dtheta + m->off_emb, s);
+}
+
+}  // namespace nnp
+
+// ============================================================== workspace
+namespace nnp {
+
+struct CallScratch {
+    SysTables t;
+    NbrScratch nb;
+    ModelBuf cons, nc;
+    RespaBuf rs;
+};
+
+// One layout serves every entry point: tables, neighbour scratch, the
+// integrator's snapshot and flags, then the two model scratch areas.
+void carve_all(Arena& a, const Model* cons, const Model* nc, int64_t n, int32_t n_rep, int64_t E, bool wgrad,
+               CallScratch& c) {
+    carve_tables(a, n_rep, c.t);
+    carve_nbr_scratch(a, n, n_rep, c.nb);
+    c.rs.pos = a.take<double>(3 * n);
+    c.rs.vel = a.take<double>(3 * n);
+    c.rs.pos_ref = a.take<double>(3 * n);
+    c.rs.f_cons = a.take<float>(3 * n);
+    c.rs.f_nc = a.take<float>(3 * n);
+    c.rs.energy = a.take<double>(n_rep);
+    if (cons) carve_model(a, cons, n, E, false, c.cons);
+    if (nc) carve_model(a, nc, n, E, wgrad, c.nc);
+}
+
+size_t call_scratch_bytes(const Model* cons, const Model* nc, int64_t n, int32_t n_rep, int64_t E) {
+    Arena a(nullptr, 0);
+    CallScratch c;
+    carve_all(a, cons, nc, n, n_rep, std::max<int64_t>(E, 1), false, c);
+    return a.used + 256;
+}
+
+}  // namespace nnp
+
+extern "C" nnp_status nnp_workspace_size(const nnp_model* cons, const nnp_model* nc, int64_t n_atoms, int32_t n_rep,
+                                         int64_t max_edges, size_t* bytes) {
+    NNP_API_BEGIN
+    NNP_REQUIRE(bytes && n_atoms >= 1 && n_rep >= 1 && max_edges >= 0, NNP_EINVAL, "bad workspace query");
+    Arena a(nullptr, 0);
+    CallScratch c;
+    carve_all(a, reinterpret_cast<const Model*>(cons), reinterpret_cast<const Model*>(nc), n_atoms, n_rep,
+              std::max<int64_t>(max_edges, 1), true, c);
+    *bytes = a.used + 256;
+    NNP_API_END
+}
+
+// ============================================================== neighbours
+extern "C" nnp_status nnp_neighbors(const nnp_system* sys, nnp_nlist* nl, void* ws, size_t ws_bytes, void* stream) {
+    NNP_API_BEGIN
+    check_system(sys);
+    NNP_REQUIRE(nl && nl->offsets && (nl->nbr || nl->capacity == 0), NNP_EINVAL, "incomplete neighbour list");
+    NNP_REQUIRE(nl->n_atoms == sys->n_atoms, NNP_EINVAL, "list rows must equal n_atoms");
+    NNP_REQUIRE(nl->cutoff > 0, NNP_EINVAL, "cutoff must be positive");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Arena a(ws, ws_bytes);
+    SysTables t;
+    carve_tables(a, sys->n_rep, t);
+    NbrScratch nb;
+    carve_nbr_scratch(a, sys->n_atoms, sys->n_rep, nb);
+    std::vector<double> hs;
+    RepGeom g = upload_tables(*sys, t, s, hs);
+    CellPlan plan = plan_cells(*sys, nl->cutoff);
+    upload_cell_plan(plan, nb, s);
+    NNP_HIP(hipMemsetAsync(nb.status, 0, sizeof(int) * 8, s));
+    launch_set_flag(t.flags, 1, s);
+    launch_build(int(sys->n_atoms), sys->pos, g, plan, nb, t.flags, nl->cutoff, nl->capacity, nl->offsets,
+                 nl->nbr, nl->rev, nullptr, s);
+    int host_status[8];
+    int total = 0;
+    NNP_HIP(hipMemcpyAsync(host_status, nb.status, sizeof(host_status), hipMemcpyDeviceToHost, s));
+    NNP_HIP(hipMemcpyAsync(&total, nb.tmp_off + sys->n_atoms, sizeof(int), hipMemcpyDeviceToHost, s));
+    NNP_HIP(hipStreamSynchronize(s));
+    nl->n_edges = total;
+    NNP_REQUIRE(host_status[2] == 0, NNP_ECAPACITY, "a neighbour row exceeds the 1024-entry limit of the builder");
+    NNP_REQUIRE(host_status[0] == 0, NNP_ECAPACITY,
+                "neighbour list needs " + std::to_string(total) + " entries, capacity " +
+                    std::to_string(nl->capacity));
+    NNP_API_END
+}
+
+// ================================================================== forces
+namespace nnp {
+
+static void check_list(const nnp_nlist* nl, const nnp_system* sys, double min_cutoff) {
+    NNP_REQUIRE(nl && nl->offsets && nl->nbr, NNP_EINVAL, "incomplete neighbour list");
+    NNP_REQUIRE(nl->n_atoms == sys->n_atoms, NNP_EINVAL, "list rows must equal n_atoms");
+    NNP_REQUIRE(nl->cutoff >= min_cutoff, NNP_EINVAL, "list radius is below the model cutoff");
+}
+
+}  // namespace nnp
+
+extern "C" nnp_status nnp_cons_energy_forces(const nnp_model* cons, const nnp_system* sys, const nnp_nlist* nl,
+                                             void* ws, size_t ws_bytes, double* energy, float* forces,
+                                             void* stream) {
+    NNP_API_BEGIN
+    NNP_REQUIRE(cons, NNP_EINVAL, "null model");
+    const Model* m = reinterpret_cast<const Model*>(cons);
+    NNP_REQUIRE(m->desc.kind == NNP_MODEL_CONS, NNP_EINVAL, "not a conservative model");
+    check_system(sys);
+    check_list(nl, sys, m->desc.cutoff);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Arena a(ws, ws_bytes);
+    CallScratch c;
+    carve_all(a, m, nullptr, sys->n_atoms, sys->n_rep, std::max<int64_t>(nl->capacity, 1), false, c);
+    std::vector<double> hs;
+    RepGeom g = upload_tables(*sys, c.t, s, hs);
+    nnp_nlist l2 = *nl;
+    const int* rev = nl->rev;
+    if (!rev) {
+        NNP_HIP(hipMemsetAsync(c.nb.status, 0, sizeof(int) * 8, s));
+        launch_set_flag(c.t.flags, 1, s);
+        launch_reverse(int(sys->n_atoms), c.t.flags, c.nb.status, nl->offsets, nl->nbr, c.cons.rev, s);
+        rev = c.cons.rev;
+    }
+    cons_eval(m, *sys, g, c.t, l2, rev, c.cons, energy, forces, s);
+    NNP_API_END
+}
+
+extern "C" nnp_status nnp_nc_forces(const nnp_model* nc, const nnp_system* sys, const nnp_nlist* nl, void* ws,
+                                    size_t ws_bytes, float* forces, void* stream) {
+    NNP_API_BEGIN
+    NNP_REQUIRE(nc && forces, NNP_EINVAL, "null argument");
+    const Model* m = reinterpret_cast<const Model*>(nc);
+    NNP_REQUIRE(m->desc.kind == NNP_MODEL_NC, NNP_EINVAL, "not an NC model");
+    check_system(sys);
+    check_list(nl, sys, m->desc.cutoff);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Arena a(ws, ws_bytes);
+    CallScratch c;
+    carve_all(a, nullptr, m, sys->n_atoms, sys->n_rep, std::max<int64_t>(nl->capacity, 1), false, c);
+    std::vector<double> hs;
+    RepGeom g = upload_tables(*sys, c.t, s, hs);
+    nc_eval(m, *sys, g, *nl, c.nc, forces, s);
+    NNP_API_END
+}
+
+extern "C" nnp_status nnp_nc_weight_grad(const nnp_model* nc, const nnp_system* sys, const nnp_nlist* nl,
+                                         const float* dl_df, float* dl_dtheta, void* ws, size_t ws_bytes,
+                                         void* stream) {
+    NNP_API_BEGIN
+    NNP_REQUIRE(nc && dl_df && dl_dtheta, NNP_EINVAL, "null argument");
+    const Model* m = reinterpret_cast<const Model*>(nc);
+    NNP_REQUIRE(m->desc.kind == NNP_MODEL_NC, NNP_EINVAL, "not an NC model");
+    check_system(sys);
+    check_list(nl, sys, m->desc.cutoff);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Arena a(ws, ws_bytes);
+    CallScratch c;
+    carve_all(a, nullptr, m, sys->n_atoms, sys->n_rep, std::max<int64_t>(nl->capacity, 1), true, c);
+    std::vector<double> hs;
+    RepGeom g = upload_tables(*sys, c.t, s, hs);
+    nc_wgrad(m, *sys, g, *nl, c.nc, dl_df, dl_dtheta, s);
+    NNP_API_END
+}
+
+// ==================================================================== Adam
+namespace nnp {
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float bc1,
+                       float bc2) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / bc1;
+    const float vh = vi / bc2;
+    p[i] -= lr * mh / (sqrtf(vh) + eps);
+}
+}  // namespace nnp
+
+extern "C" nnp_status nnp_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, int64_t t,
+                                    double lr, double beta1, double beta2, double eps, void* stream) {
+    NNP_API_BEGIN
+    NNP_REQUIRE(param && grad && m && v && n >= 0 && t >= 1, NNP_EINVAL, "bad Adam arguments");
+    const float bc1 = float(1.0 - std::pow(beta1, double(t)));
+    const float bc2 = float(1.0 - std::pow(beta2, double(t)));
+    k_adam<<<cdiv(n, 256), 256, 0, static_cast<hipStream_t>(stream)>>>(param, grad, m, v, n, float(lr), float(beta1),
+                                                                        float(beta2), float(eps), bc1, bc2);
+    NNP_LAUNCH_CHECK();
+    NNP_API_END
+}
+
+// ===================================================================== HMR
+extern "C" nnp_status nnp_hmr_masses(int64_t n, const int32_t* bonded_heavy, const double* mass, double h_mass,
+                                     int32_t mode, double* out_mass) {
+    NNP_API_BEGIN
+    NNP_REQUIRE(n >= 0 && bonded_heavy && mass && out_mass, NNP_EINVAL, "null argument");
+    NNP_REQUIRE(mode == 0 || mode == 1, NNP_EINVAL, "mode must be 0 (set) or 1 (add)");
+    std::vector<double> m(mass, mass + n);
+    for (int64_t a = 0; a < n; ++a) {
+        const int32_t h = bonded_heavy[a];
+        if (h < 0) continue;
+        NNP_REQUIRE(h < n && bonded_heavy[h] < 0, NNP_EINVAL, "bonded_heavy must point to a heavy atom");
+        const double nm = mode == 0 ? h_mass : mass[a] + h_mass;
+        m[h] -= nm - mass[a];
+        m[a] = nm;
+    }
+    for (int64_t a = 0; a < n; ++a) NNP_REQUIRE(m[a] > 0, NNP_EINVAL, "repartitioning leaves a non-positive mass");
+    std::memcpy(out_mass, m.data(), sizeof(double) * n);
+    NNP_API_END
+}
+
+// ============================================================== integrator
+namespace nnp {
+
+struct PinnedFlags {
+    int* host = nullptr;
+    PinnedFlags() {
+        if (hipHostMalloc(reinterpret_cast<void**>(&host), 64 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+            host = nullptr;
+    }
+};
+
+static int* pinned_flags() {
+    static thread_local PinnedFlags pf;
+    NNP_REQUIRE(pf.host != nullptr, NNP_EDEVICE, "could not allocate pinned host memory");
+    return pf.host;
+}
+
+void check_respa(const respa_state* st, const respa_params* p, const Model* cons, const Model* nc) {
+    NNP_REQUIRE(st && p && cons, NNP_EINVAL, "null argument");
+    NNP_REQUIRE(cons->desc.kind == NNP_MODEL_CONS, NNP_EINVAL, "first model must be conservative");
+    NNP_REQUIRE(p->mode == NNP_MODE_DMTS_NC || p->mode == NNP_MODE_STS, NNP_EINVAL, "unknown mode");
+    if (p->mode == NNP_MODE_DMTS_NC) {
+        NNP_REQUIRE(nc && nc->desc.kind == NNP_MODEL_NC, NNP_EINVAL, "DMTS-NC needs an NC model");
+        NNP_REQUIRE(p->n_inner >= 1, NNP_EINVAL, "n_inner must be >= 1");
+        NNP_REQUIRE(st->f_nc && st->nl_nc.offsets && st->nl_nc.nbr, NNP_EINVAL, "DMTS-NC needs f_nc and the NC list");
+    }
+    NNP_REQUIRE(p->dt_outer_fs > 0 && p->temperature_K >= 0 && p->skin >= 0, NNP_EINVAL, "bad integrator parameters");
+    NNP_REQUIRE(st->pos && st->vel && st->mass && st->gamma && st->f_cons && st->energy && st->pos_ref, NNP_EINVAL,
+                "incomplete state");
+    NNP_REQUIRE(st->sys.pos == st->pos, NNP_EINVAL, "state.sys.pos must alias state.pos");
+    NNP_REQUIRE(st->nl_cons.offsets && st->nl_cons.nbr && st->nl_cons.rev, NNP_EINVAL,
+                "the conservative list needs offsets, nbr and rev");
+    NNP_REQUIRE(st->nl_cons.n_atoms == st->sys.n_atoms, NNP_EINVAL, "list rows must equal n_atoms");
+}
+
+}  // namespace nnp
+
+namespace nnp {
+
+// Advances a packed system by n_outer outer steps.  Replica r draws its
+// normals with key (seeds[r], streams[r]) and O-step index step_base[r] + k,
+// k counting the O-steps of this call.  rep_bad (host, n_rep, optional)
+// receives per-replica non-finite flags at each check; without it any
+// non-finite replica fails the call.
+nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const respa_params* p, int32_t n_outer,
+                     void* ws, size_t ws_bytes, hipStream_t s, const uint64_t* seeds, const uint64_t* streams,
+                     const uint64_t* step_base, int* rep_bad) {
+    check_respa(st, p, cons, nc);
+    check_system(&st->sys);
+    NNP_REQUIRE(n_outer >= 0, NNP_EINVAL, "n_outer must be >= 0");
+    const bool dmts = p->mode == NNP_MODE_DMTS_NC;
+    const int n = int(st->sys.n_atoms);
+    const int R = st->sys.n_rep;
+    Arena a(ws, ws_bytes);
+    CallScratch c;
+    const int64_t E = std::max<int64_t>({st->nl_cons.capacity, dmts ? st->nl_nc.capacity : 0, int64_t(1)});
+    carve_all(a, cons, dmts ? nc : nullptr, n, R, E, false, c);
+    std::vector<double> hs;
+    RepGeom g = upload_tables(st->sys, c.t, s, hs);
+    NNP_HIP(hipMemcpyAsync(c.t.seed, seeds, sizeof(uint64_t) * R, hipMemcpyHostToDevice, s));
+    NNP_HIP(hipMemcpyAsync(c.t.stream, streams, sizeof(uint64_t) * R, hipMemcpyHostToDevice, s));
+    NNP_HIP(hipMemcpyAsync(c.t.step_base, step_base, sizeof(uint64_t) * R, hipMemcpyHostToDevice, s));
+    const double rc_cons = cons->desc.cutoff + p->skin;
+    const double rc_nc = dmts ? nc->desc.cutoff + p->skin : 0.0;
+    CellPlan plan = plan_cells(st->sys, rc_cons);
+    upload_cell_plan(plan, c.nb, s);
+    // flags: [0] rebuild trigger, [8..10] NC list status; nb.status: conservative list
+    int* trig = c.t.flags;
+    int* nc_status = c.t.flags + 8;
+    NNP_HIP(hipMemsetAsync(c.t.flags, 0, sizeof(int) * 16, s));
+    NNP_HIP(hipMemsetAsync(c.t.rep_bad, 0, sizeof(int) * R, s));
+    NNP_HIP(hipMemsetAsync(c.nb.status, 0, sizeof(int) * 8, s));
+    NNP_HIP(hipMemsetAsync(c.t.rebuilds, 0, sizeof(long long), s));
+
+    nnp_nlist lc = st->nl_cons, ln = st->nl_nc;
+    auto rebuild_if_flagged = [&]() {
+        launch_build(n, st->pos, g, plan, c.nb, trig, rc_cons, lc.capacity, lc.offsets, lc.nbr, lc.rev, st->pos_ref,
+                     s);
+        if (dmts)
+            launch_filter(n, st->pos, g, c.nb, trig, lc.offsets, lc.nbr, rc_nc, ln.capacity, ln.offsets, ln.nbr,
+                          nullptr, nc_status, s);
+        launch_finish_rebuild(trig, c.t.rebuilds, s);
+    };
+    const double disp_thr = 0.5 * p->skin;
+    BaoaArgs ba{};
+    ba.n = n;
+    ba.pos = st->pos;
+    ba.vel = st->vel;
+    ba.mass = st->mass;
+    ba.gamma = st->gamma;
+    ba.temperature = p->temperature_K;
+    ba.rep_of_atom = g.rep_of_atom;
+    ba.rep_start = c.t.rep_start;
+    ba.seed = c.t.seed;
+    ba.stream = c.t.stream;
+    ba.step_base = c.t.step_base;
+    ba.ffl = p->thermostat == NNP_THERMO_FFL;
+    ba.pos_ref = st->pos_ref;
+    ba.disp_thr2 = disp_thr * disp_thr;
+    ba.flag = trig;
+
+    auto eval_cons = [&]() { cons_eval(cons, st->sys, g, c.t, lc, lc.rev, c.cons, st->energy, st->f_cons, s); };
+    auto eval_nc = [&]() { nc_eval(nc, st->sys, g, ln, c.nc, st->f_nc, s); };
+
+    int* hflags = pinned_flags();
+    std::vector<int> bad(R);
+    auto read_status = [&]() {
+        NNP_HIP(hipMemcpyAsync(hflags, c.t.flags, sizeof(int) * 16, hipMemcpyDeviceToHost, s));
+        NNP_HIP(hipMemcpyAsync(hflags + 16, c.nb.status, sizeof(int) * 8, hipMemcpyDeviceToHost, s));
+        NNP_HIP(hipMemcpyAsync(hflags + 32, c.t.rebuilds, sizeof(long long), hipMemcpyDeviceToHost, s));
+        NNP_HIP(hipMemcpyAsync(bad.data(), c.t.rep_bad, sizeof(int) * R, hipMemcpyDeviceToHost, s));
+        NNP_HIP(hipStreamSynchronize(s));
+    };
+    auto snapshot = [&](bool save) {
+        const size_t d3 = sizeof(double) * 3 * size_t(n), f3 = sizeof(float) * 3 * size_t(n);
+        auto cp = [&](void* dst, const void* src, size_t bytes) {
+            NNP_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
+        };
+        if (save) {
+            cp(c.rs.pos, st->pos, d3); cp(c.rs.vel, st->vel, d3); cp(c.rs.pos_ref, st->pos_ref, d3);
+            cp(c.rs.f_cons, st->f_cons, f3); if (dmts) cp(c.rs.f_nc, st->f_nc, f3);
+            cp(c.rs.energy, st->energy, sizeof(double) * R);
+        } else {
+            cp(st->pos, c.rs.pos, d3); cp(st->vel, c.rs.vel, d3); cp(st->pos_ref, c.rs.pos_ref, d3);
+            cp(st->f_cons, c.rs.f_cons, f3); if (dmts) cp(st->f_nc, c.rs.f_nc, f3);
+            cp(st->energy, c.rs.energy, sizeof(double) * R);
+        }
+    };
+    long long rebuilds_seen = 0;
+    uint64_t offset = 0;  // O-steps done in this call
+    auto check = [&](uint64_t offset_at_snapshot, bool can_restore) -> nnp_status {
+        read_status();
+        long long rb;
+        std::memcpy(&rb, hflags + 32, sizeof(long long));
+        st->n_rebuilds += rb - rebuilds_seen;
+        rebuilds_seen = rb;
+        const bool row_long = hflags[16 + 2] != 0 || hflags[8 + 2] != 0;
+        const bool over_cons = hflags[16 + 0] != 0;
+        const bool over_nc = hflags[8 + 0] != 0;
+        if (row_long || over_cons || over_nc) {
+            if (over_cons) st->nl_cons.n_edges = hflags[16 + 1];
+            if (over_nc) st->nl_nc.n_edges = hflags[8 + 1];
+            if (can_restore) {
+                snapshot(false);
+                st->step -= offset - offset_at_snapshot;
+                offset = offset_at_snapshot;
+                NNP_HIP(hipStreamSynchronize(s));
+            }
+            st->lists_valid = 0;
+            set_error(row_long ? "a neighbour row exceeds the 1024-entry limit of the builder"
+                               : "neighbour list capacity exceeded; grow the buffer to n_edges and call again");
+            return NNP_ECAPACITY;
+        }
+        bool any_bad = false;
+        for (int r = 0; r < R; ++r) {
+            any_bad |= bad[r] != 0;
+            if (rep_bad) rep_bad[r] = bad[r];
+        }
+        if (any_bad && !rep_bad) {
+            set_error("non-finite positions or velocities");
+            return NNP_EUNSTABLE;
+        }
+        return NNP_OK;
+    };
+
+    if (!st->lists_valid) {
+        // empty rows until the first build succeeds, so a failed build never
+        // leaves uninitialised offsets behind
+        NNP_HIP(hipMemsetAsync(lc.offsets, 0, sizeof(int) * (size_t(n) + 1), s));
+        if (dmts) NNP_HIP(hipMemsetAsync(ln.offsets, 0, sizeof(int) * (size_t(n) + 1), s));
+        launch_set_flag(trig, 1, s);
+        rebuild_if_flagged();
+        st->lists_valid = 1;
+    }
+    if (st->first_step) {
+        if (dmts) eval_nc();
+        eval_cons();
+        st->first_step = 0;
+    }
+    {
+        nnp_status e = check(0, false);
+        if (e != NNP_OK) return e;
+    }
+    const int check_every = std::max(1, p->check_every);
+    const int n_in = dmts ? p->n_inner : 1;
+    const double D = p->dt_outer_fs;
+    const double d = D / n_in;
+    uint64_t snap_offset = 0;
+    snapshot(true);
+    for (int o = 0; o < n_outer; ++o) {
+        if (dmts) {
+            launch_kick(n, st->vel, st->mass, st->f_cons, st->f_nc, 0.5 * D, s);
+            for (int k = 0; k < n_in; ++k) {
+                ba.force = st->f_nc;
+                ba.dt = d;
+                ba.step_offset = offset;
+                launch_baoa(ba, s);
+                rebuild_if_flagged();
+                eval_nc();
+                launch_kick(n, st->vel, st->mass, st->f_nc, nullptr, 0.5 * d, s);
+                offset += 1;
+                st->step += 1;
+            }
+            eval_cons();
+            launch_kick(n, st->vel, st->mass, st->f_cons, st->f_nc, 0.5 * D, s);
+        } else {
+            ba.force = st->f_cons;
+            ba.dt = D;
+            ba.step_offset = offset;
+            launch_baoa(ba, s);
+            rebuild_if_flagged();
+            eval_cons();
+            launch_kick(n, st->vel, st->mass, st->f_cons, nullptr, 0.5 * D, s);
+            offset += 1;
+            st->step += 1;
+        }
+        launch_kinetic(R, c.t.rep_start, n, st->pos, st->vel, st->mass, st->ke ? st->ke + int64_t(o) * R : nullptr,
+                       c.t.rep_bad, s);
+        if ((o + 1) % check_every == 0 || o + 1 == n_outer) {
+            nnp_status e = check(snap_offset, true);
+            if (e != NNP_OK) return e;
+            snap_offset = offset;
+            if (o + 1 < n_outer) snapshot(true);
+        }
+    }
+    return NNP_OK;
+}
+
+}  // namespace nnp
+
+extern "C" nnp_status respa_step(const nnp_model* cons_h, const nnp_model* nc_h, respa_state* st,
+                                 const respa_params* p, int32_t n_outer, void* ws, size_t ws_bytes, void* stream) {
+    NNP_API_BEGIN
+    NNP_REQUIRE(st && p, NNP_EINVAL, "null argument");
+    const int R = st->sys.n_rep;
+    NNP_REQUIRE(R >= 1, NNP_EINVAL, "n_rep must be >= 1");
+    std::vector<uint64_t> seeds(R, p->seed), streams(R), base(R, st->step);
+    for (int r = 0; r < R; ++r) streams[r] = p->stream_id + uint64_t(r);
+    nnp_status e = respa_run(reinterpret_cast<const Model*>(cons_h), reinterpret_cast<const Model*>(nc_h), st, p,
+                             n_outer, ws, ws_bytes, static_cast<hipStream_t>(stream), seeds.data(), streams.data(),
+                             base.data(), nullptr);
+    if (e != NNP_OK) return e;
+    NNP_API_END
+}

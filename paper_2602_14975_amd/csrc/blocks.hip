@@ -1,0 +1,437 @@
+// Per-atom elementwise pieces of the embedding block and the readout, and
+// the non-conservative pair head (paper, Methods: q_ih, k_ih, c_ijh, F_ij,
+// F_i = sum_j (F_ij - F_ji)).  The dense contractions around them run in
+// gemm.hip; the edge loops of the embedding in mp.hip.
+#include "common.h"
+#include "kernels.h"
+
+namespace nnp {
+
+// s0[i] = emb[t_i]; v0[i] = 0
+__global__ void k_embed(int n, int F, int S, const int* __restrict__ species, const float* __restrict__ emb,
+                        float* __restrict__ s, float* __restrict__ v) {
+    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= int64_t(n) * F) return;
+    int i = int(t / F), f = int(t % F);
+    const int sp = min(max(species[i], 0), S - 1);  // out-of-range species read row 0 or S-1, never past the table
+    s[t] = emb[sp * F + f];
+    v[(int64_t(i) * 3 + 0) * F + f] = 0.f;
+    v[(int64_t(i) * 3 + 1) * F + f] = 0.f;
+    v[(int64_t(i) * 3 + 2) * F + f] = 0.f;
+}
+
+// X[i] = [smid_i ; sqrt(sum_al Vv[i][al]^2 + 1e-8)], UV rows [Uv (F) | Vv (F)] per component.
+__global__ void k_build_x(int n, int F, const float* __restrict__ smid, const float* __restrict__ UV,
+                          float* __restrict__ X) {
+    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= int64_t(n) * F) return;
+    int i = int(t / F), f = int(t % F);
+    float acc = 1e-8f;
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+        float vv = UV[(int64_t(i) * 3 + al) * 2 * F + F + f];
+        acc = fmaf(vv, vv, acc);
+    }
+    X[int64_t(i) * 2 * F + f] = smid[t];
+    X[int64_t(i) * 2 * F + F + f] = sqrtf(acc);
+}
+
+// s_out = smid + p + q * sum_al Uv Vv ; v_out = vmid + o * Uv
+__global__ void k_update_combine(int n, int F, const float* __restrict__ smid, const float* __restrict__ vmid,
+                                 const float* __restrict__ UV, const float* __restrict__ pqo,
+                                 float* __restrict__ s_out, float* __restrict__ v_out) {
+    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= int64_t(n) * F) return;
+    int i = int(t / F), f = int(t % F);
+    const float* h = pqo + int64_t(i) * 3 * F;
+    float dot = 0.f, uv[3];
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+        const float* row = UV + (int64_t(i) * 3 + al) * 2 * F;
+        uv[al] = row[f];
+        dot = fmaf(row[f], row[F + f], dot);
+    }
+    s_out[t] = smid[t] + h[f] + h[F + f] * dot;
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+        int64_t idx = (int64_t(i) * 3 + al) * F + f;
+        v_out[idx] = vmid[idx] + h[2 * F + f] * uv[al];
+    }
+}
+
+// Reverse of k_update_combine: g_pqo and the Uv/Vv adjoints (the norm path
+// of Vv is added by k_norm_bwd).
+__global__ void k_update_combine_bwd(int n, int F, const float* __restrict__ UV, const float* __restrict__ pqo,
+                                     const float* __restrict__ gs, const float* __restrict__ gv,
+                                     float* __restrict__ gpqo, float* __restrict__ gUV) {
+    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= int64_t(n) * F) return;
+    int i = int(t / F), f = int(t % F);
+    const float* h = pqo + int64_t(i) * 3 * F;
+    const float q = h[F + f], o = h[2 * F + f];
+    const float g = gs[t];
+    float dot = 0.f, go = 0.f;
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+        const float* row = UV + (int64_t(i) * 3 + al) * 2 * F;
+        const float u = row[f], vv = row[F + f];
+        const float gva = gv[(int64_t(i) * 3 + al) * F + f];
+        dot = fmaf(u, vv, dot);
+        go = fmaf(gva, u, go);
+        float* grow = gUV + (int64_t(i) * 3 + al) * 2 * F;
+        grow[f] = g * q * vv + gva * o;
+        grow[F + f] = g * q * u;
+    }
+    float* gh = gpqo + int64_t(i) * 3 * F;
+    gh[f] = g;
+    gh[F + f] = g * dot;
+    gh[2 * F + f] = go;
+}
+
+// g_smid = gs + gX[:, :F];  gVv[al] += gX[:, F:] * Vv[al] / nrm
+__global__ void k_norm_bwd(int n, int F, const float* __restrict__ gs, const float* __restrict__ gX,
+                           const float* __restrict__ X, const float* __restrict__ UV, float* __restrict__ gsmid,
+                           float* __restrict__ gUV) {
+    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= int64_t(n) * F) return;
+    int i = int(t / F), f = int(t % F);
+    gsmid[t] = gs[t] + gX[int64_t(i) * 2 * F + f];
+    const float gn = gX[int64_t(i) * 2 * F + F + f] / X[int64_t(i) * 2 * F + F + f];
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+        const int64_t idx = (int64_t(i) * 3 + al) * 2 * F + F + f;
+        gUV[idx] = fmaf(gn, UV[idx], gUV[idx]);
+    }
+}
+
+// E_i = wo . z_i + beta[t_i] (z = silu(Wo s + bo) from the GEMM epilogue)
+__global__ void k_readout(int n, int F, int S, const float* __restrict__ z, const float* __restrict__ wo,
+                          const float* __restrict__ beta, const int* __restrict__ species, float* __restrict__ Ei) {
+    int lane = threadIdx.x & 63;
+    int i = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (i >= n) return;
+    float acc = 0.f;
+    for (int f = lane; f < F; f += 64) acc = fmaf(wo[f], z[int64_t(i) * F + f], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) Ei[i] = acc + beta[min(max(species[i], 0), S - 1)];
+}
+
+// g_ao = wo * silu'(a_o)  (dE/dE_i = 1)
+__global__ void k_readout_bwd(int n, int F, const float* __restrict__ ao, const float* __restrict__ wo,
+                              float* __restrict__ gao) {
+    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= int64_t(n) * F) return;
+    gao[t] = wo[t % F] * silu_grad(ao[t]);
+}
+
+// Per-replica float64 sums in a fixed order (one block per replica).
+__global__ void __launch_bounds__(256) k_rep_sum(const int64_t* __restrict__ rep_start, const float* __restrict__ x,
+                                                 double* __restrict__ out) {
+    __shared__ double red[256];
+    int r = blockIdx.x;
+    int64_t a0 = rep_start[r], a1 = rep_start[r + 1];
+    double s = 0.0;
+    for (int64_t a = a0 + threadIdx.x; a < a1; a += 256) s += double(x[a]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[r] = red[0];
+}
+
+// Species-embedding adjoint: g_emb[t][f] = sum over atoms of species t of g_s0[i][f] (fixed order).
+__global__ void k_emb_grad(int n, int F, int S, const int* __restrict__ species, const float* __restrict__ gs0,
+                           float* __restrict__ gemb) {
+    int t = blockIdx.x;   // species
+    int f = threadIdx.x;  // feature (blockDim >= F)
+    if (f >= F) return;
+    float acc = 0.f;
+    for (int i = 0; i < n; ++i)
+        if (species[i] == t) acc += gs0[int64_t(i) * F + f];
+    gemb[t * F + f] = acc;
+}
+
+// ------------------------------------------------------------- NC head ----
+// Per owner atom i (one wavefront), lanes over the CSR entries of its row.
+// QK rows: [q (H x n_c) | k (H x n_c)]; Vh rows [n][3][n_l].
+constexpr int kNs = 8, kNl = 2, kNc = 8, kH = kNs + kNl;
+
+struct HeadEdge {
+    float ef[kNs];  // B_h(r) u(r/rc)
+    float u[3];
+    int j;
+};
+
+__device__ __forceinline__ bool head_edge(const MpGeom& mg, int i, int e, double xi, double yi, double zi,
+                                          double L, double inv, HeadEdge& he) {
+    const int n = mg.n;
+    const int j = mg.nbr[e];
+    double dx, dy, dz;
+    if (!pair_rule(xi, yi, zi, mg.pos[j], mg.pos[n + j], mg.pos[2 * n + j], L, inv, mg.rc2, dx, dy, dz)) return false;
+    const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+    const double rc = mg.rc;
+    const double theta = M_PI * r / rc;
+    double sn, cs;
+    sincos(theta, &sn, &cs);
+    const double d = r / rc, d2 = d * d, d5 = d2 * d2 * d;
+    const double env = 1.0 - 21.0 * d5 + 35.0 * d5 * d - 15.0 * d5 * d2;
+    const double pre = mg.bessel_norm / r * env;
+    double s_prev = 0.0, s_cur = sn;
+#pragma unroll
+    for (int h = 0; h < kNs; ++h) {
+        he.ef[h] = float(pre * s_cur);
+        const double s_next = 2.0 * cs * s_cur - s_prev;
+        s_prev = s_cur;
+        s_cur = s_next;
+    }
+    he.u[0] = float(dx / r);
+    he.u[1] = float(dy / r);
+    he.u[2] = float(dz / r);
+    he.j = j;
+    return true;
+}
+
+__device__ __forceinline__ void head_coeffs(const float* qa, const float* kb, float* c) {
+    const float scale = 0.35355339059327373f;  // 1/sqrt(n_c), n_c = 8
+#pragma unroll
+    for (int h = 0; h < kH; ++h) {
+        const float4 a0 = *reinterpret_cast<const float4*>(qa + h * kNc);
+        const float4 a1 = *reinterpret_cast<const float4*>(qa + h * kNc + 4);
+        const float4 b0 = *reinterpret_cast<const float4*>(kb + h * kNc);
+        const float4 b1 = *reinterpret_cast<const float4*>(kb + h * kNc + 4);
+        float acc = a0.x * b0.x;
+        acc = fmaf(a0.y, b0.y, acc); acc = fmaf(a0.z, b0.z, acc); acc = fmaf(a0.w, b0.w, acc);
+        acc = fmaf(a1.x, b1.x, acc); acc = fmaf(a1.y, b1.y, acc); acc = fmaf(a1.z, b1.z, acc);
+        acc = fmaf(a1.w, b1.w, acc);
+        c[h] = acc * scale;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __restrict__ QK, const float* __restrict__ Vh,
+                                                  float* __restrict__ Fout, int accum) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= mg.n) return;
+    const int n = mg.n;
+    double L, inv;
+    mg.geom.get(i, L, inv);
+    const double xi = mg.pos[i], yi = mg.pos[n + i], zi = mg.pos[2 * n + i];
+    const float* qi = QK + int64_t(i) * 2 * kH * kNc;
+    const float* ki = qi + kH * kNc;
+    float Vi[kNl][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int h = 0; h < kNl; ++h) Vi[h][a] = Vh[(int64_t(i) * 3 + a) * kNl + h];
+    float fx = 0.f, fy = 0.f, fz = 0.f;
+    for (int e = mg.off[i] + lane; e < mg.off[i + 1]; e += 64) {
+        HeadEdge he;
+        if (!head_edge(mg, i, e, xi, yi, zi, L, inv, he)) continue;
+        const int j = he.j;
+        const float* qj = QK + int64_t(j) * 2 * kH * kNc;
+        const float* kj = qj + kH * kNc;
+        float cij[kH], cji[kH];
+        head_coeffs(qi, kj, cij);
+        head_coeffs(qj, ki, cji);
+        float Sij = 0.f, Sji = 0.f;
+#pragma unroll
+        for (int h = 0; h < kNs; ++h) {
+            Sij = fmaf(cij[h], he.ef[h], Sij);
+            Sji = fmaf(cji[h], he.ef[h], Sji);
+        }
+        float Dij[3], Dji[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Dij[a] = he.u[a] + cij[kNs] * Vi[0][a] + cij[kNs + 1] * Vi[1][a];
+            Dji[a] = -he.u[a] + cji[kNs] * Vh[(int64_t(j) * 3 + a) * kNl] +
+                     cji[kNs + 1] * Vh[(int64_t(j) * 3 + a) * kNl + 1];
+        }
+        fx += Sij * Dij[0] - Sji * Dji[0];
+        fy += Sij * Dij[1] - Sji * Dji[1];
+        fz += Sij * Dij[2] - Sji * Dji[2];
+    }
+    fx = wave_sum(fx);
+    fy = wave_sum(fy);
+    fz = wave_sum(fz);
+    if (lane == 0) {
+        if (accum) {
+            Fout[i] += fx; Fout[n + i] += fy; Fout[2 * n + i] += fz;
+        } else {
+            Fout[i] = fx; Fout[n + i] = fy; Fout[2 * n + i] = fz;
+        }
+    }
+}
+
+// Reverse of the head for a loss with dL/dF_i = gF_i: each directed edge
+// (i, j) carries a_ij = gF_i - gF_j as the adjoint of F_ij.  The owner i
+// accumulates only its own adjoints, so no atomics are needed: q_i and V_i
+// from its edges (i, j) (first sweep), k_i from the reverse edges (j, i)
+// (second sweep).  In each sweep, phase 1 (lanes over edges) forms the
+// coefficient adjoints dL/dc and stages them in LDS; phase 2 (lanes over the
+// (head, channel) pairs) gathers the neighbour's k or q row.
+__global__ void __launch_bounds__(64) k_head_bwd(MpGeom mg, const float* __restrict__ QK, const float* __restrict__ Vh,
+                                                 const float* __restrict__ gF, float* __restrict__ gQK,
+                                                 float* __restrict__ gVh) {
+    __shared__ float gc[64][kH];
+    __shared__ int jj[64];
+    __shared__ float gv_part[64][kNl * 3];
+    const int lane = threadIdx.x;
+    const int i = blockIdx.x;
+    const int n = mg.n;
+    double L, inv;
+    mg.geom.get(i, L, inv);
+    const double xi = mg.pos[i], yi = mg.pos[n + i], zi = mg.pos[2 * n + i];
+    const float* qi = QK + int64_t(i) * 2 * kH * kNc;
+    const float* ki = qi + kH * kNc;
+    float Vi[kNl][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int h = 0; h < kNl; ++h) Vi[h][a] = Vh[(int64_t(i) * 3 + a) * kNl + h];
+    const float gFi[3] = {gF[i], gF[n + i], gF[2 * n + i]};
+    const float scale = 0.35355339059327373f;  // 1/sqrt(n_c)
+    const int e0 = mg.off[i], e1 = mg.off[i + 1];
+    float* gq = gQK + int64_t(i) * 2 * kH * kNc;
+    float* gk = gq + kH * kNc;
+    float gv_acc[kNl * 3] = {};
+    for (int sweep = 0; sweep < 2; ++sweep) {
+        float acc0 = 0.f, acc1 = 0.f;  // (h, c) = lane and 64 + lane (lane < 16)
+        for (int base = e0; base < e1; base += 64) {
+            const int e = base + lane;
+            HeadEdge he;
+            const bool ok = e < e1 && head_edge(mg, i, e, xi, yi, zi, L, inv, he);
+            if (ok) {
+                const int j = he.j;
+                const float* qj = QK + int64_t(j) * 2 * kH * kNc;
+                const float* kj = qj + kH * kNc;
+                float aij[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) aij[a] = gFi[a] - gF[a * n + j];
+                float c[kH];
+                if (sweep == 0) {
+                    head_coeffs(qi, kj, c);  // c_ijh
+                    float S = 0.f;
+#pragma unroll
+                    for (int h = 0; h < kNs; ++h) S = fmaf(c[h], he.ef[h], S);
+                    float D[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) D[a] = he.u[a] + c[kNs] * Vi[0][a] + c[kNs + 1] * Vi[1][a];
+                    const float gS = aij[0] * D[0] + aij[1] * D[1] + aij[2] * D[2];
+#pragma unroll
+                    for (int h = 0; h < kNs; ++h) gc[lane][h] = gS * he.ef[h];
+#pragma unroll
+                    for (int h = 0; h < kNl; ++h) {
+                        gc[lane][kNs + h] = S * (aij[0] * Vi[h][0] + aij[1] * Vi[h][1] + aij[2] * Vi[h][2]);
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) gv_acc[h * 3 + a] = fmaf(aij[a] * S, c[kNs + h], gv_acc[h * 3 + a]);
+                    }
+                } else {
+                    head_coeffs(qj, ki, c);  // c_jih
+                    float Vj[kNl][3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+#pragma unroll
+                        for (int h = 0; h < kNl; ++h) Vj[h][a] = Vh[(int64_t(j) * 3 + a) * kNl + h];
+                    float S = 0.f;
+#pragma unroll
+                    for (int h = 0; h < kNs; ++h) S = fmaf(c[h], he.ef[h], S);
+                    float D[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) D[a] = -he.u[a] + c[kNs] * Vj[0][a] + c[kNs + 1] * Vj[1][a];
+                    // the adjoint of F_ji is -aij
+                    const float gS = -(aij[0] * D[0] + aij[1] * D[1] + aij[2] * D[2]);
+#pragma unroll
+                    for (int h = 0; h < kNs; ++h) gc[lane][h] = gS * he.ef[h];
+#pragma unroll
+                    for (int h = 0; h < kNl; ++h)
+                        gc[lane][kNs + h] = -S * (aij[0] * Vj[h][0] + aij[1] * Vj[h][1] + aij[2] * Vj[h][2]);
+                }
+                jj[lane] = j;
+            } else {
+                jj[lane] = -1;
+            }
+            __syncthreads();
+            const int cnt = min(64, e1 - base);
+            for (int t = 0; t < cnt; ++t) {
+                const int j = jj[t];
+                if (j < 0) continue;
+                // sweep 0 gathers k_j, sweep 1 gathers q_j
+                const float* row = QK + int64_t(j) * 2 * kH * kNc + (sweep == 0 ? kH * kNc : 0);
+                acc0 = fmaf(gc[t][lane / kNc] * scale, row[lane], acc0);
+                if (lane < 16) acc1 = fmaf(gc[t][(64 + lane) / kNc] * scale, row[64 + lane], acc1);
+            }
+            __syncthreads();
+        }
+        float* out = sweep == 0 ? gq : gk;
+        out[lane] = acc0;
+        if (lane < 16) out[64 + lane] = acc1;
+    }
+#pragma unroll
+    for (int t = 0; t < kNl * 3; ++t) gv_part[lane][t] = gv_acc[t];
+    __syncthreads();
+    if (lane < kNl * 3) {
+        float s = 0.f;
+        for (int t = 0; t < 64; ++t) s += gv_part[t][lane];
+        const int h = lane / 3, a = lane % 3;
+        gVh[(int64_t(i) * 3 + a) * kNl + h] = s;
+    }
+}
+
+// ------------------------------------------------------------------- host --
+static int ew_blocks(int64_t count) { return cdiv(count, 256); }
+
+void launch_embed(int n, int F, int S, const int* species, const float* emb, float* s, float* v, hipStream_t st) {
+    k_embed<<<ew_blocks(int64_t(n) * F), 256, 0, st>>>(n, F, S, species, emb, s, v);
+    NNP_LAUNCH_CHECK();
+}
+void launch_build_x(int n, int F, const float* smid, const float* UV, float* X, hipStream_t st) {
+    k_build_x<<<ew_blocks(int64_t(n) * F), 256, 0, st>>>(n, F, smid, UV, X);
+    NNP_LAUNCH_CHECK();
+}
+void launch_update_combine(int n, int F, const float* smid, const float* vmid, const float* UV, const float* pqo,
+                           float* s_out, float* v_out, hipStream_t st) {
+    k_update_combine<<<ew_blocks(int64_t(n) * F), 256, 0, st>>>(n, F, smid, vmid, UV, pqo, s_out, v_out);
+    NNP_LAUNCH_CHECK();
+}
+void launch_update_combine_bwd(int n, int F, const float* UV, const float* pqo, const float* gs, const float* gv,
+                               float* gpqo, float* gUV, hipStream_t st) {
+    k_update_combine_bwd<<<ew_blocks(int64_t(n) * F), 256, 0, st>>>(n, F, UV, pqo, gs, gv, gpqo, gUV);
+    NNP_LAUNCH_CHECK();
+}
+void launch_norm_bwd(int n, int F, const float* gs, const float* gX, const float* X, const float* UV, float* gsmid,
+                     float* gUV, hipStream_t st) {
+    k_norm_bwd<<<ew_blocks(int64_t(n) * F), 256, 0, st>>>(n, F, gs, gX, X, UV, gsmid, gUV);
+    NNP_LAUNCH_CHECK();
+}
+void launch_readout(int n, int F, int S, const float* z, const float* wo, const float* beta, const int* species, float* Ei,
+                    hipStream_t st) {
+    k_readout<<<cdiv(n, 4), 256, 0, st>>>(n, F, S, z, wo, beta, species, Ei);
+    NNP_LAUNCH_CHECK();
+}
+void launch_readout_bwd(int n, int F, const float* ao, const float* wo, float* gao, hipStream_t st) {
+    k_readout_bwd<<<ew_blocks(int64_t(n) * F), 256, 0, st>>>(n, F, ao, wo, gao);
+    NNP_LAUNCH_CHECK();
+}
+void launch_rep_sum(int n_rep, const int64_t* rep_start, const float* x, double* out, hipStream_t st) {
+    k_rep_sum<<<n_rep, 256, 0, st>>>(rep_start, x, out);
+    NNP_LAUNCH_CHECK();
+}
+void launch_emb_grad(int n, int F, int S, const int* species, const float* gs0, float* gemb, hipStream_t st) {
+    k_emb_grad<<<S, 128, 0, st>>>(n, F, S, species, gs0, gemb);
+    NNP_LAUNCH_CHECK();
+}
+void launch_head_fwd(const MpGeom& mg, const float* QK, const float* Vh, float* F, bool accum, hipStream_t st) {
+    if (mg.n <= 0) return;
+    k_head_fwd<<<cdiv(mg.n, 4), 256, 0, st>>>(mg, QK, Vh, F, accum);
+    NNP_LAUNCH_CHECK();
+}
+void launch_head_bwd(const MpGeom& mg, const float* QK, const float* Vh, const float* gF, float* gQK, float* gVh,
+                     hipStream_t st) {
+    if (mg.n <= 0) return;
+    k_head_bwd<<<mg.n, 64, 0, st>>>(mg, QK, Vh, gF, gQK, gVh);
+    NNP_LAUNCH_CHECK();
+}
+
+}  // namespace nnp

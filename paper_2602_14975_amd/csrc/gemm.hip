@@ -1,0 +1,188 @@
+// Dense per-atom contractions (the perceptrons of both models).
+//
+// C(m, n) = epi( sum_k A(m, k) B(k, n) + bias(n) ) with strided operands, so
+// one kernel serves the forward products X W^T (B stored [N][K]), the input
+// adjoints G W (B stored [K][N]) and, per chunk of rows, the weight
+// adjoints G^T X.  Tiles of 64 x 64 outputs, 16-deep K slices staged in LDS,
+// 4 x 4 outputs per thread, fp32 accumulation.
+//
+// Epilogues: SILU stores the pre-activation (for the reverse pass) and
+// writes silu(y); DSILU multiplies by silu'(pre(m, n)); ACCUM adds into C.
+#include "common.h"
+#include "kernels.h"
+#include "model.h"
+
+namespace nnp {
+
+constexpr int TM = 64, TN = 64, TK = 16;
+
+__global__ void __launch_bounds__(256)
+k_gemm(GemmArgs g) {
+    __shared__ float As[TK][TM + 4];
+    __shared__ float Bs[TK][TN + 4];
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+    const int64_t zoff_a = int64_t(blockIdx.z) * g.chunk_rows;  // split-K over rows of A^T
+    const float* A = g.A;
+    const float* B = g.B;
+    int kbeg = 0, kend = g.K;
+    if (g.chunk_rows > 0) {
+        kbeg = int(zoff_a);
+        kend = min(g.K, int(zoff_a + g.chunk_rows));
+    }
+    float acc[4][4] = {};
+    for (int k0 = kbeg; k0 < kend; k0 += TK) {
+        // stage A tile (TM x TK) and B tile (TK x TN)
+        for (int t = tid; t < TM * TK; t += 256) {
+            int mm, kk;
+            if (g.sak == 1) { mm = t / TK; kk = t % TK; } else { kk = t / TM; mm = t % TM; }
+            int m = m0 + mm, k = k0 + kk;
+            As[kk][mm] = (m < g.M && k < kend) ? A[int64_t(m) * g.sam + int64_t(k) * g.sak] : 0.f;
+        }
+        for (int t = tid; t < TN * TK; t += 256) {
+            int nn, kk;
+            if (g.sbk == 1) { nn = t / TK; kk = t % TK; } else { kk = t / TN; nn = t % TN; }
+            int n = n0 + nn, k = k0 + kk;
+            Bs[kk][nn] = (n < g.N && k < kend) ? B[int64_t(k) * g.sbk + int64_t(n) * g.sbn] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < TK; ++kk) {
+            float a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = As[kk][ty * 4 + r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx * 4 + c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] = fmaf(a[r], b[c], acc[r][c]);
+        }
+        __syncthreads();
+    }
+    float* C = g.C + int64_t(blockIdx.z) * g.chunk_stride;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        int m = m0 + ty * 4 + r;
+        if (m >= g.M) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            int n = n0 + tx * 4 + c;
+            if (n >= g.N) continue;
+            float y = acc[r][c];
+            if (g.bias) y += g.bias[n];
+            int64_t idx = int64_t(m) * g.ldc + n;
+            if (g.epi == EPI_SILU) {
+                if (g.pre) g.pre[int64_t(m) * g.ldp + n] = y;
+                y = silu(y);
+            } else if (g.epi == EPI_DSILU) {
+                y *= silu_grad(g.pre[int64_t(m) * g.ldp + n]);
+            }
+            if (g.accum) y += C[idx];
+            C[idx] = y;
+        }
+    }
+}
+
+void launch_gemm(const GemmArgs& g, hipStream_t stream) {
+    if (g.M <= 0 || g.N <= 0) return;
+    dim3 grid(cdiv(g.M, TM), cdiv(g.N, TN), 1);
+    k_gemm<<<grid, 256, 0, stream>>>(g);
+    NNP_LAUNCH_CHECK();
+}
+
+// out = X W^T + b (X [M][K] row-major, W [N][K]), optional SiLU (saving pre).
+void gemm_xwt(int M, int N, int K, const float* X, int ldx, const float* W, const float* b, float* out,
+              int ldo, int epi, float* pre, int ldp, bool accum, hipStream_t s) {
+    GemmArgs g{};
+    g.M = M; g.N = N; g.K = K;
+    g.A = X; g.sam = ldx; g.sak = 1;
+    g.B = W; g.sbk = 1; g.sbn = K;
+    g.C = out; g.ldc = ldo; g.bias = b; g.epi = epi; g.pre = pre; g.ldp = ldp; g.accum = accum;
+    launch_gemm(g, s);
+}
+
+// out = G W (G [M][N] row-major, W [N][K]) -> [M][K]; optional silu'(pre) factor.
+void gemm_gw(int M, int N, int K, const float* G, int ldg, const float* W, float* out, int ldo, int epi,
+             const float* pre, int ldp, bool accum, hipStream_t s) {
+    GemmArgs g{};
+    g.M = M; g.N = K; g.K = N;
+    g.A = G; g.sam = ldg; g.sak = 1;
+    g.B = W; g.sbk = K; g.sbn = 1;
+    g.C = out; g.ldc = ldo; g.epi = epi; g.pre = const_cast<float*>(pre); g.ldp = ldp; g.accum = accum;
+    launch_gemm(g, s);
+}
+
+// Weight adjoint dW[N][K] += sum_m G[m][n] X[m][k], deterministic: chunks of
+// rows write partials that k_reduce_chunks adds in chunk order.
+__global__ void k_reduce_chunks(int64_t count, int nchunks, const float* __restrict__ part, int64_t stride,
+                                float* __restrict__ out, int accum) {
+    int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    float s = 0.f;
+    for (int c = 0; c < nchunks; ++c) s += part[int64_t(c) * stride + t];
+    out[t] = accum ? out[t] + s : s;
+}
+
+void gemm_wgrad(int M, int N, int K, const float* G, int ldg, const float* X, int ldx, float* dW, float* scratch,
+                int chunk, bool accum, hipStream_t s) {
+    if (M <= 0) return;
+    int nch = cdiv(M, chunk);
+    GemmArgs g{};
+    g.M = N; g.N = K; g.K = M;
+    g.A = G; g.sam = 1; g.sak = ldg;   // A(n, m) = G[m][n]
+    g.B = X; g.sbk = ldx; g.sbn = 1;   // B(m, k) = X[m][k]
+    g.C = scratch; g.ldc = K; g.chunk_rows = chunk; g.chunk_stride = int64_t(N) * K;
+    dim3 grid(cdiv(N, TM), cdiv(K, TN), nch);
+    k_gemm<<<grid, 256, 0, s>>>(g);
+    int64_t cnt = int64_t(N) * K;
+    k_reduce_chunks<<<cdiv(cnt, 256), 256, 0, s>>>(cnt, nch, scratch, cnt, dW, accum);
+    NNP_LAUNCH_CHECK();
+}
+
+// Column sums db[n] (+)= sum_m G[m][n] in fixed order (chunks of rows).
+__global__ void k_colsum_partial(int M, int N, const float* __restrict__ G, int ldg, int chunk,
+                                 float* __restrict__ part) {
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    int c = blockIdx.y;
+    if (n >= N) return;
+    int m0 = c * chunk, m1 = min(M, m0 + chunk);
+    float s = 0.f;
+    for (int m = m0; m < m1; ++m) s += G[int64_t(m) * ldg + n];
+    part[int64_t(c) * N + n] = s;
+}
+
+void colsum(int M, int N, const float* G, int ldg, float* db, float* scratch, int chunk, bool accum,
+            hipStream_t s) {
+    if (M <= 0) return;
+    int nch = cdiv(M, chunk);
+    k_colsum_partial<<<dim3(cdiv(N, 64), nch), 64, 0, s>>>(M, N, G, ldg, chunk, scratch);
+    k_reduce_chunks<<<cdiv(N, 256), 256, 0, s>>>(N, nch, scratch, N, db, accum);
+    NNP_LAUNCH_CHECK();
+}
+
+}  // namespace nnp
+
+namespace nnp {
+void launch_reduce_chunks(int64_t count, int nchunks, const float* part, int64_t stride, float* out, bool accum,
+                          hipStream_t s) {
+    k_reduce_chunks<<<cdiv(count, 256), 256, 0, s>>>(count, nchunks, part, stride, out, accum);
+    NNP_LAUNCH_CHECK();
+}
+
+// [rows][K + 1] (filter weights then bias per row) -> Wr [rows][K], br [rows]
+__global__ void k_split_filter_grad(int rows, int K, const float* __restrict__ sum, float* __restrict__ dWr,
+                                    float* __restrict__ dbr) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * (K + 1)) return;
+    int r = t / (K + 1), k = t % (K + 1);
+    if (k < K) dWr[r * K + k] = sum[t];
+    else dbr[r] = sum[t];
+}
+
+void launch_split_filter_grad(int rows, int K, const float* sum, float* dWr, float* dbr, hipStream_t s) {
+    k_split_filter_grad<<<cdiv(rows * (K + 1), 256), 256, 0, s>>>(rows, K, sum, dWr, dbr);
+    NNP_LAUNCH_CHECK();
+}
+}  // namespace nnp

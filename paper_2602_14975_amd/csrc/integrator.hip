@@ -1,0 +1,165 @@
+// Float64 Langevin integration on the device (paper, Methods
+// "Multi-time-step integrator", Algorithm 1, "High Hydrogen Friction", and
+// the Fast-Forward Langevin update).  Positions and velocities are [3][n]
+// float64; forces are float32 and promoted before use.
+//
+// Random numbers: Philox-4x64-10 (Salmon et al., SC'11) keyed by
+// (seed_r, stream_r) of the atom's replica with counter (local atom index,
+// O-step index, 0, 0); the four words map to uniforms ((w >> 11) + 0.5) 2^-53
+// and Box-Muller gives the x, y, z normals.
+#include "common.h"
+#include "kernels.h"
+
+namespace nnp {
+
+constexpr double kAcc = 4.184e-4;                        // kcal/mol/A/amu -> A/fs^2
+constexpr double kKb = 8.31446261815324 / 4184.0;        // kcal/mol/K
+
+__device__ __forceinline__ void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64_t& c2, uint64_t& c3, uint64_t k0,
+                                              uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+        const uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+}
+
+__device__ __forceinline__ double u01(uint64_t w) { return (double(w >> 11) + 0.5) * 0x1p-53; }
+
+__device__ __forceinline__ void normals3(uint64_t atom, uint64_t step, uint64_t k0, uint64_t k1, double g[3]) {
+    uint64_t c0 = atom, c1 = step, c2 = 0, c3 = 0;
+    philox4x64_10(c0, c1, c2, c3, k0, k1);
+    const double u0 = u01(c0), u1 = u01(c1), u2 = u01(c2), u3 = u01(c3);
+    const double r0 = sqrt(-2.0 * log(u0)), r1 = sqrt(-2.0 * log(u2));
+    g[0] = r0 * cos(2.0 * M_PI * u1);
+    g[1] = r0 * sin(2.0 * M_PI * u1);
+    g[2] = r1 * cos(2.0 * M_PI * u3);
+}
+
+// v += coef * (Fa - Fb) / m   (Fb may be null)
+__global__ void k_kick(int n, double* __restrict__ vel, const double* __restrict__ mass, const float* __restrict__ Fa,
+                       const float* __restrict__ Fb, double coef) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double im = 1.0 / mass[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double f = double(Fa[a * n + i]);
+        if (Fb) f -= double(Fb[a * n + i]);
+        vel[a * n + i] += coef * f * im;
+    }
+}
+
+// Fused B(d/2) A(d/2) O(d) A(d/2) with the displacement trigger of the
+// Verlet lists (flag set when an atom moved more than the threshold since
+// the last build, or is not finite).
+__global__ void k_baoa(BaoaArgs a) {
+    const int n = a.n;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool over = false;
+    if (i < n) {
+        const int r = a.rep_of_atom ? a.rep_of_atom[i] : 0;
+        const double m = a.mass[i];
+        const double im = 1.0 / m;
+        const double hd = 0.5 * a.dt;
+        double x[3], v[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x[c] = a.pos[c * n + i];
+            v[c] = a.vel[c * n + i];
+            v[c] += hd * kAcc * double(a.force[c * n + i]) * im;
+            x[c] += hd * v[c];
+        }
+        // O step
+        const double gamma = a.gamma[i] * 1e-3;  // ps^-1 -> fs^-1
+        const double c1 = exp(-gamma * a.dt);
+        const double sigma = sqrt((1.0 - c1 * c1) * kKb * a.temperature * kAcc * im);
+        const uint64_t local = uint64_t(i - a.rep_start[r]);
+        const uint64_t step = a.step_base[r] + a.step_offset;
+        double g[3];
+        normals3(local, step, a.seed[r], a.stream[r], g);
+        double nv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nv[c] = c1 * v[c] + sigma * g[c];
+        if (a.ffl) {
+            const double n_old = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            const double n_new = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+            if (n_old > 0.0) {
+                const double s = n_new / n_old;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) nv[c] = v[c] * s;
+            }
+        }
+        double d2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            x[c] += hd * nv[c];
+            a.pos[c * n + i] = x[c];
+            a.vel[c * n + i] = nv[c];
+            if (a.pos_ref) {
+                const double d = x[c] - a.pos_ref[c * n + i];
+                d2 += d * d;
+            }
+        }
+        over = a.pos_ref && !(d2 <= a.disp_thr2);
+    }
+    if (a.flag && __ballot(over) != 0ull && (threadIdx.x & 63) == 0) atomicOr(a.flag, 1);
+}
+
+// Per-replica kinetic energy (fixed-order float64 reduction, one block per
+// replica) and a per-replica finiteness flag of positions and velocities.
+__global__ void __launch_bounds__(256) k_kinetic(const int64_t* __restrict__ rep_start, int n,
+                                                 const double* __restrict__ pos, const double* __restrict__ vel,
+                                                 const double* __restrict__ mass, double* __restrict__ ke,
+                                                 int* __restrict__ bad) {
+    __shared__ double red[256];
+    const int r = blockIdx.x;
+    const int64_t a0 = rep_start[r], a1 = rep_start[r + 1];
+    double s = 0.0;
+    bool nonfinite = false;
+    for (int64_t i = a0 + threadIdx.x; i < a1; i += 256) {
+        double v2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double v = vel[c * int64_t(n) + i];
+            const double x = pos[c * int64_t(n) + i];
+            v2 += v * v;
+            nonfinite |= !isfinite(v) || !isfinite(x);
+        }
+        s += mass[i] * v2;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && ke) ke[r] = 0.5 * red[0] / kAcc;
+    if (nonfinite && bad) atomicOr(bad + r, 1);
+}
+
+// ------------------------------------------------------------------- host --
+void launch_kick(int n, double* vel, const double* mass, const float* Fa, const float* Fb, double half_dt,
+                 hipStream_t s) {
+    k_kick<<<cdiv(n, 256), 256, 0, s>>>(n, vel, mass, Fa, Fb, half_dt * kAcc);
+    NNP_LAUNCH_CHECK();
+}
+
+void launch_baoa(const BaoaArgs& a, hipStream_t s) {
+    k_baoa<<<cdiv(a.n, 256), 256, 0, s>>>(a);
+    NNP_LAUNCH_CHECK();
+}
+
+void launch_kinetic(int n_rep, const int64_t* rep_start, int n, const double* pos, const double* vel,
+                    const double* mass, double* ke, int* bad, hipStream_t s) {
+    k_kinetic<<<n_rep, 256, 0, s>>>(rep_start, n, pos, vel, mass, ke, bad);
+    NNP_LAUNCH_CHECK();
+}
+
+}  // namespace nnp

@@ -1,0 +1,142 @@
+// Launchers and argument blocks of the libnnp kernels (internal).
+#pragma once
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace nnp {
+
+// ---------------------------------------------------------------- neighbours
+struct CellPlan {
+    std::vector<int> m;     // cells per side per replica (1 = whole replica)
+    std::vector<int> base;  // first global cell of each replica
+    int n_cells = 0;
+};
+
+struct NbrScratch {
+    int *grid_m, *grid_base, *cell_of_atom, *slot_of_atom, *cell_count, *cell_start, *cell_atoms, *counts,
+        *tmp_off, *status;
+};
+
+CellPlan plan_cells(const nnp_system& sys, double radius);
+int64_t max_cells(int64_t n_atoms, int32_t n_rep);
+void carve_nbr_scratch(Arena& a, int64_t n, int32_t n_rep, NbrScratch& s);
+void upload_cell_plan(const CellPlan& plan, NbrScratch& s, hipStream_t stream);
+void launch_build(int n, const double* pos, const RepGeom& geom, const CellPlan& plan, NbrScratch& s, const int* run,
+                  double radius, int64_t capacity, int* offsets, int* nbr, int* rev, double* pos_ref,
+                  hipStream_t stream);
+void launch_filter(int n, const double* pos, const RepGeom& geom, NbrScratch& s, const int* run, const int* off_in,
+                   const int* nbr_in, double radius, int64_t capacity, int* offsets, int* nbr, int* rev, int* status,
+                   hipStream_t stream);
+void launch_set_flag(int* flag, int value, hipStream_t stream);
+void launch_disp_check(int n, const double* pos, const double* ref, double thr, int* flag, hipStream_t stream);
+void launch_finish_rebuild(int* flag, long long* n_rebuilds, hipStream_t stream);
+
+// --------------------------------------------------------------------- GEMM
+enum { EPI_NONE = 0, EPI_SILU = 1, EPI_DSILU = 2 };
+
+struct GemmArgs {
+    int M, N, K;
+    const float* A;
+    int64_t sam, sak;
+    const float* B;
+    int64_t sbk, sbn;
+    float* C;
+    int64_t ldc;
+    const float* bias;
+    int epi;
+    float* pre;
+    int64_t ldp;
+    int accum;
+    int64_t chunk_rows;    // > 0: split the K range into chunks along grid.z
+    int64_t chunk_stride;  // C offset between chunks
+};
+
+void launch_gemm(const GemmArgs& g, hipStream_t s);
+void gemm_xwt(int M, int N, int K, const float* X, int ldx, const float* W, const float* b, float* out, int ldo,
+              int epi, float* pre, int ldp, bool accum, hipStream_t s);
+void gemm_gw(int M, int N, int K, const float* G, int ldg, const float* W, float* out, int ldo, int epi,
+             const float* pre, int ldp, bool accum, hipStream_t s);
+void gemm_wgrad(int M, int N, int K, const float* G, int ldg, const float* X, int ldx, float* dW, float* scratch,
+                int chunk, bool accum, hipStream_t s);
+void colsum(int M, int N, const float* G, int ldg, float* db, float* scratch, int chunk, bool accum, hipStream_t s);
+
+// ------------------------------------------------------------ edge kernels
+struct MpGeom {
+    int n;
+    const double* pos;
+    RepGeom geom;
+    const int* off;
+    const int* nbr;
+    double rc, rc2, bessel_norm;
+};
+
+struct MpFwd {
+    const float *s_in, *v_in, *phi, *Wr, *br;
+    float *s_out, *v_out;
+};
+
+struct MpBwd {
+    const float *v_in, *phi, *gsm, *gvm, *Wr, *br;
+    float *gphi, *gv_in;
+    float* edge_g;      // [E][3] accumulated position gradients (GEO)
+    float* wgrad_part;  // [blocks][3F][K + 1] filter weight adjoints (WGRAD)
+};
+
+int mp_blocks(int n, int F);
+void launch_message_fwd(int F, int K, int cut, const MpGeom& mg, const MpFwd& a, hipStream_t s);
+void launch_message_bwd(int F, int K, int cut, const MpGeom& mg, const MpBwd& a, bool geo, bool wgrad,
+                        hipStream_t s);
+void launch_assemble_forces(int n, const int* off, const int* rev, const float* g, float* F, bool accum,
+                            hipStream_t s);
+
+// ----------------------------------------------------------- block kernels
+void launch_embed(int n, int F, int S, const int* species, const float* emb, float* s, float* v, hipStream_t st);
+void launch_build_x(int n, int F, const float* smid, const float* UV, float* X, hipStream_t st);
+void launch_update_combine(int n, int F, const float* smid, const float* vmid, const float* UV, const float* pqo,
+                           float* s_out, float* v_out, hipStream_t st);
+void launch_update_combine_bwd(int n, int F, const float* UV, const float* pqo, const float* gs, const float* gv,
+                               float* gpqo, float* gUV, hipStream_t st);
+void launch_norm_bwd(int n, int F, const float* gs, const float* gX, const float* X, const float* UV, float* gsmid,
+                     float* gUV, hipStream_t st);
+void launch_readout(int n, int F, int S, const float* z, const float* wo, const float* beta, const int* species, float* Ei,
+                    hipStream_t st);
+void launch_readout_bwd(int n, int F, const float* ao, const float* wo, float* gao, hipStream_t st);
+void launch_rep_sum(int n_rep, const int64_t* rep_start, const float* x, double* out, hipStream_t st);
+void launch_emb_grad(int n, int F, int S, const int* species, const float* gs0, float* gemb, hipStream_t st);
+void launch_head_fwd(const MpGeom& mg, const float* QK, const float* Vh, float* F, bool accum, hipStream_t st);
+void launch_head_bwd(const MpGeom& mg, const float* QK, const float* Vh, const float* gF, float* gQK, float* gVh,
+                     hipStream_t st);
+
+// -------------------------------------------------------------- integrator
+struct BaoaArgs {
+    int n;
+    double* pos;
+    double* vel;
+    const double* mass;
+    const double* gamma;
+    const float* force;
+    double dt;
+    double temperature;
+    const int32_t* rep_of_atom;
+    const int64_t* rep_start;
+    const uint64_t* seed;
+    const uint64_t* stream;
+    const uint64_t* step_base;
+    uint64_t step_offset;
+    int ffl;
+    const double* pos_ref;
+    double disp_thr2;
+    int* flag;
+};
+
+void launch_kick(int n, double* vel, const double* mass, const float* Fa, const float* Fb, double half_dt,
+                 hipStream_t s);
+void launch_baoa(const BaoaArgs& a, hipStream_t s);
+void launch_kinetic(int n_rep, const int64_t* rep_start, int n, const double* pos, const double* vel,
+                    const double* mass, double* ke, int* bad, hipStream_t s);
+
+}  // namespace nnp

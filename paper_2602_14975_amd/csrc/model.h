@@ -1,0 +1,73 @@
+// Device-side model object and the scratch layout of one force evaluation.
+#pragma once
+
+#include "common.h"
+#include "kernels.h"
+
+namespace nnp {
+
+constexpr int kMaxLayers = 4;
+constexpr int kChunk = 2048;  // rows per partial sum in weight adjoints
+
+struct LayerOff {
+    int64_t W1, b1, W2, b2, Wr, br, U, V, M1, m1, M2, m2;
+};
+
+// Weights live as one float32 device vector in manifest order; every tensor
+// is addressed by its manifest offset (U and V are adjacent, so [U; V] is a
+// single [2F][F] matrix; likewise [Wq; Wk] is one [2 H n_c][F] matrix).
+struct Model {
+    nnp_model_desc desc{};
+    float* w = nullptr;
+    int64_t n_weights = 0;
+    int64_t off_emb = 0, off_Wo = 0, off_bo = 0, off_wo = 0, off_beta = 0, off_Wq = 0, off_Wk = 0, off_WV = 0;
+    LayerOff loff[kMaxLayers]{};
+    void layout();
+    int n_layers() const { return desc.kind == NNP_MODEL_CONS ? desc.n_layers : 1; }
+    const float* p(int64_t off) const { return w + off; }
+};
+
+struct LayerBuf {
+    float *h1, *zphi, *phi, *smid, *vmid, *UV, *X, *a1, *z, *pqo;
+};
+
+struct ModelBuf {
+    float* s[kMaxLayers + 1];
+    float* v[kMaxLayers + 1];
+    LayerBuf layer[kMaxLayers];
+    float *ao = nullptr, *zo = nullptr, *Ei = nullptr;
+    float *QK = nullptr, *Vh = nullptr, *gQK = nullptr, *gVh = nullptr;
+    float *gs = nullptr, *gs2 = nullptr, *gv = nullptr, *gv2 = nullptr, *gpqo = nullptr, *ga1 = nullptr,
+          *gX = nullptr, *gUV = nullptr, *gphi = nullptr, *gh1 = nullptr;
+    float* edge_g = nullptr;
+    int* rev = nullptr;
+    float *chunk_part = nullptr, *mp_part = nullptr, *filt_sum = nullptr;
+};
+
+struct SysTables {
+    int64_t* rep_start;
+    double *box, *inv_box;
+    uint64_t *seed, *stream, *step_base;
+    int* flags;
+    int* rep_bad;
+    long long* rebuilds;
+};
+
+struct RespaBuf {
+    double *pos, *vel, *pos_ref, *energy;
+    float *f_cons, *f_nc;
+};
+
+void launch_reverse(int n, const int* run, const int* status, const int* offsets, const int* nbr, int* rev,
+                    hipStream_t s);
+void launch_reduce_chunks(int64_t count, int nchunks, const float* part, int64_t stride, float* out, bool accum,
+                          hipStream_t s);
+struct CallScratch;
+size_t call_scratch_bytes(const Model* cons, const Model* nc, int64_t n, int32_t n_rep, int64_t E);
+void check_system(const nnp_system* sys);
+nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const respa_params* p, int32_t n_outer,
+                     void* ws, size_t ws_bytes, hipStream_t s, const uint64_t* seeds, const uint64_t* streams,
+                     const uint64_t* step_base, int* rep_bad);
+void launch_split_filter_grad(int rows, int K, const float* sum, float* dWr, float* dbr, hipStream_t s);
+
+}  // namespace nnp

@@ -1,0 +1,434 @@
+// Periodic cell-list neighbour build (gfx950).
+//
+// Pipeline for a packed multi-replica system (one launch each, every kernel
+// a no-op when the device flag `run` is zero, so a rebuild can be decided on
+// the device without a host round trip):
+//   cell_assign  atom -> cell (per-replica grid of m^3 cells of edge >= rc,
+//                or a single cell holding the whole replica when m < 3),
+//                counting-sort slot by atomic increment, and a copy of the
+//                positions as the reference for the displacement trigger
+//   scan         exclusive prefix sums of the cell counts
+//   cell_fill    cell-sorted atom array
+//   nbr_count    one wavefront per atom: 27-cell stencil, float64 pair rule
+//   scan         row offsets
+//   nbr_fill     same tests, ballot compaction into LDS, rank sort so each
+//                row lists j ascending, then a coalesced row store
+//   nbr_reverse  rev[e] for e = (i, j): position of i in row j (binary search)
+// A second list at a smaller radius is filtered from the first row by row
+// (filter_count / scan / filter_fill), which keeps row order.
+#include "common.h"
+#include "kernels.h"
+#include "model.h"
+
+namespace nnp {
+
+constexpr int kWaves = 4;          // wavefronts per block for per-atom kernels
+constexpr int kMaxRow = 1024;      // longest row the fill kernels can sort
+
+__global__ void k_set_flag(int* flag, int value) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *flag = value;
+}
+
+__global__ void k_cell_assign(int n, const double* __restrict__ pos, RepGeom geom,
+                              const int* __restrict__ grid_m, const int* __restrict__ grid_base,
+                              const int* __restrict__ run, int* __restrict__ cell_of_atom,
+                              int* __restrict__ slot_of_atom, int* __restrict__ cell_count,
+                              double* __restrict__ pos_ref) {
+    if (*run == 0) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int r = geom.rep_of_atom ? geom.rep_of_atom[i] : 0;
+    double L, inv;
+    geom.get(i, L, inv);
+    int m = grid_m[r];
+    double x = pos[i], y = pos[n + i], z = pos[2 * n + i];
+    if (pos_ref) {
+        pos_ref[i] = x;
+        pos_ref[n + i] = y;
+        pos_ref[2 * n + i] = z;
+    }
+    int cell = grid_base[r];
+    if (m > 1) {
+        int c[3];
+        double p[3] = {x, y, z};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double w = p[a] - L * floor(p[a] * inv);
+            int ci = int(w * inv * double(m));
+            c[a] = ci < 0 ? 0 : (ci >= m ? m - 1 : ci);
+        }
+        cell += (c[0] * m + c[1]) * m + c[2];
+    }
+    cell_of_atom[i] = cell;
+    slot_of_atom[i] = atomicAdd(&cell_count[cell], 1);
+}
+
+// Exclusive scan of in[0..n) into out[0..n] (out[n] = total), one block.
+__global__ void __launch_bounds__(1024) k_scan(int n, const int* __restrict__ in,
+                                                int* __restrict__ out, const int* __restrict__ run) {
+    if (run && *run == 0) return;
+    __shared__ int partial[1024];
+    int t = threadIdx.x;
+    int per = (n + 1023) / 1024;
+    int lo = t * per, hi = min(n, lo + per);
+    int sum = 0;
+    for (int k = lo; k < hi; ++k) sum += in[k];
+    partial[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = t >= off ? partial[t - off] : 0;
+        __syncthreads();
+        partial[t] += v;
+        __syncthreads();
+    }
+    int run_sum = partial[t] - sum;
+    for (int k = lo; k < hi; ++k) {
+        out[k] = run_sum;
+        run_sum += in[k];
+    }
+    if (t == 1023) out[n] = partial[1023];
+}
+
+__global__ void k_cell_fill(int n, const int* __restrict__ run, const int* __restrict__ cell_of_atom,
+                            const int* __restrict__ slot_of_atom, const int* __restrict__ cell_start,
+                            int* __restrict__ cell_atoms) {
+    if (*run == 0) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cell_atoms[cell_start[cell_of_atom[i]] + slot_of_atom[i]] = i;
+}
+
+// Iterates over the stencil cells of atom i; calls body(j) for every
+// candidate (lanes split each cell's member list).
+struct Stencil {
+    const int* grid_m;
+    const int* grid_base;
+    const int* cell_of_atom;
+    const int* cell_start;
+    const int* cell_atoms;
+};
+
+template <class Body>
+__device__ __forceinline__ void for_candidates(const Stencil& st, int i, int r, int lane, Body body) {
+    int m = st.grid_m[r];
+    int base = st.grid_base[r];
+    int cell = st.cell_of_atom[i];
+    if (m == 1) {
+        const int s = st.cell_start[cell], e = st.cell_start[cell + 1];
+        const int trips = (e - s + 63) / 64;  // uniform across the wavefront
+        for (int k = 0; k < trips; ++k) {
+            const int t = s + k * 64 + lane;
+            body(t < e ? st.cell_atoms[t] : -1);
+        }
+        return;
+    }
+    int local = cell - base;
+    int cx = local / (m * m), cy = (local / m) % m, cz = local % m;
+    for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dz = -1; dz <= 1; ++dz) {
+                int ax = (cx + dx + m) % m, ay = (cy + dy + m) % m, az = (cz + dz + m) % m;
+                int c = base + (ax * m + ay) * m + az;
+                int s = st.cell_start[c], e = st.cell_start[c + 1];
+                int cnt = e - s;
+                int trips = (cnt + 63) / 64;
+                for (int k = 0; k < trips; ++k) {
+                    int t = s + k * 64 + lane;
+                    body(t < e ? st.cell_atoms[t] : -1);
+                }
+            }
+}
+
+__global__ void __launch_bounds__(64 * kWaves)
+k_nbr_count(int n, const double* __restrict__ pos, RepGeom geom, Stencil st, double rc2,
+            const int* __restrict__ run, int* __restrict__ counts, int* __restrict__ status) {
+    if (*run == 0) return;
+    int lane = threadIdx.x & 63;
+    int i = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (i >= n) return;  // whole wavefront exits together
+    int r = geom.rep_of_atom ? geom.rep_of_atom[i] : 0;
+    double L, inv;
+    geom.get(i, L, inv);
+    double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+    int cnt = 0;
+    for_candidates(st, i, r, lane, [&](int j) {
+        if (j >= 0 && j != i) {
+            double dx, dy, dz;
+            if (pair_rule(xi, yi, zi, pos[j], pos[n + j], pos[2 * n + j], L, inv, rc2, dx, dy, dz))
+                ++cnt;
+        }
+    });
+    float tot = wave_sum(float(cnt));
+    if (lane == 0) {
+        const int c = int(tot + 0.5f);
+        counts[i] = c;
+        if (c > kMaxRow) status[2] = 1;  // the fill kernel cannot sort this row: build nothing
+    }
+}
+
+// Rank sort of `cnt` distinct values in LDS row[] into out[] (global).
+__device__ __forceinline__ void rank_sort_store(const int* row, int cnt, int lane, int* out) {
+    for (int t = lane; t < cnt; t += 64) {
+        int v = row[t];
+        int rank = 0;
+        for (int u = 0; u < cnt; ++u) rank += row[u] < v;
+        out[rank] = v;
+    }
+}
+
+__global__ void __launch_bounds__(64 * kWaves)
+k_nbr_fill(int n, const double* __restrict__ pos, RepGeom geom, Stencil st, double rc2,
+           const int* __restrict__ run, const int* __restrict__ tmp_off, int64_t capacity,
+           int* __restrict__ offsets, int* __restrict__ nbr, int* __restrict__ status) {
+    if (*run == 0) return;
+    __shared__ int rows[kWaves][kMaxRow];
+    int lane = threadIdx.x & 63;
+    int w = threadIdx.x >> 6;
+    int i = blockIdx.x * kWaves + w;
+    if (i >= n) return;
+    int total = tmp_off[n];
+    if (status[2] != 0) return;  // a row is longer than kMaxRow: keep the previous list intact
+    if (int64_t(total) > capacity) {
+        if (i == 0 && lane == 0) {
+            status[0] = 1;      // capacity overflow
+            status[1] = total;  // required entries
+        }
+        return;
+    }
+    int r = geom.rep_of_atom ? geom.rep_of_atom[i] : 0;
+    double L, inv;
+    geom.get(i, L, inv);
+    double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+    int fill = 0;
+    int* row = rows[w];
+    for_candidates(st, i, r, lane, [&](int j) {
+        bool ok = false;
+        if (j >= 0 && j != i) {
+            double dx, dy, dz;
+            ok = pair_rule(xi, yi, zi, pos[j], pos[n + j], pos[2 * n + j], L, inv, rc2, dx, dy, dz);
+        }
+        uint64_t bal = __ballot(ok);
+        int pre = __popcll(bal & ((1ull << lane) - 1ull));
+        if (ok && fill + pre < kMaxRow) row[fill + pre] = j;
+        fill += __popcll(bal);
+    });
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    int start = tmp_off[i];
+    if (fill != tmp_off[i + 1] - start) {
+        if (lane == 0) status[3] = 1;  // count and fill disagree (not expected)
+    }
+    fill = min(fill, tmp_off[i + 1] - start);
+    if (lane == 0) {
+        offsets[i] = start;
+        if (i == n - 1) offsets[n] = total;
+    }
+    rank_sort_store(row, fill, lane, nbr + start);
+}
+
+// Second list at a smaller radius, filtered from a first list row by row.
+__global__ void __launch_bounds__(64 * kWaves)
+k_filter_count(int n, const double* __restrict__ pos, RepGeom geom, const int* __restrict__ off_in,
+               const int* __restrict__ nbr_in, double rc2, const int* __restrict__ run,
+               int* __restrict__ counts) {
+    if (*run == 0) return;
+    int lane = threadIdx.x & 63;
+    int i = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (i >= n) return;
+    double L, inv;
+    geom.get(i, L, inv);
+    double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+    int cnt = 0;
+    for (int e = off_in[i] + lane; e < off_in[i + 1]; e += 64) {
+        int j = nbr_in[e];
+        double dx, dy, dz;
+        cnt += pair_rule(xi, yi, zi, pos[j], pos[n + j], pos[2 * n + j], L, inv, rc2, dx, dy, dz);
+    }
+    float tot = wave_sum(float(cnt));
+    if (lane == 0) counts[i] = int(tot + 0.5f);
+}
+
+__global__ void __launch_bounds__(64 * kWaves)
+k_filter_fill(int n, const double* __restrict__ pos, RepGeom geom, const int* __restrict__ off_in,
+              const int* __restrict__ nbr_in, double rc2, const int* __restrict__ run,
+              const int* __restrict__ tmp_off, int64_t capacity, int* __restrict__ offsets,
+              int* __restrict__ nbr, int* __restrict__ status) {
+    if (*run == 0) return;
+    int lane = threadIdx.x & 63;
+    int i = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (i >= n) return;
+    int total = tmp_off[n];
+    if (int64_t(total) > capacity) {
+        if (i == 0 && lane == 0) {
+            status[0] = 1;
+            status[1] = total;
+        }
+        return;
+    }
+    double L, inv;
+    geom.get(i, L, inv);
+    double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
+    int out = tmp_off[i];
+    int s = off_in[i], e_end = off_in[i + 1];
+    for (int base = s; base < e_end; base += 64) {
+        int e = base + lane;
+        bool ok = false;
+        int j = -1;
+        if (e < e_end) {
+            j = nbr_in[e];
+            double dx, dy, dz;
+            ok = pair_rule(xi, yi, zi, pos[j], pos[n + j], pos[2 * n + j], L, inv, rc2, dx, dy, dz);
+        }
+        uint64_t bal = __ballot(ok);
+        int pre = __popcll(bal & ((1ull << lane) - 1ull));
+        if (ok) nbr[out + pre] = j;
+        out += __popcll(bal);
+    }
+    if (lane == 0) {
+        offsets[i] = tmp_off[i];
+        if (i == n - 1) offsets[n] = total;
+    }
+}
+
+__global__ void __launch_bounds__(64 * kWaves)
+k_nbr_reverse(int n, const int* __restrict__ run, const int* __restrict__ status,
+              const int* __restrict__ offsets, const int* __restrict__ nbr, int* __restrict__ rev) {
+    if (*run == 0 || status[0] != 0 || status[2] != 0) return;
+    int lane = threadIdx.x & 63;
+    int i = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (i >= n) return;
+    for (int e = offsets[i] + lane; e < offsets[i + 1]; e += 64) {
+        int j = nbr[e];
+        int lo = offsets[j], hi = offsets[j + 1];  // search i in row j (ascending)
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (nbr[mid] < i) lo = mid + 1; else hi = mid;
+        }
+        rev[e] = (lo < offsets[j + 1] && nbr[lo] == i) ? lo : e;
+    }
+}
+
+__global__ void k_disp_check(int n, const double* __restrict__ pos, const double* __restrict__ ref,
+                             double thr2, int* __restrict__ flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool over = false;
+    if (i < n) {
+        double dx = pos[i] - ref[i], dy = pos[n + i] - ref[n + i], dz = pos[2 * n + i] - ref[2 * n + i];
+        double d2 = dx * dx + dy * dy + dz * dz;
+        over = !(d2 <= thr2);  // NaN also triggers
+    }
+    if (__ballot(over) != 0ull && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+__global__ void k_finish_rebuild(int* flag, long long* n_rebuilds) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        if (*flag) {
+            if (n_rebuilds) *n_rebuilds += 1;
+            *flag = 0;
+        }
+    }
+}
+
+// ------------------------------------------------------------------- host --
+
+CellPlan plan_cells(const nnp_system& sys, double radius) {
+    CellPlan p;
+    p.m.resize(sys.n_rep);
+    p.base.resize(sys.n_rep);
+    int total = 0;
+    for (int r = 0; r < sys.n_rep; ++r) {
+        double L = sys.box[r];
+        NNP_REQUIRE(L > 0 && radius < 0.5 * L, NNP_EINVAL,
+                    "pair radius must be below half the box edge (replica " + std::to_string(r) + ")");
+        int64_t nr = sys.rep_start[r + 1] - sys.rep_start[r];
+        int m = int(std::floor(L / (radius * (1.0 + 1e-9))));
+        while (m >= 3 && int64_t(m) * m * m > 2 * nr + 27) --m;
+        if (m < 3) m = 1;
+        p.m[r] = m;
+        p.base[r] = total;
+        total += m * m * m;
+    }
+    p.n_cells = total;
+    return p;
+}
+
+int64_t max_cells(int64_t n_atoms, int32_t n_rep) { return 2 * n_atoms + 27 * int64_t(n_rep) + 1; }
+
+void carve_nbr_scratch(Arena& a, int64_t n, int32_t n_rep, NbrScratch& s) {
+    int64_t C = max_cells(n, n_rep);
+    s.grid_m = a.take<int>(n_rep);
+    s.grid_base = a.take<int>(n_rep);
+    s.cell_of_atom = a.take<int>(n);
+    s.slot_of_atom = a.take<int>(n);
+    s.cell_count = a.take<int>(C + 1);
+    s.cell_start = a.take<int>(C + 1);
+    s.cell_atoms = a.take<int>(n);
+    s.counts = a.take<int>(n);
+    s.tmp_off = a.take<int>(n + 1);
+    s.status = a.take<int>(8);
+}
+
+void upload_cell_plan(const CellPlan& plan, NbrScratch& s, hipStream_t stream) {
+    NNP_HIP(hipMemcpyAsync(s.grid_m, plan.m.data(), plan.m.size() * sizeof(int), hipMemcpyHostToDevice, stream));
+    NNP_HIP(hipMemcpyAsync(s.grid_base, plan.base.data(), plan.base.size() * sizeof(int),
+                           hipMemcpyHostToDevice, stream));
+}
+
+void launch_build(int n, const double* pos, const RepGeom& geom, const CellPlan& plan, NbrScratch& s,
+                  const int* run, double radius, int64_t capacity, int* offsets, int* nbr, int* rev,
+                  double* pos_ref, hipStream_t stream) {
+    NNP_HIP(hipMemsetAsync(s.cell_count, 0, sizeof(int) * (plan.n_cells + 1), stream));
+    k_cell_assign<<<cdiv(n, 256), 256, 0, stream>>>(n, pos, geom, s.grid_m, s.grid_base, run, s.cell_of_atom,
+                                                    s.slot_of_atom, s.cell_count, pos_ref);
+    k_scan<<<1, 1024, 0, stream>>>(plan.n_cells, s.cell_count, s.cell_start, run);
+    k_cell_fill<<<cdiv(n, 256), 256, 0, stream>>>(n, run, s.cell_of_atom, s.slot_of_atom, s.cell_start,
+                                                  s.cell_atoms);
+    Stencil st{s.grid_m, s.grid_base, s.cell_of_atom, s.cell_start, s.cell_atoms};
+    double rc2 = radius * radius;
+    k_nbr_count<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, pos, geom, st, rc2, run, s.counts, s.status);
+    k_scan<<<1, 1024, 0, stream>>>(n, s.counts, s.tmp_off, run);
+    k_nbr_fill<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, pos, geom, st, rc2, run, s.tmp_off, capacity,
+                                                            offsets, nbr, s.status);
+    if (rev)
+        k_nbr_reverse<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, run, s.status, offsets, nbr, rev);
+    NNP_LAUNCH_CHECK();
+}
+
+void launch_filter(int n, const double* pos, const RepGeom& geom, NbrScratch& s, const int* run,
+                   const int* off_in, const int* nbr_in, double radius, int64_t capacity, int* offsets,
+                   int* nbr, int* rev, int* status, hipStream_t stream) {
+    double rc2 = radius * radius;
+    k_filter_count<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, pos, geom, off_in, nbr_in, rc2, run, s.counts);
+    k_scan<<<1, 1024, 0, stream>>>(n, s.counts, s.tmp_off, run);
+    k_filter_fill<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, pos, geom, off_in, nbr_in, rc2, run, s.tmp_off,
+                                                               capacity, offsets, nbr, status);
+    if (rev)
+        k_nbr_reverse<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, run, status, offsets, nbr, rev);
+    NNP_LAUNCH_CHECK();
+}
+
+void launch_set_flag(int* flag, int value, hipStream_t stream) {
+    k_set_flag<<<1, 64, 0, stream>>>(flag, value);
+    NNP_LAUNCH_CHECK();
+}
+
+void launch_disp_check(int n, const double* pos, const double* ref, double thr, int* flag, hipStream_t stream) {
+    k_disp_check<<<cdiv(n, 256), 256, 0, stream>>>(n, pos, ref, thr * thr, flag);
+    NNP_LAUNCH_CHECK();
+}
+
+void launch_finish_rebuild(int* flag, long long* n_rebuilds, hipStream_t stream) {
+    k_finish_rebuild<<<1, 64, 0, stream>>>(flag, n_rebuilds);
+    NNP_LAUNCH_CHECK();
+}
+
+}  // namespace nnp
+
+namespace nnp {
+void launch_reverse(int n, const int* run, const int* status, const int* offsets, const int* nbr, int* rev,
+                    hipStream_t s) {
+    k_nbr_reverse<<<cdiv(n, kWaves), 64 * kWaves, 0, s>>>(n, run, status, offsets, nbr, rev);
+    NNP_LAUNCH_CHECK();
+}
+}  // namespace nnp

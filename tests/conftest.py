@@ -33,6 +33,6 @@ def gpu_lib():
     import torch
     if not torch.cuda.is_available():
         pytest.fail("GPU test selected but no GPU is visible")
-    import paper_2602_14975_amd as nnp
+    from paper_2602_14975_amd import nnp
     nnp.lib()  # raises if the shared library is missing
     return nnp

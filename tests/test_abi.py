@@ -1,0 +1,103 @@
+"""CPU checks of the C interface: the library loads, exports every function
+that include/nnp.h declares, and its host-only entry points behave."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import integrator as oi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nnp.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2602_14975_amd import _abi
+    return _abi.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("nnp_neighbors", "nnp_cons_energy_forces", "nnp_nc_forces", "respa_step", "replica_submit",
+                     "replica_poll", "nnp_nc_weight_grad", "nnp_server_progress"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert missing == []
+
+
+def test_binding_covers_every_symbol(lib):
+    from paper_2602_14975_amd import _abi
+    assert sorted(_abi.PROTOTYPES) == _declared()
+
+
+def test_structure_sizes_match_c():
+    from paper_2602_14975_amd import _abi
+    # sizes follow from the C layout rules on x86-64
+    assert C.sizeof(_abi.ModelDesc) == 10 * 4 + 8 + 8 + 8
+    assert C.sizeof(_abi.System) == 8 + 8 + 6 * 8
+    assert C.sizeof(_abi.NList) == 3 * 8 + 3 * 8 + 8
+    assert C.sizeof(_abi.RespaParams) == 8 + 4 * 4 + 8 + 8 + 8 + 8
+
+
+def test_abi_version_and_error_string(lib):
+    assert lib.nnp_abi_version() == 1
+    assert isinstance(lib.nnp_last_error(), bytes)
+
+
+def test_hmr_matches_oracle(lib):
+    from paper_2602_14975_amd import nnp
+    s = synth.solvated_chain(25, 40, seed=3)
+    m0 = s.standard_masses()
+    for mode in ("set", "add"):
+        got = nnp.nnp_hmr_masses(s.bonded_heavy, m0, 3.0, mode)
+        want = oi.hmr_masses(s.species, s.bonded_heavy, m0, 3.0, mode)
+        assert np.array_equal(got, want)
+
+
+def test_hmr_rejects_bad_topology(lib):
+    from paper_2602_14975_amd import _abi, nnp
+    with pytest.raises(_abi.NnpError):
+        nnp.nnp_hmr_masses(np.array([1, 0], np.int32), np.array([1.0, 1.0]))  # H bonded to an H
+    with pytest.raises(_abi.NnpError):
+        nnp.nnp_hmr_masses(np.array([-1, 0], np.int32), np.array([1.0, 1.008]), 5.0, "set")  # negative heavy mass
+
+
+def test_entry_points_reject_null_arguments_without_a_gpu(lib):
+    from paper_2602_14975_amd import _abi
+    nl = _abi.NList()
+    assert lib.nnp_neighbors(None, C.byref(nl), None, 0, None) == _abi.NNP_EINVAL
+    assert b"incomplete" in lib.nnp_last_error()
+    desc = _abi.ModelDesc()
+    desc.kind = 7
+    h = C.c_void_p()
+    assert lib.nnp_model_create(C.byref(desc), C.byref(h)) == _abi.NNP_EINVAL
+    size = C.c_size_t()
+    assert lib.nnp_workspace_size(None, None, 0, 1, 0, C.byref(size)) == _abi.NNP_EINVAL
+    assert lib.nnp_workspace_size(None, None, 100, 1, 1000, C.byref(size)) == _abi.NNP_OK
+    assert size.value > 0
+
+
+def test_model_create_rejects_wrong_weight_count(lib):
+    from paper_2602_14975_amd import _abi
+    w = np.zeros(10)
+    d = _abi.ModelDesc(0, 4, 32, 2, 16, 5, 8, 2, 8, 0, 5.0, w.ctypes.data_as(C.POINTER(C.c_double)), 10)
+    h = C.c_void_p()
+    assert lib.nnp_model_create(C.byref(d), C.byref(h)) == _abi.NNP_EINVAL
+    assert b"manifest needs" in lib.nnp_last_error()
+    n_ok = synth.manifest_size(synth.CONS_CFG0)
+    assert str(n_ok).encode() in lib.nnp_last_error()

@@ -1,0 +1,121 @@
+"""GPU parity of respa_step (Algorithm 1, BAOAB, HMR, HHF, FFL) against the
+oracle's integrator on short horizons with the same Philox streams."""
+
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import integrator as oi
+from oracle import models as om
+from oracle import neighbors as onb
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_fns(cons_spec, cw, nc_spec, nw, species, box):
+    def cons_fn(x):
+        off, nbr = onb.pairs_bruteforce(x, box, cons_spec.cutoff)
+        return om.cons_energy_forces(cons_spec, cw, x, species, box, off, nbr)[1]
+
+    def nc_fn(x):
+        off, nbr = onb.pairs_bruteforce(x, box, nc_spec.cutoff)
+        return om.nc_forces(nc_spec, nw, x, species, box, off, nbr)
+
+    return cons_fn, nc_fn
+
+
+def _run_pair(nnp, s, masses, gamma, mode, dt, n_inner, n_outer, thermostat="langevin", seed=4000, skin=1.0):
+    cons_spec, nc_spec = synth.CONS_CFG0, synth.NC_CFG0
+    cw = synth.random_weights(cons_spec, 2000)
+    nw = synth.random_weights(nc_spec, 3000)
+    cons = nnp.Model.from_spec(cons_spec, cw)
+    nc = nnp.Model.from_spec(nc_spec, nw)
+    v0 = synth.maxwell_boltzmann(masses, 300.0, 5000)
+    system = nnp.DeviceSystem(s.pos, s.species, s.box)
+    prm = nnp.respa_params(dt, n_inner, 300.0, seed=seed, stream_id=0, mode=mode, thermostat=thermostat, skin=skin)
+    traj = nnp.Trajectory(cons, nc if mode == "dmts_nc" else None, system, v0, masses, gamma, prm)
+    ke = torch.zeros(n_outer, 1, dtype=torch.float64, device="cuda")
+    traj.respa_step(n_outer, ke)
+    cons_fn, nc_fn = _oracle_fns(cons_spec, cw, nc_spec, nw, s.species, s.box)
+    st = oi.State(s.pos.copy(), v0.copy(), masses.copy())
+    p = oi.LangevinParams(dt, n_inner if mode == "dmts_nc" else 1, 300.0, gamma, seed=seed, stream=0,
+                          thermostat=thermostat)
+    kes = []
+    for _ in range(n_outer):
+        if mode == "dmts_nc":
+            oi.dmts_nc_step(st, cons_fn, nc_fn, p)
+        else:
+            oi.baoab_step(st, cons_fn, p)
+        kes.append(oi.kinetic_energy(st.v, st.m))
+    return traj, st, ke.cpu().numpy()[:, 0], np.array(kes)
+
+
+def _compare(traj, st, ke, kes):
+    x, v = traj.positions(), traj.velocities()
+    assert traj.step_count == st.step
+    assert np.max(np.abs(x - st.x)) <= 2e-6
+    assert np.max(np.abs(v - st.v)) <= 1e-5 * np.max(np.abs(st.v))
+    np.testing.assert_allclose(ke, kes, rtol=1e-5)
+
+
+def test_dmts_nc_matches_oracle(gpu_lib):
+    s = synth.water_config(0)
+    m = s.standard_masses()
+    g = np.ones(s.n)
+    _compare(*_run_pair(gpu_lib, s, m, g, "dmts_nc", 2.0, 4, 10))
+
+
+def test_sts_matches_oracle(gpu_lib):
+    s = synth.water_config(0)
+    m = s.standard_masses()
+    g = np.ones(s.n)
+    _compare(*_run_pair(gpu_lib, s, m, g, "sts", 0.5, 1, 20))
+
+
+def test_hmr_hhf_matches_oracle(gpu_lib):
+    s = synth.water_config(0)
+    m = gpu_lib.nnp_hmr_masses(s.bonded_heavy, s.standard_masses(), 3.0, "set")
+    assert np.array_equal(m, oi.hmr_masses(s.species, s.bonded_heavy, s.standard_masses(), 3.0, "set"))
+    g = oi.friction_per_atom(s.species, [100.0, 1.0, 1.0, 1.0])
+    _compare(*_run_pair(gpu_lib, s, m, g, "dmts_nc", 4.0, 4, 5))
+
+
+def test_ffl_matches_oracle(gpu_lib):
+    s = synth.water_config(0)
+    m = s.standard_masses()
+    g = oi.friction_per_atom(s.species, [10.0, 1.0, 1.0, 1.0])
+    _compare(*_run_pair(gpu_lib, s, m, g, "dmts_nc", 2.0, 4, 5, thermostat="ffl"))
+
+
+def test_skin_does_not_change_trajectory(gpu_lib):
+    s = synth.water_config(0)
+    m = s.standard_masses()
+    g = np.ones(s.n)
+    a = _run_pair(gpu_lib, s, m, g, "dmts_nc", 2.0, 4, 6, skin=0.2)[0]
+    b = _run_pair(gpu_lib, s, m, g, "dmts_nc", 2.0, 4, 6, skin=1.1)[0]
+    assert np.array_equal(a.positions(), b.positions())
+    assert np.array_equal(a.velocities(), b.velocities())
+    assert a.n_rebuilds > b.n_rebuilds >= 1
+
+
+def test_full_size_dmts_nc_runs(gpu_lib):
+    """12,288 atoms at full widths: a few outer steps stay finite, keep the
+    temperature near 300 K, and conserve nothing spurious (net force of the
+    NC model ~ 0)."""
+    s = synth.water_config(1)
+    m = s.standard_masses()
+    cons = gpu_lib.Model.from_spec(synth.CONS_CFG1, synth.random_weights(synth.CONS_CFG1, 2001))
+    nc = gpu_lib.Model.from_spec(synth.NC_CFG1, synth.random_weights(synth.NC_CFG1, 3001))
+    v0 = synth.maxwell_boltzmann(m, 300.0, 5001)
+    system = gpu_lib.DeviceSystem(s.pos, s.species, s.box)
+    prm = gpu_lib.respa_params(4.0, 8, 300.0, seed=4001)
+    traj = gpu_lib.Trajectory(cons, nc, system, v0, m, np.ones(s.n), prm)
+    ke = torch.zeros(3, 1, dtype=torch.float64, device="cuda")
+    traj.respa_step(3, ke)
+    T = 2 * ke.cpu().numpy()[:, 0] / (3 * s.n * oi.KB)
+    assert np.all(np.isfinite(T)) and np.all(np.abs(T - 300) < 30)
+    fnc = traj.f_nc.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(fnc.sum(1)) <= 1e-5 * np.abs(fnc).sum()
