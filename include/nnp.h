@@ -315,6 +315,16 @@ nnp_status nnp_server_step_latencies(nnp_server* server, double* out, int64_t ca
 /* Server clock now (seconds). */
 double nnp_server_clock(const nnp_server* server);
 
+/* ------------------------------------------------------------- diagnostics
+ * Device-time measurement of named launch sites ("message_fwd",
+ * "message_bwd", "nc_message_fwd", "nc_message_bwd", "head_fwd", "gemm",
+ * "nbr_fill", "baoa").  While a site is enabled each of its launches is
+ * bracketed by two HIP events on the launch's stream; nnp_timer_read waits
+ * for them and returns the summed duration (ms) and the number of launches
+ * (reset != 0 clears the record). */
+nnp_status nnp_timer_enable(const char* site, int32_t on);
+nnp_status nnp_timer_read(const char* site, double* total_ms, int64_t* launches, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -88,6 +88,8 @@ PROTOTYPES = {
     "nnp_server_progress": (C.c_int32, [vp, C.c_int32, C.POINTER(C.c_int32)]),
     "nnp_server_step_latencies": (C.c_int32, [vp, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_int64)]),
     "nnp_server_clock": (C.c_double, [vp]),
+    "nnp_timer_enable": (C.c_int32, [C.c_char_p, C.c_int32]),
+    "nnp_timer_read": (C.c_int32, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
 }
 
 _LIB = None

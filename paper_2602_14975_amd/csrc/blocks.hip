@@ -209,11 +209,17 @@ __device__ __forceinline__ void head_coeffs(const float* qa, const float* kb, fl
     }
 }
 
+// Lanes take one CSR entry each; the contributions of the entries that pass
+// the pair rule are compacted (ballot) into LDS and added by one lane in row
+// order, so the sum does not depend on how many extra Verlet entries the row
+// holds or where batch boundaries fall.
 __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __restrict__ QK, const float* __restrict__ Vh,
                                                   float* __restrict__ Fout, int accum) {
+    __shared__ float contrib[4][64][3];
     const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= mg.n) return;
+    const int w = threadIdx.x >> 6;
+    const int i = blockIdx.x * 4 + w;
+    if (i >= mg.n) return;  // whole wavefront
     const int n = mg.n;
     double L, inv;
     mg.geom.get(i, L, inv);
@@ -225,36 +231,50 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int h = 0; h < kNl; ++h) Vi[h][a] = Vh[(int64_t(i) * 3 + a) * kNl + h];
-    float fx = 0.f, fy = 0.f, fz = 0.f;
-    for (int e = mg.off[i] + lane; e < mg.off[i + 1]; e += 64) {
+    float fx = 0.f, fy = 0.f, fz = 0.f;  // running sums (lane 0)
+    const int e0 = mg.off[i], e1 = mg.off[i + 1];
+    for (int base = e0; base < e1; base += 64) {
+        const int e = base + lane;
         HeadEdge he;
-        if (!head_edge(mg, i, e, xi, yi, zi, L, inv, he)) continue;
-        const int j = he.j;
-        const float* qj = QK + int64_t(j) * 2 * kH * kNc;
-        const float* kj = qj + kH * kNc;
-        float cij[kH], cji[kH];
-        head_coeffs(qi, kj, cij);
-        head_coeffs(qj, ki, cji);
-        float Sij = 0.f, Sji = 0.f;
+        const bool ok = e < e1 && head_edge(mg, i, e, xi, yi, zi, L, inv, he);
+        const uint64_t bal = __ballot(ok);
+        if (ok) {
+            const int j = he.j;
+            const float* qj = QK + int64_t(j) * 2 * kH * kNc;
+            const float* kj = qj + kH * kNc;
+            float cij[kH], cji[kH];
+            head_coeffs(qi, kj, cij);
+            head_coeffs(qj, ki, cji);
+            float Sij = 0.f, Sji = 0.f;
 #pragma unroll
-        for (int h = 0; h < kNs; ++h) {
-            Sij = fmaf(cij[h], he.ef[h], Sij);
-            Sji = fmaf(cji[h], he.ef[h], Sji);
-        }
-        float Dij[3], Dji[3];
+            for (int h = 0; h < kNs; ++h) {
+                Sij = fmaf(cij[h], he.ef[h], Sij);
+                Sji = fmaf(cji[h], he.ef[h], Sji);
+            }
+            const int pre = __popcll(bal & ((1ull << lane) - 1ull));
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            Dij[a] = he.u[a] + cij[kNs] * Vi[0][a] + cij[kNs + 1] * Vi[1][a];
-            Dji[a] = -he.u[a] + cji[kNs] * Vh[(int64_t(j) * 3 + a) * kNl] +
-                     cji[kNs + 1] * Vh[(int64_t(j) * 3 + a) * kNl + 1];
+            for (int a = 0; a < 3; ++a) {
+                const float Dij = he.u[a] + cij[kNs] * Vi[0][a] + cij[kNs + 1] * Vi[1][a];
+                const float Dji = -he.u[a] + cji[kNs] * Vh[(int64_t(j) * 3 + a) * kNl] +
+                                  cji[kNs + 1] * Vh[(int64_t(j) * 3 + a) * kNl + 1];
+                contrib[w][pre][a] = Sij * Dij - Sji * Dji;
+            }
         }
-        fx += Sij * Dij[0] - Sji * Dji[0];
-        fy += Sij * Dij[1] - Sji * Dji[1];
-        fz += Sij * Dij[2] - Sji * Dji[2];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (lane == 0) {
+            const int cnt = __popcll(bal);
+            for (int t = 0; t < cnt; ++t) {
+                fx += contrib[w][t][0];
+                fy += contrib[w][t][1];
+                fz += contrib[w][t][2];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
-    fx = wave_sum(fx);
-    fy = wave_sum(fy);
-    fz = wave_sum(fz);
     if (lane == 0) {
         if (accum) {
             Fout[i] += fx; Fout[n + i] += fy; Fout[2 * n + i] += fz;
@@ -276,7 +296,7 @@ __global__ void __launch_bounds__(64) k_head_bwd(MpGeom mg, const float* __restr
                                                  float* __restrict__ gVh) {
     __shared__ float gc[64][kH];
     __shared__ int jj[64];
-    __shared__ float gv_part[64][kNl * 3];
+    __shared__ float gvc[64][kNl * 3];  // per-entry V adjoint contributions (sweep 0)
     const int lane = threadIdx.x;
     const int i = blockIdx.x;
     const int n = mg.n;
@@ -295,7 +315,7 @@ __global__ void __launch_bounds__(64) k_head_bwd(MpGeom mg, const float* __restr
     const int e0 = mg.off[i], e1 = mg.off[i + 1];
     float* gq = gQK + int64_t(i) * 2 * kH * kNc;
     float* gk = gq + kH * kNc;
-    float gv_acc[kNl * 3] = {};
+    float gv_acc = 0.f;  // lane < 6: component (h, a) = (lane / 3, lane % 3)
     for (int sweep = 0; sweep < 2; ++sweep) {
         float acc0 = 0.f, acc1 = 0.f;  // (h, c) = lane and 64 + lane (lane < 16)
         for (int base = e0; base < e1; base += 64) {
@@ -325,7 +345,7 @@ __global__ void __launch_bounds__(64) k_head_bwd(MpGeom mg, const float* __restr
                     for (int h = 0; h < kNl; ++h) {
                         gc[lane][kNs + h] = S * (aij[0] * Vi[h][0] + aij[1] * Vi[h][1] + aij[2] * Vi[h][2]);
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) gv_acc[h * 3 + a] = fmaf(aij[a] * S, c[kNs + h], gv_acc[h * 3 + a]);
+                        for (int a = 0; a < 3; ++a) gvc[lane][h * 3 + a] = aij[a] * S * c[kNs + h];
                     }
                 } else {
                     head_coeffs(qj, ki, c);  // c_jih
@@ -361,6 +381,7 @@ __global__ void __launch_bounds__(64) k_head_bwd(MpGeom mg, const float* __restr
                 const float* row = QK + int64_t(j) * 2 * kH * kNc + (sweep == 0 ? kH * kNc : 0);
                 acc0 = fmaf(gc[t][lane / kNc] * scale, row[lane], acc0);
                 if (lane < 16) acc1 = fmaf(gc[t][(64 + lane) / kNc] * scale, row[64 + lane], acc1);
+                if (sweep == 0 && lane < kNl * 3) gv_acc += gvc[t][lane];
             }
             __syncthreads();
         }
@@ -368,14 +389,9 @@ __global__ void __launch_bounds__(64) k_head_bwd(MpGeom mg, const float* __restr
         out[lane] = acc0;
         if (lane < 16) out[64 + lane] = acc1;
     }
-#pragma unroll
-    for (int t = 0; t < kNl * 3; ++t) gv_part[lane][t] = gv_acc[t];
-    __syncthreads();
     if (lane < kNl * 3) {
-        float s = 0.f;
-        for (int t = 0; t < 64; ++t) s += gv_part[t][lane];
         const int h = lane / 3, a = lane % 3;
-        gVh[(int64_t(i) * 3 + a) * kNl + h] = s;
+        gVh[(int64_t(i) * 3 + a) * kNl + h] = gv_acc;
     }
 }
 
@@ -424,6 +440,7 @@ void launch_emb_grad(int n, int F, int S, const int* species, const float* gs0, 
 }
 void launch_head_fwd(const MpGeom& mg, const float* QK, const float* Vh, float* F, bool accum, hipStream_t st) {
     if (mg.n <= 0) return;
+    ScopedTimer timer("head_fwd", st);
     k_head_fwd<<<cdiv(mg.n, 4), 256, 0, st>>>(mg, QK, Vh, F, accum);
     NNP_LAUNCH_CHECK();
 }

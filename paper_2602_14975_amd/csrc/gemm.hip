@@ -88,6 +88,7 @@ k_gemm(GemmArgs g) {
 void launch_gemm(const GemmArgs& g, hipStream_t stream) {
     if (g.M <= 0 || g.N <= 0) return;
     dim3 grid(cdiv(g.M, TM), cdiv(g.N, TN), 1);
+    ScopedTimer timer("gemm", stream);
     k_gemm<<<grid, 256, 0, stream>>>(g);
     NNP_LAUNCH_CHECK();
 }

@@ -152,6 +152,7 @@ void launch_kick(int n, double* vel, const double* mass, const float* Fa, const 
 }
 
 void launch_baoa(const BaoaArgs& a, hipStream_t s) {
+    ScopedTimer timer("baoa", s);
     k_baoa<<<cdiv(a.n, 256), 256, 0, s>>>(a);
     NNP_LAUNCH_CHECK();
 }

@@ -9,6 +9,17 @@
 
 namespace nnp {
 
+// Brackets one launch with HIP events when its site is enabled
+// (nnp_timer_enable); otherwise costs one branch.
+struct ScopedTimer {
+    const char* name;
+    hipStream_t stream;
+    hipEvent_t a = nullptr, b = nullptr;
+    bool active = false;
+    ScopedTimer(const char* site, hipStream_t s);
+    ~ScopedTimer();
+};
+
 // ---------------------------------------------------------------- neighbours
 struct CellPlan {
     std::vector<int> m;     // cells per side per replica (1 = whole replica)

@@ -420,6 +420,7 @@ int mp_blocks(int n, int F) {
 
 void launch_message_fwd(int F, int K, int cut, const MpGeom& mg, const MpFwd& a, hipStream_t s) {
     if (mg.n <= 0) return;
+    ScopedTimer timer(cut == 0 ? "message_fwd" : "nc_message_fwd", s);
     NNP_DISPATCH_MP(128, 16, 0, (fwd_inst<128, 16, 0>(mg, a, s)));
     NNP_DISPATCH_MP(64, 16, 0, (fwd_inst<64, 16, 0>(mg, a, s)));
     NNP_DISPATCH_MP(32, 16, 0, (fwd_inst<32, 16, 0>(mg, a, s)));
@@ -436,6 +437,7 @@ void launch_message_fwd(int F, int K, int cut, const MpGeom& mg, const MpFwd& a,
 void launch_message_bwd(int F, int K, int cut, const MpGeom& mg, const MpBwd& a, bool geo, bool wgrad,
                         hipStream_t s) {
     if (mg.n <= 0) return;
+    ScopedTimer timer(cut == 0 ? "message_bwd" : "nc_message_bwd", s);
     NNP_DISPATCH_MP(128, 16, 0, (bwd_inst<128, 16, 0>(mg, a, geo, wgrad, s)));
     NNP_DISPATCH_MP(64, 16, 0, (bwd_inst<64, 16, 0>(mg, a, geo, wgrad, s)));
     NNP_DISPATCH_MP(32, 16, 0, (bwd_inst<32, 16, 0>(mg, a, geo, wgrad, s)));

@@ -388,6 +388,7 @@ void launch_build(int n, const double* pos, const RepGeom& geom, const CellPlan&
     double rc2 = radius * radius;
     k_nbr_count<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, pos, geom, st, rc2, run, s.counts, s.status);
     k_scan<<<1, 1024, 0, stream>>>(n, s.counts, s.tmp_off, run);
+    ScopedTimer timer("nbr_fill", stream);
     k_nbr_fill<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, pos, geom, st, rc2, run, s.tmp_off, capacity,
                                                             offsets, nbr, s.status);
     if (rev)
