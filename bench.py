@@ -42,12 +42,11 @@ def _ns_per_day(dt_fs, steps, seconds):
 
 def message_bwd_flops_per_edge(F, K):
     """Algorithmic FP32 flops of the conservative message reverse per
-    directed edge within the cutoff (one layer): the filter w = Wr e + br f
-    and its radial derivative (2 x 3F x K multiply-adds), the message
-    adjoints of both directions (13 F multiply-adds per feature group, see
-    the kernel), and the reductions of the radial and unit-vector adjoints
-    (4 F adds)."""
-    return 2 * (2 * 3 * F * K) + 2 * 13 * F + 4 * F
+    directed edge within the cutoff (one layer): the filter w = Wr e f + br f
+    and its radial derivative (2 x 3F x K multiply-adds = 12 F K flops) and
+    the adjoint products of both messages of the pair (about 40 multiply-adds
+    per feature = 80 F flops)."""
+    return 12 * F * K + 80 * F
 
 
 def run_gpu(args):

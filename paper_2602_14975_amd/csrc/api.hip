@@ -231,8 +231,6 @@ void carve_model(Arena& a, const Model* m, int64_t n, int64_t E, bool for_wgrad,
         b.gUV = a.take<float>(n * 6 * F);
         b.gphi = a.take<float>(n * 3 * F);
         b.gh1 = a.take<float>(n * F);
-        b.edge_g = a.take<float>(E * 3);
-        b.rev = a.take<int>(E);
     } else {
         const int64_t HC = 2 * int64_t(m->desc.n_s + m->desc.n_l) * m->desc.n_c;
         b.QK = a.take<float>(n * HC);
@@ -269,14 +267,14 @@ void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, Mode
     for (int l = 0; l < m->n_layers(); ++l) {
         const LayerOff& lo = m->loff[l];
         LayerBuf& lb = b.layer[l];
-        gemm_xwt(n, F, F, b.s[l], F, m->p(lo.W1), m->p(lo.b1), lb.zphi, F, EPI_SILU, lb.h1, F, false, s);
-        gemm_xwt(n, 3 * F, F, lb.zphi, F, m->p(lo.W2), m->p(lo.b2), lb.phi, 3 * F, EPI_NONE, nullptr, 0, false, s);
+        gemm_xwt(n, F, F, b.s[l], F, m->p(lo.W1), m->p(lo.b1), lb.zphi, F, EPI_SILU, lb.h1, F, false, s, m->bf16());
+        gemm_xwt(n, 3 * F, F, lb.zphi, F, m->p(lo.W2), m->p(lo.b2), lb.phi, 3 * F, EPI_NONE, nullptr, 0, false, s, m->bf16());
         MpFwd a{b.s[l], b.v[l], lb.phi, m->p(lo.Wr), m->p(lo.br), lb.smid, lb.vmid};
         launch_message_fwd(F, K, cut, mg, a, s);
-        gemm_xwt(3 * n, 2 * F, F, lb.vmid, F, m->p(lo.U), nullptr, lb.UV, 2 * F, EPI_NONE, nullptr, 0, false, s);
+        gemm_xwt(3 * n, 2 * F, F, lb.vmid, F, m->p(lo.U), nullptr, lb.UV, 2 * F, EPI_NONE, nullptr, 0, false, s, m->bf16());
         launch_build_x(n, F, lb.smid, lb.UV, lb.X, s);
-        gemm_xwt(n, F, 2 * F, lb.X, 2 * F, m->p(lo.M1), m->p(lo.m1), lb.z, F, EPI_SILU, lb.a1, F, false, s);
-        gemm_xwt(n, 3 * F, F, lb.z, F, m->p(lo.M2), m->p(lo.m2), lb.pqo, 3 * F, EPI_NONE, nullptr, 0, false, s);
+        gemm_xwt(n, F, 2 * F, lb.X, 2 * F, m->p(lo.M1), m->p(lo.m1), lb.z, F, EPI_SILU, lb.a1, F, false, s, m->bf16());
+        gemm_xwt(n, 3 * F, F, lb.z, F, m->p(lo.M2), m->p(lo.m2), lb.pqo, 3 * F, EPI_NONE, nullptr, 0, false, s, m->bf16());
         launch_update_combine(n, F, lb.smid, lb.vmid, lb.UV, lb.pqo, b.s[l + 1], b.v[l + 1], s);
     }
 }
@@ -284,8 +282,8 @@ void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, Mode
 // Reverse of one embedding layer.  In: gs, gv = adjoints of the layer
 // output.  Out: gs, gv = adjoints of the layer input (buffers swapped).
 // With `dtheta`, the weight adjoints of the layer are written too.
-void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float* edge_g, float* dtheta,
-                    hipStream_t s) {
+void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float* force, bool accum_force,
+                    float* dtheta, hipStream_t s) {
     const int n = mg.n;
     const int F = m->desc.width, K = m->desc.n_rbf;
     const int cut = m->desc.kind == NNP_MODEL_CONS ? 0 : 1;
@@ -297,15 +295,16 @@ void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float*
         gemm_wgrad(n, 3 * F, F, b.gpqo, 3 * F, lb.z, F, dtheta + lo.M2, b.chunk_part, kChunk, false, s);
         colsum(n, 3 * F, b.gpqo, 3 * F, dtheta + lo.m2, b.chunk_part, kChunk, false, s);
     }
-    gemm_gw(n, 3 * F, F, b.gpqo, 3 * F, m->p(lo.M2), b.ga1, F, EPI_DSILU, lb.a1, F, false, s);
+    gemm_gw(n, 3 * F, F, b.gpqo, 3 * F, m->p(lo.M2), b.ga1, F, EPI_DSILU, lb.a1, F, false, s, m->bf16());
     if (wg) {
         gemm_wgrad(n, F, 2 * F, b.ga1, F, lb.X, 2 * F, dtheta + lo.M1, b.chunk_part, kChunk, false, s);
         colsum(n, F, b.ga1, F, dtheta + lo.m1, b.chunk_part, kChunk, false, s);
     }
-    gemm_gw(n, F, 2 * F, b.ga1, F, m->p(lo.M1), b.gX, 2 * F, EPI_NONE, nullptr, 0, false, s);
+    gemm_gw(n, F, 2 * F, b.ga1, F, m->p(lo.M1), b.gX, 2 * F, EPI_NONE, nullptr, 0, false, s, m->bf16());
     launch_norm_bwd(n, F, b.gs, b.gX, lb.X, lb.UV, b.gs2, b.gUV, s);  // gs2 = g_smid
     if (wg) gemm_wgrad(3 * n, 2 * F, F, b.gUV, 2 * F, lb.vmid, F, dtheta + lo.U, b.chunk_part, kChunk, false, s);
-    gemm_gw(3 * n, 2 * F, F, b.gUV, 2 * F, m->p(lo.U), b.gv, F, EPI_NONE, nullptr, 0, true, s);  // gv = g_vmid
+    gemm_gw(3 * n, 2 * F, F, b.gUV, 2 * F, m->p(lo.U), b.gv, F, EPI_NONE, nullptr, 0, true, s,
+            m->bf16());  // gv = g_vmid
     MpBwd a{};
     a.v_in = b.v[l];
     a.phi = lb.phi;
@@ -315,9 +314,10 @@ void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float*
     a.br = m->p(lo.br);
     a.gphi = b.gphi;
     a.gv_in = b.gv2;
-    a.edge_g = edge_g;
+    a.force = force;
+    a.accum_force = accum_force;
     a.wgrad_part = wg ? b.mp_part : nullptr;
-    launch_message_bwd(F, K, cut, mg, a, edge_g != nullptr, wg, s);
+    launch_message_bwd(F, K, cut, mg, a, force != nullptr, wg, s);
     if (wg) {
         const int nb = mp_blocks(n, F);
         const int64_t cnt = int64_t(3) * F * (K + 1);
@@ -326,12 +326,12 @@ void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float*
         gemm_wgrad(n, 3 * F, F, b.gphi, 3 * F, lb.zphi, F, dtheta + lo.W2, b.chunk_part, kChunk, false, s);
         colsum(n, 3 * F, b.gphi, 3 * F, dtheta + lo.b2, b.chunk_part, kChunk, false, s);
     }
-    gemm_gw(n, 3 * F, F, b.gphi, 3 * F, m->p(lo.W2), b.gh1, F, EPI_DSILU, lb.h1, F, false, s);
+    gemm_gw(n, 3 * F, F, b.gphi, 3 * F, m->p(lo.W2), b.gh1, F, EPI_DSILU, lb.h1, F, false, s, m->bf16());
     if (wg) {
         gemm_wgrad(n, F, F, b.gh1, F, b.s[l], F, dtheta + lo.W1, b.chunk_part, kChunk, false, s);
         colsum(n, F, b.gh1, F, dtheta + lo.b1, b.chunk_part, kChunk, false, s);
     }
-    gemm_gw(n, F, F, b.gh1, F, m->p(lo.W1), b.gs2, F, EPI_NONE, nullptr, 0, true, s);  // gs2 = g_s_in
+    gemm_gw(n, F, F, b.gh1, F, m->p(lo.W1), b.gs2, F, EPI_NONE, nullptr, 0, true, s, m->bf16());  // g_s_in
     std::swap(b.gs, b.gs2);
     std::swap(b.gv, b.gv2);
 }
@@ -346,27 +346,26 @@ MpGeom make_geom(const Model* m, const nnp_system& sys, const RepGeom& geom, con
     mg.rc = m->desc.cutoff;
     mg.rc2 = m->desc.cutoff * m->desc.cutoff;
     mg.bessel_norm = std::sqrt(2.0 / m->desc.cutoff);
+    mg.pi_over_rc = M_PI / m->desc.cutoff;
+    mg.inv_rc = 1.0 / m->desc.cutoff;
     return mg;
 }
 
 void cons_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const SysTables& t, const nnp_nlist& nl,
-               const int* rev, ModelBuf& b, double* energy, float* forces, hipStream_t s) {
+               ModelBuf& b, double* energy, float* forces, hipStream_t s) {
     const int n = int(sys.n_atoms);
     const int F = m->desc.width;
     MpGeom mg = make_geom(m, sys, geom, nl);
     embed_forward(m, sys, mg, b, s);
     const int L = m->n_layers();
-    gemm_xwt(n, F, F, b.s[L], F, m->p(m->off_Wo), m->p(m->off_bo), b.zo, F, EPI_SILU, b.ao, F, false, s);
+    gemm_xwt(n, F, F, b.s[L], F, m->p(m->off_Wo), m->p(m->off_bo), b.zo, F, EPI_SILU, b.ao, F, false, s, m->bf16());
     launch_readout(n, F, m->desc.n_species, b.zo, m->p(m->off_wo), m->p(m->off_beta), sys.species, b.Ei, s);
     if (energy) launch_rep_sum(sys.n_rep, t.rep_start, b.Ei, energy, s);
     if (!forces) return;
     launch_readout_bwd(n, F, b.ao, m->p(m->off_wo), b.gs2, s);
-    gemm_gw(n, F, F, b.gs2, F, m->p(m->off_Wo), b.gs, F, EPI_NONE, nullptr, 0, false, s);
+    gemm_gw(n, F, F, b.gs2, F, m->p(m->off_Wo), b.gs, F, EPI_NONE, nullptr, 0, false, s, m->bf16());
     NNP_HIP(hipMemsetAsync(b.gv, 0, sizeof(float) * size_t(n) * 3 * F, s));
-    const int64_t E = nl.capacity;
-    NNP_HIP(hipMemsetAsync(b.edge_g, 0, sizeof(float) * size_t(E) * 3, s));
-    for (int l = L - 1; l >= 0; --l) layer_backward(m, l, mg, b, b.edge_g, nullptr, s);
-    launch_assemble_forces(n, nl.offsets, rev, b.edge_g, forces, false, s);
+    for (int l = L - 1; l >= 0; --l) layer_backward(m, l, mg, b, forces, l != L - 1, nullptr, s);
 }
 
 void nc_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const nnp_nlist& nl, ModelBuf& b,
@@ -376,9 +375,9 @@ void nc_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const n
     const int HC = 2 * (m->desc.n_s + m->desc.n_l) * m->desc.n_c;
     MpGeom mg = make_geom(m, sys, geom, nl);
     embed_forward(m, sys, mg, b, s);
-    gemm_xwt(n, HC, F, b.s[1], F, m->p(m->off_Wq), nullptr, b.QK, HC, EPI_NONE, nullptr, 0, false, s);
+    gemm_xwt(n, HC, F, b.s[1], F, m->p(m->off_Wq), nullptr, b.QK, HC, EPI_NONE, nullptr, 0, false, s, m->bf16());
     gemm_xwt(3 * n, m->desc.n_l, F, b.v[1], F, m->p(m->off_WV), nullptr, b.Vh, m->desc.n_l, EPI_NONE, nullptr, 0,
-             false, s);
+             false, s, m->bf16());
     launch_head_fwd(mg, b.QK, b.Vh, forces, false, s);
 }
 
@@ -390,14 +389,14 @@ void nc_wgrad(const Model* m, const nnp_system& sys, const RepGeom& geom, const 
     const int HC = 2 * (m->desc.n_s + m->desc.n_l) * m->desc.n_c;
     MpGeom mg = make_geom(m, sys, geom, nl);
     embed_forward(m, sys, mg, b, s);
-    gemm_xwt(n, HC, F, b.s[1], F, m->p(m->off_Wq), nullptr, b.QK, HC, EPI_NONE, nullptr, 0, false, s);
-    gemm_xwt(3 * n, nl_, F, b.v[1], F, m->p(m->off_WV), nullptr, b.Vh, nl_, EPI_NONE, nullptr, 0, false, s);
+    gemm_xwt(n, HC, F, b.s[1], F, m->p(m->off_Wq), nullptr, b.QK, HC, EPI_NONE, nullptr, 0, false, s, m->bf16());
+    gemm_xwt(3 * n, nl_, F, b.v[1], F, m->p(m->off_WV), nullptr, b.Vh, nl_, EPI_NONE, nullptr, 0, false, s, m->bf16());
     launch_head_bwd(mg, b.QK, b.Vh, dl_df, b.gQK, b.gVh, s);
     gemm_wgrad(n, HC, F, b.gQK, HC, b.s[1], F, dtheta + m->off_Wq, b.chunk_part, kChunk, false, s);
-    gemm_gw(n, HC, F, b.gQK, HC, m->p(m->off_Wq), b.gs, F, EPI_NONE, nullptr, 0, false, s);
+    gemm_gw(n, HC, F, b.gQK, HC, m->p(m->off_Wq), b.gs, F, EPI_NONE, nullptr, 0, false, s, m->bf16());
     gemm_wgrad(3 * n, nl_, F, b.gVh, nl_, b.v[1], F, dtheta + m->off_WV, b.chunk_part, kChunk, false, s);
-    gemm_gw(3 * n, nl_, F, b.gVh, nl_, m->p(m->off_WV), b.gv, F, EPI_NONE, nullptr, 0, false, s);
-    layer_backward(m, 0, mg, b, nullptr, dtheta, s);
+    gemm_gw(3 * n, nl_, F, b.gVh, nl_, m->p(m->off_WV), b.gv, F, EPI_NONE, nullptr, 0, false, s, m->bf16());
+    layer_backward(m, 0, mg, b, nullptr, false, dtheta, s);
     launch_emb_grad(n, F, m->desc.n_species, sys.species, b.gs, dtheta + m->off_emb, s);
 }
 
@@ -510,15 +509,7 @@ extern "C" nnp_status nnp_cons_energy_forces(const nnp_model* cons, const nnp_sy
     carve_all(a, m, nullptr, sys->n_atoms, sys->n_rep, std::max<int64_t>(nl->capacity, 1), false, c);
     std::vector<double> hs;
     RepGeom g = upload_tables(*sys, c.t, s, hs);
-    nnp_nlist l2 = *nl;
-    const int* rev = nl->rev;
-    if (!rev) {
-        NNP_HIP(hipMemsetAsync(c.nb.status, 0, sizeof(int) * 8, s));
-        launch_set_flag(c.t.flags, 1, s);
-        launch_reverse(int(sys->n_atoms), c.t.flags, c.nb.status, nl->offsets, nl->nbr, c.cons.rev, s);
-        rev = c.cons.rev;
-    }
-    cons_eval(m, *sys, g, c.t, l2, rev, c.cons, energy, forces, s);
+    cons_eval(m, *sys, g, c.t, *nl, c.cons, energy, forces, s);
     NNP_API_END
 }
 
@@ -639,8 +630,7 @@ void check_respa(const respa_state* st, const respa_params* p, const Model* cons
     NNP_REQUIRE(st->pos && st->vel && st->mass && st->gamma && st->f_cons && st->energy && st->pos_ref, NNP_EINVAL,
                 "incomplete state");
     NNP_REQUIRE(st->sys.pos == st->pos, NNP_EINVAL, "state.sys.pos must alias state.pos");
-    NNP_REQUIRE(st->nl_cons.offsets && st->nl_cons.nbr && st->nl_cons.rev, NNP_EINVAL,
-                "the conservative list needs offsets, nbr and rev");
+    NNP_REQUIRE(st->nl_cons.offsets && st->nl_cons.nbr, NNP_EINVAL, "the conservative list needs offsets and nbr");
     NNP_REQUIRE(st->nl_cons.n_atoms == st->sys.n_atoms, NNP_EINVAL, "list rows must equal n_atoms");
 }
 
@@ -710,7 +700,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     ba.disp_thr2 = disp_thr * disp_thr;
     ba.flag = trig;
 
-    auto eval_cons = [&]() { cons_eval(cons, st->sys, g, c.t, lc, lc.rev, c.cons, st->energy, st->f_cons, s); };
+    auto eval_cons = [&]() { cons_eval(cons, st->sys, g, c.t, lc, c.cons, st->energy, st->f_cons, s); };
     auto eval_nc = [&]() { nc_eval(nc, st->sys, g, ln, c.nc, st->f_nc, s); };
 
     int* hflags = pinned_flags();

@@ -14,104 +14,130 @@
 
 namespace nnp {
 
-constexpr int TM = 64, TN = 64, TK = 16;
+constexpr int TM = 64, TN = 64;
 
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef short short4_t __attribute__((ext_vector_type(4)));
+
+// float32 -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ short bf16_bits(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return short(u >> 16);
+}
+
+// One 64 x 64 output tile per block of four wavefronts; wavefront w owns the
+// 32 x 32 sub-tile (w / 2, w % 2) and accumulates it with MFMA in float32:
+// v_mfma_f32_32x32x2f32 (operands float32) or v_mfma_f32_32x32x8bf16_1k
+// (operands rounded to bfloat16).  Operand lane layout of the 32 x 32 x k
+// instructions: lane l supplies row (col) l % 32 and k-group l / 32; the
+// accumulator holds column l % 32, rows 8 (r / 4) + 4 (l / 32) + r % 4.
+template <bool BF16>
 __global__ void __launch_bounds__(256)
 k_gemm(GemmArgs g) {
+    constexpr int TK = BF16 ? 32 : 16;
     __shared__ float As[TK][TM + 4];
     __shared__ float Bs[TK][TN + 4];
     const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
-    const int64_t zoff_a = int64_t(blockIdx.z) * g.chunk_rows;  // split-K over rows of A^T
-    const float* A = g.A;
-    const float* B = g.B;
     int kbeg = 0, kend = g.K;
     if (g.chunk_rows > 0) {
-        kbeg = int(zoff_a);
-        kend = min(g.K, int(zoff_a + g.chunk_rows));
+        kbeg = int(int64_t(blockIdx.z) * g.chunk_rows);
+        kend = min(g.K, int(int64_t(blockIdx.z) * g.chunk_rows + g.chunk_rows));
     }
-    float acc[4][4] = {};
+    floatx16 acc = {};
     for (int k0 = kbeg; k0 < kend; k0 += TK) {
-        // stage A tile (TM x TK) and B tile (TK x TN)
         for (int t = tid; t < TM * TK; t += 256) {
             int mm, kk;
             if (g.sak == 1) { mm = t / TK; kk = t % TK; } else { kk = t / TM; mm = t % TM; }
-            int m = m0 + mm, k = k0 + kk;
-            As[kk][mm] = (m < g.M && k < kend) ? A[int64_t(m) * g.sam + int64_t(k) * g.sak] : 0.f;
+            const int m = m0 + mm, k = k0 + kk;
+            As[kk][mm] = (m < g.M && k < kend) ? g.A[int64_t(m) * g.sam + int64_t(k) * g.sak] : 0.f;
         }
         for (int t = tid; t < TN * TK; t += 256) {
             int nn, kk;
             if (g.sbk == 1) { nn = t / TK; kk = t % TK; } else { kk = t / TN; nn = t % TN; }
-            int n = n0 + nn, k = k0 + kk;
-            Bs[kk][nn] = (n < g.N && k < kend) ? B[int64_t(k) * g.sbk + int64_t(n) * g.sbn] : 0.f;
+            const int n = n0 + nn, k = k0 + kk;
+            Bs[kk][nn] = (n < g.N && k < kend) ? g.B[int64_t(k) * g.sbk + int64_t(n) * g.sbn] : 0.f;
         }
         __syncthreads();
+        const int row = lane & 31, grp = lane >> 5;
+        if constexpr (BF16) {
 #pragma unroll
-        for (int kk = 0; kk < TK; ++kk) {
-            float a[4], b[4];
+            for (int kk = 0; kk < TK; kk += 8) {
+                short4_t a, b;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = As[kk][ty * 4 + r];
+                for (int q = 0; q < 4; ++q) {
+                    a[q] = bf16_bits(As[kk + 4 * grp + q][wr + row]);
+                    b[q] = bf16_bits(Bs[kk + 4 * grp + q][wc + row]);
+                }
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+            }
+        } else {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx * 4 + c];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r][c] = fmaf(a[r], b[c], acc[r][c]);
+            for (int kk = 0; kk < TK; kk += 2) {
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[kk + grp][wr + row], Bs[kk + grp][wc + row], acc, 0,
+                                                           0, 0);
+            }
         }
         __syncthreads();
     }
     float* C = g.C + int64_t(blockIdx.z) * g.chunk_stride;
+    const int col = n0 + wc + (lane & 31);
+    if (col >= g.N) return;
+    const float bias = g.bias ? g.bias[col] : 0.f;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        int m = m0 + ty * 4 + r;
+    for (int r = 0; r < 16; ++r) {
+        const int m = m0 + wr + (r >> 2) * 8 + (lane >> 5) * 4 + (r & 3);
         if (m >= g.M) continue;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            int n = n0 + tx * 4 + c;
-            if (n >= g.N) continue;
-            float y = acc[r][c];
-            if (g.bias) y += g.bias[n];
-            int64_t idx = int64_t(m) * g.ldc + n;
-            if (g.epi == EPI_SILU) {
-                if (g.pre) g.pre[int64_t(m) * g.ldp + n] = y;
-                y = silu(y);
-            } else if (g.epi == EPI_DSILU) {
-                y *= silu_grad(g.pre[int64_t(m) * g.ldp + n]);
-            }
-            if (g.accum) y += C[idx];
-            C[idx] = y;
+        float y = acc[r] + bias;
+        const int64_t idx = int64_t(m) * g.ldc + col;
+        if (g.epi == EPI_SILU) {
+            if (g.pre) g.pre[int64_t(m) * g.ldp + col] = y;
+            y = silu(y);
+        } else if (g.epi == EPI_DSILU) {
+            y *= silu_grad(g.pre[int64_t(m) * g.ldp + col]);
         }
+        if (g.accum) y += C[idx];
+        C[idx] = y;
     }
+}
+
+static void gemm_dispatch(const GemmArgs& g, dim3 grid, hipStream_t stream) {
+    if (g.bf16) k_gemm<true><<<grid, 256, 0, stream>>>(g);
+    else k_gemm<false><<<grid, 256, 0, stream>>>(g);
 }
 
 void launch_gemm(const GemmArgs& g, hipStream_t stream) {
     if (g.M <= 0 || g.N <= 0) return;
     dim3 grid(cdiv(g.M, TM), cdiv(g.N, TN), 1);
     ScopedTimer timer("gemm", stream);
-    k_gemm<<<grid, 256, 0, stream>>>(g);
+    gemm_dispatch(g, grid, stream);
     NNP_LAUNCH_CHECK();
 }
 
 // out = X W^T + b (X [M][K] row-major, W [N][K]), optional SiLU (saving pre).
 void gemm_xwt(int M, int N, int K, const float* X, int ldx, const float* W, const float* b, float* out,
-              int ldo, int epi, float* pre, int ldp, bool accum, hipStream_t s) {
+              int ldo, int epi, float* pre, int ldp, bool accum, hipStream_t s, bool bf16) {
     GemmArgs g{};
     g.M = M; g.N = N; g.K = K;
     g.A = X; g.sam = ldx; g.sak = 1;
     g.B = W; g.sbk = 1; g.sbn = K;
     g.C = out; g.ldc = ldo; g.bias = b; g.epi = epi; g.pre = pre; g.ldp = ldp; g.accum = accum;
+    g.bf16 = bf16;
     launch_gemm(g, s);
 }
 
 // out = G W (G [M][N] row-major, W [N][K]) -> [M][K]; optional silu'(pre) factor.
 void gemm_gw(int M, int N, int K, const float* G, int ldg, const float* W, float* out, int ldo, int epi,
-             const float* pre, int ldp, bool accum, hipStream_t s) {
+             const float* pre, int ldp, bool accum, hipStream_t s, bool bf16) {
     GemmArgs g{};
     g.M = M; g.N = K; g.K = N;
     g.A = G; g.sam = ldg; g.sak = 1;
     g.B = W; g.sbk = K; g.sbn = 1;
     g.C = out; g.ldc = ldo; g.epi = epi; g.pre = const_cast<float*>(pre); g.ldp = ldp; g.accum = accum;
+    g.bf16 = bf16;
     launch_gemm(g, s);
 }
 
@@ -136,7 +162,7 @@ void gemm_wgrad(int M, int N, int K, const float* G, int ldg, const float* X, in
     g.B = X; g.sbk = ldx; g.sbn = 1;   // B(m, k) = X[m][k]
     g.C = scratch; g.ldc = K; g.chunk_rows = chunk; g.chunk_stride = int64_t(N) * K;
     dim3 grid(cdiv(N, TM), cdiv(K, TN), nch);
-    k_gemm<<<grid, 256, 0, s>>>(g);
+    gemm_dispatch(g, grid, s);
     int64_t cnt = int64_t(N) * K;
     k_reduce_chunks<<<cdiv(cnt, 256), 256, 0, s>>>(cnt, nch, scratch, cnt, dW, accum);
     NNP_LAUNCH_CHECK();

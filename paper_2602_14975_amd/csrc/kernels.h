@@ -64,13 +64,14 @@ struct GemmArgs {
     int accum;
     int64_t chunk_rows;    // > 0: split the K range into chunks along grid.z
     int64_t chunk_stride;  // C offset between chunks
+    int bf16;              // operands rounded to bfloat16 (float32 accumulation)
 };
 
 void launch_gemm(const GemmArgs& g, hipStream_t s);
 void gemm_xwt(int M, int N, int K, const float* X, int ldx, const float* W, const float* b, float* out, int ldo,
-              int epi, float* pre, int ldp, bool accum, hipStream_t s);
+              int epi, float* pre, int ldp, bool accum, hipStream_t s, bool bf16 = false);
 void gemm_gw(int M, int N, int K, const float* G, int ldg, const float* W, float* out, int ldo, int epi,
-             const float* pre, int ldp, bool accum, hipStream_t s);
+             const float* pre, int ldp, bool accum, hipStream_t s, bool bf16 = false);
 void gemm_wgrad(int M, int N, int K, const float* G, int ldg, const float* X, int ldx, float* dW, float* scratch,
                 int chunk, bool accum, hipStream_t s);
 void colsum(int M, int N, const float* G, int ldg, float* db, float* scratch, int chunk, bool accum, hipStream_t s);
@@ -82,7 +83,7 @@ struct MpGeom {
     RepGeom geom;
     const int* off;
     const int* nbr;
-    double rc, rc2, bessel_norm;
+    double rc, rc2, bessel_norm, pi_over_rc, inv_rc;
 };
 
 struct MpFwd {
@@ -93,7 +94,8 @@ struct MpFwd {
 struct MpBwd {
     const float *v_in, *phi, *gsm, *gvm, *Wr, *br;
     float *gphi, *gv_in;
-    float* edge_g;      // [E][3] accumulated position gradients (GEO)
+    float* force;       // [3][n] forces -dE/dx (GEO): written, or added to with accum_force
+    int accum_force;
     float* wgrad_part;  // [blocks][3F][K + 1] filter weight adjoints (WGRAD)
 };
 
@@ -101,8 +103,6 @@ int mp_blocks(int n, int F);
 void launch_message_fwd(int F, int K, int cut, const MpGeom& mg, const MpFwd& a, hipStream_t s);
 void launch_message_bwd(int F, int K, int cut, const MpGeom& mg, const MpBwd& a, bool geo, bool wgrad,
                         hipStream_t s);
-void launch_assemble_forces(int n, const int* off, const int* rev, const float* g, float* F, bool accum,
-                            hipStream_t s);
 
 // ----------------------------------------------------------- block kernels
 void launch_embed(int n, int F, int S, const int* species, const float* emb, float* s, float* v, hipStream_t st);

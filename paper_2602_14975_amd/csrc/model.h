@@ -25,6 +25,7 @@ struct Model {
     void layout();
     int n_layers() const { return desc.kind == NNP_MODEL_CONS ? desc.n_layers : 1; }
     const float* p(int64_t off) const { return w + off; }
+    bool bf16() const { return desc.precision == NNP_BF16; }
 };
 
 struct LayerBuf {
@@ -39,8 +40,6 @@ struct ModelBuf {
     float *QK = nullptr, *Vh = nullptr, *gQK = nullptr, *gVh = nullptr;
     float *gs = nullptr, *gs2 = nullptr, *gv = nullptr, *gv2 = nullptr, *gpqo = nullptr, *ga1 = nullptr,
           *gX = nullptr, *gUV = nullptr, *gphi = nullptr, *gh1 = nullptr;
-    float* edge_g = nullptr;
-    int* rev = nullptr;
     float *chunk_part = nullptr, *mp_part = nullptr, *filt_sum = nullptr;
 };
 

@@ -1,9 +1,11 @@
 // Edge kernels of the embedding block: the message step and its reverse.
 //
-// Layout: one atom per group of G = min(F, 64) lanes (64 / G atoms per
-// wavefront), each lane owning F / G feature columns.  Per-atom feature rows
-// are [n][F] (s), [n][3][F] (v) and [n][3F] (phi = [a|b|c] channels), so the
-// lanes of a group read a neighbour's row with unit stride.
+// Layout: one feature column per lane.  An atom is handled by WPA = F / 64
+// wavefronts when F > 64 (each owns 64 consecutive columns), otherwise by a
+// group of G = F lanes (64 / G atoms per wavefront); a neighbour's row is
+// read with unit stride across the lanes.  Splitting wide rows over two
+// wavefronts halves the filter weights each lane keeps in registers.
+// Per-atom rows are [n][F] (s), [n][3][F] (v) and [n][3F] (phi = [a|b|c]).
 //
 // Edge geometry is formed once per edge and batch: the group's lanes take
 // one CSR entry each, apply the float64 pair rule at the model cutoff (this
@@ -15,13 +17,21 @@
 //
 // Forward (per layer, synchronous: every term reads the layer input):
 //   s_i += sum_j phi_a[j] w_a;  v_i[al] += sum_j (phi_b[j] w_b v_j[al] + u[al] phi_c[j] w_c)
-// Reverse, owner-computes (atom o gathers everything that reaches it, no
-// atomics, fixed order): for each neighbour n of o,
-//   (A) o receives from n: g_w = dL/dw of the message n -> o, which gives the
-//       edge's position gradient dL/dr_on = d u + (g_u - (g_u.u) u) / r,
-//       d = sum_f g_w . dw/dr, and (NC only) the filter weight adjoints;
-//   (B) o sends to n: the adjoints of phi_o and v_o from n's message adjoints.
-// Forces are assembled afterwards as F_o = sum_e (g_e - g_rev(e)).
+//
+// Reverse, owner-computes (atom o gathers everything that reaches it; no
+// atomics; fixed order per atom).  For each neighbour n of o, with the layer
+// adjoints gs = dL/ds_mid and gv = dL/dv_mid of both atoms:
+//   (B) o as sender of the message o -> n: adjoints of phi_o and v_o;
+//   (A) o as receiver of n -> o and (A') o as sender of o -> n: the filter
+//       adjoints g_w of both messages share w(r) and dw/dr, so the pair's
+//       contribution to the force on o,
+//         -dE/dx_o (pair) = (d_A + d_A') u + (P(g_uA) - P(g_uA')) / r,
+//         d = sum_f g_w . dw/dr,  P = 1 - u u^T,
+//       is linear in per-lane partial sums; each lane accumulates its share
+//       over all edges and the group is reduced once per atom.
+//   With weight adjoints requested (NC distillation), the filter weight
+//   adjoints of the message n -> o are accumulated as well (each directed
+//   message is counted by its receiver).
 #include "common.h"
 #include "kernels.h"
 
@@ -35,38 +45,38 @@ struct EdgeSlot {
     float def[K];   // d/dr [e_k(r) f(r)]
     float fc, dfc;  // f(r), f'(r)
     float u[3];
-    float r;
+    float ir;       // 1 / r
     int j, e;
 };
 
-// Radial values of one edge (float64 Chebyshev recurrence for sin(k theta)).
+// Radial values of one edge: float64 Chebyshev recurrence for sin(k theta)
+// and cos(k theta), theta = pi r / rc.
 template <int K, int CUT, bool DERIV>
 __device__ __forceinline__ void radial(double r, const MpGeom& mg, float* ef, float* def, float& fc, float& dfc) {
-    const double rc = mg.rc;
-    const double theta = M_PI * r / rc;
+    const double theta = mg.pi_over_rc * r;
     double sn, cs;
     sincos(theta, &sn, &cs);
     double f, df;
     if (CUT == 0) {
         f = 0.5 * (cs + 1.0);
-        df = -0.5 * sn * M_PI / rc;
+        df = -0.5 * sn * mg.pi_over_rc;
     } else {
-        const double d = r / rc;
+        const double d = r * mg.inv_rc;
         const double d2 = d * d, d4 = d2 * d2, d5 = d4 * d;
         f = 1.0 - 21.0 * d5 + 35.0 * d5 * d - 15.0 * d5 * d2;
-        df = (-105.0 * d4 + 210.0 * d5 - 105.0 * d5 * d) / rc;  // -p(p+1)(p+2)/2 d^4 (1-d)^2 / rc
+        df = (-105.0 * d4 + 210.0 * d5 - 105.0 * d5 * d) * mg.inv_rc;  // -p(p+1)(p+2)/2 d^4 (1-d)^2 / rc
     }
-    const double norm = mg.bessel_norm;
     const double inv_r = 1.0 / r;
-    double s_prev = 0.0, s_cur = sn;                 // sin(0), sin(theta)
-    double c_prev = 1.0, c_cur = cs;                 // cos(0), cos(theta)
+    const double nr = mg.bessel_norm * inv_r;
+    double s_prev = 0.0, s_cur = sn;  // sin(0), sin(theta)
+    double c_prev = 1.0, c_cur = cs;  // cos(0), cos(theta)
 #pragma unroll
     for (int k = 1; k <= K; ++k) {
-        const double ek = norm * s_cur * inv_r;
+        const double ek = nr * s_cur;
         ef[k - 1] = float(ek * f);
         if (DERIV) {
             // d/dr [sin(k pi r/rc)/r] = (k pi/rc) cos(k theta)/r - sin(k theta)/r^2
-            const double dek = norm * ((double(k) * M_PI / rc) * c_cur * inv_r - s_cur * inv_r * inv_r);
+            const double dek = nr * (double(k) * mg.pi_over_rc * c_cur - s_cur * inv_r);
             def[k - 1] = float(dek * f + ek * df);
         }
         const double s_next = 2.0 * cs * s_cur - s_prev;
@@ -78,12 +88,17 @@ __device__ __forceinline__ void radial(double r, const MpGeom& mg, float* ef, fl
     dfc = float(df);
 }
 
-// Stages one batch of edges of atom i (lanes l of its group) into LDS.
-// Returns the number of surviving edges of this group in `cnt`.
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Stages one batch of edges of atom i (lane l of its group takes entry e)
+// into LDS; returns the number of surviving edges of this group.
 template <int G, int K, int CUT, bool DERIV>
-__device__ __forceinline__ int stage_batch(const MpGeom& mg, int i, bool active, int e, int e_end, int l, int g,
-                                           double xi, double yi, double zi, double L, double inv,
-                                           EdgeSlot<K>* slots) {
+__device__ __forceinline__ int stage_batch(const MpGeom& mg, bool active, int e, int e_end, int l, int g, double xi,
+                                           double yi, double zi, double L, double inv, EdgeSlot<K>* slots) {
     bool ok = false;
     double dx = 0, dy = 0, dz = 0;
     int j = -1;
@@ -97,41 +112,73 @@ __device__ __forceinline__ int stage_batch(const MpGeom& mg, int i, bool active,
     const uint64_t mine = bal & gmask;
     const int pre = __popcll(mine & ((1ull << (g * G + l)) - 1ull));
     if (ok) {
-        const double r2 = (dx * dx + dy * dy) + dz * dz;
-        const double r = sqrt(r2);
+        const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+        const double ir = 1.0 / r;
         EdgeSlot<K>& s = slots[pre];
         radial<K, CUT, DERIV>(r, mg, s.ef, s.def, s.fc, s.dfc);
-        s.u[0] = float(dx / r);
-        s.u[1] = float(dy / r);
-        s.u[2] = float(dz / r);
-        s.r = float(r);
+        s.u[0] = float(dx * ir);
+        s.u[1] = float(dy * ir);
+        s.u[2] = float(dz * ir);
+        s.ir = float(ir);
         s.j = j;
         s.e = e;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    wave_sync_lds();
     return __popcll(mine);
 }
 
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+template <int FPL>
+struct Vec {
+    float x[FPL];
+};
+
+template <int FPL>
+__device__ __forceinline__ Vec<FPL> ldv(const float* p) {
+    Vec<FPL> r;
+    if constexpr (FPL == 2) {
+        const float2 t = *reinterpret_cast<const float2*>(p);
+        r.x[0] = t.x;
+        r.x[1] = t.y;
+    } else if constexpr (FPL == 4) {
+        const float4 t = *reinterpret_cast<const float4*>(p);
+        r.x[0] = t.x; r.x[1] = t.y; r.x[2] = t.z; r.x[3] = t.w;
+    } else {
+#pragma unroll
+        for (int q = 0; q < FPL; ++q) r.x[q] = p[q];
+    }
+    return r;
 }
+
+template <int FPL>
+__device__ __forceinline__ void stv(float* p, const float* v) {
+    if constexpr (FPL == 2) {
+        *reinterpret_cast<float2*>(p) = make_float2(v[0], v[1]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < FPL; ++q) p[q] = v[q];
+    }
+}
+
+template <int F>
+struct MpShape {
+    static constexpr int G = F >= 64 ? 64 : F;         // lanes per atom within a wavefront
+    static constexpr int WPA = F / G;                  // wavefronts per atom
+    static constexpr int APW = 64 / G;                 // atoms per wavefront
+    static constexpr int APB = kMpWaves / WPA * APW;   // atoms per block
+};
 
 template <int F, int K, int CUT>
 __global__ void __launch_bounds__(64 * kMpWaves)
 k_message_fwd(MpGeom mg, MpFwd a) {
-    constexpr int G = F >= 64 ? 64 : F;
-    constexpr int FPL = F / G;
-    constexpr int APW = 64 / G;
+    using S = MpShape<F>;
+    constexpr int G = S::G, APW = S::APW, WPA = S::WPA, FPL = 1;
     __shared__ EdgeSlot<K> slots_all[kMpWaves][APW][G];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane / G, l = lane % G;
-    const int i = (blockIdx.x * kMpWaves + w) * APW + g;
+    const int i = blockIdx.x * S::APB + (w / WPA) * APW + g;
     const bool active = i < mg.n;
     const int n = mg.n;
+    const int f0 = (w % WPA) * 64 + l;
     EdgeSlot<K>* slots = slots_all[w][g];
 
     float wr[3][FPL][K], bb[3][FPL];
@@ -139,7 +186,7 @@ k_message_fwd(MpGeom mg, MpFwd a) {
     for (int p = 0; p < 3; ++p)
 #pragma unroll
         for (int q = 0; q < FPL; ++q) {
-            const int row = p * F + l + q * G;
+            const int row = p * F + f0 + q;
 #pragma unroll
             for (int k = 0; k < K; ++k) wr[p][q][k] = a.Wr[row * K + k];
             bb[p][q] = a.br[row];
@@ -154,16 +201,16 @@ k_message_fwd(MpGeom mg, MpFwd a) {
         xi = mg.pos[i]; yi = mg.pos[n + i]; zi = mg.pos[2 * n + i];
     }
     for (int base = 0; __ballot(start + base < end) != 0ull; base += G) {
-        const int cnt = stage_batch<G, K, CUT, false>(mg, i, active, start + base + l, end, l, g, xi, yi, zi, L,
-                                                       inv, slots);
+        const int cnt =
+            stage_batch<G, K, CUT, false>(mg, active, start + base + l, end, l, g, xi, yi, zi, L, inv, slots);
         for (int t = 0; t < cnt; ++t) {
             const EdgeSlot<K>& s = slots[t];
-            const int j = s.j;
-            const float* phj = a.phi + int64_t(j) * 3 * F;
-            const float* vj = a.v_in + int64_t(j) * 3 * F;
+            const float* phj = a.phi + int64_t(s.j) * 3 * F + f0;
+            const float* vj = a.v_in + int64_t(s.j) * 3 * F + f0;
+            const Vec<FPL> pa = ldv<FPL>(phj), pb = ldv<FPL>(phj + F), pc = ldv<FPL>(phj + 2 * F);
+            const Vec<FPL> v0 = ldv<FPL>(vj), v1 = ldv<FPL>(vj + F), v2 = ldv<FPL>(vj + 2 * F);
 #pragma unroll
             for (int q = 0; q < FPL; ++q) {
-                const int f = l + q * G;
                 float wa = bb[0][q] * s.fc, wb = bb[1][q] * s.fc, wc = bb[2][q] * s.fc;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
@@ -171,40 +218,46 @@ k_message_fwd(MpGeom mg, MpFwd a) {
                     wb = fmaf(wr[1][q][k], s.ef[k], wb);
                     wc = fmaf(wr[2][q][k], s.ef[k], wc);
                 }
-                const float pa = phj[f], pb = phj[F + f] * wb, pc = phj[2 * F + f] * wc;
-                sacc[q] = fmaf(pa, wa, sacc[q]);
-#pragma unroll
-                for (int al = 0; al < 3; ++al) vacc[al][q] += pb * vj[al * F + f] + s.u[al] * pc;
+                const float b = pb.x[q] * wb, c = pc.x[q] * wc;
+                sacc[q] = fmaf(pa.x[q], wa, sacc[q]);
+                vacc[0][q] += b * v0.x[q] + s.u[0] * c;
+                vacc[1][q] += b * v1.x[q] + s.u[1] * c;
+                vacc[2][q] += b * v2.x[q] + s.u[2] * c;
             }
         }
         wave_sync_lds();
     }
     if (active) {
+        float out[FPL];
+        const Vec<FPL> si = ldv<FPL>(a.s_in + int64_t(i) * F + f0);
 #pragma unroll
-        for (int q = 0; q < FPL; ++q) {
-            const int f = l + q * G;
-            a.s_out[int64_t(i) * F + f] = a.s_in[int64_t(i) * F + f] + sacc[q];
+        for (int q = 0; q < FPL; ++q) out[q] = si.x[q] + sacc[q];
+        stv<FPL>(a.s_out + int64_t(i) * F + f0, out);
 #pragma unroll
-            for (int al = 0; al < 3; ++al) {
-                const int64_t idx = (int64_t(i) * 3 + al) * F + f;
-                a.v_out[idx] = a.v_in[idx] + vacc[al][q];
-            }
+        for (int al = 0; al < 3; ++al) {
+            const int64_t idx = (int64_t(i) * 3 + al) * F + f0;
+            const Vec<FPL> vi = ldv<FPL>(a.v_in + idx);
+#pragma unroll
+            for (int q = 0; q < FPL; ++q) out[q] = vi.x[q] + vacc[al][q];
+            stv<FPL>(a.v_out + idx, out);
         }
     }
 }
 
 template <int F, int K, int CUT, bool GEO, bool WGRAD>
-__global__ void __launch_bounds__(64 * kMpWaves)
+__global__ void __launch_bounds__(64 * kMpWaves, 2)
 k_message_bwd(MpGeom mg, MpBwd a) {
-    constexpr int G = F >= 64 ? 64 : F;
-    constexpr int FPL = F / G;
-    constexpr int APW = 64 / G;
+    using S = MpShape<F>;
+    constexpr int G = S::G, APW = S::APW, WPA = S::WPA, FPL = 1;
+    static_assert(!WGRAD || WPA == 1, "filter weight adjoints need one wavefront per atom");
     __shared__ EdgeSlot<K> slots_all[kMpWaves][APW][G];
+    __shared__ float fpart[kMpWaves][APW][3];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane / G, l = lane % G;
-    const int i = (blockIdx.x * kMpWaves + w) * APW + g;
+    const int i = blockIdx.x * S::APB + (w / WPA) * APW + g;
     const bool active = i < mg.n;
     const int n = mg.n;
+    const int f0 = (w % WPA) * 64 + l;
     EdgeSlot<K>* slots = slots_all[w][g];
 
     float wr[3][FPL][K], bb[3][FPL];
@@ -212,14 +265,15 @@ k_message_bwd(MpGeom mg, MpBwd a) {
     for (int p = 0; p < 3; ++p)
 #pragma unroll
         for (int q = 0; q < FPL; ++q) {
-            const int row = p * F + l + q * G;
+            const int row = p * F + f0 + q;
 #pragma unroll
             for (int k = 0; k < K; ++k) wr[p][q][k] = a.Wr[row * K + k];
             bb[p][q] = a.br[row];
         }
-    // own data of atom i (owner)
+    // own rows of the owner atom o = i
     float ph_o[3][FPL] = {}, v_o[3][FPL] = {}, gs_o[FPL] = {}, gv_o[3][FPL] = {};
     float gph[3][FPL] = {}, gvacc[3][FPL] = {};
+    float fx = 0.f, fy = 0.f, fz = 0.f;  // per-lane share of the force on o
     float gwr[WGRAD ? 3 : 1][WGRAD ? FPL : 1][WGRAD ? K : 1] = {};
     float gbr[WGRAD ? 3 : 1][WGRAD ? FPL : 1] = {};
     int start = 0, end = 0;
@@ -229,34 +283,44 @@ k_message_bwd(MpGeom mg, MpBwd a) {
         end = mg.off[i + 1];
         mg.geom.get(i, L, inv);
         xi = mg.pos[i]; yi = mg.pos[n + i]; zi = mg.pos[2 * n + i];
+        const float* pho = a.phi + int64_t(i) * 3 * F + f0;
 #pragma unroll
-        for (int q = 0; q < FPL; ++q) {
-            const int f = l + q * G;
+        for (int p = 0; p < 3; ++p) {
+            const Vec<FPL> t = ldv<FPL>(pho + p * F);
 #pragma unroll
-            for (int p = 0; p < 3; ++p) ph_o[p][q] = a.phi[int64_t(i) * 3 * F + p * F + f];
-#pragma unroll
-            for (int al = 0; al < 3; ++al) {
-                v_o[al][q] = a.v_in[(int64_t(i) * 3 + al) * F + f];
-                gv_o[al][q] = a.gvm[(int64_t(i) * 3 + al) * F + f];
-            }
-            gs_o[q] = a.gsm[int64_t(i) * F + f];
+            for (int q = 0; q < FPL; ++q) ph_o[p][q] = t.x[q];
         }
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+            const Vec<FPL> tv = ldv<FPL>(a.v_in + (int64_t(i) * 3 + al) * F + f0);
+            const Vec<FPL> tg = ldv<FPL>(a.gvm + (int64_t(i) * 3 + al) * F + f0);
+#pragma unroll
+            for (int q = 0; q < FPL; ++q) {
+                v_o[al][q] = tv.x[q];
+                gv_o[al][q] = tg.x[q];
+            }
+        }
+        const Vec<FPL> tg = ldv<FPL>(a.gsm + int64_t(i) * F + f0);
+#pragma unroll
+        for (int q = 0; q < FPL; ++q) gs_o[q] = tg.x[q];
     }
     for (int base = 0; __ballot(start + base < end) != 0ull; base += G) {
-        const int cnt = stage_batch<G, K, CUT, GEO>(mg, i, active, start + base + l, end, l, g, xi, yi, zi, L,
-                                                     inv, slots);
+        const int cnt =
+            stage_batch<G, K, CUT, GEO>(mg, active, start + base + l, end, l, g, xi, yi, zi, L, inv, slots);
         for (int t = 0; t < cnt; ++t) {
             const EdgeSlot<K>& s = slots[t];
             const int j = s.j;
-            const float* phj = a.phi + int64_t(j) * 3 * F;
-            const float* vj = a.v_in + int64_t(j) * 3 * F;
-            const float* gvj = a.gvm + int64_t(j) * 3 * F;
-            const float gsj_dummy = 0.f;
-            (void)gsj_dummy;
+            const float* phj = a.phi + int64_t(j) * 3 * F + f0;
+            const float* vj = a.v_in + int64_t(j) * 3 * F + f0;
+            const float* gvj = a.gvm + int64_t(j) * 3 * F + f0;
+            const Vec<FPL> pa = ldv<FPL>(phj), pb = ldv<FPL>(phj + F), pc = ldv<FPL>(phj + 2 * F);
+            const Vec<FPL> vj0 = ldv<FPL>(vj), vj1 = ldv<FPL>(vj + F), vj2 = ldv<FPL>(vj + 2 * F);
+            const Vec<FPL> g0 = ldv<FPL>(gvj), g1 = ldv<FPL>(gvj + F), g2 = ldv<FPL>(gvj + 2 * F);
+            const Vec<FPL> gsn = ldv<FPL>(a.gsm + int64_t(j) * F + f0);
+            const float u0 = s.u[0], u1 = s.u[1], u2 = s.u[2];
             float dr = 0.f, gu0 = 0.f, gu1 = 0.f, gu2 = 0.f;
 #pragma unroll
             for (int q = 0; q < FPL; ++q) {
-                const int f = l + q * G;
                 float w[3], dw[3];
 #pragma unroll
                 for (int p = 0; p < 3; ++p) {
@@ -270,22 +334,26 @@ k_message_bwd(MpGeom mg, MpBwd a) {
                         w[p] = fmaf(wr[p][q][k], s.ef[k], w[p]);
                         if (GEO) dw[p] = fmaf(wr[p][q][k], s.def[k], dw[p]);
                     }
-                const float pa = phj[f], pb = phj[F + f], pc = phj[2 * F + f];
-                const float vj0 = vj[f], vj1 = vj[F + f], vj2 = vj[2 * F + f];
-                const float gvj0 = gvj[f], gvj1 = gvj[F + f], gvj2 = gvj[2 * F + f];
-                const float gsj = a.gsm[int64_t(j) * F + f];
-                // (A) o receives from j
-                const float gva = gv_o[0][q] * vj0 + gv_o[1][q] * vj1 + gv_o[2][q] * vj2;
-                const float gvu = gv_o[0][q] * s.u[0] + gv_o[1][q] * s.u[1] + gv_o[2][q] * s.u[2];
-                const float gwa = gs_o[q] * pa;
-                const float gwb = pb * gva;
-                const float gwc = pc * gvu;
+                // projections shared by several terms
+                const float gvo_vn = gv_o[0][q] * vj0.x[q] + gv_o[1][q] * vj1.x[q] + gv_o[2][q] * vj2.x[q];
+                const float gvo_u = gv_o[0][q] * u0 + gv_o[1][q] * u1 + gv_o[2][q] * u2;
+                const float gvn_vo = g0.x[q] * v_o[0][q] + g1.x[q] * v_o[1][q] + g2.x[q] * v_o[2][q];
+                const float gvn_u = g0.x[q] * u0 + g1.x[q] * u1 + g2.x[q] * u2;
+                // (A) message n -> o: filter adjoints
+                const float gwa = gs_o[q] * pa.x[q];
+                const float gwb = pb.x[q] * gvo_vn;
+                const float gwc = pc.x[q] * gvo_u;
                 if (GEO) {
-                    dr += gwa * dw[0] + gwb * dw[1] + gwc * dw[2];
-                    const float pcw = pc * w[2];
-                    gu0 = fmaf(gv_o[0][q], pcw, gu0);
-                    gu1 = fmaf(gv_o[1][q], pcw, gu1);
-                    gu2 = fmaf(gv_o[2][q], pcw, gu2);
+                    // (A') message o -> n (unit vector -u): filter adjoints
+                    const float gwa2 = gsn.x[q] * ph_o[0][q];
+                    const float gwb2 = ph_o[1][q] * gvn_vo;
+                    const float gwc2 = -ph_o[2][q] * gvn_u;
+                    dr += (gwa + gwa2) * dw[0] + (gwb + gwb2) * dw[1] + (gwc + gwc2) * dw[2];
+                    // g_uA - g_uA': adjoints of the unit vector of each message
+                    const float cA = pc.x[q] * w[2], cB = ph_o[2][q] * w[2];
+                    gu0 += gv_o[0][q] * cA - g0.x[q] * cB;
+                    gu1 += gv_o[1][q] * cA - g1.x[q] * cB;
+                    gu2 += gv_o[2][q] * cA - g2.x[q] * cB;
                 }
                 if (WGRAD) {
 #pragma unroll
@@ -298,43 +366,63 @@ k_message_bwd(MpGeom mg, MpBwd a) {
                     gbr[1][q] = fmaf(gwb, s.fc, gbr[1][q]);
                     gbr[2][q] = fmaf(gwc, s.fc, gbr[2][q]);
                 }
-                // (B) o sends to j (unit vector of that edge is -u)
-                gph[0][q] = fmaf(gsj, w[0], gph[0][q]);
-                gph[1][q] = fmaf(w[1], gvj0 * v_o[0][q] + gvj1 * v_o[1][q] + gvj2 * v_o[2][q], gph[1][q]);
-                gph[2][q] = fmaf(-w[2], gvj0 * s.u[0] + gvj1 * s.u[1] + gvj2 * s.u[2], gph[2][q]);
+                // (B) o sends to n (unit vector of that message is -u)
+                gph[0][q] = fmaf(gsn.x[q], w[0], gph[0][q]);
+                gph[1][q] = fmaf(w[1], gvn_vo, gph[1][q]);
+                gph[2][q] = fmaf(-w[2], gvn_u, gph[2][q]);
                 const float wbp = w[1] * ph_o[1][q];
-                gvacc[0][q] = fmaf(gvj0, wbp, gvacc[0][q]);
-                gvacc[1][q] = fmaf(gvj1, wbp, gvacc[1][q]);
-                gvacc[2][q] = fmaf(gvj2, wbp, gvacc[2][q]);
+                gvacc[0][q] = fmaf(g0.x[q], wbp, gvacc[0][q]);
+                gvacc[1][q] = fmaf(g1.x[q], wbp, gvacc[1][q]);
+                gvacc[2][q] = fmaf(g2.x[q], wbp, gvacc[2][q]);
             }
             if (GEO) {
-                dr = group_sum<G>(dr);
-                gu0 = group_sum<G>(gu0);
-                gu1 = group_sum<G>(gu1);
-                gu2 = group_sum<G>(gu2);
-                if (l == 0) {
-                    const float ud = gu0 * s.u[0] + gu1 * s.u[1] + gu2 * s.u[2];
-                    const float ir = 1.0f / s.r;
-                    float* ge = a.edge_g + int64_t(s.e) * 3;
-                    ge[0] += dr * s.u[0] + (gu0 - ud * s.u[0]) * ir;
-                    ge[1] += dr * s.u[1] + (gu1 - ud * s.u[1]) * ir;
-                    ge[2] += dr * s.u[2] + (gu2 - ud * s.u[2]) * ir;
-                }
+                // this lane's share of (d_A + d_A') u + P(g_uA - g_uA') / r
+                const float ud = gu0 * u0 + gu1 * u1 + gu2 * u2;
+                fx += dr * u0 + (gu0 - ud * u0) * s.ir;
+                fy += dr * u1 + (gu1 - ud * u1) * s.ir;
+                fz += dr * u2 + (gu2 - ud * u2) * s.ir;
             }
         }
         wave_sync_lds();
     }
-    if (active) {
-#pragma unroll
-        for (int q = 0; q < FPL; ++q) {
-            const int f = l + q * G;
-#pragma unroll
-            for (int p = 0; p < 3; ++p) a.gphi[int64_t(i) * 3 * F + p * F + f] = gph[p][q];
-#pragma unroll
-            for (int al = 0; al < 3; ++al) {
-                const int64_t idx = (int64_t(i) * 3 + al) * F + f;
-                a.gv_in[idx] = gv_o[al][q] + gvacc[al][q];
+    if (GEO) {
+        fx = group_sum<G>(fx);
+        fy = group_sum<G>(fy);
+        fz = group_sum<G>(fz);
+        if (WPA > 1) {
+            // combine the wavefronts of the atom in a fixed order
+            if (l == 0) {
+                fpart[w][g][0] = fx;
+                fpart[w][g][1] = fy;
+                fpart[w][g][2] = fz;
             }
+            __syncthreads();
+            if (w % WPA == 0) {
+                fx = fy = fz = 0.f;
+                for (int k = 0; k < WPA; ++k) {
+                    fx += fpart[w + k][g][0];
+                    fy += fpart[w + k][g][1];
+                    fz += fpart[w + k][g][2];
+                }
+            }
+        }
+        if (active && l == 0 && w % WPA == 0) {
+            if (a.accum_force) {
+                a.force[i] += fx; a.force[n + i] += fy; a.force[2 * n + i] += fz;
+            } else {
+                a.force[i] = fx; a.force[n + i] = fy; a.force[2 * n + i] = fz;
+            }
+        }
+    }
+    if (active) {
+        float out[FPL];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) stv<FPL>(a.gphi + int64_t(i) * 3 * F + p * F + f0, gph[p]);
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+#pragma unroll
+            for (int q = 0; q < FPL; ++q) out[q] = gv_o[al][q] + gvacc[al][q];
+            stv<FPL>(a.gv_in + (int64_t(i) * 3 + al) * F + f0, out);
         }
     }
     if (WGRAD) {
@@ -346,7 +434,7 @@ k_message_bwd(MpGeom mg, MpBwd a) {
         for (int p = 0; p < 3; ++p)
 #pragma unroll
             for (int q = 0; q < FPL; ++q) {
-                const int row = p * F + l + q * G;
+                const int row = p * F + f0 + q;
 #pragma unroll
                 for (int k = 0; k < K; ++k) red[slot][row * (K + 1) + k] = gwr[p][q][k];
                 red[slot][row * (K + 1) + K] = gbr[p][q];
@@ -360,40 +448,17 @@ k_message_bwd(MpGeom mg, MpBwd a) {
     }
 }
 
-// Forces from per-edge position gradients: F_o = sum_e (g_e - g_rev(e)).
-__global__ void k_assemble_forces(int n, const int* __restrict__ off, const int* __restrict__ rev,
-                                  const float* __restrict__ g, float* __restrict__ F, int accum) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float fx = 0.f, fy = 0.f, fz = 0.f;
-    for (int e = off[i]; e < off[i + 1]; ++e) {
-        const int r = rev[e];
-        fx += g[3 * e] - g[3 * r];
-        fy += g[3 * e + 1] - g[3 * r + 1];
-        fz += g[3 * e + 2] - g[3 * r + 2];
-    }
-    if (accum) {
-        F[i] += fx; F[n + i] += fy; F[2 * n + i] += fz;
-    } else {
-        F[i] = fx; F[n + i] = fy; F[2 * n + i] = fz;
-    }
-}
-
 // ------------------------------------------------------------------- host --
 
 template <int F, int K, int CUT>
 static void fwd_inst(const MpGeom& mg, const MpFwd& a, hipStream_t s) {
-    constexpr int APW = 64 / (F >= 64 ? 64 : F);
-    int atoms_per_block = kMpWaves * APW;
-    k_message_fwd<F, K, CUT><<<cdiv(mg.n, atoms_per_block), 64 * kMpWaves, 0, s>>>(mg, a);
+    k_message_fwd<F, K, CUT><<<cdiv(mg.n, MpShape<F>::APB), 64 * kMpWaves, 0, s>>>(mg, a);
 }
 
 template <int F, int K, int CUT>
 static void bwd_inst(const MpGeom& mg, const MpBwd& a, bool geo, bool wgrad, hipStream_t s) {
-    constexpr int APW = 64 / (F >= 64 ? 64 : F);
-    int atoms_per_block = kMpWaves * APW;
-    dim3 grid(cdiv(mg.n, atoms_per_block));
-    if constexpr (CUT == 1) {
+    dim3 grid(cdiv(mg.n, MpShape<F>::APB));
+    if constexpr (CUT == 1 && F <= 64) {
         // filter weight adjoints exist for the NC embedding only
         if (wgrad) {
             if (geo) k_message_bwd<F, K, CUT, true, true><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
@@ -411,8 +476,8 @@ static void bwd_inst(const MpGeom& mg, const MpBwd& a, bool geo, bool wgrad, hip
 }
 
 int mp_blocks(int n, int F) {
-    int G = F >= 64 ? 64 : F;
-    return cdiv(n, kMpWaves * (64 / G));
+    const int G = F >= 64 ? 64 : F;
+    return cdiv(n, kMpWaves / (F / G) * (64 / G));
 }
 
 #define NNP_DISPATCH_MP(F_, K_, CUT_, CALL)                                          \
@@ -451,10 +516,5 @@ void launch_message_bwd(int F, int K, int cut, const MpGeom& mg, const MpBwd& a,
     throw Fail{NNP_EINVAL};
 }
 
-void launch_assemble_forces(int n, const int* off, const int* rev, const float* g, float* F, bool accum,
-                            hipStream_t s) {
-    k_assemble_forces<<<cdiv(n, 256), 256, 0, s>>>(n, off, rev, g, F, accum);
-    NNP_LAUNCH_CHECK();
-}
 
 }  // namespace nnp

@@ -83,7 +83,7 @@ struct PackedLayout {
     double *pos, *vel, *mass, *gamma, *energy, *pos_ref, *box_dev, *ke;
     int32_t *species, *rep_of_atom;
     float *f_cons, *f_nc;
-    int *off_c, *nbr_c, *rev_c, *off_n, *nbr_n;
+    int *off_c, *nbr_c, *off_n, *nbr_n;
     char* ws;
     size_t ws_bytes;
 };
@@ -112,7 +112,6 @@ static size_t carve_packed(Server& sv, const std::vector<Replica*>& set, char* b
     L.ke = a.take<double>(R);
     L.off_c = a.take<int>(N + 1);
     L.nbr_c = a.take<int>(Ec);
-    L.rev_c = a.take<int>(Ec);
     L.off_n = a.take<int>(N + 1);
     L.nbr_n = a.take<int>(En);
     const size_t wsb = call_scratch_bytes(sv.cons, sv.nc, std::max<int64_t>(N, 1), std::max(R, 1),
@@ -205,7 +204,7 @@ static void upload(Server& sv) {
     st.f_nc = L.f_nc;
     st.energy = L.energy;
     st.pos_ref = L.pos_ref;
-    st.nl_cons = nnp_nlist{N, Ec, 0, L.off_c, L.nbr_c, L.rev_c, sv.cons->desc.cutoff + sv.p.skin};
+    st.nl_cons = nnp_nlist{N, Ec, 0, L.off_c, L.nbr_c, nullptr, sv.cons->desc.cutoff + sv.p.skin};
     st.nl_nc = nnp_nlist{N, En, 0, L.off_n, L.nbr_n, nullptr, sv.nc->desc.cutoff + sv.p.skin};
     st.first_step = 1;
     st.lists_valid = 0;

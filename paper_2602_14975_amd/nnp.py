@@ -213,7 +213,7 @@ class Trajectory:
         cl = probe.c()
         lib().nnp_neighbors(C.byref(system.c()), C.byref(cl), _ptr(ws0), ws0.numel(), _stream())
         cap = int(cl.n_edges * capacity_factor) + 1024
-        self.nl_cons = NeighborList(n, rc_c, cap, with_rev=True)
+        self.nl_cons = NeighborList(n, rc_c, cap, with_rev=False)
         if self.dmts:
             rc_n = nc.cutoff + params.skin
             self.nl_nc = NeighborList(n, rc_n, max(int(cap * (rc_n / rc_c) ** 3 * 1.2), 1024), with_rev=False)
