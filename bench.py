@@ -132,6 +132,90 @@ def run_oracle(s, cw, nw):
     return {"E": E, "F": F, "Fn": Fn, "t_cons": t_cons, "t_nc": t_nc, "t_nb": t_nb, "threads": threads}
 
 
+def run_serving(n_replicas, n_steps, per_atom_step_s, load=0.8, budget_frac=0.25, seed=30000, max_slots=64):
+    """Continuous batching of replicas of 300-6,000 atoms (30% with a chain),
+    DMTS-NC 4 fs x 8 with BF16 perceptrons, Poisson arrivals at `load` times
+    the estimated saturated rate, HBM budget = budget_frac of the summed
+    footprints."""
+    import torch
+
+    import synth
+    from paper_2602_14975_amd import _abi, nnp, serve
+
+    reps = synth.replica_mix(n_replicas=n_replicas)
+    cons = nnp.Model.from_spec(synth.CONS_CFG1, synth.random_weights(synth.CONS_CFG1, 2004), precision=_abi.NNP_BF16)
+    nc = nnp.Model.from_spec(synth.NC_CFG1, synth.random_weights(synth.NC_CFG1, 3004), precision=_abi.NNP_BF16)
+    prm = nnp.respa_params(4.0, 8, 300.0, seed=4004, skin=1.0)
+    probe = serve.Server(cons, nc, prm, 64 << 20, 1)
+    sizes = [probe.replica_bytes(r.n, r.box) for r in reps]
+    probe.close()
+    budget = max(int(budget_frac * sum(sizes)), max(sizes) + (16 << 20))
+    mean_atoms = float(np.mean([r.n for r in reps]))
+    rate = load / (mean_atoms * n_steps * per_atom_step_s)
+    arrivals = synth.systems.poisson_arrivals(n_replicas, rate, seed)
+    srv = serve.Server(cons, nc, prm, budget, max_slots)
+    torch.cuda.synchronize()
+    rep = serve.run(srv, reps, arrivals, n_steps, 4.0)
+    srv.close()
+    rep.update({"steps_per_replica": n_steps, "arrival_rate_per_s": round(rate, 3), "hbm_budget_MiB": budget >> 20,
+                "budget_frac_of_total": budget_frac, "max_slots": max_slots, "atoms_total": int(sum(r.n for r in reps)),
+                "precision": "bf16 perceptrons, fp32 edge filter and forces, fp64 integration"})
+    for k in ("latency_p50_ms", "latency_p99_ms", "aggregate_ns_per_day", "wall_s", "queue_delay_mean_s",
+              "queue_delay_p99_s"):
+        rep[k] = round(rep[k], 4)
+    return rep
+
+
+def run_chain(args):
+    """Solvated 600-heavy-atom chain + 30,000 waters (~92k atoms), HMR (H set
+    to 3 amu) and high hydrogen friction (100 ps^-1 on H, 1 elsewhere),
+    DMTS-NC 10 fs x 10, BF16 perceptrons.  Also reports the BF16-vs-FP32
+    force error at the starting configuration."""
+    import torch
+
+    import synth
+    from paper_2602_14975_amd import _abi, nnp
+
+    s = synth.solvated_chain(600, 30000, seed=1002)
+    cw = synth.random_weights(synth.CONS_CFG1, 2002)
+    nw = synth.random_weights(synth.NC_CFG1, 3002)
+    out = {}
+    forces = {}
+    for prec in (_abi.NNP_FP32, _abi.NNP_BF16):
+        cons = nnp.Model.from_spec(synth.CONS_CFG1, cw, precision=prec)
+        nc = nnp.Model.from_spec(synth.NC_CFG1, nw, precision=prec)
+        system = nnp.DeviceSystem(s.pos, s.species, s.box)
+        nl = nnp.NeighborList(system.n, 5.0, int(system.n * 60))
+        ws = nnp.workspace(cons, nc, system.n, 1, nl.capacity)
+        nnp.nnp_neighbors(system, nl, ws)
+        _, fc = nnp.nnp_cons_energy_forces(cons, system, nl, ws)
+        fn = nnp.nnp_nc_forces(nc, system, nl, ws)
+        forces[prec] = (fc.double(), fn.double())
+    rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    out["bf16_vs_fp32_force_rel_rmse"] = {"cons": rel(forces[1][0], forces[0][0]),
+                                          "nc": rel(forces[1][1], forces[0][1])}
+    m = nnp.nnp_hmr_masses(s.bonded_heavy, s.standard_masses(), 3.0, "set")
+    gamma = np.where(s.species == 0, 100.0, 1.0)
+    v0 = synth.maxwell_boltzmann(m, 300.0, 5002)
+    cons = nnp.Model.from_spec(synth.CONS_CFG1, cw, precision=_abi.NNP_BF16)
+    nc = nnp.Model.from_spec(synth.NC_CFG1, nw, precision=_abi.NNP_BF16)
+    system = nnp.DeviceSystem(s.pos, s.species, s.box)
+    prm = nnp.respa_params(10.0, 10, 300.0, seed=4002, skin=1.0, check_every=args.check_every)
+    traj = nnp.Trajectory(cons, nc, system, v0, m, gamma, prm)
+    traj.respa_step(max(1, args.warmup))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ke = torch.zeros(args.steps, 1, dtype=torch.float64, device="cuda")
+    traj.respa_step(args.steps, ke)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    T = 2 * ke.cpu().numpy()[:, 0] / (3 * s.n * 8.31446261815324 / 4184.0)
+    out.update({"atoms": int(s.n), "box_A": round(s.box, 3), "ns_per_day": round(_ns_per_day(10.0, args.steps, t), 3),
+                "ms_per_step": round(t / args.steps * 1e3, 3), "temperature_mean_K": round(float(T.mean()), 2),
+                "list_rebuilds": traj.n_rebuilds})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,11 +223,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--no-oracle", action="store_true", help="skip the host oracle leg")
+    ap.add_argument("--workload", default="water", choices=["water", "serve", "chain"])
+    ap.add_argument("--serve-replicas", type=int, default=32)
+    ap.add_argument("--serve-steps", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "serve":
+        rep = run_serving(256, 500, per_atom_step_s=0.5e-6)
+        print(json.dumps({"metric": "p50/p99 replica step latency; aggregate ns/day", "workload": "serving_256x500",
+                          **rep}), flush=True)
+        return
+    if args.workload == "chain":
+        print(json.dumps({"metric": "ns/day DMTS-NC (BF16), solvated chain", "workload": "chain92k_hmr_hhf_10fs_x10",
+                          **run_chain(args)}), flush=True)
+        return
 
     g = run_gpu(args)
     s = g["system"]
@@ -174,6 +271,9 @@ def main():
         "list_rebuilds": g["rebuilds"], "gpu": g["gpu_name"],
         "roofline": roof,
     }
+    if args.serve_replicas > 0:
+        per_atom = g["t_dmts"] / args.steps / s.n
+        out["serving"] = run_serving(args.serve_replicas, args.serve_steps, per_atom)
     if not args.no_oracle:
         o = run_oracle(s, g["cw"], g["nw"])
         e_gpu, f_gpu, fn_gpu = g["gpu_forces"]

@@ -189,6 +189,13 @@ nnp_status nnp_nc_weight_grad(const nnp_model* nc, const nnp_system* sys, const 
                               const float* dl_df, float* dl_dtheta, void* ws, size_t ws_bytes,
                               void* stream);
 
+/* Force-matching loss of the distillation: loss = mean over the `count`
+ * entries of (f - f_ref)^2 (device float64 scalar), and, if grad is not
+ * NULL, grad = dloss/df = 2 (f - f_ref) / count (device float32).  The sum is
+ * taken in a fixed order.  ws: device scratch of at least 8 KiB. */
+nnp_status nnp_force_mse(const float* f, const float* f_ref, int64_t count, double* loss, float* grad,
+                         void* ws, size_t ws_bytes, void* stream);
+
 /* One Adam step on a device float32 parameter vector (in place):
  * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; with bias corrections for
  * step t (>= 1): p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
@@ -312,6 +319,10 @@ nnp_status nnp_server_progress(nnp_server* server, int32_t max_outer_steps, int3
 /* Copies up to cap per-replica step latencies (seconds between consecutive
  * outer-step completions of a replica; the first from its admission). */
 nnp_status nnp_server_step_latencies(nnp_server* server, double* out, int64_t cap, int64_t* n_out);
+/* Device bytes that one replica of n atoms in a box of edge `box` occupies
+ * when resident alone (state, neighbour lists and scratch); a resident set
+ * needs about the sum of its members'. */
+nnp_status nnp_server_replica_bytes(const nnp_server* server, int64_t n, double box, size_t* bytes);
 /* Server clock now (seconds). */
 double nnp_server_clock(const nnp_server* server);
 

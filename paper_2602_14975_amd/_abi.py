@@ -74,6 +74,7 @@ PROTOTYPES = {
     "nnp_cons_energy_forces": (C.c_int32, [vp, C.POINTER(System), C.POINTER(NList), vp, C.c_size_t, vp, vp, vp]),
     "nnp_nc_forces": (C.c_int32, [vp, C.POINTER(System), C.POINTER(NList), vp, C.c_size_t, vp, vp]),
     "nnp_nc_weight_grad": (C.c_int32, [vp, C.POINTER(System), C.POINTER(NList), vp, vp, vp, C.c_size_t, vp]),
+    "nnp_force_mse": (C.c_int32, [vp, vp, C.c_int64, vp, vp, vp, C.c_size_t, vp]),
     "nnp_adam_step": (C.c_int32, [vp, vp, vp, vp, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double,
                                   C.c_double, vp]),
     "nnp_hmr_masses": (C.c_int32, [C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_double,
@@ -87,6 +88,7 @@ PROTOTYPES = {
                                  C.POINTER(C.c_double)]),
     "nnp_server_progress": (C.c_int32, [vp, C.c_int32, C.POINTER(C.c_int32)]),
     "nnp_server_step_latencies": (C.c_int32, [vp, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_int64)]),
+    "nnp_server_replica_bytes": (C.c_int32, [vp, C.c_int64, C.c_double, C.POINTER(C.c_size_t)]),
     "nnp_server_clock": (C.c_double, [vp]),
     "nnp_timer_enable": (C.c_int32, [C.c_char_p, C.c_int32]),
     "nnp_timer_read": (C.c_int32, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),

@@ -580,6 +580,52 @@ extern "C" nnp_status nnp_adam_step(float* param, const float* grad, float* m, f
     NNP_API_END
 }
 
+// =============================================================== force MSE
+namespace nnp {
+// loss partials per block (fixed order) and dL/dF = 2 (F - F_ref) / count
+__global__ void __launch_bounds__(256) k_force_mse(int64_t count, const float* __restrict__ f,
+                                                   const float* __restrict__ ref, float* __restrict__ grad,
+                                                   double* __restrict__ part) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    const double scale = 2.0 / double(count);
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < count; i += int64_t(gridDim.x) * 256) {
+        const float d = f[i] - ref[i];
+        acc += double(d) * double(d);
+        if (grad) grad[i] = float(scale * double(d));
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ void k_sum_parts(int nparts, const double* __restrict__ part, int64_t count, double* __restrict__ loss) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int k = 0; k < nparts; ++k) s += part[k];
+        *loss = s / double(count);
+    }
+}
+}  // namespace nnp
+
+extern "C" nnp_status nnp_force_mse(const float* f, const float* f_ref, int64_t count, double* loss, float* grad,
+                                    void* ws, size_t ws_bytes, void* stream) {
+    NNP_API_BEGIN
+    NNP_REQUIRE(f && f_ref && loss && count > 0, NNP_EINVAL, "bad force-MSE arguments");
+    constexpr int kParts = 1024;
+    NNP_REQUIRE(ws && ws_bytes >= kParts * sizeof(double), NNP_EINVAL, "workspace below 8 KiB");
+    const int blocks = int(std::min<int64_t>(kParts, (count + 255) / 256));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* part = static_cast<double*>(ws);
+    k_force_mse<<<blocks, 256, 0, s>>>(count, f, f_ref, grad, part);
+    k_sum_parts<<<1, 64, 0, s>>>(blocks, part, count, loss);
+    NNP_LAUNCH_CHECK();
+    NNP_API_END
+}
+
 // ===================================================================== HMR
 extern "C" nnp_status nnp_hmr_masses(int64_t n, const int32_t* bonded_heavy, const double* mass, double h_mass,
                                      int32_t mode, double* out_mass) {

@@ -35,7 +35,8 @@ __device__ __forceinline__ short bf16_bits(float x) {
 template <bool BF16>
 __global__ void __launch_bounds__(256)
 k_gemm(GemmArgs g) {
-    constexpr int TK = BF16 ? 32 : 16;
+    constexpr int TK = 32;
+    constexpr int PER = TM * TK / 256;  // staged elements per thread and operand
     __shared__ float As[TK][TM + 4];
     __shared__ float Bs[TK][TN + 4];
     const int tid = threadIdx.x;
@@ -47,22 +48,42 @@ k_gemm(GemmArgs g) {
         kbeg = int(int64_t(blockIdx.z) * g.chunk_rows);
         kend = min(g.K, int(int64_t(blockIdx.z) * g.chunk_rows + g.chunk_rows));
     }
-    floatx16 acc = {};
-    for (int k0 = kbeg; k0 < kend; k0 += TK) {
-        for (int t = tid; t < TM * TK; t += 256) {
+    // Element t of a staged tile: along k when that is the contiguous
+    // dimension of the operand (coalesced), along m / n otherwise.
+    float ra[PER], rb[PER];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int t = tid + u * 256;
             int mm, kk;
             if (g.sak == 1) { mm = t / TK; kk = t % TK; } else { kk = t / TM; mm = t % TM; }
             const int m = m0 + mm, k = k0 + kk;
-            As[kk][mm] = (m < g.M && k < kend) ? g.A[int64_t(m) * g.sam + int64_t(k) * g.sak] : 0.f;
+            ra[u] = (m < g.M && k < kend) ? g.A[int64_t(m) * g.sam + int64_t(k) * g.sak] : 0.f;
+            int nn, kb;
+            if (g.sbk == 1) { nn = t / TK; kb = t % TK; } else { kb = t / TN; nn = t % TN; }
+            const int nc = n0 + nn, kc = k0 + kb;
+            rb[u] = (nc < g.N && kc < kend) ? g.B[int64_t(kc) * g.sbk + int64_t(nc) * g.sbn] : 0.f;
         }
-        for (int t = tid; t < TN * TK; t += 256) {
-            int nn, kk;
-            if (g.sbk == 1) { nn = t / TK; kk = t % TK; } else { kk = t / TN; nn = t % TN; }
-            const int n = n0 + nn, k = k0 + kk;
-            Bs[kk][nn] = (n < g.N && k < kend) ? g.B[int64_t(k) * g.sbk + int64_t(n) * g.sbn] : 0.f;
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int t = tid + u * 256;
+            int mm, kk;
+            if (g.sak == 1) { mm = t / TK; kk = t % TK; } else { kk = t / TM; mm = t % TM; }
+            As[kk][mm] = ra[u];
+            int nn, kb;
+            if (g.sbk == 1) { nn = t / TK; kb = t % TK; } else { kb = t / TN; nn = t % TN; }
+            Bs[kb][nn] = rb[u];
         }
+    };
+    floatx16 acc = {};
+    const int row = lane & 31, grp = lane >> 5;
+    if (kbeg < kend) load(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += TK) {
+        store();
         __syncthreads();
-        const int row = lane & 31, grp = lane >> 5;
+        if (k0 + TK < kend) load(k0 + TK);  // next tile in flight during the MFMAs
         if constexpr (BF16) {
 #pragma unroll
             for (int kk = 0; kk < TK; kk += 8) {
@@ -76,10 +97,9 @@ k_gemm(GemmArgs g) {
             }
         } else {
 #pragma unroll
-            for (int kk = 0; kk < TK; kk += 2) {
+            for (int kk = 0; kk < TK; kk += 2)
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[kk + grp][wr + row], Bs[kk + grp][wc + row], acc, 0,
                                                            0, 0);
-            }
         }
         __syncthreads();
     }

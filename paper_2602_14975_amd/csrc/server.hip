@@ -310,6 +310,22 @@ extern "C" void nnp_server_destroy(nnp_server* server) {
     delete sv;
 }
 
+extern "C" nnp_status nnp_server_replica_bytes(const nnp_server* server, int64_t n, double box, size_t* bytes) {
+    try {
+        NNP_REQUIRE(server && bytes && n >= 1 && box > 0, NNP_EINVAL, "bad argument");
+        Server& sv = *const_cast<Server*>(reinterpret_cast<const Server*>(server));
+        Replica r;
+        r.n = n;
+        r.box = box;
+        std::lock_guard<std::mutex> lk(sv.mu);
+        set_caps(sv, &r);
+        *bytes = footprint(sv, {&r});
+    } catch (const Fail& f) {
+        return f.code;
+    }
+    return NNP_OK;
+}
+
 extern "C" double nnp_server_clock(const nnp_server* server) {
     return server ? reinterpret_cast<const Server*>(server)->now() : 0.0;
 }

@@ -89,8 +89,12 @@ class DeviceSystem:
         self.rep_of_atom = torch.as_tensor(rep, device=device)
         self.box_dev = torch.as_tensor(self.box, device=device)
 
-    def c(self):
-        return _abi.System(self.n, self.n_rep, self.pos.data_ptr(), self.species.data_ptr(),
+    def c(self, pos=None):
+        """C view; `pos` (device float64 [3][n]) replaces the stored positions."""
+        p = self.pos if pos is None else pos
+        if p.dtype != torch.float64 or tuple(p.shape) != (3, self.n) or not p.is_contiguous():
+            raise ValueError("positions must be a contiguous float64 [3][n] tensor")
+        return _abi.System(self.n, self.n_rep, p.data_ptr(), self.species.data_ptr(),
                            self.rep_of_atom.data_ptr() if self.n_rep > 1 else None,
                            self.box_dev.data_ptr() if self.n_rep > 1 else None,
                            self.rep_start.ctypes.data_as(C.POINTER(C.c_int64)),
@@ -172,6 +176,14 @@ def nnp_nc_weight_grad(model, system, nlist, dl_df, ws, out=None):
     check(lib().nnp_nc_weight_grad(model.handle, C.byref(system.c()), C.byref(nlist.c()), _ptr(dl_df), _ptr(out),
                                    _ptr(ws), ws.numel(), _stream()))
     return out
+
+
+def nnp_force_mse(f, f_ref, ws, grad=None):
+    """Returns (loss float64 [1], grad) with grad = 2 (f - f_ref) / f.numel()."""
+    loss = torch.empty(1, dtype=torch.float64, device=f.device)
+    check(lib().nnp_force_mse(_ptr(f), _ptr(f_ref), f.numel(), _ptr(loss), _ptr(grad), _ptr(ws), ws.numel(),
+                              _stream()))
+    return loss, grad
 
 
 def nnp_adam_step(param, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -165,3 +165,37 @@ def test_adam_matches_torch(gpu_lib):
         ref.grad = g.clone()
         opt.step()
     assert torch.allclose(p, ref.detach(), rtol=0, atol=1e-6)
+
+
+BF16_TOL = 1e-2  # force relative RMSE bound for BF16 perceptrons
+
+
+@pytest.mark.parametrize("which", ["water", "chain"])
+def test_bf16_forces_within_bound(gpu_lib, which):
+    from paper_2602_14975_amd import _abi
+    from paper_2602_14975_amd.nnp import DeviceSystem, workspace
+    if which == "water":
+        s = synth.water_config(3)
+    else:
+        s = synth.solvated_chain(40, 700, seed=77)
+    print(f"case bf16 {which} n={s.n}", flush=True)
+    cw = synth.random_weights(synth.CONS_CFG1, 2010)
+    nw = synth.random_weights(synth.NC_CFG1, 3010)
+    cons = gpu_lib.Model.from_spec(synth.CONS_CFG1, cw, precision=_abi.NNP_BF16)
+    nc = gpu_lib.Model.from_spec(synth.NC_CFG1, nw, precision=_abi.NNP_BF16)
+    system = DeviceSystem(s.pos, s.species, s.box)
+    nl = gpu_list(gpu_lib, system, 5.0)
+    ws = workspace(cons, nc, system.n, 1, nl.capacity)
+    e, f = gpu_lib.nnp_cons_energy_forces(cons, system, nl, ws)
+    fn = gpu_lib.nnp_nc_forces(nc, system, nl, ws)
+    off, nbr = oracle_list(s.pos, s.box, 5.0)
+    E, F = om.cons_energy_forces(synth.CONS_CFG1, cw, s.pos, s.species, s.box, off, nbr)
+    off3, nbr3 = oracle_list(s.pos, s.box, 3.5)
+    Fn = om.nc_forces(synth.NC_CFG1, nw, s.pos, s.species, s.box, off3, nbr3)
+    err_c = rel_rmse(f.cpu().numpy().T, F)
+    err_n = rel_rmse(fn.cpu().numpy().T, Fn)
+    print(f"bf16 force rel RMSE cons {err_c:.2e} nc {err_n:.2e}", flush=True)
+    assert err_c <= BF16_TOL and err_n <= BF16_TOL
+    assert err_c > 1e-6  # the BF16 path is really taken
+    f64 = f.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(f64.sum(1)) <= 1e-5 * np.abs(f64).sum()
