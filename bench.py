@@ -216,6 +216,54 @@ def run_chain(args):
     return out
 
 
+def run_copy(mib=512, reps=5):
+    """A plain device copy of known size (torch's copy kernel), the
+    calibration point for the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    return {"bytes_read_per_copy": src.numel() * 4, "bytes_written_per_copy": src.numel() * 4,
+            "copies": reps, "GBps": round(2 * src.numel() * 4 / t / 1e9, 1)}
+
+
+def run_distill(args):
+    """Distillation of the NC model (1 x 32) onto the conservative model
+    (3 x 128) on the 1,536-atom box: 2,000 frames from a 0.5 fs NVT run
+    (2 ps equilibration, one frame per 10 fs), 1,800 training / 200
+    validation frames, batch 16, FP32 Adam lr 1e-3."""
+    import torch
+
+    import synth
+    from paper_2602_14975_amd import distill, nnp
+
+    s = synth.water_config(3)
+    cons = nnp.Model.from_spec(synth.CONS_CFG1, synth.random_weights(synth.CONS_CFG1, 2003))
+    nw = synth.random_weights(synth.NC_CFG1, 3003)
+    nc = nnp.Model.from_spec(synth.NC_CFG1, nw)
+    t0 = time.perf_counter()
+    pos, frc = distill.generate_frames(cons, s, s.standard_masses(), np.ones(s.n), n_frames=args.frames,
+                                       equil_steps=4000, every=20)
+    torch.cuda.synchronize()
+    t_frames = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    d, hist = distill.train(nc, nw, pos, frc, s.species, s.box, s.n, steps=args.train_steps,
+                            n_val=max(1, args.frames // 10), batch=16, lr=1e-3, log_every=max(1, args.train_steps // 20))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    fref = frc.double()
+    label_rms = float(torch.sqrt((fref * fref).mean()))
+    return {"frames": args.frames, "frame_generation_s": round(t_frames, 2), "train_steps": args.train_steps,
+            "train_s": round(t_train, 2), "ms_per_train_step": round(t_train / args.train_steps * 1e3, 3),
+            "label_force_rms": round(label_rms, 4),
+            "val_force_rmse_history": [(int(k), round(v, 5)) for k, v in hist]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,7 +271,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--no-oracle", action="store_true", help="skip the host oracle leg")
-    ap.add_argument("--workload", default="water", choices=["water", "serve", "chain"])
+    ap.add_argument("--workload", default="water", choices=["water", "serve", "chain", "copy", "distill"])
+    ap.add_argument("--frames", type=int, default=2000)
+    ap.add_argument("--train-steps", type=int, default=10000)
     ap.add_argument("--serve-replicas", type=int, default=32)
     ap.add_argument("--serve-steps", type=int, default=50)
     args = ap.parse_args()
@@ -236,6 +286,13 @@ def main():
         rep = run_serving(256, 500, per_atom_step_s=0.5e-6)
         print(json.dumps({"metric": "p50/p99 replica step latency; aggregate ns/day", "workload": "serving_256x500",
                           **rep}), flush=True)
+        return
+    if args.workload == "copy":
+        print(json.dumps({"workload": "device_copy_512MiB", **run_copy()}), flush=True)
+        return
+    if args.workload == "distill":
+        print(json.dumps({"metric": "distillation force RMSE vs steps", "workload": "distill_water1536",
+                          **run_distill(args)}), flush=True)
         return
     if args.workload == "chain":
         print(json.dumps({"metric": "ns/day DMTS-NC (BF16), solvated chain", "workload": "chain92k_hmr_hhf_10fs_x10",

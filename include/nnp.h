@@ -212,7 +212,11 @@ nnp_status nnp_adam_step(float* param, const float* grad, float* m, float* v, in
 nnp_status nnp_hmr_masses(int64_t n, const int32_t* bonded_heavy, const double* mass,
                           double h_mass, int32_t mode, double* out_mass);
 
-enum { NNP_MODE_DMTS_NC = 0, NNP_MODE_STS = 1 };
+/* NNP_MODE_DMTS_NC: Algorithm 1 with the NC model as the fast force.
+ * NNP_MODE_STS: BAOAB with the conservative force only.
+ * NNP_MODE_DMTS: the same splitting with a small conservative model as the
+ * fast force (the distilled conservative scheme the paper compares with). */
+enum { NNP_MODE_DMTS_NC = 0, NNP_MODE_STS = 1, NNP_MODE_DMTS = 2 };
 enum { NNP_THERMO_LANGEVIN = 0, NNP_THERMO_FFL = 1 };
 
 typedef struct {
@@ -226,6 +230,16 @@ typedef struct {
     uint64_t stream_id;     /* Philox key word 1 for replica 0; replica r uses stream_id + r */
     double skin;            /* Verlet skin (A) of both lists; lists are rebuilt when an
                                atom has moved more than skin/2 since the last build */
+    /* Rewind procedure (paper, Methods "Preventing rare model disagreements"):
+     * when rewind_threshold > 0, a frame is saved every save_every outer steps;
+     * after each outer step the disagreement sqrt(mean_i |F_i - F_fast,i|^2) of
+     * every replica is measured, and if one exceeds the threshold the whole
+     * system returns to the saved frame (positions, velocities, forces and the
+     * O-step counter), runs sts_after_rewind BAOAB steps of size delta with the
+     * conservative force, re-evaluates the fast force and resumes MTS. */
+    double rewind_threshold;  /* kcal/mol/A; 0 disables */
+    int32_t save_every;       /* >= 1 */
+    int32_t sts_after_rewind; /* >= 0 */
 } respa_params;
 
 /* Device-resident trajectory state.  All pointers are caller-owned device
@@ -241,16 +255,18 @@ typedef struct {
     double* energy;        /* [n_rep] conservative energy at the last evaluation */
     double* pos_ref;       /* [3][n] positions at the last list build */
     nnp_nlist nl_cons;     /* conservative list (cutoff + skin) */
-    nnp_nlist nl_nc;       /* NC list (NC cutoff + skin); unused in STS mode */
+    nnp_nlist nl_nc;       /* fast-force list (its cutoff + skin); unused in STS mode */
     uint64_t step;         /* O-steps done so far (advanced by the call) */
     int32_t first_step;    /* 1: evaluate F and F_NC before the first kick */
     int32_t lists_valid;   /* 0: build both lists before the first use */
     double* ke;            /* [n_outer][n_rep] kinetic energy after each outer
                               step (kcal/mol), or NULL */
     int64_t n_rebuilds;    /* out: list rebuilds performed (accumulates) */
+    int64_t n_rewinds;     /* out: rewinds performed (accumulates) */
 } respa_state;
 
-/* Advances the state by n_outer outer steps of Algorithm 1 (DMTS-NC:
+/* Advances the state by n_outer outer steps of Algorithm 1 (DMTS-NC, or
+ * DMTS with `nc` a conservative model:
  * v += (D/2) M^-1 (F - F_NC); n x [B(d/2), A(d/2), O(d), A(d/2), F_NC, B(d/2)];
  * F; v += (D/2) M^-1 (F - F_NC)), or of BAOAB with the conservative force
  * (STS).  The O step is v <- c v + sqrt((1 - c^2) kT/m) G, c = exp(-gamma d),

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libnnp.so")
 NNP_OK, NNP_EINVAL, NNP_ENOMEM, NNP_ECAPACITY, NNP_EDEVICE, NNP_EUNSTABLE, NNP_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 NNP_MODEL_CONS, NNP_MODEL_NC = 0, 1
 NNP_FP32, NNP_BF16 = 0, 1
-NNP_MODE_DMTS_NC, NNP_MODE_STS = 0, 1
+NNP_MODE_DMTS_NC, NNP_MODE_STS, NNP_MODE_DMTS = 0, 1, 2
 NNP_THERMO_LANGEVIN, NNP_THERMO_FFL = 0, 1
 REPLICA_QUEUED, REPLICA_RUNNING, REPLICA_DONE, REPLICA_FAILED = 0, 1, 2, 3
 
@@ -40,14 +40,15 @@ class NList(C.Structure):
 class RespaParams(C.Structure):
     _fields_ = [("dt_outer_fs", C.c_double), ("n_inner", C.c_int32), ("mode", C.c_int32),
                 ("thermostat", C.c_int32), ("check_every", C.c_int32), ("temperature_K", C.c_double),
-                ("seed", C.c_uint64), ("stream_id", C.c_uint64), ("skin", C.c_double)]
+                ("seed", C.c_uint64), ("stream_id", C.c_uint64), ("skin", C.c_double),
+                ("rewind_threshold", C.c_double), ("save_every", C.c_int32), ("sts_after_rewind", C.c_int32)]
 
 
 class RespaState(C.Structure):
     _fields_ = [("sys", System), ("pos", vp), ("vel", vp), ("mass", vp), ("gamma", vp), ("f_cons", vp),
                 ("f_nc", vp), ("energy", vp), ("pos_ref", vp), ("nl_cons", NList), ("nl_nc", NList),
                 ("step", C.c_uint64), ("first_step", C.c_int32), ("lists_valid", C.c_int32), ("ke", vp),
-                ("n_rebuilds", C.c_int64)]
+                ("n_rebuilds", C.c_int64), ("n_rewinds", C.c_int64)]
 
 
 class ReplicaDesc(C.Structure):

@@ -409,7 +409,10 @@ struct CallScratch {
     SysTables t;
     NbrScratch nb;
     ModelBuf cons, nc;
-    RespaBuf rs;
+    RespaBuf rs;       // snapshot for capacity failures
+    RespaBuf frame;    // saved frame of the rewind procedure
+    double* inner_energy = nullptr;
+    double* disagree = nullptr;
 };
 
 // One layout serves every entry point: tables, neighbour scratch, the
@@ -424,6 +427,14 @@ void carve_all(Arena& a, const Model* cons, const Model* nc, int64_t n, int32_t 
     c.rs.f_cons = a.take<float>(3 * n);
     c.rs.f_nc = a.take<float>(3 * n);
     c.rs.energy = a.take<double>(n_rep);
+    c.frame.pos = a.take<double>(3 * n);
+    c.frame.vel = a.take<double>(3 * n);
+    c.frame.pos_ref = a.take<double>(3 * n);
+    c.frame.f_cons = a.take<float>(3 * n);
+    c.frame.f_nc = a.take<float>(3 * n);
+    c.frame.energy = a.take<double>(n_rep);
+    c.inner_energy = a.take<double>(n_rep);
+    c.disagree = a.take<double>(n_rep);
     if (cons) carve_model(a, cons, n, E, false, c.cons);
     if (nc) carve_model(a, nc, n, E, wgrad, c.nc);
 }
@@ -666,13 +677,22 @@ static int* pinned_flags() {
 void check_respa(const respa_state* st, const respa_params* p, const Model* cons, const Model* nc) {
     NNP_REQUIRE(st && p && cons, NNP_EINVAL, "null argument");
     NNP_REQUIRE(cons->desc.kind == NNP_MODEL_CONS, NNP_EINVAL, "first model must be conservative");
-    NNP_REQUIRE(p->mode == NNP_MODE_DMTS_NC || p->mode == NNP_MODE_STS, NNP_EINVAL, "unknown mode");
-    if (p->mode == NNP_MODE_DMTS_NC) {
-        NNP_REQUIRE(nc && nc->desc.kind == NNP_MODEL_NC, NNP_EINVAL, "DMTS-NC needs an NC model");
+    NNP_REQUIRE(p->mode == NNP_MODE_DMTS_NC || p->mode == NNP_MODE_STS || p->mode == NNP_MODE_DMTS, NNP_EINVAL,
+                "unknown mode");
+    if (p->mode != NNP_MODE_STS) {
+        const int want = p->mode == NNP_MODE_DMTS_NC ? NNP_MODEL_NC : NNP_MODEL_CONS;
+        NNP_REQUIRE(nc && nc->desc.kind == want, NNP_EINVAL,
+                    p->mode == NNP_MODE_DMTS_NC ? "DMTS-NC needs an NC model as the fast force"
+                                                : "DMTS needs a conservative model as the fast force");
         NNP_REQUIRE(p->n_inner >= 1, NNP_EINVAL, "n_inner must be >= 1");
-        NNP_REQUIRE(st->f_nc && st->nl_nc.offsets && st->nl_nc.nbr, NNP_EINVAL, "DMTS-NC needs f_nc and the NC list");
+        NNP_REQUIRE(st->f_nc && st->nl_nc.offsets && st->nl_nc.nbr, NNP_EINVAL,
+                    "multi-time-stepping needs f_nc and the fast-force list");
+        NNP_REQUIRE(nc->desc.cutoff <= cons->desc.cutoff, NNP_EINVAL,
+                    "the fast-force cutoff must not exceed the conservative one");
     }
     NNP_REQUIRE(p->dt_outer_fs > 0 && p->temperature_K >= 0 && p->skin >= 0, NNP_EINVAL, "bad integrator parameters");
+    NNP_REQUIRE(p->rewind_threshold >= 0 && (p->rewind_threshold == 0 || (p->save_every >= 1 && p->sts_after_rewind >= 0)),
+                NNP_EINVAL, "bad rewind parameters");
     NNP_REQUIRE(st->pos && st->vel && st->mass && st->gamma && st->f_cons && st->energy && st->pos_ref, NNP_EINVAL,
                 "incomplete state");
     NNP_REQUIRE(st->sys.pos == st->pos, NNP_EINVAL, "state.sys.pos must alias state.pos");
@@ -680,9 +700,28 @@ void check_respa(const respa_state* st, const respa_params* p, const Model* cons
     NNP_REQUIRE(st->nl_cons.n_atoms == st->sys.n_atoms, NNP_EINVAL, "list rows must equal n_atoms");
 }
 
-}  // namespace nnp
-
-namespace nnp {
+// Per-replica disagreement sqrt(mean_i |F_i - F_fast,i|^2), fixed-order
+// float64 reduction, one block per replica.
+__global__ void __launch_bounds__(256) k_disagreement(const int64_t* __restrict__ rep_start, int n,
+                                                      const float* __restrict__ fa, const float* __restrict__ fb,
+                                                      double* __restrict__ out) {
+    __shared__ double red[256];
+    const int r = blockIdx.x;
+    const int64_t a0 = rep_start[r], a1 = rep_start[r + 1];
+    double acc = 0.0;
+    for (int64_t i = a0 + threadIdx.x; i < a1; i += 256)
+        for (int c = 0; c < 3; ++c) {
+            const double d = double(fa[c * int64_t(n) + i]) - double(fb[c * int64_t(n) + i]);
+            acc += d * d;
+        }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[r] = sqrt(red[0] / double(max<int64_t>(a1 - a0, 1)));
+}
 
 // Advances a packed system by n_outer outer steps.  Replica r draws its
 // normals with key (seeds[r], streams[r]) and O-step index step_base[r] + k,
@@ -695,23 +734,28 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     check_respa(st, p, cons, nc);
     check_system(&st->sys);
     NNP_REQUIRE(n_outer >= 0, NNP_EINVAL, "n_outer must be >= 0");
-    const bool dmts = p->mode == NNP_MODE_DMTS_NC;
+    const bool mts = p->mode != NNP_MODE_STS;
+    const bool inner_nc = mts && nc->desc.kind == NNP_MODEL_NC;
+    const bool rewind = mts && p->rewind_threshold > 0;
     const int n = int(st->sys.n_atoms);
     const int R = st->sys.n_rep;
     Arena a(ws, ws_bytes);
     CallScratch c;
-    const int64_t E = std::max<int64_t>({st->nl_cons.capacity, dmts ? st->nl_nc.capacity : 0, int64_t(1)});
-    carve_all(a, cons, dmts ? nc : nullptr, n, R, E, false, c);
+    const int64_t E = std::max<int64_t>({st->nl_cons.capacity, mts ? st->nl_nc.capacity : 0, int64_t(1)});
+    carve_all(a, cons, mts ? nc : nullptr, n, R, E, false, c);
+    RespaBuf& frame = c.frame;
+    double* disagree = c.disagree;
+    double* inner_energy = c.inner_energy;
     std::vector<double> hs;
     RepGeom g = upload_tables(st->sys, c.t, s, hs);
     NNP_HIP(hipMemcpyAsync(c.t.seed, seeds, sizeof(uint64_t) * R, hipMemcpyHostToDevice, s));
     NNP_HIP(hipMemcpyAsync(c.t.stream, streams, sizeof(uint64_t) * R, hipMemcpyHostToDevice, s));
     NNP_HIP(hipMemcpyAsync(c.t.step_base, step_base, sizeof(uint64_t) * R, hipMemcpyHostToDevice, s));
     const double rc_cons = cons->desc.cutoff + p->skin;
-    const double rc_nc = dmts ? nc->desc.cutoff + p->skin : 0.0;
+    const double rc_nc = mts ? nc->desc.cutoff + p->skin : 0.0;
     CellPlan plan = plan_cells(st->sys, rc_cons);
     upload_cell_plan(plan, c.nb, s);
-    // flags: [0] rebuild trigger, [8..10] NC list status; nb.status: conservative list
+    // flags: [0] rebuild trigger, [8..10] fast-force list status; nb.status: conservative list
     int* trig = c.t.flags;
     int* nc_status = c.t.flags + 8;
     NNP_HIP(hipMemsetAsync(c.t.flags, 0, sizeof(int) * 16, s));
@@ -723,7 +767,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     auto rebuild_if_flagged = [&]() {
         launch_build(n, st->pos, g, plan, c.nb, trig, rc_cons, lc.capacity, lc.offsets, lc.nbr, lc.rev, st->pos_ref,
                      s);
-        if (dmts)
+        if (mts)
             launch_filter(n, st->pos, g, c.nb, trig, lc.offsets, lc.nbr, rc_nc, ln.capacity, ln.offsets, ln.nbr,
                           nullptr, nc_status, s);
         launch_finish_rebuild(trig, c.t.rebuilds, s);
@@ -747,10 +791,14 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     ba.flag = trig;
 
     auto eval_cons = [&]() { cons_eval(cons, st->sys, g, c.t, lc, c.cons, st->energy, st->f_cons, s); };
-    auto eval_nc = [&]() { nc_eval(nc, st->sys, g, ln, c.nc, st->f_nc, s); };
+    auto eval_inner = [&]() {
+        if (inner_nc) nc_eval(nc, st->sys, g, ln, c.nc, st->f_nc, s);
+        else cons_eval(nc, st->sys, g, c.t, ln, c.nc, inner_energy, st->f_nc, s);
+    };
 
     int* hflags = pinned_flags();
     std::vector<int> bad(R);
+    std::vector<double> dis(R);
     auto read_status = [&]() {
         NNP_HIP(hipMemcpyAsync(hflags, c.t.flags, sizeof(int) * 16, hipMemcpyDeviceToHost, s));
         NNP_HIP(hipMemcpyAsync(hflags + 16, c.nb.status, sizeof(int) * 8, hipMemcpyDeviceToHost, s));
@@ -758,23 +806,23 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         NNP_HIP(hipMemcpyAsync(bad.data(), c.t.rep_bad, sizeof(int) * R, hipMemcpyDeviceToHost, s));
         NNP_HIP(hipStreamSynchronize(s));
     };
-    auto snapshot = [&](bool save) {
+    auto copy_state = [&](RespaBuf& dst_buf, bool save) {
         const size_t d3 = sizeof(double) * 3 * size_t(n), f3 = sizeof(float) * 3 * size_t(n);
         auto cp = [&](void* dst, const void* src, size_t bytes) {
             NNP_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s));
         };
         if (save) {
-            cp(c.rs.pos, st->pos, d3); cp(c.rs.vel, st->vel, d3); cp(c.rs.pos_ref, st->pos_ref, d3);
-            cp(c.rs.f_cons, st->f_cons, f3); if (dmts) cp(c.rs.f_nc, st->f_nc, f3);
-            cp(c.rs.energy, st->energy, sizeof(double) * R);
+            cp(dst_buf.pos, st->pos, d3); cp(dst_buf.vel, st->vel, d3); cp(dst_buf.pos_ref, st->pos_ref, d3);
+            cp(dst_buf.f_cons, st->f_cons, f3); if (mts) cp(dst_buf.f_nc, st->f_nc, f3);
+            cp(dst_buf.energy, st->energy, sizeof(double) * R);
         } else {
-            cp(st->pos, c.rs.pos, d3); cp(st->vel, c.rs.vel, d3); cp(st->pos_ref, c.rs.pos_ref, d3);
-            cp(st->f_cons, c.rs.f_cons, f3); if (dmts) cp(st->f_nc, c.rs.f_nc, f3);
-            cp(st->energy, c.rs.energy, sizeof(double) * R);
+            cp(st->pos, dst_buf.pos, d3); cp(st->vel, dst_buf.vel, d3); cp(st->pos_ref, dst_buf.pos_ref, d3);
+            cp(st->f_cons, dst_buf.f_cons, f3); if (mts) cp(st->f_nc, dst_buf.f_nc, f3);
+            cp(st->energy, dst_buf.energy, sizeof(double) * R);
         }
     };
     long long rebuilds_seen = 0;
-    uint64_t offset = 0;  // O-steps done in this call
+    uint64_t offset = 0;  // O-steps since the start of the call (the counter the kernels add to step_base)
     auto check = [&](uint64_t offset_at_snapshot, bool can_restore) -> nnp_status {
         read_status();
         long long rb;
@@ -788,7 +836,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
             if (over_cons) st->nl_cons.n_edges = hflags[16 + 1];
             if (over_nc) st->nl_nc.n_edges = hflags[8 + 1];
             if (can_restore) {
-                snapshot(false);
+                copy_state(c.rs, false);
                 st->step -= offset - offset_at_snapshot;
                 offset = offset_at_snapshot;
                 NNP_HIP(hipStreamSynchronize(s));
@@ -814,13 +862,13 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         // empty rows until the first build succeeds, so a failed build never
         // leaves uninitialised offsets behind
         NNP_HIP(hipMemsetAsync(lc.offsets, 0, sizeof(int) * (size_t(n) + 1), s));
-        if (dmts) NNP_HIP(hipMemsetAsync(ln.offsets, 0, sizeof(int) * (size_t(n) + 1), s));
+        if (mts) NNP_HIP(hipMemsetAsync(ln.offsets, 0, sizeof(int) * (size_t(n) + 1), s));
         launch_set_flag(trig, 1, s);
         rebuild_if_flagged();
         st->lists_valid = 1;
     }
     if (st->first_step) {
-        if (dmts) eval_nc();
+        if (mts) eval_inner();
         eval_cons();
         st->first_step = 0;
     }
@@ -828,38 +876,73 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         nnp_status e = check(0, false);
         if (e != NNP_OK) return e;
     }
-    const int check_every = std::max(1, p->check_every);
-    const int n_in = dmts ? p->n_inner : 1;
+    const int check_every = rewind ? 1 : std::max(1, p->check_every);
+    const int n_in = mts ? p->n_inner : 1;
     const double D = p->dt_outer_fs;
     const double d = D / n_in;
-    uint64_t snap_offset = 0;
-    snapshot(true);
-    for (int o = 0; o < n_outer; ++o) {
-        if (dmts) {
-            launch_kick(n, st->vel, st->mass, st->f_cons, st->f_nc, 0.5 * D, s);
-            for (int k = 0; k < n_in; ++k) {
-                ba.force = st->f_nc;
-                ba.dt = d;
-                ba.step_offset = offset;
-                launch_baoa(ba, s);
-                rebuild_if_flagged();
-                eval_nc();
-                launch_kick(n, st->vel, st->mass, st->f_nc, nullptr, 0.5 * d, s);
-                offset += 1;
-                st->step += 1;
-            }
-            eval_cons();
-            launch_kick(n, st->vel, st->mass, st->f_cons, st->f_nc, 0.5 * D, s);
-        } else {
-            ba.force = st->f_cons;
-            ba.dt = D;
+
+    // one BAOAB step of size dt with the conservative force
+    auto sts_step = [&](double dt) {
+        ba.force = st->f_cons;
+        ba.dt = dt;
+        ba.step_offset = offset;
+        launch_baoa(ba, s);
+        rebuild_if_flagged();
+        eval_cons();
+        launch_kick(n, st->vel, st->mass, st->f_cons, nullptr, 0.5 * dt, s);
+        offset += 1;
+        st->step += 1;
+    };
+    // one outer step of Algorithm 1
+    auto mts_step = [&]() {
+        launch_kick(n, st->vel, st->mass, st->f_cons, st->f_nc, 0.5 * D, s);
+        for (int k = 0; k < n_in; ++k) {
+            ba.force = st->f_nc;
+            ba.dt = d;
             ba.step_offset = offset;
             launch_baoa(ba, s);
             rebuild_if_flagged();
-            eval_cons();
-            launch_kick(n, st->vel, st->mass, st->f_cons, nullptr, 0.5 * D, s);
+            eval_inner();
+            launch_kick(n, st->vel, st->mass, st->f_nc, nullptr, 0.5 * d, s);
             offset += 1;
             st->step += 1;
+        }
+        eval_cons();
+        launch_kick(n, st->vel, st->mass, st->f_cons, st->f_nc, 0.5 * D, s);
+    };
+
+    uint64_t snap_offset = 0;
+    copy_state(c.rs, true);
+    uint64_t frame_offset = 0;
+    int since_save = 0;
+    for (int o = 0; o < n_outer; ++o) {
+        if (rewind && since_save % p->save_every == 0) {
+            copy_state(frame, true);
+            frame_offset = offset;
+            since_save = 0;
+        }
+        if (mts) mts_step();
+        else sts_step(D);
+        ++since_save;
+        if (rewind) {
+            k_disagreement<<<R, 256, 0, s>>>(c.t.rep_start, n, st->f_cons, st->f_nc, disagree);
+            NNP_LAUNCH_CHECK();
+            NNP_HIP(hipMemcpyAsync(dis.data(), disagree, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+            NNP_HIP(hipStreamSynchronize(s));
+            bool trip = false;
+            for (int r = 0; r < R; ++r) trip |= !(dis[r] <= p->rewind_threshold);
+            if (trip) {
+                // back to the saved frame (state and O-step counter), STS, then MTS again
+                copy_state(frame, false);
+                st->step -= offset - frame_offset;
+                offset = frame_offset;
+                launch_set_flag(trig, 1, s);
+                rebuild_if_flagged();
+                for (int k = 0; k < p->sts_after_rewind; ++k) sts_step(d);
+                eval_inner();
+                st->n_rewinds += 1;
+                since_save = 0;
+            }
         }
         launch_kinetic(R, c.t.rep_start, n, st->pos, st->vel, st->mass, st->ke ? st->ke + int64_t(o) * R : nullptr,
                        c.t.rep_bad, s);
@@ -867,7 +950,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
             nnp_status e = check(snap_offset, true);
             if (e != NNP_OK) return e;
             snap_offset = offset;
-            if (o + 1 < n_outer) snapshot(true);
+            if (o + 1 < n_outer) copy_state(c.rs, true);
         }
     }
     return NNP_OK;

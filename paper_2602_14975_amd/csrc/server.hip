@@ -284,6 +284,7 @@ extern "C" nnp_status nnp_server_create(const nnp_model* cons, const nnp_model* 
                     "model kinds do not match");
         sv->p = *params;
         sv->p.check_every = 1;
+        sv->p.rewind_threshold = 0.0;  // replicas fail alone; a rewind would move every resident replica
         sv->budget = hbm_budget_bytes;
         sv->max_slots = max_slots;
         sv->t0 = std::chrono::steady_clock::now();

@@ -210,7 +210,7 @@ class Trajectory:
         self.cons, self.nc, self.sys = cons, nc, system
         n = system.n
         self.params = params
-        self.dmts = params.mode == _abi.NNP_MODE_DMTS_NC
+        self.dmts = params.mode in (_abi.NNP_MODE_DMTS_NC, _abi.NNP_MODE_DMTS)
         self.vel = torch.as_tensor(np.ascontiguousarray(np.asarray(vel, dtype=np.float64).T), device=DEV)
         self.mass = torch.as_tensor(np.asarray(masses, dtype=np.float64), device=DEV)
         self.gamma = torch.as_tensor(np.asarray(gamma, dtype=np.float64), device=DEV)
@@ -236,13 +236,14 @@ class Trajectory:
         self.first_step = 1
         self.lists_valid = 0
         self.n_rebuilds = 0
+        self.n_rewinds = 0
 
     def _state(self, ke):
         return _abi.RespaState(self.sys.c(), self.sys.pos.data_ptr(), self.vel.data_ptr(), self.mass.data_ptr(),
                                self.gamma.data_ptr(), self.f_cons.data_ptr(), self.f_nc.data_ptr(),
                                self.energy.data_ptr(), self.pos_ref.data_ptr(), self.nl_cons.c(), self.nl_nc.c(),
                                self.step_count, self.first_step, self.lists_valid,
-                               ke.data_ptr() if ke is not None else None, self.n_rebuilds)
+                               ke.data_ptr() if ke is not None else None, self.n_rebuilds, self.n_rewinds)
 
     def respa_step(self, n_outer, ke=None):
         """Advances by n_outer outer steps (growing list buffers on
@@ -256,6 +257,7 @@ class Trajectory:
             self.first_step = int(st.first_step)
             self.lists_valid = int(st.lists_valid)
             self.n_rebuilds = int(st.n_rebuilds)
+            self.n_rewinds = int(st.n_rewinds)
             if code == _abi.NNP_ECAPACITY:
                 need_c, need_n = int(st.nl_cons.n_edges), int(st.nl_nc.n_edges)
                 if need_c > self.nl_cons.capacity:
@@ -280,9 +282,12 @@ class Trajectory:
         return self.vel.T.cpu().numpy()
 
 
+_MODES = {"dmts_nc": _abi.NNP_MODE_DMTS_NC, "sts": _abi.NNP_MODE_STS, "dmts": _abi.NNP_MODE_DMTS}
+
+
 def respa_params(dt_outer, n_inner, temperature=300.0, seed=4000, stream_id=0, mode="dmts_nc", thermostat="langevin",
-                 skin=1.0, check_every=1):
-    return _abi.RespaParams(float(dt_outer), int(n_inner),
-                            _abi.NNP_MODE_DMTS_NC if mode == "dmts_nc" else _abi.NNP_MODE_STS,
+                 skin=1.0, check_every=1, rewind_threshold=0.0, save_every=1, sts_after_rewind=0):
+    return _abi.RespaParams(float(dt_outer), int(n_inner), _MODES[mode],
                             _abi.NNP_THERMO_FFL if thermostat == "ffl" else _abi.NNP_THERMO_LANGEVIN,
-                            int(check_every), float(temperature), int(seed), int(stream_id), float(skin))
+                            int(check_every), float(temperature), int(seed), int(stream_id), float(skin),
+                            float(rewind_threshold), int(save_every), int(sts_after_rewind))

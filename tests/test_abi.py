@@ -45,13 +45,34 @@ def test_binding_covers_every_symbol(lib):
     assert sorted(_abi.PROTOTYPES) == _declared()
 
 
-def test_structure_sizes_match_c():
+def test_structure_layouts_match_the_header(tmp_path):
+    """Compiles the header with gcc and compares every field offset and
+    structure size with the ctypes mirror used by the binding."""
+    import shutil
+    import subprocess
     from paper_2602_14975_amd import _abi
-    # sizes follow from the C layout rules on x86-64
-    assert C.sizeof(_abi.ModelDesc) == 10 * 4 + 8 + 8 + 8
-    assert C.sizeof(_abi.System) == 8 + 8 + 6 * 8
-    assert C.sizeof(_abi.NList) == 3 * 8 + 3 * 8 + 8
-    assert C.sizeof(_abi.RespaParams) == 8 + 4 * 4 + 8 + 8 + 8 + 8
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    structs = {"nnp_model_desc": _abi.ModelDesc, "nnp_system": _abi.System, "nnp_nlist": _abi.NList,
+               "respa_params": _abi.RespaParams, "respa_state": _abi.RespaState, "replica_desc": _abi.ReplicaDesc,
+               "replica_status": _abi.ReplicaStatus}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {"]
+    for cname, cls in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-std=c11", str(src), "-o", str(exe)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    for cname, cls in structs.items():
+        assert int(got[cname]) == C.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(cls, fname).offset, f"{cname}.{fname}"
 
 
 def test_abi_version_and_error_string(lib):

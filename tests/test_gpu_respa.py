@@ -119,3 +119,84 @@ def test_full_size_dmts_nc_runs(gpu_lib):
     assert np.all(np.isfinite(T)) and np.all(np.abs(T - 300) < 30)
     fnc = traj.f_nc.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(fnc.sum(1)) <= 1e-5 * np.abs(fnc).sum()
+
+
+def _models_cfg0(nnp):
+    cw = synth.random_weights(synth.CONS_CFG0, 2000)
+    nw = synth.random_weights(synth.NC_CFG0, 3000)
+    return nnp.Model.from_spec(synth.CONS_CFG0, cw), cw, nnp.Model.from_spec(synth.NC_CFG0, nw), nw
+
+
+def test_dmts_with_conservative_fast_model_matches_oracle(gpu_lib):
+    """The distilled conservative scheme: a small one-layer conservative
+    model at 3.5 A as the fast force of the same splitting."""
+    from synth.weights import ModelSpec
+    small = ModelSpec("cons", 16, 1, 16, 3.5)
+    s = synth.water_config(0)
+    m = s.standard_masses()
+    cons, cw, _, _ = _models_cfg0(gpu_lib)
+    sw = synth.random_weights(small, 2100)
+    fast = gpu_lib.Model.from_spec(small, sw)
+    v0 = synth.maxwell_boltzmann(m, 300.0, 5000)
+    system = gpu_lib.DeviceSystem(s.pos, s.species, s.box)
+    prm = gpu_lib.respa_params(2.0, 4, 300.0, seed=4000, mode="dmts")
+    traj = gpu_lib.Trajectory(cons, fast, system, v0, m, np.ones(s.n), prm)
+    traj.respa_step(6)
+    cons_fn, _ = _oracle_fns(synth.CONS_CFG0, cw, synth.NC_CFG0, None, s.species, s.box)
+
+    def fast_fn(x):
+        off, nbr = onb.pairs_bruteforce(x, s.box, 3.5)
+        return om.cons_energy_forces(small, sw, x, s.species, s.box, off, nbr)[1]
+
+    st = oi.State(s.pos.copy(), v0.copy(), m.copy())
+    p = oi.LangevinParams(2.0, 4, 300.0, np.ones(s.n), seed=4000)
+    for _ in range(6):
+        oi.dmts_nc_step(st, cons_fn, fast_fn, p)
+    assert np.max(np.abs(traj.positions() - st.x)) <= 2e-6
+    assert np.max(np.abs(traj.velocities() - st.v)) <= 1e-5 * np.max(np.abs(st.v))
+
+
+def _traj(nnp, mode, dt, n_inner, **kw):
+    s = synth.water_config(0)
+    m = s.standard_masses()
+    cons, _, nc, _ = _models_cfg0(nnp)
+    v0 = synth.maxwell_boltzmann(m, 300.0, 5000)
+    system = nnp.DeviceSystem(s.pos, s.species, s.box)
+    prm = nnp.respa_params(dt, n_inner, 300.0, seed=4000, mode=mode, **kw)
+    return nnp.Trajectory(cons, nc if mode != "sts" else None, system, v0, m, np.ones(s.n), prm), (cons, nc)
+
+
+def test_rewind_never_tripping_changes_nothing(gpu_lib):
+    a, ka = _traj(gpu_lib, "dmts_nc", 2.0, 4)
+    b, kb = _traj(gpu_lib, "dmts_nc", 2.0, 4, rewind_threshold=1e9, save_every=2, sts_after_rewind=3)
+    a.respa_step(5)
+    b.respa_step(5)
+    assert b.n_rewinds == 0
+    assert np.array_equal(a.positions(), b.positions()) and np.array_equal(a.velocities(), b.velocities())
+
+
+def test_rewind_always_tripping_is_single_time_stepping(gpu_lib):
+    """Saving every outer step and rewinding after each one, followed by
+    n_inner BAOAB steps of delta, reproduces a plain BAOAB run of step delta
+    (same Philox counters) bit for bit."""
+    a, ka = _traj(gpu_lib, "dmts_nc", 2.0, 4, rewind_threshold=1e-12, save_every=1, sts_after_rewind=4)
+    b, kb = _traj(gpu_lib, "sts", 0.5, 1)
+    a.respa_step(3)
+    b.respa_step(12)
+    assert a.n_rewinds == 3 and a.step_count == b.step_count == 12
+    assert np.array_equal(a.positions(), b.positions()) and np.array_equal(a.velocities(), b.velocities())
+
+
+def test_rewind_triggers_on_a_disagreeing_model(gpu_lib):
+    s = synth.water_config(0)
+    m = s.standard_masses()
+    cons, _, _, nw = _models_cfg0(gpu_lib)
+    bad = gpu_lib.Model.from_spec(synth.NC_CFG0, nw * 3.0)  # far from the conservative forces
+    v0 = synth.maxwell_boltzmann(m, 300.0, 5000)
+    system = gpu_lib.DeviceSystem(s.pos, s.species, s.box)
+    prm = gpu_lib.respa_params(2.0, 4, 300.0, seed=4000, rewind_threshold=1.0, save_every=2, sts_after_rewind=8)
+    traj = gpu_lib.Trajectory(cons, bad, system, v0, m, np.ones(s.n), prm)
+    ke = torch.zeros(10, 1, dtype=torch.float64, device="cuda")
+    traj.respa_step(10, ke)
+    assert traj.n_rewinds >= 1
+    assert np.all(np.isfinite(traj.positions())) and np.all(np.isfinite(ke.cpu().numpy()))
