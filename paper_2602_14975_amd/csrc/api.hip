@@ -204,6 +204,12 @@ void carve_model(Arena& a, const Model* m, int64_t n, int64_t E, bool for_wgrad,
         b.s[l] = a.take<float>(n * F);
         b.v[l] = a.take<float>(n * 3 * F);
     }
+    const int64_t S = m->desc.n_species;
+    b.h1_tab = a.take<float>(S * F);
+    b.z_tab = a.take<float>(S * F);
+    b.phi_tab = a.take<float>(S * 3 * F);
+    b.gphi_tab = a.take<float>(S * 3 * F);
+    b.gh1_tab = a.take<float>(S * F);
     for (int l = 0; l < L; ++l) {
         LayerBuf& lb = b.layer[l];
         lb.h1 = a.take<float>(n * F);
@@ -256,25 +262,47 @@ void carve_model(Arena& a, const Model* m, int64_t n, int64_t E, bool for_wgrad,
     }
 }
 
-// Embedding forward: species embedding, then each layer's perceptron,
-// message and update block.  Every intermediate needed by the reverse pass
-// stays in `b`.
+// Embedding forward.  The first layer's perceptron input is the species
+// embedding, so its phi is evaluated once per species (a table of S rows);
+// the message kernel then reads phi_tab[t_j] and the zero vector input
+// implicitly.  Every intermediate needed by the reverse pass stays in `b`.
 void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, ModelBuf& b, hipStream_t s) {
     const int n = int(sys.n_atoms);
-    const int F = m->desc.width, K = m->desc.n_rbf;
+    const int F = m->desc.width, K = m->desc.n_rbf, S = m->desc.n_species;
     const int cut = m->desc.kind == NNP_MODEL_CONS ? 0 : 1;
-    launch_embed(n, F, m->desc.n_species, sys.species, m->p(m->off_emb), b.s[0], b.v[0], s);
     for (int l = 0; l < m->n_layers(); ++l) {
         const LayerOff& lo = m->loff[l];
         LayerBuf& lb = b.layer[l];
-        gemm_xwt(n, F, F, b.s[l], F, m->p(lo.W1), m->p(lo.b1), lb.zphi, F, EPI_SILU, lb.h1, F, false, s, m->bf16());
-        gemm_xwt(n, 3 * F, F, lb.zphi, F, m->p(lo.W2), m->p(lo.b2), lb.phi, 3 * F, EPI_NONE, nullptr, 0, false, s, m->bf16());
-        MpFwd a{b.s[l], b.v[l], lb.phi, m->p(lo.Wr), m->p(lo.br), lb.smid, lb.vmid};
+        MpFwd a{};
+        a.Wr = m->p(lo.Wr);
+        a.br = m->p(lo.br);
+        a.s_out = lb.smid;
+        a.v_out = lb.vmid;
+        if (l == 0) {
+            gemm_xwt(S, F, F, m->p(m->off_emb), F, m->p(lo.W1), m->p(lo.b1), b.z_tab, F, EPI_SILU, b.h1_tab, F,
+                     false, s, m->bf16());
+            gemm_xwt(S, 3 * F, F, b.z_tab, F, m->p(lo.W2), m->p(lo.b2), b.phi_tab, 3 * F, EPI_NONE, nullptr, 0,
+                     false, s, m->bf16());
+            a.species = sys.species;
+            a.phi_tab = b.phi_tab;
+            a.emb = m->p(m->off_emb);
+        } else {
+            gemm_xwt(n, F, F, b.s[l], F, m->p(lo.W1), m->p(lo.b1), lb.zphi, F, EPI_SILU, lb.h1, F, false, s,
+                     m->bf16());
+            gemm_xwt(n, 3 * F, F, lb.zphi, F, m->p(lo.W2), m->p(lo.b2), lb.phi, 3 * F, EPI_NONE, nullptr, 0, false,
+                     s, m->bf16());
+            a.s_in = b.s[l];
+            a.v_in = b.v[l];
+            a.phi = lb.phi;
+        }
         launch_message_fwd(F, K, cut, mg, a, s);
-        gemm_xwt(3 * n, 2 * F, F, lb.vmid, F, m->p(lo.U), nullptr, lb.UV, 2 * F, EPI_NONE, nullptr, 0, false, s, m->bf16());
+        gemm_xwt(3 * n, 2 * F, F, lb.vmid, F, m->p(lo.U), nullptr, lb.UV, 2 * F, EPI_NONE, nullptr, 0, false, s,
+                 m->bf16());
         launch_build_x(n, F, lb.smid, lb.UV, lb.X, s);
-        gemm_xwt(n, F, 2 * F, lb.X, 2 * F, m->p(lo.M1), m->p(lo.m1), lb.z, F, EPI_SILU, lb.a1, F, false, s, m->bf16());
-        gemm_xwt(n, 3 * F, F, lb.z, F, m->p(lo.M2), m->p(lo.m2), lb.pqo, 3 * F, EPI_NONE, nullptr, 0, false, s, m->bf16());
+        gemm_xwt(n, F, 2 * F, lb.X, 2 * F, m->p(lo.M1), m->p(lo.m1), lb.z, F, EPI_SILU, lb.a1, F, false, s,
+                 m->bf16());
+        gemm_xwt(n, 3 * F, F, lb.z, F, m->p(lo.M2), m->p(lo.m2), lb.pqo, 3 * F, EPI_NONE, nullptr, 0, false, s,
+                 m->bf16());
         launch_update_combine(n, F, lb.smid, lb.vmid, lb.UV, lb.pqo, b.s[l + 1], b.v[l + 1], s);
     }
 }
@@ -306,8 +334,6 @@ void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float*
     gemm_gw(3 * n, 2 * F, F, b.gUV, 2 * F, m->p(lo.U), b.gv, F, EPI_NONE, nullptr, 0, true, s,
             m->bf16());  // gv = g_vmid
     MpBwd a{};
-    a.v_in = b.v[l];
-    a.phi = lb.phi;
     a.gsm = b.gs2;
     a.gvm = b.gv;
     a.Wr = m->p(lo.Wr);
@@ -317,12 +343,40 @@ void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float*
     a.force = force;
     a.accum_force = accum_force;
     a.wgrad_part = wg ? b.mp_part : nullptr;
+    if (l == 0) {
+        a.species = mg.species;
+        a.phi_tab = b.phi_tab;
+        a.want_gphi = wg;  // forces alone need no adjoint of the first layer's input
+    } else {
+        a.v_in = b.v[l];
+        a.phi = lb.phi;
+        a.want_gphi = 1;
+    }
     launch_message_bwd(F, K, cut, mg, a, force != nullptr, wg, s);
     if (wg) {
         const int nb = mp_blocks(n, F);
         const int64_t cnt = int64_t(3) * F * (K + 1);
         launch_reduce_chunks(cnt, nb, b.mp_part, cnt, b.filt_sum, false, s);
         launch_split_filter_grad(3 * F, K, b.filt_sum, dtheta + lo.Wr, dtheta + lo.br, s);
+    }
+    if (l == 0) {
+        if (wg) {
+            // phi was evaluated per species: reduce its adjoints per species and
+            // differentiate the table; the embedding gets the pass-through
+            // adjoint of s plus the perceptron path.
+            const int S = m->desc.n_species;
+            launch_emb_grad(n, 3 * F, S, mg.species, b.gphi, b.gphi_tab, s);
+            gemm_wgrad(S, 3 * F, F, b.gphi_tab, 3 * F, b.z_tab, F, dtheta + lo.W2, b.chunk_part, kChunk, false, s);
+            colsum(S, 3 * F, b.gphi_tab, 3 * F, dtheta + lo.b2, b.chunk_part, kChunk, false, s);
+            gemm_gw(S, 3 * F, F, b.gphi_tab, 3 * F, m->p(lo.W2), b.gh1_tab, F, EPI_DSILU, b.h1_tab, F, false, s);
+            gemm_wgrad(S, F, F, b.gh1_tab, F, m->p(m->off_emb), F, dtheta + lo.W1, b.chunk_part, kChunk, false, s);
+            colsum(S, F, b.gh1_tab, F, dtheta + lo.b1, b.chunk_part, kChunk, false, s);
+            launch_emb_grad(n, F, S, mg.species, b.gs2, dtheta + m->off_emb, s);
+            gemm_gw(S, F, F, b.gh1_tab, F, m->p(lo.W1), dtheta + m->off_emb, F, EPI_NONE, nullptr, 0, true, s);
+        }
+        return;
+    }
+    if (wg) {
         gemm_wgrad(n, 3 * F, F, b.gphi, 3 * F, lb.zphi, F, dtheta + lo.W2, b.chunk_part, kChunk, false, s);
         colsum(n, 3 * F, b.gphi, 3 * F, dtheta + lo.b2, b.chunk_part, kChunk, false, s);
     }
@@ -340,6 +394,8 @@ MpGeom make_geom(const Model* m, const nnp_system& sys, const RepGeom& geom, con
     MpGeom mg{};
     mg.n = int(sys.n_atoms);
     mg.pos = sys.pos;
+    mg.species = sys.species;
+    mg.n_species = m->desc.n_species;
     mg.geom = geom;
     mg.off = nl.offsets;
     mg.nbr = nl.nbr;
@@ -374,6 +430,32 @@ void nc_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const n
     const int F = m->desc.width;
     const int HC = 2 * (m->desc.n_s + m->desc.n_l) * m->desc.n_c;
     MpGeom mg = make_geom(m, sys, geom, nl);
+    if (F <= 32) {
+        // inference: species-table perceptron, message, then one fused kernel
+        // for the update block and the projections (no intermediates kept)
+        const int K = m->desc.n_rbf, S = m->desc.n_species;
+        const LayerOff& lo = m->loff[0];
+        LayerBuf& lb = b.layer[0];
+        gemm_xwt(S, F, F, m->p(m->off_emb), F, m->p(lo.W1), m->p(lo.b1), b.z_tab, F, EPI_SILU, b.h1_tab, F, false,
+                 s, m->bf16());
+        gemm_xwt(S, 3 * F, F, b.z_tab, F, m->p(lo.W2), m->p(lo.b2), b.phi_tab, 3 * F, EPI_NONE, nullptr, 0, false,
+                 s, m->bf16());
+        MpFwd a{};
+        a.Wr = m->p(lo.Wr);
+        a.br = m->p(lo.br);
+        a.s_out = lb.smid;
+        a.v_out = lb.vmid;
+        a.species = sys.species;
+        a.phi_tab = b.phi_tab;
+        a.emb = m->p(m->off_emb);
+        launch_message_fwd(F, K, 1, mg, a, s);
+        NcUpdateArgs u{n, lb.smid, lb.vmid, m->p(lo.U), m->p(lo.M1), m->p(lo.m1), m->p(lo.M2), m->p(lo.m2),
+                       m->p(m->off_Wq), m->p(m->off_WV), b.QK, b.Vh};
+        if (launch_nc_update_proj(u, F, m->bf16(), s)) {
+            launch_head_fwd(mg, b.QK, b.Vh, forces, false, s);
+            return;
+        }
+    }
     embed_forward(m, sys, mg, b, s);
     gemm_xwt(n, HC, F, b.s[1], F, m->p(m->off_Wq), nullptr, b.QK, HC, EPI_NONE, nullptr, 0, false, s, m->bf16());
     gemm_xwt(3 * n, m->desc.n_l, F, b.v[1], F, m->p(m->off_WV), nullptr, b.Vh, m->desc.n_l, EPI_NONE, nullptr, 0,
@@ -397,7 +479,6 @@ void nc_wgrad(const Model* m, const nnp_system& sys, const RepGeom& geom, const 
     gemm_wgrad(3 * n, nl_, F, b.gVh, nl_, b.v[1], F, dtheta + m->off_WV, b.chunk_part, kChunk, false, s);
     gemm_gw(3 * n, nl_, F, b.gVh, nl_, m->p(m->off_WV), b.gv, F, EPI_NONE, nullptr, 0, false, s, m->bf16());
     layer_backward(m, 0, mg, b, nullptr, false, dtheta, s);
-    launch_emb_grad(n, F, m->desc.n_species, sys.species, b.gs, dtheta + m->off_emb, s);
 }
 
 }  // namespace nnp
@@ -701,9 +782,12 @@ void check_respa(const respa_state* st, const respa_params* p, const Model* cons
 }
 
 // Per-replica disagreement sqrt(mean_i |F_i - F_fast,i|^2), fixed-order
-// float64 reduction, one block per replica.
+// float64 reduction, one block per replica.  Non-finite positions or
+// velocities count as infinite disagreement (such atoms leave every
+// neighbour list, so their forces alone would not show the failure).
 __global__ void __launch_bounds__(256) k_disagreement(const int64_t* __restrict__ rep_start, int n,
                                                       const float* __restrict__ fa, const float* __restrict__ fb,
+                                                      const double* __restrict__ pos, const double* __restrict__ vel,
                                                       double* __restrict__ out) {
     __shared__ double red[256];
     const int r = blockIdx.x;
@@ -713,6 +797,7 @@ __global__ void __launch_bounds__(256) k_disagreement(const int64_t* __restrict_
         for (int c = 0; c < 3; ++c) {
             const double d = double(fa[c * int64_t(n) + i]) - double(fb[c * int64_t(n) + i]);
             acc += d * d;
+            if (!isfinite(pos[c * int64_t(n) + i]) || !isfinite(vel[c * int64_t(n) + i])) acc = INFINITY;
         }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -925,7 +1010,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         else sts_step(D);
         ++since_save;
         if (rewind) {
-            k_disagreement<<<R, 256, 0, s>>>(c.t.rep_start, n, st->f_cons, st->f_nc, disagree);
+            k_disagreement<<<R, 256, 0, s>>>(c.t.rep_start, n, st->f_cons, st->f_nc, st->pos, st->vel, disagree);
             NNP_LAUNCH_CHECK();
             NNP_HIP(hipMemcpyAsync(dis.data(), disagree, sizeof(double) * R, hipMemcpyDeviceToHost, s));
             NNP_HIP(hipStreamSynchronize(s));

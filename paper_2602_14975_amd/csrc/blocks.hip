@@ -2,6 +2,8 @@
 // the non-conservative pair head (paper, Methods: q_ih, k_ih, c_ijh, F_ij,
 // F_i = sum_j (F_ij - F_ji)).  The dense contractions around them run in
 // gemm.hip; the edge loops of the embedding in mp.hip.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -141,16 +143,17 @@ __global__ void __launch_bounds__(256) k_rep_sum(const int64_t* __restrict__ rep
     if (threadIdx.x == 0) out[r] = red[0];
 }
 
-// Species-embedding adjoint: g_emb[t][f] = sum over atoms of species t of g_s0[i][f] (fixed order).
+// Per-species column sums: out[t][f] = sum over atoms of species t of x[i][f]
+// (fixed order), for the adjoints of per-species tables.
 __global__ void k_emb_grad(int n, int F, int S, const int* __restrict__ species, const float* __restrict__ gs0,
                            float* __restrict__ gemb) {
-    int t = blockIdx.x;   // species
-    int f = threadIdx.x;  // feature (blockDim >= F)
-    if (f >= F) return;
-    float acc = 0.f;
-    for (int i = 0; i < n; ++i)
-        if (species[i] == t) acc += gs0[int64_t(i) * F + f];
-    gemb[t * F + f] = acc;
+    const int t = blockIdx.x;  // species
+    for (int f = threadIdx.x; f < F; f += blockDim.x) {
+        float acc = 0.f;
+        for (int i = 0; i < n; ++i)
+            if (species[i] == t) acc += gs0[int64_t(i) * F + f];
+        gemb[t * F + f] = acc;
+    }
 }
 
 // ------------------------------------------------------------- NC head ----
@@ -393,6 +396,144 @@ __global__ void __launch_bounds__(64) k_head_bwd(MpGeom mg, const float* __restr
         const int h = lane / 3, a = lane % 3;
         gVh[(int64_t(i) * 3 + a) * kNl + h] = gv_acc;
     }
+}
+
+// ------------------------------------------------- fused NC update block --
+// Update block of the one-layer NC embedding followed by its q/k and vector
+// projections, for widths F <= 32: per atom, one lane per feature column.
+// Weights are staged transposed in LDS once per block ([in][out], so the
+// lanes of a group read consecutive addresses) and the block walks over
+// groups of atoms.  With BF16, weights and every perceptron input are
+// rounded to bfloat16 and products accumulate in float32, as in the MFMA
+// GEMMs of the general path.
+__device__ __forceinline__ float bf16_round(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xFFFF0000u);
+}
+
+template <int F, bool BF16>
+__global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
+    constexpr int HC = 2 * kH * kNc;  // q and k outputs
+    constexpr int APB = 256 / F;      // atoms per block pass
+    extern __shared__ float lds[];
+    float* UVt = lds;                  // [F][2F]   (U; V)^T
+    float* M1t = UVt + 2 * F * F;      // [2F][F]
+    float* M2t = M1t + 2 * F * F;      // [F][3F]
+    float* Qt = M2t + 3 * F * F;       // [F][HC]
+    float* Vt = Qt + F * HC;           // [F][kNl]
+    float* m1 = Vt + F * kNl;          // [F]
+    float* m2 = m1 + F;                // [3F]
+    float* work = m2 + 3 * F;          // per atom: sm[F], vm[3F], x[2F], z[F], so[F], vo[3F]
+    auto rnd = [](float x) { return BF16 ? bf16_round(x) : x; };
+    for (int t = threadIdx.x; t < 2 * F * F; t += 256) {
+        const int o = t / F, k = t % F;  // UV[o][k], o < 2F
+        UVt[k * 2 * F + o] = rnd(a.UV[t]);
+        const int o1 = t / (2 * F), k1 = t % (2 * F);  // M1[o1][k1]
+        M1t[k1 * F + o1] = rnd(a.M1[t]);
+    }
+    for (int t = threadIdx.x; t < 3 * F * F; t += 256) {
+        const int o = t / F, k = t % F;
+        M2t[k * 3 * F + o] = rnd(a.M2[t]);
+    }
+    for (int t = threadIdx.x; t < HC * F; t += 256) {
+        const int o = t / F, k = t % F;
+        Qt[k * HC + o] = rnd(a.Wqk[t]);
+    }
+    for (int t = threadIdx.x; t < kNl * F; t += 256) {
+        const int o = t / F, k = t % F;
+        Vt[k * kNl + o] = rnd(a.WV[t]);
+    }
+    for (int t = threadIdx.x; t < F; t += 256) m1[t] = a.m1[t];
+    for (int t = threadIdx.x; t < 3 * F; t += 256) m2[t] = a.m2[t];
+    const int g = threadIdx.x / F, f = threadIdx.x % F;
+    float* sm = work + g * 11 * F;
+    float* vm = sm + F;
+    float* x = vm + 3 * F;
+    float* z = x + 2 * F;
+    float* so = z + F;
+    float* vo = so + F;
+    const int n = a.n;
+    for (int base = blockIdx.x * APB; base < n; base += gridDim.x * APB) {
+        const int i = base + g;
+        const bool act = i < n;
+        __syncthreads();  // weights staged / previous pass done with the work rows
+        sm[f] = act ? a.smid[int64_t(i) * F + f] : 0.f;
+#pragma unroll
+        for (int al = 0; al < 3; ++al) vm[al * F + f] = act ? a.vmid[(int64_t(i) * 3 + al) * F + f] : 0.f;
+        __syncthreads();
+        float Uv[3] = {}, Vv[3] = {};
+        for (int k = 0; k < F; ++k) {
+            const float uw = UVt[k * 2 * F + f], vw = UVt[k * 2 * F + F + f];
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+                const float vk = rnd(vm[al * F + k]);
+                Uv[al] = fmaf(uw, vk, Uv[al]);
+                Vv[al] = fmaf(vw, vk, Vv[al]);
+            }
+        }
+        float nn = 1e-8f;
+#pragma unroll
+        for (int al = 0; al < 3; ++al) nn = fmaf(Vv[al], Vv[al], nn);
+        x[f] = sm[f];
+        x[F + f] = sqrtf(nn);
+        __syncthreads();
+        float a1 = m1[f];
+        for (int k = 0; k < 2 * F; ++k) a1 = fmaf(M1t[k * F + f], rnd(x[k]), a1);
+        z[f] = silu(a1);
+        __syncthreads();
+        float pq[3] = {m2[f], m2[F + f], m2[2 * F + f]};
+        for (int k = 0; k < F; ++k) {
+            const float zk = rnd(z[k]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pq[c] = fmaf(M2t[k * 3 * F + c * F + f], zk, pq[c]);
+        }
+        const float dot = Uv[0] * Vv[0] + Uv[1] * Vv[1] + Uv[2] * Vv[2];
+        so[f] = sm[f] + pq[0] + pq[1] * dot;
+#pragma unroll
+        for (int al = 0; al < 3; ++al) vo[al * F + f] = vm[al * F + f] + pq[2] * Uv[al];
+        __syncthreads();
+        if (act) {
+            for (int c = f; c < HC; c += F) {
+                float acc = 0.f;
+                for (int k = 0; k < F; ++k) acc = fmaf(Qt[k * HC + c], rnd(so[k]), acc);
+                a.QK[int64_t(i) * HC + c] = acc;
+            }
+            if (f < 3 * kNl) {
+                const int h = f / 3, al = f % 3;
+                float acc = 0.f;
+                for (int k = 0; k < F; ++k) acc = fmaf(Vt[k * kNl + h], rnd(vo[al * F + k]), acc);
+                a.Vh[(int64_t(i) * 3 + al) * kNl + h] = acc;
+            }
+        }
+    }
+}
+
+size_t nc_update_lds_bytes(int F) {
+    const int HC = 2 * kH * kNc;
+    return sizeof(float) * (size_t(2 * F * F + 2 * F * F + 3 * F * F + F * HC + F * kNl + F + 3 * F) +
+                            size_t(256 / F) * 11 * F);
+}
+
+bool launch_nc_update_proj(const NcUpdateArgs& a, int F, bool bf16, hipStream_t st) {
+    if (a.n <= 0) return true;
+    const size_t lds = nc_update_lds_bytes(F);
+    const int blocks = std::min(cdiv(a.n, 256 / F), 1024);
+    ScopedTimer timer("nc_update", st);
+    if (F == 32) {
+        if (bf16) k_nc_update_proj<32, true><<<blocks, 256, lds, st>>>(a);
+        else k_nc_update_proj<32, false><<<blocks, 256, lds, st>>>(a);
+    } else if (F == 16) {
+        if (bf16) k_nc_update_proj<16, true><<<blocks, 256, lds, st>>>(a);
+        else k_nc_update_proj<16, false><<<blocks, 256, lds, st>>>(a);
+    } else if (F == 8) {
+        if (bf16) k_nc_update_proj<8, true><<<blocks, 256, lds, st>>>(a);
+        else k_nc_update_proj<8, false><<<blocks, 256, lds, st>>>(a);
+    } else {
+        return false;
+    }
+    NNP_LAUNCH_CHECK();
+    return true;
 }
 
 // ------------------------------------------------------------------- host --

@@ -80,6 +80,8 @@ void colsum(int M, int N, const float* G, int ldg, float* db, float* scratch, in
 struct MpGeom {
     int n;
     const double* pos;
+    const int* species;
+    int n_species;  // species indices are clamped to [0, n_species) before any table lookup
     RepGeom geom;
     const int* off;
     const int* nbr;
@@ -89,11 +91,18 @@ struct MpGeom {
 struct MpFwd {
     const float *s_in, *v_in, *phi, *Wr, *br;
     float *s_out, *v_out;
+    // first layer: inputs are s = emb[t], v = 0, and phi = phi_tab[t] per species
+    const int* species;
+    const float* phi_tab;  // [S][3F] or nullptr
+    const float* emb;      // [S][F]
 };
 
 struct MpBwd {
     const float *v_in, *phi, *gsm, *gvm, *Wr, *br;
     float *gphi, *gv_in;
+    const int* species;
+    const float* phi_tab;  // first layer: phi = phi_tab[t], v_in = 0 (gv_in is not written)
+    int want_gphi;         // write the phi adjoints
     float* force;       // [3][n] forces -dE/dx (GEO): written, or added to with accum_force
     int accum_force;
     float* wgrad_part;  // [blocks][3F][K + 1] filter weight adjoints (WGRAD)
@@ -121,6 +130,16 @@ void launch_emb_grad(int n, int F, int S, const int* species, const float* gs0, 
 void launch_head_fwd(const MpGeom& mg, const float* QK, const float* Vh, float* F, bool accum, hipStream_t st);
 void launch_head_bwd(const MpGeom& mg, const float* QK, const float* Vh, const float* gF, float* gQK, float* gVh,
                      hipStream_t st);
+
+struct NcUpdateArgs {
+    int n;
+    const float *smid, *vmid;                          // message outputs [n][F], [n][3][F]
+    const float *UV, *M1, *m1, *M2, *m2, *Wqk, *WV;     // layer and projection weights (manifest layout)
+    float *QK, *Vh;                                    // [n][2 H n_c], [n][3][n_l]
+};
+// Fused update block + q/k/V projections of the NC embedding (widths <= 32);
+// returns false when the width is not supported by the fused kernel.
+bool launch_nc_update_proj(const NcUpdateArgs& a, int F, bool bf16, hipStream_t st);
 
 // -------------------------------------------------------------- integrator
 struct BaoaArgs {

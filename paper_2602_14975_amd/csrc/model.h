@@ -41,6 +41,8 @@ struct ModelBuf {
     float *gs = nullptr, *gs2 = nullptr, *gv = nullptr, *gv2 = nullptr, *gpqo = nullptr, *ga1 = nullptr,
           *gX = nullptr, *gUV = nullptr, *gphi = nullptr, *gh1 = nullptr;
     float *chunk_part = nullptr, *mp_part = nullptr, *filt_sum = nullptr;
+    // first layer per species: pre-activation, hidden, phi, and adjoints
+    float *h1_tab = nullptr, *z_tab = nullptr, *phi_tab = nullptr, *gphi_tab = nullptr, *gh1_tab = nullptr;
 };
 
 struct SysTables {

@@ -46,7 +46,7 @@ struct EdgeSlot {
     float fc, dfc;  // f(r), f'(r)
     float u[3];
     float ir;       // 1 / r
-    int j, e;
+    int j, e, t;    // neighbour, CSR entry, neighbour species
 };
 
 // Radial values of one edge: float64 Chebyshev recurrence for sin(k theta)
@@ -98,7 +98,8 @@ __device__ __forceinline__ void wave_sync_lds() {
 // into LDS; returns the number of surviving edges of this group.
 template <int G, int K, int CUT, bool DERIV>
 __device__ __forceinline__ int stage_batch(const MpGeom& mg, bool active, int e, int e_end, int l, int g, double xi,
-                                           double yi, double zi, double L, double inv, EdgeSlot<K>* slots) {
+                                           double yi, double zi, double L, double inv, EdgeSlot<K>* slots,
+                                           const int* species) {
     bool ok = false;
     double dx = 0, dy = 0, dz = 0;
     int j = -1;
@@ -122,6 +123,7 @@ __device__ __forceinline__ int stage_batch(const MpGeom& mg, bool active, int e,
         s.ir = float(ir);
         s.j = j;
         s.e = e;
+        s.t = species ? min(max(species[j], 0), mg.n_species - 1) : 0;
     }
     wave_sync_lds();
     return __popcll(mine);
@@ -167,7 +169,7 @@ struct MpShape {
     static constexpr int APB = kMpWaves / WPA * APW;   // atoms per block
 };
 
-template <int F, int K, int CUT>
+template <int F, int K, int CUT, bool L0>
 __global__ void __launch_bounds__(64 * kMpWaves)
 k_message_fwd(MpGeom mg, MpFwd a) {
     using S = MpShape<F>;
@@ -201,42 +203,56 @@ k_message_fwd(MpGeom mg, MpFwd a) {
         xi = mg.pos[i]; yi = mg.pos[n + i]; zi = mg.pos[2 * n + i];
     }
     for (int base = 0; __ballot(start + base < end) != 0ull; base += G) {
-        const int cnt =
-            stage_batch<G, K, CUT, false>(mg, active, start + base + l, end, l, g, xi, yi, zi, L, inv, slots);
+        const int cnt = stage_batch<G, K, CUT, false>(mg, active, start + base + l, end, l, g, xi, yi, zi, L, inv,
+                                                       slots, L0 ? a.species : nullptr);
         for (int t = 0; t < cnt; ++t) {
             const EdgeSlot<K>& s = slots[t];
-            const float* phj = a.phi + int64_t(s.j) * 3 * F + f0;
-            const float* vj = a.v_in + int64_t(s.j) * 3 * F + f0;
+            const float* phj = L0 ? a.phi_tab + s.t * 3 * F + f0 : a.phi + int64_t(s.j) * 3 * F + f0;
             const Vec<FPL> pa = ldv<FPL>(phj), pb = ldv<FPL>(phj + F), pc = ldv<FPL>(phj + 2 * F);
-            const Vec<FPL> v0 = ldv<FPL>(vj), v1 = ldv<FPL>(vj + F), v2 = ldv<FPL>(vj + 2 * F);
+            Vec<FPL> v0{}, v1{}, v2{};
+            if (!L0) {  // the first layer's vector input is zero
+                const float* vj = a.v_in + int64_t(s.j) * 3 * F + f0;
+                v0 = ldv<FPL>(vj);
+                v1 = ldv<FPL>(vj + F);
+                v2 = ldv<FPL>(vj + 2 * F);
+            }
 #pragma unroll
             for (int q = 0; q < FPL; ++q) {
                 float wa = bb[0][q] * s.fc, wb = bb[1][q] * s.fc, wc = bb[2][q] * s.fc;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     wa = fmaf(wr[0][q][k], s.ef[k], wa);
-                    wb = fmaf(wr[1][q][k], s.ef[k], wb);
+                    if (!L0) wb = fmaf(wr[1][q][k], s.ef[k], wb);
                     wc = fmaf(wr[2][q][k], s.ef[k], wc);
                 }
-                const float b = pb.x[q] * wb, c = pc.x[q] * wc;
+                const float c = pc.x[q] * wc;
                 sacc[q] = fmaf(pa.x[q], wa, sacc[q]);
-                vacc[0][q] += b * v0.x[q] + s.u[0] * c;
-                vacc[1][q] += b * v1.x[q] + s.u[1] * c;
-                vacc[2][q] += b * v2.x[q] + s.u[2] * c;
+                if (L0) {
+                    vacc[0][q] += s.u[0] * c;
+                    vacc[1][q] += s.u[1] * c;
+                    vacc[2][q] += s.u[2] * c;
+                } else {
+                    const float b = pb.x[q] * wb;
+                    vacc[0][q] += b * v0.x[q] + s.u[0] * c;
+                    vacc[1][q] += b * v1.x[q] + s.u[1] * c;
+                    vacc[2][q] += b * v2.x[q] + s.u[2] * c;
+                }
             }
         }
         wave_sync_lds();
     }
     if (active) {
         float out[FPL];
-        const Vec<FPL> si = ldv<FPL>(a.s_in + int64_t(i) * F + f0);
+        const int ti = L0 ? min(max(a.species[i], 0), mg.n_species - 1) : 0;
+        const Vec<FPL> si = ldv<FPL>(L0 ? a.emb + ti * F + f0 : a.s_in + int64_t(i) * F + f0);
 #pragma unroll
         for (int q = 0; q < FPL; ++q) out[q] = si.x[q] + sacc[q];
         stv<FPL>(a.s_out + int64_t(i) * F + f0, out);
 #pragma unroll
         for (int al = 0; al < 3; ++al) {
             const int64_t idx = (int64_t(i) * 3 + al) * F + f0;
-            const Vec<FPL> vi = ldv<FPL>(a.v_in + idx);
+            Vec<FPL> vi{};
+            if (!L0) vi = ldv<FPL>(a.v_in + idx);
 #pragma unroll
             for (int q = 0; q < FPL; ++q) out[q] = vi.x[q] + vacc[al][q];
             stv<FPL>(a.v_out + idx, out);
@@ -244,7 +260,7 @@ k_message_fwd(MpGeom mg, MpFwd a) {
     }
 }
 
-template <int F, int K, int CUT, bool GEO, bool WGRAD>
+template <int F, int K, int CUT, bool GEO, bool WGRAD, bool L0>
 __global__ void __launch_bounds__(64 * kMpWaves, 2)
 k_message_bwd(MpGeom mg, MpBwd a) {
     using S = MpShape<F>;
@@ -283,7 +299,8 @@ k_message_bwd(MpGeom mg, MpBwd a) {
         end = mg.off[i + 1];
         mg.geom.get(i, L, inv);
         xi = mg.pos[i]; yi = mg.pos[n + i]; zi = mg.pos[2 * n + i];
-        const float* pho = a.phi + int64_t(i) * 3 * F + f0;
+        const int ti = L0 ? min(max(a.species[i], 0), mg.n_species - 1) : 0;
+        const float* pho = L0 ? a.phi_tab + ti * 3 * F + f0 : a.phi + int64_t(i) * 3 * F + f0;
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
             const Vec<FPL> t = ldv<FPL>(pho + p * F);
@@ -292,7 +309,8 @@ k_message_bwd(MpGeom mg, MpBwd a) {
         }
 #pragma unroll
         for (int al = 0; al < 3; ++al) {
-            const Vec<FPL> tv = ldv<FPL>(a.v_in + (int64_t(i) * 3 + al) * F + f0);
+            Vec<FPL> tv{};
+            if (!L0) tv = ldv<FPL>(a.v_in + (int64_t(i) * 3 + al) * F + f0);
             const Vec<FPL> tg = ldv<FPL>(a.gvm + (int64_t(i) * 3 + al) * F + f0);
 #pragma unroll
             for (int q = 0; q < FPL; ++q) {
@@ -305,16 +323,21 @@ k_message_bwd(MpGeom mg, MpBwd a) {
         for (int q = 0; q < FPL; ++q) gs_o[q] = tg.x[q];
     }
     for (int base = 0; __ballot(start + base < end) != 0ull; base += G) {
-        const int cnt =
-            stage_batch<G, K, CUT, GEO>(mg, active, start + base + l, end, l, g, xi, yi, zi, L, inv, slots);
+        const int cnt = stage_batch<G, K, CUT, GEO>(mg, active, start + base + l, end, l, g, xi, yi, zi, L, inv,
+                                                     slots, L0 ? a.species : nullptr);
         for (int t = 0; t < cnt; ++t) {
             const EdgeSlot<K>& s = slots[t];
             const int j = s.j;
-            const float* phj = a.phi + int64_t(j) * 3 * F + f0;
-            const float* vj = a.v_in + int64_t(j) * 3 * F + f0;
+            const float* phj = L0 ? a.phi_tab + s.t * 3 * F + f0 : a.phi + int64_t(j) * 3 * F + f0;
             const float* gvj = a.gvm + int64_t(j) * 3 * F + f0;
             const Vec<FPL> pa = ldv<FPL>(phj), pb = ldv<FPL>(phj + F), pc = ldv<FPL>(phj + 2 * F);
-            const Vec<FPL> vj0 = ldv<FPL>(vj), vj1 = ldv<FPL>(vj + F), vj2 = ldv<FPL>(vj + 2 * F);
+            Vec<FPL> vj0{}, vj1{}, vj2{};
+            if (!L0) {  // the first layer's vector input is zero
+                const float* vj = a.v_in + int64_t(j) * 3 * F + f0;
+                vj0 = ldv<FPL>(vj);
+                vj1 = ldv<FPL>(vj + F);
+                vj2 = ldv<FPL>(vj + 2 * F);
+            }
             const Vec<FPL> g0 = ldv<FPL>(gvj), g1 = ldv<FPL>(gvj + F), g2 = ldv<FPL>(gvj + 2 * F);
             const Vec<FPL> gsn = ldv<FPL>(a.gsm + int64_t(j) * F + f0);
             const float u0 = s.u[0], u1 = s.u[1], u2 = s.u[2];
@@ -416,13 +439,17 @@ k_message_bwd(MpGeom mg, MpBwd a) {
     }
     if (active) {
         float out[FPL];
+        if (a.want_gphi) {
 #pragma unroll
-        for (int p = 0; p < 3; ++p) stv<FPL>(a.gphi + int64_t(i) * 3 * F + p * F + f0, gph[p]);
+            for (int p = 0; p < 3; ++p) stv<FPL>(a.gphi + int64_t(i) * 3 * F + p * F + f0, gph[p]);
+        }
+        if (!L0) {
 #pragma unroll
-        for (int al = 0; al < 3; ++al) {
+            for (int al = 0; al < 3; ++al) {
 #pragma unroll
-            for (int q = 0; q < FPL; ++q) out[q] = gv_o[al][q] + gvacc[al][q];
-            stv<FPL>(a.gv_in + (int64_t(i) * 3 + al) * F + f0, out);
+                for (int q = 0; q < FPL; ++q) out[q] = gv_o[al][q] + gvacc[al][q];
+                stv<FPL>(a.gv_in + (int64_t(i) * 3 + al) * F + f0, out);
+            }
         }
     }
     if (WGRAD) {
@@ -452,17 +479,19 @@ k_message_bwd(MpGeom mg, MpBwd a) {
 
 template <int F, int K, int CUT>
 static void fwd_inst(const MpGeom& mg, const MpFwd& a, hipStream_t s) {
-    k_message_fwd<F, K, CUT><<<cdiv(mg.n, MpShape<F>::APB), 64 * kMpWaves, 0, s>>>(mg, a);
+    const dim3 grid(cdiv(mg.n, MpShape<F>::APB));
+    if (a.phi_tab) k_message_fwd<F, K, CUT, true><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
+    else k_message_fwd<F, K, CUT, false><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
 }
 
-template <int F, int K, int CUT>
-static void bwd_inst(const MpGeom& mg, const MpBwd& a, bool geo, bool wgrad, hipStream_t s) {
+template <int F, int K, int CUT, bool L0>
+static void bwd_inst_l(const MpGeom& mg, const MpBwd& a, bool geo, bool wgrad, hipStream_t s) {
     dim3 grid(cdiv(mg.n, MpShape<F>::APB));
     if constexpr (CUT == 1 && F <= 64) {
         // filter weight adjoints exist for the NC embedding only
         if (wgrad) {
-            if (geo) k_message_bwd<F, K, CUT, true, true><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
-            else k_message_bwd<F, K, CUT, false, true><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
+            if (geo) k_message_bwd<F, K, CUT, true, true, L0><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
+            else k_message_bwd<F, K, CUT, false, true, L0><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
             return;
         }
     } else {
@@ -471,8 +500,14 @@ static void bwd_inst(const MpGeom& mg, const MpBwd& a, bool geo, bool wgrad, hip
             throw Fail{NNP_EINVAL};
         }
     }
-    if (geo) k_message_bwd<F, K, CUT, true, false><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
-    else k_message_bwd<F, K, CUT, false, false><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
+    if (geo) k_message_bwd<F, K, CUT, true, false, L0><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
+    else k_message_bwd<F, K, CUT, false, false, L0><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
+}
+
+template <int F, int K, int CUT>
+static void bwd_inst(const MpGeom& mg, const MpBwd& a, bool geo, bool wgrad, hipStream_t s) {
+    if (a.phi_tab) bwd_inst_l<F, K, CUT, true>(mg, a, geo, wgrad, s);
+    else bwd_inst_l<F, K, CUT, false>(mg, a, geo, wgrad, s);
 }
 
 int mp_blocks(int n, int F) {

@@ -128,6 +128,24 @@ def test_nc_forces_water(gpu_lib, which, spec):
     assert np.linalg.norm(f.sum(0)) <= 1e-5 * np.abs(f).sum()
 
 
+@pytest.mark.parametrize("width", [8, 64])
+def test_nc_other_widths_ragged(gpu_lib, width):
+    """Width 8 takes the fused update/projection kernel, width 64 the
+    general GEMM sequence."""
+    from paper_2602_14975_amd.nnp import DeviceSystem, workspace
+    spec = ModelSpec("nc", width, 1, 8, 3.5)
+    pos, species, box = small_box(11 + width, n=101, box=11.5)
+    w = synth.random_weights(spec, 300 + width)
+    m = gpu_lib.Model.from_spec(spec, w)
+    system = DeviceSystem(pos, species, box)
+    nl = gpu_list(gpu_lib, system, 3.5)
+    ws = workspace(None, m, system.n, 1, nl.capacity)
+    f = gpu_lib.nnp_nc_forces(m, system, nl, ws).cpu().numpy().T.astype(np.float64)
+    off, nbr = oracle_list(pos, box, spec.cutoff)
+    F = om.nc_forces(spec, w, pos, species, box, off, nbr)
+    assert rel_rmse(f, F) <= FP32_TOL
+
+
 def test_nc_weight_gradient(gpu_lib):
     from paper_2602_14975_amd.nnp import DeviceSystem, workspace
     spec = synth.NC_CFG1
