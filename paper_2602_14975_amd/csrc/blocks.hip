@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
     __shared__ float contrib[4][64][3];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int i = blockIdx.x * 4 + w;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
     if (i >= mg.n) return;  // whole wavefront
     const int n = mg.n;
     double L, inv;
@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(64) k_head_bwd(MpGeom mg, const float* __restr
     __shared__ int jj[64];
     __shared__ float gvc[64][kNl * 3];  // per-entry V adjoint contributions (sweep 0)
     const int lane = threadIdx.x;
-    const int i = blockIdx.x;
+    const int i = xcd_block(blockIdx.x, gridDim.x);
     const int n = mg.n;
     double L, inv;
     mg.geom.get(i, L, inv);
@@ -426,23 +426,24 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
     float* m2 = m1 + F;                // [3F]
     float* work = m2 + 3 * F;          // per atom: sm[F], vm[3F], x[2F], z[F], so[F], vo[3F]
     auto rnd = [](float x) { return BF16 ? bf16_round(x) : x; };
+    // transposed copies: consecutive threads write consecutive LDS words
     for (int t = threadIdx.x; t < 2 * F * F; t += 256) {
-        const int o = t / F, k = t % F;  // UV[o][k], o < 2F
-        UVt[k * 2 * F + o] = rnd(a.UV[t]);
-        const int o1 = t / (2 * F), k1 = t % (2 * F);  // M1[o1][k1]
-        M1t[k1 * F + o1] = rnd(a.M1[t]);
+        const int k = t / (2 * F), o = t % (2 * F);  // UVt[k][o] = UV[o][k], k < F
+        UVt[t] = rnd(a.UV[o * F + k]);
+        const int k1 = t / F, o1 = t % F;  // M1t[k1][o1] = M1[o1][k1], k1 < 2F
+        M1t[t] = rnd(a.M1[o1 * 2 * F + k1]);
     }
     for (int t = threadIdx.x; t < 3 * F * F; t += 256) {
-        const int o = t / F, k = t % F;
-        M2t[k * 3 * F + o] = rnd(a.M2[t]);
+        const int k = t / (3 * F), o = t % (3 * F);
+        M2t[t] = rnd(a.M2[o * F + k]);
     }
     for (int t = threadIdx.x; t < HC * F; t += 256) {
-        const int o = t / F, k = t % F;
-        Qt[k * HC + o] = rnd(a.Wqk[t]);
+        const int k = t / HC, o = t % HC;
+        Qt[t] = rnd(a.Wqk[o * F + k]);
     }
     for (int t = threadIdx.x; t < kNl * F; t += 256) {
-        const int o = t / F, k = t % F;
-        Vt[k * kNl + o] = rnd(a.WV[t]);
+        const int k = t / kNl, o = t % kNl;
+        Vt[t] = rnd(a.WV[o * F + k]);
     }
     for (int t = threadIdx.x; t < F; t += 256) m1[t] = a.m1[t];
     for (int t = threadIdx.x; t < 3 * F; t += 256) m2[t] = a.m2[t];
@@ -518,7 +519,8 @@ size_t nc_update_lds_bytes(int F) {
 bool launch_nc_update_proj(const NcUpdateArgs& a, int F, bool bf16, hipStream_t st) {
     if (a.n <= 0) return true;
     const size_t lds = nc_update_lds_bytes(F);
-    const int blocks = std::min(cdiv(a.n, 256 / F), 1024);
+    // two blocks per CU fit the LDS of the widest case; each walks several passes
+    const int blocks = std::min(cdiv(a.n, 256 / F), 512);
     ScopedTimer timer("nc_update", st);
     if (F == 32) {
         if (bf16) k_nc_update_proj<32, true><<<blocks, 256, lds, st>>>(a);

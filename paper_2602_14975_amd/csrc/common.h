@@ -99,6 +99,17 @@ struct RepGeom {
 };
 
 // ------------------------------------------------------------- wave utils --
+// Workgroups of one launch are dealt out to the 8 XCDs in turn (hardware id b
+// runs on XCD b % 8).  This bijection of [0, G) hands each XCD one contiguous
+// range of logical ids instead, so that rows of spatially ordered atoms (and
+// the neighbours they gather) stay within one XCD's L2.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+    constexpr int X = 8;
+    const int x = b % X, local = b / X;
+    const int per = G / X, rem = G % X;
+    return x < rem ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+}
+
 __device__ __forceinline__ float wave_sum(float x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);

@@ -177,7 +177,8 @@ k_message_fwd(MpGeom mg, MpFwd a) {
     __shared__ EdgeSlot<K> slots_all[kMpWaves][APW][G];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane / G, l = lane % G;
-    const int i = blockIdx.x * S::APB + (w / WPA) * APW + g;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int i = blk * S::APB + (w / WPA) * APW + g;
     const bool active = i < mg.n;
     const int n = mg.n;
     const int f0 = (w % WPA) * 64 + l;
@@ -270,7 +271,8 @@ k_message_bwd(MpGeom mg, MpBwd a) {
     __shared__ float fpart[kMpWaves][APW][3];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane / G, l = lane % G;
-    const int i = blockIdx.x * S::APB + (w / WPA) * APW + g;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int i = blk * S::APB + (w / WPA) * APW + g;
     const bool active = i < mg.n;
     const int n = mg.n;
     const int f0 = (w % WPA) * 64 + l;
@@ -470,7 +472,7 @@ k_message_bwd(MpGeom mg, MpBwd a) {
         for (int t = threadIdx.x; t < 3 * F * (K + 1); t += blockDim.x) {
             float sum = 0.f;
             for (int sl = 0; sl < kMpWaves * APW; ++sl) sum += red[sl][t];
-            a.wgrad_part[int64_t(blockIdx.x) * 3 * F * (K + 1) + t] = sum;
+            a.wgrad_part[int64_t(blk) * 3 * F * (K + 1) + t] = sum;
         }
     }
 }

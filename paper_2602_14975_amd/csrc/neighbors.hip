@@ -144,7 +144,7 @@ k_nbr_count(int n, const double* __restrict__ pos, RepGeom geom, Stencil st, dou
             const int* __restrict__ run, int* __restrict__ counts, int* __restrict__ status) {
     if (*run == 0) return;
     int lane = threadIdx.x & 63;
-    int i = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    int i = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
     if (i >= n) return;  // whole wavefront exits together
     int r = geom.rep_of_atom ? geom.rep_of_atom[i] : 0;
     double L, inv;
@@ -184,7 +184,7 @@ k_nbr_fill(int n, const double* __restrict__ pos, RepGeom geom, Stencil st, doub
     __shared__ int rows[kWaves][kMaxRow];
     int lane = threadIdx.x & 63;
     int w = threadIdx.x >> 6;
-    int i = blockIdx.x * kWaves + w;
+    int i = xcd_block(blockIdx.x, gridDim.x) * kWaves + w;
     if (i >= n) return;
     int total = tmp_off[n];
     if (status[2] != 0) return;  // a row is longer than kMaxRow: keep the previous list intact
@@ -234,7 +234,7 @@ k_filter_count(int n, const double* __restrict__ pos, RepGeom geom, const int* _
                int* __restrict__ counts) {
     if (*run == 0) return;
     int lane = threadIdx.x & 63;
-    int i = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    int i = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
     if (i >= n) return;
     double L, inv;
     geom.get(i, L, inv);
@@ -256,7 +256,7 @@ k_filter_fill(int n, const double* __restrict__ pos, RepGeom geom, const int* __
               int* __restrict__ nbr, int* __restrict__ status) {
     if (*run == 0) return;
     int lane = threadIdx.x & 63;
-    int i = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    int i = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
     if (i >= n) return;
     int total = tmp_off[n];
     if (int64_t(total) > capacity) {
@@ -296,7 +296,7 @@ k_nbr_reverse(int n, const int* __restrict__ run, const int* __restrict__ status
               const int* __restrict__ offsets, const int* __restrict__ nbr, int* __restrict__ rev) {
     if (*run == 0 || status[0] != 0 || status[2] != 0) return;
     int lane = threadIdx.x & 63;
-    int i = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    int i = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
     if (i >= n) return;
     for (int e = offsets[i] + lane; e < offsets[i + 1]; e += 64) {
         int j = nbr[e];
