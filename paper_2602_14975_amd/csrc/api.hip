@@ -113,11 +113,22 @@ extern "C" nnp_status nnp_model_create(const nnp_model_desc* desc, nnp_model** o
         return NNP_ENOMEM;
     }
     e = hipMemcpy(m->w, w32.data(), sizeof(float) * m->n_weights, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&m->tab, sizeof(float) * 5 * d.n_species * d.width);
     if (e != hipSuccess) {
         (void)hipFree(m->w);
+        if (m->tab) (void)hipFree(m->tab);
         delete m;
-        set_error(std::string("hipMemcpy: ") + hipGetErrorString(e));
+        set_error(std::string("model set-up: ") + hipGetErrorString(e));
         return NNP_EDEVICE;
+    }
+    try {
+        m->refresh_tables(nullptr);
+        NNP_HIP(hipStreamSynchronize(nullptr));
+    } catch (...) {
+        (void)hipFree(m->w);
+        (void)hipFree(m->tab);
+        delete m;
+        throw;
     }
     *out = reinterpret_cast<nnp_model*>(m);
     NNP_API_END
@@ -127,6 +138,7 @@ extern "C" void nnp_model_destroy(nnp_model* model) {
     if (!model) return;
     Model* m = reinterpret_cast<Model*>(model);
     if (m->w) (void)hipFree(m->w);
+    if (m->tab) (void)hipFree(m->tab);
     delete m;
 }
 
@@ -142,6 +154,7 @@ extern "C" nnp_status nnp_model_set_weights_f32(nnp_model* model, const float* w
     NNP_REQUIRE(n_weights == m->n_weights, NNP_EINVAL, "weight count does not match the model");
     NNP_HIP(hipMemcpyAsync(m->w, weights_dev, sizeof(float) * n_weights, hipMemcpyDeviceToDevice,
                            static_cast<hipStream_t>(stream)));
+    m->refresh_tables(static_cast<hipStream_t>(stream));
     NNP_API_END
 }
 
@@ -205,9 +218,9 @@ void carve_model(Arena& a, const Model* m, int64_t n, int64_t E, bool for_wgrad,
         b.v[l] = a.take<float>(n * 3 * F);
     }
     const int64_t S = m->desc.n_species;
-    b.h1_tab = a.take<float>(S * F);
-    b.z_tab = a.take<float>(S * F);
-    b.phi_tab = a.take<float>(S * 3 * F);
+    b.h1_tab = m->h1_tab();
+    b.z_tab = m->z_tab();
+    b.phi_tab = m->phi_tab();
     b.gphi_tab = a.take<float>(S * 3 * F);
     b.gh1_tab = a.take<float>(S * F);
     for (int l = 0; l < L; ++l) {
@@ -266,6 +279,13 @@ void carve_model(Arena& a, const Model* m, int64_t n, int64_t E, bool for_wgrad,
 // embedding, so its phi is evaluated once per species (a table of S rows);
 // the message kernel then reads phi_tab[t_j] and the zero vector input
 // implicitly.  Every intermediate needed by the reverse pass stays in `b`.
+void Model::refresh_tables(hipStream_t s) {
+    const int F = desc.width, S = desc.n_species;
+    const LayerOff& lo = loff[0];
+    gemm_xwt(S, F, F, p(off_emb), F, p(lo.W1), p(lo.b1), z_tab(), F, EPI_SILU, h1_tab(), F, false, s, bf16());
+    gemm_xwt(S, 3 * F, F, z_tab(), F, p(lo.W2), p(lo.b2), phi_tab(), 3 * F, EPI_NONE, nullptr, 0, false, s, bf16());
+}
+
 void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, ModelBuf& b, hipStream_t s) {
     const int n = int(sys.n_atoms);
     const int F = m->desc.width, K = m->desc.n_rbf, S = m->desc.n_species;
@@ -279,10 +299,6 @@ void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, Mode
         a.s_out = lb.smid;
         a.v_out = lb.vmid;
         if (l == 0) {
-            gemm_xwt(S, F, F, m->p(m->off_emb), F, m->p(lo.W1), m->p(lo.b1), b.z_tab, F, EPI_SILU, b.h1_tab, F,
-                     false, s, m->bf16());
-            gemm_xwt(S, 3 * F, F, b.z_tab, F, m->p(lo.W2), m->p(lo.b2), b.phi_tab, 3 * F, EPI_NONE, nullptr, 0,
-                     false, s, m->bf16());
             a.species = sys.species;
             a.phi_tab = b.phi_tab;
             a.emb = m->p(m->off_emb);
@@ -436,10 +452,6 @@ void nc_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const n
         const int K = m->desc.n_rbf, S = m->desc.n_species;
         const LayerOff& lo = m->loff[0];
         LayerBuf& lb = b.layer[0];
-        gemm_xwt(S, F, F, m->p(m->off_emb), F, m->p(lo.W1), m->p(lo.b1), b.z_tab, F, EPI_SILU, b.h1_tab, F, false,
-                 s, m->bf16());
-        gemm_xwt(S, 3 * F, F, b.z_tab, F, m->p(lo.W2), m->p(lo.b2), b.phi_tab, 3 * F, EPI_NONE, nullptr, 0, false,
-                 s, m->bf16());
         MpFwd a{};
         a.Wr = m->p(lo.Wr);
         a.br = m->p(lo.br);

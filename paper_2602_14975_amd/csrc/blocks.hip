@@ -212,35 +212,46 @@ __device__ __forceinline__ void head_coeffs(const float* qa, const float* kb, fl
     }
 }
 
-// Lanes take one CSR entry each; the contributions of the entries that pass
-// the pair rule are compacted (ballot) into LDS and added by one lane in row
-// order, so the sum does not depend on how many extra Verlet entries the row
-// holds or where batch boundaries fall.
-__global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __restrict__ QK, const float* __restrict__ Vh,
-                                                  float* __restrict__ Fout, int accum) {
-    __shared__ float contrib[4][64][3];
+// A group of G lanes per owner atom (64 / G atoms per wavefront); lanes take
+// one CSR entry each.  The contributions of the entries that pass the pair
+// rule are compacted (ballot) into LDS and added by the group's first lane
+// in row order, so the sum does not depend on how many extra Verlet entries
+// the row holds or where batch boundaries fall.
+template <int G>
+__global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __restrict__ QK,
+                                                  const float* __restrict__ Vh, float* __restrict__ Fout, int accum) {
+    constexpr int APW = 64 / G;
+    __shared__ float contrib[4][APW][G][3];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const int i = xcd_block(blockIdx.x, gridDim.x) * 4 + w;
-    if (i >= mg.n) return;  // whole wavefront
+    const int g = lane / G, l = lane % G;
+    const int i = (xcd_block(blockIdx.x, gridDim.x) * 4 + w) * APW + g;
+    const bool active = i < mg.n;
     const int n = mg.n;
-    double L, inv;
-    mg.geom.get(i, L, inv);
-    const double xi = mg.pos[i], yi = mg.pos[n + i], zi = mg.pos[2 * n + i];
-    const float* qi = QK + int64_t(i) * 2 * kH * kNc;
-    const float* ki = qi + kH * kNc;
-    float Vi[kNl][3];
+    double L = 1, inv = 1, xi = 0, yi = 0, zi = 0;
+    int e0 = 0, e1 = 0;
+    const float* qi = QK;
+    const float* ki = QK;
+    float Vi[kNl][3] = {};
+    if (active) {
+        mg.geom.get(i, L, inv);
+        xi = mg.pos[i]; yi = mg.pos[n + i]; zi = mg.pos[2 * n + i];
+        e0 = mg.off[i];
+        e1 = mg.off[i + 1];
+        qi = QK + int64_t(i) * 2 * kH * kNc;
+        ki = qi + kH * kNc;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int h = 0; h < kNl; ++h) Vi[h][a] = Vh[(int64_t(i) * 3 + a) * kNl + h];
-    float fx = 0.f, fy = 0.f, fz = 0.f;  // running sums (lane 0)
-    const int e0 = mg.off[i], e1 = mg.off[i + 1];
-    for (int base = e0; base < e1; base += 64) {
-        const int e = base + lane;
+            for (int h = 0; h < kNl; ++h) Vi[h][a] = Vh[(int64_t(i) * 3 + a) * kNl + h];
+    }
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (g * G));
+    float fx = 0.f, fy = 0.f, fz = 0.f;  // running sums (first lane of the group)
+    for (int base = 0; __ballot(e0 + base < e1) != 0ull; base += G) {
+        const int e = e0 + base + l;
         HeadEdge he;
         const bool ok = e < e1 && head_edge(mg, i, e, xi, yi, zi, L, inv, he);
-        const uint64_t bal = __ballot(ok);
+        const uint64_t mine = __ballot(ok) & gmask;
         if (ok) {
             const int j = he.j;
             const float* qj = QK + int64_t(j) * 2 * kH * kNc;
@@ -254,31 +265,31 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
                 Sij = fmaf(cij[h], he.ef[h], Sij);
                 Sji = fmaf(cji[h], he.ef[h], Sji);
             }
-            const int pre = __popcll(bal & ((1ull << lane) - 1ull));
+            const int pre = __popcll(mine & ((1ull << lane) - 1ull));
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const float Dij = he.u[a] + cij[kNs] * Vi[0][a] + cij[kNs + 1] * Vi[1][a];
                 const float Dji = -he.u[a] + cji[kNs] * Vh[(int64_t(j) * 3 + a) * kNl] +
                                   cji[kNs + 1] * Vh[(int64_t(j) * 3 + a) * kNl + 1];
-                contrib[w][pre][a] = Sij * Dij - Sji * Dji;
+                contrib[w][g][pre][a] = Sij * Dij - Sji * Dji;
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        if (lane == 0) {
-            const int cnt = __popcll(bal);
+        if (l == 0) {
+            const int cnt = __popcll(mine);
             for (int t = 0; t < cnt; ++t) {
-                fx += contrib[w][t][0];
-                fy += contrib[w][t][1];
-                fz += contrib[w][t][2];
+                fx += contrib[w][g][t][0];
+                fy += contrib[w][g][t][1];
+                fz += contrib[w][g][t][2];
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
-    if (lane == 0) {
+    if (active && l == 0) {
         if (accum) {
             Fout[i] += fx; Fout[n + i] += fy; Fout[2 * n + i] += fz;
         } else {
@@ -584,7 +595,8 @@ void launch_emb_grad(int n, int F, int S, const int* species, const float* gs0, 
 void launch_head_fwd(const MpGeom& mg, const float* QK, const float* Vh, float* F, bool accum, hipStream_t st) {
     if (mg.n <= 0) return;
     ScopedTimer timer("head_fwd", st);
-    k_head_fwd<<<cdiv(mg.n, 4), 256, 0, st>>>(mg, QK, Vh, F, accum);
+    // 16 lanes per atom: rows of the 3.5 A list hold about 40 candidates
+    k_head_fwd<16><<<cdiv(mg.n, 16), 256, 0, st>>>(mg, QK, Vh, F, accum);
     NNP_LAUNCH_CHECK();
 }
 void launch_head_bwd(const MpGeom& mg, const float* QK, const float* Vh, const float* gF, float* gQK, float* gVh,

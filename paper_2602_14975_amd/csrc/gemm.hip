@@ -42,7 +42,16 @@ k_gemm(GemmArgs g) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+    // 1-D launches (no row chunks) number tiles so that each XCD gets a
+    // contiguous run, column tile fastest: the A rows of a run stay in its L2.
+    int bm = blockIdx.x, bn = blockIdx.y;
+    if (g.chunk_rows == 0) {
+        const int NT = (g.N + TN - 1) / TN;
+        const int L = xcd_block(blockIdx.x, gridDim.x);
+        bm = L / NT;
+        bn = L % NT;
+    }
+    const int m0 = bm * TM, n0 = bn * TN;
     int kbeg = 0, kend = g.K;
     if (g.chunk_rows > 0) {
         kbeg = int(int64_t(blockIdx.z) * g.chunk_rows);
@@ -124,6 +133,146 @@ k_gemm(GemmArgs g) {
     }
 }
 
+// Register-direct variant for operands whose k index is contiguous in both
+// A (A(m, k) = A[m * sam + k]) and B (B(k, n) = B[n * sbn + k]): no LDS
+// staging and no barriers in the k loop.  Within each 32-deep slice the
+// MFMA k slots are permuted so that every lane reads 16 consecutive k values
+// of its own row with four float4 loads; A and B use the same permutation,
+// so each product term A(m, k) B(k, n) appears exactly once.  A block of S
+// wavefronts shares one 32 x 32T output strip: wavefront w takes slices
+// w, w + S, ... and the partial sums are added in wavefront order (fixed,
+// so results are reproducible).
+template <int T, int S, bool BF16>
+__global__ void __launch_bounds__(64 * S) k_gemm_rk(GemmArgs g) {
+    __shared__ float red[S > 1 ? S - 1 : 1][T][16][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 31, h = lane >> 5;
+    const int NT = (g.N + 32 * T - 1) / (32 * T);
+    const int L = xcd_block(blockIdx.x, gridDim.x);  // column strip fastest within an XCD's run
+    const int m0 = (L / NT) * 32, n0 = (L % NT) * (32 * T);
+    const bool mok = m0 + r < g.M;
+    const float* arow = g.A + (mok ? int64_t(m0 + r) * g.sam : 0);
+    const float* brow[T];
+    bool nok[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        nok[t] = n0 + 32 * t + r < g.N;
+        brow[t] = g.B + (nok[t] ? int64_t(n0 + 32 * t + r) * g.sbn : 0);
+    }
+    floatx16 acc[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] = floatx16{};
+    const int nsl = (g.K + 31) / 32;
+    float4 a[4], b[T][4];
+    auto load = [&](int c, float4* pa, float4 (*pb)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = c * 32 + 16 * h + 4 * q;
+            const bool kok = k < g.K;  // K % 4 == 0: a float4 is wholly in or out
+            pa[q] = (mok && kok) ? *reinterpret_cast<const float4*>(arow + k) : float4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+                pb[t][q] = (nok[t] && kok) ? *reinterpret_cast<const float4*>(brow[t] + k)
+                                           : float4{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    auto slice = [&](const float4* pa, const float4 (*pb)[4]) {
+        if constexpr (BF16) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                short4_t av = {bf16_bits(pa[q].x), bf16_bits(pa[q].y), bf16_bits(pa[q].z), bf16_bits(pa[q].w)};
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    short4_t bv = {bf16_bits(pb[t][q].x), bf16_bits(pb[t][q].y), bf16_bits(pb[t][q].z),
+                                   bf16_bits(pb[t][q].w)};
+                    acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc[t], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float av[4] = {pa[q].x, pa[q].y, pa[q].z, pa[q].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+#pragma unroll
+                    for (int t = 0; t < T; ++t) {
+                        const float bv[4] = {pb[t][q].x, pb[t][q].y, pb[t][q].z, pb[t][q].w};
+                        acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[e], bv[e], acc[t], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    };
+    int c = wave;
+    if (c < nsl) load(c, a, b);
+    for (; c < nsl; c += S) {
+        float4 an[4], bn[T][4];
+        const bool more = c + S < nsl;
+        if (more) load(c + S, an, bn);  // next slice in flight during the MFMAs
+        slice(a, b);
+        if (more) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[q] = an[q];
+#pragma unroll
+                for (int t = 0; t < T; ++t) b[t][q] = bn[t][q];
+            }
+        }
+    }
+    if constexpr (S > 1) {
+        if (wave > 0) {
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) red[wave - 1][t][i][lane] = acc[t][i];
+        }
+        __syncthreads();
+        if (wave > 0) return;
+#pragma unroll
+        for (int w = 0; w < S - 1; ++w)
+#pragma unroll
+            for (int t = 0; t < T; ++t)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) acc[t][i] += red[w][t][i][lane];
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int col = n0 + 32 * t + r;
+        if (col >= g.N) continue;
+        const float bias = g.bias ? g.bias[col] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int m = m0 + (i >> 2) * 8 + h * 4 + (i & 3);
+            if (m >= g.M) continue;
+            float y = acc[t][i] + bias;
+            const int64_t idx = int64_t(m) * g.ldc + col;
+            if (g.epi == EPI_SILU) {
+                if (g.pre) g.pre[int64_t(m) * g.ldp + col] = y;
+                y = silu(y);
+            } else if (g.epi == EPI_DSILU) {
+                y *= silu_grad(g.pre[int64_t(m) * g.ldp + col]);
+            }
+            if (g.accum) y += g.C[idx];
+            g.C[idx] = y;
+        }
+    }
+}
+
+// Operands qualify for k_gemm_rk when k is contiguous in both, K and the row
+// strides are multiples of 4 and the bases 16-byte aligned.
+static bool rk_ok(const GemmArgs& g) {
+    return g.sak == 1 && g.sbk == 1 && g.K % 4 == 0 && g.sam % 4 == 0 && g.sbn % 4 == 0 &&
+           (reinterpret_cast<uintptr_t>(g.A) & 15) == 0 && (reinterpret_cast<uintptr_t>(g.B) & 15) == 0 &&
+           g.chunk_rows == 0;
+}
+
+template <int T, int S>
+static void rk_launch(const GemmArgs& g, hipStream_t stream) {
+    dim3 grid(cdiv(g.M, 32) * cdiv(g.N, 32 * T));
+    if (g.bf16) k_gemm_rk<T, S, true><<<grid, 64 * S, 0, stream>>>(g);
+    else k_gemm_rk<T, S, false><<<grid, 64 * S, 0, stream>>>(g);
+}
+
 static void gemm_dispatch(const GemmArgs& g, dim3 grid, hipStream_t stream) {
     if (g.bf16) k_gemm<true><<<grid, 256, 0, stream>>>(g);
     else k_gemm<false><<<grid, 256, 0, stream>>>(g);
@@ -131,9 +280,16 @@ static void gemm_dispatch(const GemmArgs& g, dim3 grid, hipStream_t stream) {
 
 void launch_gemm(const GemmArgs& g, hipStream_t stream) {
     if (g.M <= 0 || g.N <= 0) return;
-    dim3 grid(cdiv(g.M, TM), cdiv(g.N, TN), 1);
     ScopedTimer timer("gemm", stream);
-    gemm_dispatch(g, grid, stream);
+    if (g.N <= 160 && rk_ok(g)) {
+        // narrow outputs: more, smaller tiles and k split over the block's
+        // wavefronts fill the chip better than 64 x 64 tiles
+        if (g.K >= 128) rk_launch<1, 4>(g, stream);
+        else rk_launch<1, 1>(g, stream);
+    } else {
+        dim3 grid(cdiv(g.M, TM) * cdiv(g.N, TN), 1, 1);
+        gemm_dispatch(g, grid, stream);
+    }
     NNP_LAUNCH_CHECK();
 }
 

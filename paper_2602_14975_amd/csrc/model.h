@@ -26,6 +26,13 @@ struct Model {
     int n_layers() const { return desc.kind == NNP_MODEL_CONS ? desc.n_layers : 1; }
     const float* p(int64_t off) const { return w + off; }
     bool bf16() const { return desc.precision == NNP_BF16; }
+    // First layer per species (functions of the weights only, refreshed when
+    // the weights change): [S][F] pre-activation, [S][F] hidden, [S][3F] phi.
+    float* tab = nullptr;
+    float* h1_tab() const { return tab; }
+    float* z_tab() const { return tab + int64_t(desc.n_species) * desc.width; }
+    float* phi_tab() const { return tab + 2 * int64_t(desc.n_species) * desc.width; }
+    void refresh_tables(hipStream_t s);
 };
 
 struct LayerBuf {
