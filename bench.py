@@ -34,6 +34,9 @@ if ROOT not in sys.path:
 METRIC = "ns/day DMTS-NC vs 1-step at force RMSE vs FP64; p50/p99 replica step latency"
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz: the FP32 rate without
+# packed (two-wide) instructions, which this library's kernels are built without
+FP32_NONPACKED_PEAK_TFLOPS = 78.6
 
 
 def _ns_per_day(dt_fs, steps, seconds):
@@ -101,11 +104,15 @@ def run_gpu(args):
         return t1 - t0, traj, kt
 
     t_dmts, traj, kt = timed("dmts_nc", 4.0, 8, args.steps, args.warmup, timer_site="message_bwd")
+    v_end = traj.velocities()
+    kb = 8.31446261815324 / 4184.0  # kcal/mol/K
+    ke_end = 0.5 * float((m[:, None] * v_end * v_end).sum()) / 4.184e-4  # amu A^2/fs^2 -> kcal/mol
+    t_end = 2.0 * ke_end / (3 * s.n * kb)
     sts_steps = max(8, args.steps)
     t_sts, _, _ = timed("sts", 0.5, 1, sts_steps, args.warmup)
     return {
         "t_dmts": t_dmts, "t_sts": t_sts, "sts_steps": sts_steps, "kernel_timer": kt, "n_edges5": n_edges5,
-        "rebuilds": traj.n_rebuilds, "gpu_forces": gpu_forces, "system": s, "cw": cw, "nw": nw,
+        "rebuilds": traj.n_rebuilds, "gpu_forces": gpu_forces, "system": s, "cw": cw, "nw": nw, "t_end": t_end,
         "gpu_name": torch.cuda.get_device_name(0),
     }
 
@@ -130,6 +137,27 @@ def run_oracle(s, cw, nw):
     Fn = om.nc_forces(synth.NC_CFG1, nw, s.pos, s.species, s.box, off35, nbr35)
     t_nc = time.perf_counter() - t0
     return {"E": E, "F": F, "Fn": Fn, "t_cons": t_cons, "t_nc": t_nc, "t_nb": t_nb, "threads": threads}
+
+
+def measured_traffic():
+    """HBM bytes per message_bwd launch from the committed counter summary
+    (two rocprofv3 --pmc passes, calibrated on a plain copy), or None when
+    the kernel sources changed after the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "message_bwd_water12288_traffic.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    keys = ("traffic_bytes_per_launch", "sources", "sources_sha256")
+    fields = dict(line.strip().split(": ", 1) for line in text.splitlines()
+                  if ": " in line and line.strip().split(": ", 1)[0] in keys)
+    if len(fields) != 3:
+        return None
+    h = hashlib.sha256()
+    for f in fields["sources"].split():
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return int(fields["traffic_bytes_per_launch"]) if h.hexdigest() == fields["sources_sha256"] else None
 
 
 def run_serving(n_replicas, n_steps, per_atom_step_s, load=0.8, budget_frac=0.25, seed=30000, max_slots=64):
@@ -235,8 +263,10 @@ def run_copy(mib=512, reps=5):
 def run_distill(args):
     """Distillation of the NC model (1 x 32) onto the conservative model
     (3 x 128) on the 1,536-atom box: 2,000 frames from a 0.5 fs NVT run
-    (2 ps equilibration, one frame per 10 fs), 1,800 training / 200
-    validation frames, batch 16, FP32 Adam lr 1e-3."""
+    in 20 independent runs (0.1 ps equilibration each, then one frame per
+    5 fs), 1,800 training / 200 validation frames, batch 16, FP32 Adam
+    lr 1e-3.  The randomly initialised teacher heats up beyond a few ps, so
+    the frames come from several short runs."""
     import torch
 
     import synth
@@ -248,7 +278,7 @@ def run_distill(args):
     nc = nnp.Model.from_spec(synth.NC_CFG1, nw)
     t0 = time.perf_counter()
     pos, frc = distill.generate_frames(cons, s, s.standard_masses(), np.ones(s.n), n_frames=args.frames,
-                                       equil_steps=4000, every=20)
+                                       equil_steps=200, every=10, n_traj=20)
     torch.cuda.synchronize()
     t_frames = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -258,9 +288,10 @@ def run_distill(args):
     t_train = time.perf_counter() - t0
     fref = frc.double()
     label_rms = float(torch.sqrt((fref * fref).mean()))
+    label_max = float(fref.abs().max())
     return {"frames": args.frames, "frame_generation_s": round(t_frames, 2), "train_steps": args.train_steps,
             "train_s": round(t_train, 2), "ms_per_train_step": round(t_train / args.train_steps * 1e3, 3),
-            "label_force_rms": round(label_rms, 4),
+            "label_force_rms": round(label_rms, 4), "label_force_max": round(label_max, 3),
             "val_force_rmse_history": [(int(k), round(v, 5)) for k, v in hist]}
 
 
@@ -314,8 +345,9 @@ def main():
         achieved = flops / avg_s / 1e12
         roof = {"bound": "alu", "kernel": "k_message_bwd<128,16,cos>", "achieved": round(achieved, 2),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-                "traffic": None, "avg_launch_us": round(avg_s * 1e6, 1), "launches": launches,
-                "edges_per_launch": g["n_edges5"]}
+                "traffic": measured_traffic(), "avg_launch_us": round(avg_s * 1e6, 1), "launches": launches,
+                "edges_per_launch": g["n_edges5"],
+                "frac_of_nonpacked_fp32": round(achieved / FP32_NONPACKED_PEAK_TFLOPS, 4)}
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "ns/day", "n_gpus": 1, "steps": args.steps,
@@ -325,7 +357,7 @@ def main():
                    "cons_model": "3x128 l<=1 equivariant MP, 16 Bessel, 5 A", "nc_model": "1x32, 3.5 A",
                    "outer_dt_fs": dt, "n_inner": 8, "sts_dt_fs": 0.5, "check_every": args.check_every},
         "sts_ns_per_day": round(sts, 3), "speedup_vs_sts": round(value / sts, 3),
-        "list_rebuilds": g["rebuilds"], "gpu": g["gpu_name"],
+        "list_rebuilds": g["rebuilds"], "temperature_end_K": round(g["t_end"], 1), "gpu": g["gpu_name"],
         "roofline": roof,
     }
     if args.serve_replicas > 0:

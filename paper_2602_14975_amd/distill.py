@@ -18,20 +18,28 @@ from . import nnp
 
 
 def generate_frames(cons, system, masses, gamma, n_frames, equil_steps, every, dt=0.5, temperature=300.0,
-                    seed=4003, vel_seed=5003, skin=1.0):
+                    seed=4003, vel_seed=5003, skin=1.0, n_traj=1):
+    """Frames from `n_traj` independent trajectories (velocity and Philox
+    seeds offset by the trajectory index), n_frames / n_traj from each after
+    its own equilibration.  Several short runs keep every frame close to the
+    starting temperature for teachers whose dynamics drifts over long runs
+    (such as randomly initialised ones)."""
     import synth
-    dev = nnp.DeviceSystem(system.pos, system.species, system.box)
-    v0 = synth.maxwell_boltzmann(masses, temperature, vel_seed)
-    prm = nnp.respa_params(dt, 1, temperature, seed=seed, mode="sts", skin=skin, check_every=max(1, every))
-    traj = nnp.Trajectory(cons, None, dev, v0, masses, gamma, prm)
-    if equil_steps > 0:
-        traj.respa_step(equil_steps)
+    assert n_frames % n_traj == 0, "n_frames must be a multiple of n_traj"
+    per = n_frames // n_traj
     pos = torch.empty(n_frames, 3, system.n, dtype=torch.float64, device="cuda")
     frc = torch.empty(n_frames, 3, system.n, dtype=torch.float32, device="cuda")
-    for k in range(n_frames):
-        traj.respa_step(every)
-        pos[k].copy_(dev.pos)
-        frc[k].copy_(traj.f_cons)
+    for t in range(n_traj):
+        dev = nnp.DeviceSystem(system.pos, system.species, system.box)
+        v0 = synth.maxwell_boltzmann(masses, temperature, vel_seed + t)
+        prm = nnp.respa_params(dt, 1, temperature, seed=seed + t, mode="sts", skin=skin, check_every=1)
+        traj = nnp.Trajectory(cons, None, dev, v0, masses, gamma, prm)
+        if equil_steps > 0:
+            traj.respa_step(equil_steps)
+        for k in range(per):
+            traj.respa_step(every)
+            pos[t * per + k].copy_(dev.pos)
+            frc[t * per + k].copy_(traj.f_cons)
     return pos, frc
 
 
