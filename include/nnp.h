@@ -263,6 +263,8 @@ typedef struct {
                               step (kcal/mol), or NULL */
     int64_t n_rebuilds;    /* out: list rebuilds performed (accumulates) */
     int64_t n_rewinds;     /* out: rewinds performed (accumulates) */
+    int64_t n_replays;     /* out: intervals replayed after a list went stale
+                              between two predicted rebuilds (accumulates) */
 } respa_state;
 
 /* Advances the state by n_outer outer steps of Algorithm 1 (DMTS-NC, or
@@ -273,6 +275,12 @@ typedef struct {
  * G from Philox-4x64-10 with key (seed, stream_id + r) and counter
  * (atom index within its replica, O-step index, 0, 0), Box-Muller on the four
  * uniforms ((w >> 11) + 0.5) 2^-53; FFL keeps each atom's velocity direction.
+ * Lists are rebuilt when an atom moved more than skin/2 since the last
+ * build.  Multiple-time-step runs without rewinding decide this once per
+ * outer step, from the largest displacement so far and its growth over the
+ * previous outer step; should an inner step still exceed skin/2, the
+ * interval since the last check is replayed with the check after every
+ * inner step (n_replays counts these; the numbers are the same either way).
  * Every `check_every` outer steps the call synchronises and checks list
  * capacity and finiteness; on NNP_ECAPACITY the state is restored to the
  * start of the failing outer step (grow the list buffers and call again);

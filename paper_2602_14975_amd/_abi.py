@@ -48,7 +48,8 @@ class RespaState(C.Structure):
     _fields_ = [("sys", System), ("pos", vp), ("vel", vp), ("mass", vp), ("gamma", vp), ("f_cons", vp),
                 ("f_nc", vp), ("energy", vp), ("pos_ref", vp), ("nl_cons", NList), ("nl_nc", NList),
                 ("step", C.c_uint64), ("first_step", C.c_int32), ("lists_valid", C.c_int32), ("ke", vp),
-                ("n_rebuilds", C.c_int64), ("n_rewinds", C.c_int64)]
+                ("n_rebuilds", C.c_int64), ("n_rewinds", C.c_int64),
+                ("n_replays", C.c_int64)]
 
 
 class ReplicaDesc(C.Structure):

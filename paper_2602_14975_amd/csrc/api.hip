@@ -114,9 +114,12 @@ extern "C" nnp_status nnp_model_create(const nnp_model_desc* desc, nnp_model** o
     }
     e = hipMemcpy(m->w, w32.data(), sizeof(float) * m->n_weights, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&m->tab, sizeof(float) * 5 * d.n_species * d.width);
+    if (e == hipSuccess && d.kind == NNP_MODEL_NC && d.width <= 32)
+        e = hipMalloc(&m->ncw, sizeof(float) * Model::ncw_count(d.width));
     if (e != hipSuccess) {
         (void)hipFree(m->w);
         if (m->tab) (void)hipFree(m->tab);
+        if (m->ncw) (void)hipFree(m->ncw);
         delete m;
         set_error(std::string("model set-up: ") + hipGetErrorString(e));
         return NNP_EDEVICE;
@@ -127,6 +130,7 @@ extern "C" nnp_status nnp_model_create(const nnp_model_desc* desc, nnp_model** o
     } catch (...) {
         (void)hipFree(m->w);
         (void)hipFree(m->tab);
+        if (m->ncw) (void)hipFree(m->ncw);
         delete m;
         throw;
     }
@@ -139,6 +143,7 @@ extern "C" void nnp_model_destroy(nnp_model* model) {
     Model* m = reinterpret_cast<Model*>(model);
     if (m->w) (void)hipFree(m->w);
     if (m->tab) (void)hipFree(m->tab);
+    if (m->ncw) (void)hipFree(m->ncw);
     delete m;
 }
 
@@ -284,6 +289,7 @@ void Model::refresh_tables(hipStream_t s) {
     const LayerOff& lo = loff[0];
     gemm_xwt(S, F, F, p(off_emb), F, p(lo.W1), p(lo.b1), z_tab(), F, EPI_SILU, h1_tab(), F, false, s, bf16());
     gemm_xwt(S, 3 * F, F, z_tab(), F, p(lo.W2), p(lo.b2), phi_tab(), 3 * F, EPI_NONE, nullptr, 0, false, s, bf16());
+    if (ncw) transpose_nc_weights(F, p(lo.U), p(lo.M1), p(lo.M2), p(off_Wq), p(off_WV), bf16(), ncw, s);
 }
 
 void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, ModelBuf& b, hipStream_t s) {
@@ -461,9 +467,8 @@ void nc_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const n
         a.phi_tab = b.phi_tab;
         a.emb = m->p(m->off_emb);
         launch_message_fwd(F, K, 1, mg, a, s);
-        NcUpdateArgs u{n, lb.smid, lb.vmid, m->p(lo.U), m->p(lo.M1), m->p(lo.m1), m->p(lo.M2), m->p(lo.m2),
-                       m->p(m->off_Wq), m->p(m->off_WV), b.QK, b.Vh};
-        if (launch_nc_update_proj(u, F, m->bf16(), s)) {
+        NcUpdateArgs u{n, lb.smid, lb.vmid, m->ncw, m->p(lo.m1), m->p(lo.m2), b.QK, b.Vh};
+        if (m->ncw && launch_nc_update_proj(u, F, m->bf16(), s)) {
             launch_head_fwd(mg, b.QK, b.Vh, forces, false, s);
             return;
         }
@@ -825,6 +830,9 @@ __global__ void __launch_bounds__(256) k_disagreement(const int64_t* __restrict_
 // k counting the O-steps of this call.  rep_bad (host, n_rep, optional)
 // receives per-replica non-finite flags at each check; without it any
 // non-finite replica fails the call.
+// internal: a list went stale between predicted rebuilds (never returned)
+constexpr nnp_status NNP_ESTALE_INTERNAL = static_cast<nnp_status>(-100);
+
 nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const respa_params* p, int32_t n_outer,
                      void* ws, size_t ws_bytes, hipStream_t s, const uint64_t* seeds, const uint64_t* streams,
                      const uint64_t* step_base, int* rep_bad) {
@@ -852,8 +860,11 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     const double rc_nc = mts ? nc->desc.cutoff + p->skin : 0.0;
     CellPlan plan = plan_cells(st->sys, rc_cons);
     upload_cell_plan(plan, c.nb, s);
-    // flags: [0] rebuild trigger, [8..10] fast-force list status; nb.status: conservative list
+    // flags: [0] rebuild trigger, [4] stale-list flag of the predictive mode, [5..6]
+    // displacement record, [8..10] fast-force list status; nb.status: conservative list
     int* trig = c.t.flags;
+    int* stale = c.t.flags + 4;
+    unsigned* maxd2 = reinterpret_cast<unsigned*>(c.t.flags + 5);
     int* nc_status = c.t.flags + 8;
     NNP_HIP(hipMemsetAsync(c.t.flags, 0, sizeof(int) * 16, s));
     NNP_HIP(hipMemsetAsync(c.t.rep_bad, 0, sizeof(int) * R, s));
@@ -867,7 +878,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         if (mts)
             launch_filter(n, st->pos, g, c.nb, trig, lc.offsets, lc.nbr, rc_nc, ln.capacity, ln.offsets, ln.nbr,
                           nullptr, nc_status, s);
-        launch_finish_rebuild(trig, c.t.rebuilds, s);
+        launch_finish_rebuild(trig, c.t.rebuilds, maxd2, s);
     };
     const double disp_thr = 0.5 * p->skin;
     BaoaArgs ba{};
@@ -886,6 +897,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     ba.pos_ref = st->pos_ref;
     ba.disp_thr2 = disp_thr * disp_thr;
     ba.flag = trig;
+    ba.maxd2 = maxd2;
 
     auto eval_cons = [&]() { cons_eval(cons, st->sys, g, c.t, lc, c.cons, st->energy, st->f_cons, s); };
     auto eval_inner = [&]() {
@@ -926,6 +938,8 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         std::memcpy(&rb, hflags + 32, sizeof(long long));
         st->n_rebuilds += rb - rebuilds_seen;
         rebuilds_seen = rb;
+        // a stale list may have produced anything else flagged here as well
+        if (hflags[4] != 0) return NNP_ESTALE_INTERNAL;
         const bool row_long = hflags[16 + 2] != 0 || hflags[8 + 2] != 0;
         const bool over_cons = hflags[16 + 0] != 0;
         const bool over_nc = hflags[8 + 0] != 0;
@@ -990,15 +1004,24 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         offset += 1;
         st->step += 1;
     };
-    // one outer step of Algorithm 1
-    auto mts_step = [&]() {
+    // One outer step of Algorithm 1.  Predictive mode decides on a rebuild
+    // once per outer step (from the displacement record) and lets k_baoa only
+    // flag a list that went stale; strict mode rebuilds after any inner step
+    // whose displacement check fires.  Both give the same numbers whenever
+    // no stale flag is raised (results do not depend on when lists are built).
+    auto mts_step = [&](bool strict) {
+        if (!strict) {
+            launch_predict_rebuild(maxd2, disp_thr, trig, s);
+            rebuild_if_flagged();
+        }
+        ba.flag = strict ? trig : stale;
         launch_kick(n, st->vel, st->mass, st->f_cons, st->f_nc, 0.5 * D, s);
         for (int k = 0; k < n_in; ++k) {
             ba.force = st->f_nc;
             ba.dt = d;
             ba.step_offset = offset;
             launch_baoa(ba, s);
-            rebuild_if_flagged();
+            if (strict) rebuild_if_flagged();
             eval_inner();
             launch_kick(n, st->vel, st->mass, st->f_nc, nullptr, 0.5 * d, s);
             offset += 1;
@@ -1008,17 +1031,28 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         launch_kick(n, st->vel, st->mass, st->f_cons, st->f_nc, 0.5 * D, s);
     };
 
+    // predictive rebuilds for multiple-time-step runs without rewinding; a
+    // stale list found at a check sends the run back to the last snapshot,
+    // which is replayed in strict mode
+    const bool predictive = mts && !rewind && n_in > 1;
+    if (predictive) {
+        // the displacement record starts empty: begin from fresh lists
+        launch_set_flag(trig, 1, s);
+        rebuild_if_flagged();
+    }
     uint64_t snap_offset = 0;
+    int snap_o = 0, strict_until = 0;
     copy_state(c.rs, true);
     uint64_t frame_offset = 0;
     int since_save = 0;
     for (int o = 0; o < n_outer; ++o) {
+        const bool strict = !predictive || o < strict_until;
         if (rewind && since_save % p->save_every == 0) {
             copy_state(frame, true);
             frame_offset = offset;
             since_save = 0;
         }
-        if (mts) mts_step();
+        if (mts) mts_step(strict);
         else sts_step(D);
         ++since_save;
         if (rewind) {
@@ -1045,8 +1079,24 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
                        c.t.rep_bad, s);
         if ((o + 1) % check_every == 0 || o + 1 == n_outer) {
             nnp_status e = check(snap_offset, true);
+            if (e == NNP_ESTALE_INTERNAL) {
+                // back to the snapshot; replay up to here with strict rebuilds
+                copy_state(c.rs, false);
+                st->step -= offset - snap_offset;
+                offset = snap_offset;
+                strict_until = o + 1;
+                o = snap_o - 1;
+                st->n_replays += 1;
+                NNP_HIP(hipMemsetAsync(c.t.flags + 4, 0, sizeof(int) * 12, s));  // stale, record, fast-list status
+                NNP_HIP(hipMemsetAsync(c.nb.status, 0, sizeof(int) * 8, s));
+                NNP_HIP(hipMemsetAsync(c.t.rep_bad, 0, sizeof(int) * R, s));
+                launch_set_flag(trig, 1, s);
+                rebuild_if_flagged();
+                continue;
+            }
             if (e != NNP_OK) return e;
             snap_offset = offset;
+            snap_o = o + 1;
             if (o + 1 < n_outer) copy_state(c.rs, true);
         }
     }

@@ -412,8 +412,9 @@ __global__ void __launch_bounds__(64) k_head_bwd(MpGeom mg, const float* __restr
 // ------------------------------------------------- fused NC update block --
 // Update block of the one-layer NC embedding followed by its q/k and vector
 // projections, for widths F <= 32: per atom, one lane per feature column.
-// Weights are staged transposed in LDS once per block ([in][out], so the
-// lanes of a group read consecutive addresses) and the block walks over
+// The model keeps an [in][out] copy of these weights (rounded for BF16
+// models), so staging it into LDS once per block is a straight 16-byte copy;
+// lanes of a group then read consecutive LDS words, and the block walks over
 // groups of atoms.  With BF16, weights and every perceptron input are
 // rounded to bfloat16 and products accumulate in float32, as in the MFMA
 // GEMMs of the general path.
@@ -437,25 +438,9 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
     float* m2 = m1 + F;                // [3F]
     float* work = m2 + 3 * F;          // per atom: sm[F], vm[3F], x[2F], z[F], so[F], vo[3F]
     auto rnd = [](float x) { return BF16 ? bf16_round(x) : x; };
-    // transposed copies: consecutive threads write consecutive LDS words
-    for (int t = threadIdx.x; t < 2 * F * F; t += 256) {
-        const int k = t / (2 * F), o = t % (2 * F);  // UVt[k][o] = UV[o][k], k < F
-        UVt[t] = rnd(a.UV[o * F + k]);
-        const int k1 = t / F, o1 = t % F;  // M1t[k1][o1] = M1[o1][k1], k1 < 2F
-        M1t[t] = rnd(a.M1[o1 * 2 * F + k1]);
-    }
-    for (int t = threadIdx.x; t < 3 * F * F; t += 256) {
-        const int k = t / (3 * F), o = t % (3 * F);
-        M2t[t] = rnd(a.M2[o * F + k]);
-    }
-    for (int t = threadIdx.x; t < HC * F; t += 256) {
-        const int k = t / HC, o = t % HC;
-        Qt[t] = rnd(a.Wqk[o * F + k]);
-    }
-    for (int t = threadIdx.x; t < kNl * F; t += 256) {
-        const int k = t / kNl, o = t % kNl;
-        Vt[t] = rnd(a.WV[o * F + k]);
-    }
+    constexpr int NW = 7 * F * F + HC * F + kNl * F;  // contiguous [in][out] copy, multiple of 4
+    for (int t = threadIdx.x; t < NW / 4; t += 256)
+        reinterpret_cast<float4*>(lds)[t] = reinterpret_cast<const float4*>(a.wt)[t];
     for (int t = threadIdx.x; t < F; t += 256) m1[t] = a.m1[t];
     for (int t = threadIdx.x; t < 3 * F; t += 256) m2[t] = a.m2[t];
     const int g = threadIdx.x / F, f = threadIdx.x % F;
@@ -475,6 +460,7 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
         for (int al = 0; al < 3; ++al) vm[al * F + f] = act ? a.vmid[(int64_t(i) * 3 + al) * F + f] : 0.f;
         __syncthreads();
         float Uv[3] = {}, Vv[3] = {};
+#pragma unroll 8
         for (int k = 0; k < F; ++k) {
             const float uw = UVt[k * 2 * F + f], vw = UVt[k * 2 * F + F + f];
 #pragma unroll
@@ -491,10 +477,12 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
         x[F + f] = sqrtf(nn);
         __syncthreads();
         float a1 = m1[f];
+#pragma unroll 8
         for (int k = 0; k < 2 * F; ++k) a1 = fmaf(M1t[k * F + f], rnd(x[k]), a1);
         z[f] = silu(a1);
         __syncthreads();
         float pq[3] = {m2[f], m2[F + f], m2[2 * F + f]};
+#pragma unroll 8
         for (int k = 0; k < F; ++k) {
             const float zk = rnd(z[k]);
 #pragma unroll
@@ -521,16 +509,46 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
     }
 }
 
+__global__ void k_transpose_nc(int F, const float* __restrict__ UV, const float* __restrict__ M1,
+                               const float* __restrict__ M2, const float* __restrict__ Wqk,
+                               const float* __restrict__ WV, int bf16, float* __restrict__ out) {
+    constexpr int HC = 2 * kH * kNc;
+    const int64_t total = 7 * int64_t(F) * F + int64_t(HC) * F + kNl * F;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    // segments [F][2F], [2F][F], [F][3F], [F][HC], [F][kNl]: element (k, o) = W[o][k]
+    int64_t r = t;
+    float v;
+    if (r < 2 * F * F) {
+        v = UV[(r % (2 * F)) * F + r / (2 * F)];
+    } else if ((r -= 2 * F * F) < 2 * F * F) {
+        v = M1[(r % F) * 2 * F + r / F];
+    } else if ((r -= 2 * F * F) < 3 * F * F) {
+        v = M2[(r % (3 * F)) * F + r / (3 * F)];
+    } else if ((r -= 3 * F * F) < int64_t(HC) * F) {
+        v = Wqk[(r % HC) * F + r / HC];
+    } else {
+        r -= int64_t(HC) * F;
+        v = WV[(r % kNl) * F + r / kNl];
+    }
+    out[t] = bf16 ? bf16_round(v) : v;
+}
+
+void transpose_nc_weights(int F, const float* UV, const float* M1, const float* M2, const float* Wqk,
+                          const float* WV, bool bf16, float* out, hipStream_t st) {
+    const int64_t total = 7 * int64_t(F) * F + int64_t(2 * kH * kNc) * F + kNl * F;
+    k_transpose_nc<<<cdiv(total, 256), 256, 0, st>>>(F, UV, M1, M2, Wqk, WV, bf16 ? 1 : 0, out);
+    NNP_LAUNCH_CHECK();
+}
+
 size_t nc_update_lds_bytes(int F) {
     const int HC = 2 * kH * kNc;
-    return sizeof(float) * (size_t(2 * F * F + 2 * F * F + 3 * F * F + F * HC + F * kNl + F + 3 * F) +
-                            size_t(256 / F) * 11 * F);
+    return sizeof(float) * (size_t(7 * F * F + F * HC + F * kNl + F + 3 * F) + size_t(256 / F) * 11 * F);
 }
 
 bool launch_nc_update_proj(const NcUpdateArgs& a, int F, bool bf16, hipStream_t st) {
     if (a.n <= 0) return true;
     const size_t lds = nc_update_lds_bytes(F);
-    // two blocks per CU fit the LDS of the widest case; each walks several passes
     const int blocks = std::min(cdiv(a.n, 256 / F), 512);
     ScopedTimer timer("nc_update", st);
     if (F == 32) {

@@ -63,6 +63,7 @@ __global__ void k_baoa(BaoaArgs a) {
     const int n = a.n;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     bool over = false;
+    float dmax = 0.f;
     if (i < n) {
         const int r = a.rep_of_atom ? a.rep_of_atom[i] : 0;
         const double m = a.mass[i];
@@ -108,8 +109,13 @@ __global__ void k_baoa(BaoaArgs a) {
             }
         }
         over = a.pos_ref && !(d2 <= a.disp_thr2);
+        dmax = over && !(d2 <= 3.0e38) ? 3.0e38f : float(d2);  // finite bits for the record
     }
     if (a.flag && __ballot(over) != 0ull && (threadIdx.x & 63) == 0) atomicOr(a.flag, 1);
+    if (a.maxd2) {
+        for (int o = 32; o > 0; o >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, o));
+        if ((threadIdx.x & 63) == 0) atomicMax(a.maxd2, __float_as_uint(dmax));
+    }
 }
 
 // Per-replica kinetic energy (fixed-order float64 reduction, one block per

@@ -44,7 +44,14 @@ void launch_filter(int n, const double* pos, const RepGeom& geom, NbrScratch& s,
                    hipStream_t stream);
 void launch_set_flag(int* flag, int value, hipStream_t stream);
 void launch_disp_check(int n, const double* pos, const double* ref, double thr, int* flag, hipStream_t stream);
-void launch_finish_rebuild(int* flag, long long* n_rebuilds, hipStream_t stream);
+// Ends a (possibly skipped) rebuild: counts it, clears the trigger and, with
+// `maxd2`, restarts the displacement record ([0] since the build, [1] at the
+// previous decision).
+void launch_finish_rebuild(int* flag, long long* n_rebuilds, unsigned* maxd2, hipStream_t stream);
+// Per-outer-step decision: set `flag` when the largest displacement since
+// the last build, extrapolated over one more outer step from its growth
+// during the previous one, may reach `thr`.
+void launch_predict_rebuild(unsigned* maxd2, double thr, int* flag, hipStream_t stream);
 
 // --------------------------------------------------------------------- GEMM
 enum { EPI_NONE = 0, EPI_SILU = 1, EPI_DSILU = 2 };
@@ -134,12 +141,15 @@ void launch_head_bwd(const MpGeom& mg, const float* QK, const float* Vh, const f
 struct NcUpdateArgs {
     int n;
     const float *smid, *vmid;                          // message outputs [n][F], [n][3][F]
-    const float *UV, *M1, *m1, *M2, *m2, *Wqk, *WV;     // layer and projection weights (manifest layout)
+    const float *wt, *m1, *m2;                          // transposed weights (see transpose_nc_weights), biases
     float *QK, *Vh;                                    // [n][2 H n_c], [n][3][n_l]
 };
 // Fused update block + q/k/V projections of the NC embedding (widths <= 32);
 // returns false when the width is not supported by the fused kernel.
 bool launch_nc_update_proj(const NcUpdateArgs& a, int F, bool bf16, hipStream_t st);
+// [in][out] copies of U|V, M1, M2, W_qk and W_V (rounded to bfloat16 when bf16)
+void transpose_nc_weights(int F, const float* UV, const float* M1, const float* M2, const float* Wqk,
+                          const float* WV, bool bf16, float* out, hipStream_t st);
 
 // -------------------------------------------------------------- integrator
 struct BaoaArgs {
@@ -160,7 +170,8 @@ struct BaoaArgs {
     int ffl;
     const double* pos_ref;
     double disp_thr2;
-    int* flag;
+    int* flag;         // set when an atom moved more than sqrt(disp_thr2) since the last build
+    unsigned* maxd2;   // optional: running maximum of the squared displacement (float bits)
 };
 
 void launch_kick(int n, double* vel, const double* mass, const float* Fa, const float* Fb, double half_dt,

@@ -32,6 +32,11 @@ struct Model {
     float* h1_tab() const { return tab; }
     float* z_tab() const { return tab + int64_t(desc.n_species) * desc.width; }
     float* phi_tab() const { return tab + 2 * int64_t(desc.n_species) * desc.width; }
+    // NC models of width <= 32: the update-block and projection weights
+    // transposed to [in][out] (UV, M1, M2, W_qk, W_V), BF16-rounded for BF16
+    // models; refreshed with the tables.
+    float* ncw = nullptr;
+    static int64_t ncw_count(int F) { return 7 * int64_t(F) * F + int64_t(2 * 10 * 8) * F + 2 * int64_t(F); }
     void refresh_tables(hipStream_t s);
 };
 

@@ -321,12 +321,29 @@ __global__ void k_disp_check(int n, const double* __restrict__ pos, const double
     if (__ballot(over) != 0ull && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
-__global__ void k_finish_rebuild(int* flag, long long* n_rebuilds) {
+__global__ void k_finish_rebuild(int* flag, long long* n_rebuilds, unsigned* maxd2) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         if (*flag) {
             if (n_rebuilds) *n_rebuilds += 1;
+            if (maxd2) {
+                maxd2[0] = 0u;
+                maxd2[1] = 0u;
+            }
             *flag = 0;
         }
+    }
+}
+
+// maxd2 holds non-negative floats as bits (their order is that of the
+// unsigned integers).  Growth over the last outer step is extrapolated
+// twice over; the hard per-step check in k_baoa guards the rest.
+__global__ void k_predict_rebuild(unsigned* maxd2, double thr, int* flag) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double d = sqrt(double(__uint_as_float(maxd2[0])));
+        const double dp = sqrt(double(__uint_as_float(maxd2[1])));
+        const double pred = d + 2.0 * fmax(d - dp, 0.0);
+        if (!(pred < thr)) *flag = 1;  // also for non-finite displacements
+        maxd2[1] = maxd2[0];
     }
 }
 
@@ -419,8 +436,13 @@ void launch_disp_check(int n, const double* pos, const double* ref, double thr, 
     NNP_LAUNCH_CHECK();
 }
 
-void launch_finish_rebuild(int* flag, long long* n_rebuilds, hipStream_t stream) {
-    k_finish_rebuild<<<1, 64, 0, stream>>>(flag, n_rebuilds);
+void launch_finish_rebuild(int* flag, long long* n_rebuilds, unsigned* maxd2, hipStream_t stream) {
+    k_finish_rebuild<<<1, 64, 0, stream>>>(flag, n_rebuilds, maxd2);
+    NNP_LAUNCH_CHECK();
+}
+
+void launch_predict_rebuild(unsigned* maxd2, double thr, int* flag, hipStream_t stream) {
+    k_predict_rebuild<<<1, 64, 0, stream>>>(maxd2, thr, flag);
     NNP_LAUNCH_CHECK();
 }
 

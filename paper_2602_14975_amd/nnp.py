@@ -237,13 +237,15 @@ class Trajectory:
         self.lists_valid = 0
         self.n_rebuilds = 0
         self.n_rewinds = 0
+        self.n_replays = 0
 
     def _state(self, ke):
         return _abi.RespaState(self.sys.c(), self.sys.pos.data_ptr(), self.vel.data_ptr(), self.mass.data_ptr(),
                                self.gamma.data_ptr(), self.f_cons.data_ptr(), self.f_nc.data_ptr(),
                                self.energy.data_ptr(), self.pos_ref.data_ptr(), self.nl_cons.c(), self.nl_nc.c(),
                                self.step_count, self.first_step, self.lists_valid,
-                               ke.data_ptr() if ke is not None else None, self.n_rebuilds, self.n_rewinds)
+                               ke.data_ptr() if ke is not None else None, self.n_rebuilds, self.n_rewinds,
+                               self.n_replays)
 
     def respa_step(self, n_outer, ke=None):
         """Advances by n_outer outer steps (growing list buffers on
@@ -258,6 +260,7 @@ class Trajectory:
             self.lists_valid = int(st.lists_valid)
             self.n_rebuilds = int(st.n_rebuilds)
             self.n_rewinds = int(st.n_rewinds)
+            self.n_replays = int(st.n_replays)
             if code == _abi.NNP_ECAPACITY:
                 need_c, need_n = int(st.nl_cons.n_edges), int(st.nl_nc.n_edges)
                 if need_c > self.nl_cons.capacity:

@@ -101,6 +101,20 @@ def test_skin_does_not_change_trajectory(gpu_lib):
     assert a.n_rebuilds > b.n_rebuilds >= 1
 
 
+def test_stale_lists_are_replayed_exactly(gpu_lib):
+    """A skin too small for the per-outer-step rebuild prediction makes
+    inner steps exceed skin/2; those intervals are replayed with per-step
+    checks, and the trajectory equals one with a comfortable skin."""
+    s = synth.water_config(0)
+    m = s.standard_masses()
+    g = np.ones(s.n)
+    a = _run_pair(gpu_lib, s, m, g, "dmts_nc", 2.0, 4, 6, skin=0.04)[0]
+    b = _run_pair(gpu_lib, s, m, g, "dmts_nc", 2.0, 4, 6, skin=1.1)[0]
+    assert a.n_replays >= 1 and b.n_replays == 0
+    assert np.array_equal(a.positions(), b.positions())
+    assert np.array_equal(a.velocities(), b.velocities())
+
+
 def test_full_size_dmts_nc_runs(gpu_lib):
     """12,288 atoms at full widths: a few outer steps stay finite, keep the
     temperature near 300 K, and conserve nothing spurious (net force of the
