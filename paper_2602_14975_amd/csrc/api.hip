@@ -116,10 +116,12 @@ extern "C" nnp_status nnp_model_create(const nnp_model_desc* desc, nnp_model** o
     if (e == hipSuccess) e = hipMalloc(&m->tab, sizeof(float) * 5 * d.n_species * d.width);
     if (e == hipSuccess && d.kind == NNP_MODEL_NC && d.width <= 32)
         e = hipMalloc(&m->ncw, sizeof(float) * Model::ncw_count(d.width));
+    if (e == hipSuccess) e = hipMalloc(&m->wT, sizeof(float) * m->n_weights);
     if (e != hipSuccess) {
         (void)hipFree(m->w);
         if (m->tab) (void)hipFree(m->tab);
         if (m->ncw) (void)hipFree(m->ncw);
+        if (m->wT) (void)hipFree(m->wT);
         delete m;
         set_error(std::string("model set-up: ") + hipGetErrorString(e));
         return NNP_EDEVICE;
@@ -131,6 +133,7 @@ extern "C" nnp_status nnp_model_create(const nnp_model_desc* desc, nnp_model** o
         (void)hipFree(m->w);
         (void)hipFree(m->tab);
         if (m->ncw) (void)hipFree(m->ncw);
+        (void)hipFree(m->wT);
         delete m;
         throw;
     }
@@ -144,6 +147,7 @@ extern "C" void nnp_model_destroy(nnp_model* model) {
     if (m->w) (void)hipFree(m->w);
     if (m->tab) (void)hipFree(m->tab);
     if (m->ncw) (void)hipFree(m->ncw);
+    if (m->wT) (void)hipFree(m->wT);
     delete m;
 }
 
@@ -290,6 +294,28 @@ void Model::refresh_tables(hipStream_t s) {
     gemm_xwt(S, F, F, p(off_emb), F, p(lo.W1), p(lo.b1), z_tab(), F, EPI_SILU, h1_tab(), F, false, s, bf16());
     gemm_xwt(S, 3 * F, F, z_tab(), F, p(lo.W2), p(lo.b2), phi_tab(), 3 * F, EPI_NONE, nullptr, 0, false, s, bf16());
     if (ncw) transpose_nc_weights(F, p(lo.U), p(lo.M1), p(lo.M2), p(off_Wq), p(off_WV), bf16(), ncw, s);
+    // transposed mirror of the matrices used as G W
+    auto tr = [&](int64_t off, int rows, int cols) { launch_transpose(rows, cols, p(off), wT + off, s); };
+    for (int l = 0; l < n_layers(); ++l) {
+        const LayerOff& ll = loff[l];
+        tr(ll.W1, F, F);
+        tr(ll.W2, 3 * F, F);
+        tr(ll.U, 2 * F, F);
+        tr(ll.M1, F, 2 * F);
+        tr(ll.M2, 3 * F, F);
+    }
+    if (desc.kind == NNP_MODEL_CONS) {
+        tr(off_Wo, F, F);
+    } else {
+        tr(off_Wq, 2 * (desc.n_s + desc.n_l) * desc.n_c, F);
+        tr(off_WV, desc.n_l, F);
+    }
+}
+
+// out[M][K] = G[M][N] W[N][K] through the transposed mirror (X W^T form)
+static void gemm_gwt(const Model* m, int64_t off, int M, int N, int K, const float* G, int ldg, float* out, int ldo,
+                     int epi, const float* pre, int ldp, bool accum, hipStream_t s) {
+    gemm_xwt(M, K, N, G, ldg, m->pT(off), nullptr, out, ldo, epi, const_cast<float*>(pre), ldp, accum, s, m->bf16());
 }
 
 void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, ModelBuf& b, hipStream_t s) {
@@ -345,16 +371,15 @@ void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float*
         gemm_wgrad(n, 3 * F, F, b.gpqo, 3 * F, lb.z, F, dtheta + lo.M2, b.chunk_part, kChunk, false, s);
         colsum(n, 3 * F, b.gpqo, 3 * F, dtheta + lo.m2, b.chunk_part, kChunk, false, s);
     }
-    gemm_gw(n, 3 * F, F, b.gpqo, 3 * F, m->p(lo.M2), b.ga1, F, EPI_DSILU, lb.a1, F, false, s, m->bf16());
+    gemm_gwt(m, lo.M2, n, 3 * F, F, b.gpqo, 3 * F, b.ga1, F, EPI_DSILU, lb.a1, F, false, s);
     if (wg) {
         gemm_wgrad(n, F, 2 * F, b.ga1, F, lb.X, 2 * F, dtheta + lo.M1, b.chunk_part, kChunk, false, s);
         colsum(n, F, b.ga1, F, dtheta + lo.m1, b.chunk_part, kChunk, false, s);
     }
-    gemm_gw(n, F, 2 * F, b.ga1, F, m->p(lo.M1), b.gX, 2 * F, EPI_NONE, nullptr, 0, false, s, m->bf16());
+    gemm_gwt(m, lo.M1, n, F, 2 * F, b.ga1, F, b.gX, 2 * F, EPI_NONE, nullptr, 0, false, s);
     launch_norm_bwd(n, F, b.gs, b.gX, lb.X, lb.UV, b.gs2, b.gUV, s);  // gs2 = g_smid
     if (wg) gemm_wgrad(3 * n, 2 * F, F, b.gUV, 2 * F, lb.vmid, F, dtheta + lo.U, b.chunk_part, kChunk, false, s);
-    gemm_gw(3 * n, 2 * F, F, b.gUV, 2 * F, m->p(lo.U), b.gv, F, EPI_NONE, nullptr, 0, true, s,
-            m->bf16());  // gv = g_vmid
+    gemm_gwt(m, lo.U, 3 * n, 2 * F, F, b.gUV, 2 * F, b.gv, F, EPI_NONE, nullptr, 0, true, s);  // gv = g_vmid
     MpBwd a{};
     a.gsm = b.gs2;
     a.gvm = b.gv;
@@ -402,12 +427,12 @@ void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float*
         gemm_wgrad(n, 3 * F, F, b.gphi, 3 * F, lb.zphi, F, dtheta + lo.W2, b.chunk_part, kChunk, false, s);
         colsum(n, 3 * F, b.gphi, 3 * F, dtheta + lo.b2, b.chunk_part, kChunk, false, s);
     }
-    gemm_gw(n, 3 * F, F, b.gphi, 3 * F, m->p(lo.W2), b.gh1, F, EPI_DSILU, lb.h1, F, false, s, m->bf16());
+    gemm_gwt(m, lo.W2, n, 3 * F, F, b.gphi, 3 * F, b.gh1, F, EPI_DSILU, lb.h1, F, false, s);
     if (wg) {
         gemm_wgrad(n, F, F, b.gh1, F, b.s[l], F, dtheta + lo.W1, b.chunk_part, kChunk, false, s);
         colsum(n, F, b.gh1, F, dtheta + lo.b1, b.chunk_part, kChunk, false, s);
     }
-    gemm_gw(n, F, F, b.gh1, F, m->p(lo.W1), b.gs2, F, EPI_NONE, nullptr, 0, true, s, m->bf16());  // g_s_in
+    gemm_gwt(m, lo.W1, n, F, F, b.gh1, F, b.gs2, F, EPI_NONE, nullptr, 0, true, s);  // g_s_in
     std::swap(b.gs, b.gs2);
     std::swap(b.gv, b.gv2);
 }
@@ -441,7 +466,7 @@ void cons_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const
     if (energy) launch_rep_sum(sys.n_rep, t.rep_start, b.Ei, energy, s);
     if (!forces) return;
     launch_readout_bwd(n, F, b.ao, m->p(m->off_wo), b.gs2, s);
-    gemm_gw(n, F, F, b.gs2, F, m->p(m->off_Wo), b.gs, F, EPI_NONE, nullptr, 0, false, s, m->bf16());
+    gemm_gwt(m, m->off_Wo, n, F, F, b.gs2, F, b.gs, F, EPI_NONE, nullptr, 0, false, s);
     NNP_HIP(hipMemsetAsync(b.gv, 0, sizeof(float) * size_t(n) * 3 * F, s));
     for (int l = L - 1; l >= 0; --l) layer_backward(m, l, mg, b, forces, l != L - 1, nullptr, s);
 }
@@ -492,9 +517,9 @@ void nc_wgrad(const Model* m, const nnp_system& sys, const RepGeom& geom, const 
     gemm_xwt(3 * n, nl_, F, b.v[1], F, m->p(m->off_WV), nullptr, b.Vh, nl_, EPI_NONE, nullptr, 0, false, s, m->bf16());
     launch_head_bwd(mg, b.QK, b.Vh, dl_df, b.gQK, b.gVh, s);
     gemm_wgrad(n, HC, F, b.gQK, HC, b.s[1], F, dtheta + m->off_Wq, b.chunk_part, kChunk, false, s);
-    gemm_gw(n, HC, F, b.gQK, HC, m->p(m->off_Wq), b.gs, F, EPI_NONE, nullptr, 0, false, s, m->bf16());
+    gemm_gwt(m, m->off_Wq, n, HC, F, b.gQK, HC, b.gs, F, EPI_NONE, nullptr, 0, false, s);
     gemm_wgrad(3 * n, nl_, F, b.gVh, nl_, b.v[1], F, dtheta + m->off_WV, b.chunk_part, kChunk, false, s);
-    gemm_gw(3 * n, nl_, F, b.gVh, nl_, m->p(m->off_WV), b.gv, F, EPI_NONE, nullptr, 0, false, s, m->bf16());
+    gemm_gwt(m, m->off_WV, 3 * n, nl_, F, b.gVh, nl_, b.gv, F, EPI_NONE, nullptr, 0, false, s);
     layer_backward(m, 0, mg, b, nullptr, false, dtheta, s);
 }
 

@@ -317,6 +317,20 @@ void gemm_gw(int M, int N, int K, const float* G, int ldg, const float* W, float
     launch_gemm(g, s);
 }
 
+__global__ void k_transpose(int rows, int cols, const float* __restrict__ src, float* __restrict__ dst) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= int64_t(rows) * cols) return;
+    const int c = int(t / rows), r = int(t % rows);  // dst index t = c * rows + r
+    dst[t] = src[int64_t(r) * cols + c];
+}
+
+void launch_transpose(int rows, int cols, const float* src, float* dst, hipStream_t s) {
+    const int64_t total = int64_t(rows) * cols;
+    if (total <= 0) return;
+    k_transpose<<<cdiv(total, 256), 256, 0, s>>>(rows, cols, src, dst);
+    NNP_LAUNCH_CHECK();
+}
+
 // Weight adjoint dW[N][K] += sum_m G[m][n] X[m][k], deterministic: chunks of
 // rows write partials that k_reduce_chunks adds in chunk order.
 __global__ void k_reduce_chunks(int64_t count, int nchunks, const float* __restrict__ part, int64_t stride,

@@ -77,6 +77,8 @@ struct GemmArgs {
 void launch_gemm(const GemmArgs& g, hipStream_t s);
 void gemm_xwt(int M, int N, int K, const float* X, int ldx, const float* W, const float* b, float* out, int ldo,
               int epi, float* pre, int ldp, bool accum, hipStream_t s, bool bf16 = false);
+// dst[c][r] = src[r][c] for a rows x cols row-major matrix
+void launch_transpose(int rows, int cols, const float* src, float* dst, hipStream_t s);
 void gemm_gw(int M, int N, int K, const float* G, int ldg, const float* W, float* out, int ldo, int epi,
              const float* pre, int ldp, bool accum, hipStream_t s, bool bf16 = false);
 void gemm_wgrad(int M, int N, int K, const float* G, int ldg, const float* X, int ldx, float* dW, float* scratch,

@@ -36,6 +36,11 @@ struct Model {
     // transposed to [in][out] (UV, M1, M2, W_qk, W_V), BF16-rounded for BF16
     // models; refreshed with the tables.
     float* ncw = nullptr;
+    // A mirror of the weight vector in which every matrix that input adjoints
+    // multiply by (out = G W) is stored transposed at its own offset, so those
+    // products run as X W^T with k contiguous in both operands.
+    float* wT = nullptr;
+    const float* pT(int64_t off) const { return wT + off; }
     static int64_t ncw_count(int F) { return 7 * int64_t(F) * F + int64_t(2 * 10 * 8) * F + 2 * int64_t(F); }
     void refresh_tables(hipStream_t s);
 };
