@@ -240,6 +240,12 @@ typedef struct {
     double rewind_threshold;  /* kcal/mol/A; 0 disables */
     int32_t save_every;       /* >= 1 */
     int32_t sts_after_rewind; /* >= 0 */
+    /* 1: multiple-time-step runs without rewinding record one outer step as a
+     * HIP graph on the caller's stream and replay it (fewer launch gaps; the
+     * numbers are identical); 0: launch every kernel directly.  Graphs are
+     * not used while launch-site timers are enabled or for calls of fewer
+     * than three outer steps. */
+    int32_t graph;
 } respa_params;
 
 /* Device-resident trajectory state.  All pointers are caller-owned device

@@ -41,7 +41,8 @@ class RespaParams(C.Structure):
     _fields_ = [("dt_outer_fs", C.c_double), ("n_inner", C.c_int32), ("mode", C.c_int32),
                 ("thermostat", C.c_int32), ("check_every", C.c_int32), ("temperature_K", C.c_double),
                 ("seed", C.c_uint64), ("stream_id", C.c_uint64), ("skin", C.c_double),
-                ("rewind_threshold", C.c_double), ("save_every", C.c_int32), ("sts_after_rewind", C.c_int32)]
+                ("rewind_threshold", C.c_double), ("save_every", C.c_int32), ("sts_after_rewind", C.c_int32),
+                ("graph", C.c_int32)]
 
 
 class RespaState(C.Structure):

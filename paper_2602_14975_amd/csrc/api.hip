@@ -194,6 +194,7 @@ void carve_tables(Arena& a, int32_t n_rep, SysTables& t) {
     t.flags = a.take<int>(16);
     t.rep_bad = a.take<int>(n_rep);
     t.rebuilds = a.take<long long>(1);
+    t.o_step = a.take<uint64_t>(1);
 }
 
 // Uploads the replica tables of `sys` (pageable copies are staged by the
@@ -467,7 +468,7 @@ void cons_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const
     if (!forces) return;
     launch_readout_bwd(n, F, b.ao, m->p(m->off_wo), b.gs2, s);
     gemm_gwt(m, m->off_Wo, n, F, F, b.gs2, F, b.gs, F, EPI_NONE, nullptr, 0, false, s);
-    NNP_HIP(hipMemsetAsync(b.gv, 0, sizeof(float) * size_t(n) * 3 * F, s));
+    launch_zero(b.gv, int64_t(n) * 3 * F, nullptr, s);
     for (int l = L - 1; l >= 0; --l) layer_backward(m, l, mg, b, forces, l != L - 1, nullptr, s);
 }
 
@@ -881,6 +882,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     NNP_HIP(hipMemcpyAsync(c.t.seed, seeds, sizeof(uint64_t) * R, hipMemcpyHostToDevice, s));
     NNP_HIP(hipMemcpyAsync(c.t.stream, streams, sizeof(uint64_t) * R, hipMemcpyHostToDevice, s));
     NNP_HIP(hipMemcpyAsync(c.t.step_base, step_base, sizeof(uint64_t) * R, hipMemcpyHostToDevice, s));
+    launch_set_u64(c.t.o_step, 0, s);  // O-steps since the start of the call, advanced by the kicks
     const double rc_cons = cons->desc.cutoff + p->skin;
     const double rc_nc = mts ? nc->desc.cutoff + p->skin : 0.0;
     CellPlan plan = plan_cells(st->sys, rc_cons);
@@ -923,6 +925,8 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     ba.disp_thr2 = disp_thr * disp_thr;
     ba.flag = trig;
     ba.maxd2 = maxd2;
+    ba.step_offset = 0;
+    ba.step_dev = c.t.o_step;
 
     auto eval_cons = [&]() { cons_eval(cons, st->sys, g, c.t, lc, c.cons, st->energy, st->f_cons, s); };
     auto eval_inner = [&]() {
@@ -1021,11 +1025,10 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     auto sts_step = [&](double dt) {
         ba.force = st->f_cons;
         ba.dt = dt;
-        ba.step_offset = offset;
         launch_baoa(ba, s);
         rebuild_if_flagged();
         eval_cons();
-        launch_kick(n, st->vel, st->mass, st->f_cons, nullptr, 0.5 * dt, s);
+        launch_kick(n, st->vel, st->mass, st->f_cons, nullptr, 0.5 * dt, s, c.t.o_step);
         offset += 1;
         st->step += 1;
     };
@@ -1034,7 +1037,8 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     // flag a list that went stale; strict mode rebuilds after any inner step
     // whose displacement check fires.  Both give the same numbers whenever
     // no stale flag is raised (results do not depend on when lists are built).
-    auto mts_step = [&](bool strict) {
+    // (launches only; the caller advances offset and st->step by n_in)
+    auto mts_launches = [&](bool strict) {
         if (!strict) {
             launch_predict_rebuild(maxd2, disp_thr, trig, s);
             rebuild_if_flagged();
@@ -1044,22 +1048,74 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         for (int k = 0; k < n_in; ++k) {
             ba.force = st->f_nc;
             ba.dt = d;
-            ba.step_offset = offset;
             launch_baoa(ba, s);
             if (strict) rebuild_if_flagged();
             eval_inner();
-            launch_kick(n, st->vel, st->mass, st->f_nc, nullptr, 0.5 * d, s);
-            offset += 1;
-            st->step += 1;
+            launch_kick(n, st->vel, st->mass, st->f_nc, nullptr, 0.5 * d, s, c.t.o_step);
         }
         eval_cons();
         launch_kick(n, st->vel, st->mass, st->f_cons, st->f_nc, 0.5 * D, s);
+    };
+    // Predictive outer steps can be recorded once as a HIP graph and replayed:
+    // every launch argument is fixed within the call (the O-step counter and
+    // the rebuild decision live on the device) and nothing in them waits on
+    // the host.
+    struct OuterGraph {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t x = nullptr;
+        hipStream_t cs = nullptr;  // recording stream (the legacy default stream cannot record)
+        bool failed = false;
+        ~OuterGraph() {
+            if (x) (void)hipGraphExecDestroy(x);
+            if (g) (void)hipGraphDestroy(g);
+            if (cs) (void)hipStreamDestroy(cs);
+        }
+    } outer_graph;
+    auto mts_step = [&](bool strict, bool allow_graph) {
+        if (!strict && allow_graph && !outer_graph.failed) {
+            if (!outer_graph.x) {
+                // record on a private stream that first waits for the work
+                // already queued on s; the launches below then target it
+                bool ok = hipStreamCreateWithFlags(&outer_graph.cs, hipStreamNonBlocking) == hipSuccess;
+                ok = ok && hipStreamSynchronize(s) == hipSuccess;
+                const hipStream_t caller = s;
+                ok = ok && hipStreamBeginCapture(outer_graph.cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+                if (ok) {
+                    s = outer_graph.cs;
+                    try {
+                        mts_launches(false);
+                    } catch (const Fail&) {
+                        ok = false;
+                    }
+                    s = caller;
+                    hipGraph_t g = nullptr;
+                    ok = (hipStreamEndCapture(outer_graph.cs, &g) == hipSuccess) && ok && g;
+                    outer_graph.g = g;
+                    ok = ok && hipGraphInstantiate(&outer_graph.x, g, nullptr, nullptr, 0) == hipSuccess;
+                }
+                if (!ok) {
+                    // recording is an optimisation only: fall back to direct launches
+                    (void)hipGetLastError();
+                    outer_graph.failed = true;
+                }
+            }
+            if (outer_graph.x) {
+                NNP_HIP(hipGraphLaunch(outer_graph.x, s));
+            } else {
+                mts_launches(false);
+            }
+        } else {
+            mts_launches(strict);
+        }
+        offset += n_in;
+        st->step += n_in;
     };
 
     // predictive rebuilds for multiple-time-step runs without rewinding; a
     // stale list found at a check sends the run back to the last snapshot,
     // which is replayed in strict mode
     const bool predictive = mts && !rewind && n_in > 1;
+    const bool use_graph = predictive && p->graph != 0 && n_outer >= 3 && !timers_active();
     if (predictive) {
         // the displacement record starts empty: begin from fresh lists
         launch_set_flag(trig, 1, s);
@@ -1077,7 +1133,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
             frame_offset = offset;
             since_save = 0;
         }
-        if (mts) mts_step(strict);
+        if (mts) mts_step(strict, use_graph && n_outer - o >= 1);
         else sts_step(D);
         ++since_save;
         if (rewind) {
@@ -1092,6 +1148,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
                 copy_state(frame, false);
                 st->step -= offset - frame_offset;
                 offset = frame_offset;
+                launch_set_u64(c.t.o_step, offset, s);
                 launch_set_flag(trig, 1, s);
                 rebuild_if_flagged();
                 for (int k = 0; k < p->sts_after_rewind; ++k) sts_step(d);
@@ -1109,6 +1166,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
                 copy_state(c.rs, false);
                 st->step -= offset - snap_offset;
                 offset = snap_offset;
+                launch_set_u64(c.t.o_step, offset, s);
                 strict_until = o + 1;
                 o = snap_o - 1;
                 st->n_replays += 1;

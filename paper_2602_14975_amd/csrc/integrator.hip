@@ -7,6 +7,8 @@
 // (seed_r, stream_r) of the atom's replica with counter (local atom index,
 // O-step index, 0, 0); the four words map to uniforms ((w >> 11) + 0.5) 2^-53
 // and Box-Muller gives the x, y, z normals.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -44,8 +46,9 @@ __device__ __forceinline__ void normals3(uint64_t atom, uint64_t step, uint64_t 
 
 // v += coef * (Fa - Fb) / m   (Fb may be null)
 __global__ void k_kick(int n, double* __restrict__ vel, const double* __restrict__ mass, const float* __restrict__ Fa,
-                       const float* __restrict__ Fb, double coef) {
+                       const float* __restrict__ Fb, double coef, uint64_t* bump) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bump && i == 0) *bump += 1;
     if (i >= n) return;
     const double im = 1.0 / mass[i];
 #pragma unroll
@@ -82,7 +85,7 @@ __global__ void k_baoa(BaoaArgs a) {
         const double c1 = exp(-gamma * a.dt);
         const double sigma = sqrt((1.0 - c1 * c1) * kKb * a.temperature * kAcc * im);
         const uint64_t local = uint64_t(i - a.rep_start[r]);
-        const uint64_t step = a.step_base[r] + a.step_offset;
+        const uint64_t step = a.step_base[r] + a.step_offset + (a.step_dev ? *a.step_dev : 0ull);
         double g[3];
         normals3(local, step, a.seed[r], a.stream[r], g);
         double nv[3];
@@ -152,8 +155,30 @@ __global__ void __launch_bounds__(256) k_kinetic(const int64_t* __restrict__ rep
 
 // ------------------------------------------------------------------- host --
 void launch_kick(int n, double* vel, const double* mass, const float* Fa, const float* Fb, double half_dt,
-                 hipStream_t s) {
-    k_kick<<<cdiv(n, 256), 256, 0, s>>>(n, vel, mass, Fa, Fb, half_dt * kAcc);
+                 hipStream_t s, uint64_t* bump) {
+    k_kick<<<cdiv(n, 256), 256, 0, s>>>(n, vel, mass, Fa, Fb, half_dt * kAcc, bump);
+    NNP_LAUNCH_CHECK();
+}
+
+__global__ void k_set_u64(uint64_t* p, uint64_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+void launch_set_u64(uint64_t* p, uint64_t value, hipStream_t s) {
+    k_set_u64<<<1, 64, 0, s>>>(p, value);
+    NNP_LAUNCH_CHECK();
+}
+
+__global__ void k_zero(uint32_t* __restrict__ p, int64_t words, const int* __restrict__ run) {
+    if (run && *run == 0) return;
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < words; t += int64_t(gridDim.x) * blockDim.x)
+        p[t] = 0u;
+}
+
+void launch_zero(void* p, int64_t words, const int* run, hipStream_t s) {
+    if (words <= 0) return;
+    const int blocks = int(std::min<int64_t>(cdiv(words, 256), 2048));
+    k_zero<<<blocks, 256, 0, s>>>(static_cast<uint32_t*>(p), words, run);
     NNP_LAUNCH_CHECK();
 }
 

@@ -11,12 +11,16 @@ namespace nnp {
 
 // Brackets one launch with HIP events when its site is enabled
 // (nnp_timer_enable); otherwise costs one branch.
+// With `by_launch`, the events are not recorded around the launch but handed
+// to it (hipExtLaunchKernelGGL), which timestamps the kernel itself: the
+// interval then excludes dispatch gaps and host-side delays.
 struct ScopedTimer {
     const char* name;
     hipStream_t stream;
     hipEvent_t a = nullptr, b = nullptr;
     bool active = false;
-    ScopedTimer(const char* site, hipStream_t s);
+    bool by_launch = false;
+    ScopedTimer(const char* site, hipStream_t s, bool by_launch = false);
     ~ScopedTimer();
 };
 
@@ -169,6 +173,7 @@ struct BaoaArgs {
     const uint64_t* stream;
     const uint64_t* step_base;
     uint64_t step_offset;
+    const uint64_t* step_dev;  // optional device O-step counter added to step_offset
     int ffl;
     const double* pos_ref;
     double disp_thr2;
@@ -176,8 +181,14 @@ struct BaoaArgs {
     unsigned* maxd2;   // optional: running maximum of the squared displacement (float bits)
 };
 
+// v += half_dt * ACC * (Fa - Fb) / m; with `bump`, also advances that O-step
+// counter by one (read by the next k_baoa)
 void launch_kick(int n, double* vel, const double* mass, const float* Fa, const float* Fb, double half_dt,
-                 hipStream_t s);
+                 hipStream_t s, uint64_t* bump = nullptr);
+void launch_set_u64(uint64_t* p, uint64_t value, hipStream_t s);
+// zero fill as a kernel (safe inside recorded graphs); with `run`, only when *run != 0
+void launch_zero(void* p, int64_t words, const int* run, hipStream_t s);
+bool timers_active();
 void launch_baoa(const BaoaArgs& a, hipStream_t s);
 void launch_kinetic(int n_rep, const int64_t* rep_start, int n, const double* pos, const double* vel,
                     const double* mass, double* ke, int* bad, hipStream_t s);

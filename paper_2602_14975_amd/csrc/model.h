@@ -69,6 +69,7 @@ struct SysTables {
     int* flags;
     int* rep_bad;
     long long* rebuilds;
+    uint64_t* o_step;  // O-steps since the start of a respa call (read by k_baoa, advanced by the kicks)
 };
 
 struct RespaBuf {

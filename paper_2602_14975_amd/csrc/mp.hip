@@ -32,6 +32,8 @@
 //   With weight adjoints requested (NC distillation), the filter weight
 //   adjoints of the message n -> o are accumulated as well (each directed
 //   message is counted by its receiver).
+#include <hip/hip_ext.h>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -46,7 +48,7 @@ struct EdgeSlot {
     float fc, dfc;  // f(r), f'(r)
     float u[3];
     float ir;       // 1 / r
-    int j, e, t;    // neighbour, CSR entry, neighbour species
+    int j, t;       // neighbour, neighbour species
 };
 
 // Radial values of one edge: float64 Chebyshev recurrence for sin(k theta)
@@ -122,7 +124,6 @@ __device__ __forceinline__ int stage_batch(const MpGeom& mg, bool active, int e,
         s.u[2] = float(dz * ir);
         s.ir = float(ir);
         s.j = j;
-        s.e = e;
         s.t = species ? min(max(species[j], 0), mg.n_species - 1) : 0;
     }
     wave_sync_lds();
@@ -167,6 +168,11 @@ struct MpShape {
     static constexpr int WPA = F / G;                  // wavefronts per atom
     static constexpr int APW = 64 / G;                 // atoms per wavefront
     static constexpr int APB = kMpWaves / WPA * APW;   // atoms per block
+    // With several wavefronts per atom, the first one stages each batch of
+    // edges for all of them (block barriers around the batch): the edge
+    // geometry is computed once per atom and the slots take less LDS.
+    static constexpr bool SHARED = WPA > 1;
+    static constexpr int SLOT_SETS = SHARED ? kMpWaves / WPA : kMpWaves;
 };
 
 template <int F, int K, int CUT, bool L0>
@@ -174,7 +180,8 @@ __global__ void __launch_bounds__(64 * kMpWaves)
 k_message_fwd(MpGeom mg, MpFwd a) {
     using S = MpShape<F>;
     constexpr int G = S::G, APW = S::APW, WPA = S::WPA, FPL = 1;
-    __shared__ EdgeSlot<K> slots_all[kMpWaves][APW][G];
+    __shared__ EdgeSlot<K> slots_all[S::SLOT_SETS][APW][G];
+    __shared__ int batch_cnt[S::SLOT_SETS];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane / G, l = lane % G;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -182,7 +189,7 @@ k_message_fwd(MpGeom mg, MpFwd a) {
     const bool active = i < mg.n;
     const int n = mg.n;
     const int f0 = (w % WPA) * 64 + l;
-    EdgeSlot<K>* slots = slots_all[w][g];
+    EdgeSlot<K>* slots = slots_all[S::SHARED ? w / WPA : w][g];
 
     float wr[3][FPL][K], bb[3][FPL];
 #pragma unroll
@@ -203,9 +210,23 @@ k_message_fwd(MpGeom mg, MpFwd a) {
         mg.geom.get(i, L, inv);
         xi = mg.pos[i]; yi = mg.pos[n + i]; zi = mg.pos[2 * n + i];
     }
-    for (int base = 0; __ballot(start + base < end) != 0ull; base += G) {
-        const int cnt = stage_batch<G, K, CUT, false>(mg, active, start + base + l, end, l, g, xi, yi, zi, L, inv,
-                                                       slots, L0 ? a.species : nullptr);
+    for (int base = 0; S::SHARED ? __syncthreads_or(start + base < end) != 0
+                                 : __ballot(start + base < end) != 0ull;
+         base += G) {
+        int cnt;
+        if constexpr (S::SHARED) {
+            if (w % WPA == 0) {
+                const int c = stage_batch<G, K, CUT, false>(mg, active, start + base + l, end, l, g, xi, yi, zi, L,
+                                                          inv, slots, L0 ? a.species : nullptr);
+                if (lane == 0) batch_cnt[w / WPA] = c;
+            }
+            __syncthreads();
+            cnt = __builtin_amdgcn_readfirstlane(batch_cnt[w / WPA]);  // wavefront-uniform
+        } else {
+            cnt = stage_batch<G, K, CUT, false>(mg, active, start + base + l, end, l, g, xi, yi, zi, L, inv, slots,
+                                              L0 ? a.species : nullptr);
+        }
+#pragma unroll 1
         for (int t = 0; t < cnt; ++t) {
             const EdgeSlot<K>& s = slots[t];
             const float* phj = L0 ? a.phi_tab + s.t * 3 * F + f0 : a.phi + int64_t(s.j) * 3 * F + f0;
@@ -240,7 +261,8 @@ k_message_fwd(MpGeom mg, MpFwd a) {
                 }
             }
         }
-        wave_sync_lds();
+        if constexpr (S::SHARED) __syncthreads();  // the slots are restaged next
+        else wave_sync_lds();
     }
     if (active) {
         float out[FPL];
@@ -267,7 +289,8 @@ k_message_bwd(MpGeom mg, MpBwd a) {
     using S = MpShape<F>;
     constexpr int G = S::G, APW = S::APW, WPA = S::WPA, FPL = 1;
     static_assert(!WGRAD || WPA == 1, "filter weight adjoints need one wavefront per atom");
-    __shared__ EdgeSlot<K> slots_all[kMpWaves][APW][G];
+    __shared__ EdgeSlot<K> slots_all[S::SLOT_SETS][APW][G];
+    __shared__ int batch_cnt[S::SLOT_SETS];
     __shared__ float fpart[kMpWaves][APW][3];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane / G, l = lane % G;
@@ -276,7 +299,7 @@ k_message_bwd(MpGeom mg, MpBwd a) {
     const bool active = i < mg.n;
     const int n = mg.n;
     const int f0 = (w % WPA) * 64 + l;
-    EdgeSlot<K>* slots = slots_all[w][g];
+    EdgeSlot<K>* slots = slots_all[S::SHARED ? w / WPA : w][g];
 
     float wr[3][FPL][K], bb[3][FPL];
 #pragma unroll
@@ -324,9 +347,23 @@ k_message_bwd(MpGeom mg, MpBwd a) {
 #pragma unroll
         for (int q = 0; q < FPL; ++q) gs_o[q] = tg.x[q];
     }
-    for (int base = 0; __ballot(start + base < end) != 0ull; base += G) {
-        const int cnt = stage_batch<G, K, CUT, GEO>(mg, active, start + base + l, end, l, g, xi, yi, zi, L, inv,
-                                                     slots, L0 ? a.species : nullptr);
+    for (int base = 0; S::SHARED ? __syncthreads_or(start + base < end) != 0
+                                 : __ballot(start + base < end) != 0ull;
+         base += G) {
+        int cnt;
+        if constexpr (S::SHARED) {
+            if (w % WPA == 0) {
+                const int c = stage_batch<G, K, CUT, GEO>(mg, active, start + base + l, end, l, g, xi, yi, zi, L,
+                                                          inv, slots, L0 ? a.species : nullptr);
+                if (lane == 0) batch_cnt[w / WPA] = c;
+            }
+            __syncthreads();
+            cnt = __builtin_amdgcn_readfirstlane(batch_cnt[w / WPA]);  // wavefront-uniform
+        } else {
+            cnt = stage_batch<G, K, CUT, GEO>(mg, active, start + base + l, end, l, g, xi, yi, zi, L, inv, slots,
+                                              L0 ? a.species : nullptr);
+        }
+#pragma unroll 1
         for (int t = 0; t < cnt; ++t) {
             const EdgeSlot<K>& s = slots[t];
             const int j = s.j;
@@ -408,7 +445,8 @@ k_message_bwd(MpGeom mg, MpBwd a) {
                 fz += dr * u2 + (gu2 - ud * u2) * s.ir;
             }
         }
-        wave_sync_lds();
+        if constexpr (S::SHARED) __syncthreads();  // the slots are restaged next
+        else wave_sync_lds();
     }
     if (GEO) {
         fx = group_sum<G>(fx);
@@ -479,21 +517,29 @@ k_message_bwd(MpGeom mg, MpBwd a) {
 
 // ------------------------------------------------------------------- host --
 
+// launches `kern`, timestamped by the launch itself when the site is timed
+template <typename Kern, typename... Args>
+static void launch_k(const ScopedTimer& t, Kern kern, dim3 grid, hipStream_t s, Args... args) {
+    if (t.active && t.by_launch) hipExtLaunchKernelGGL(kern, grid, dim3(64 * kMpWaves), 0, s, t.a, t.b, 0, args...);
+    else kern<<<grid, 64 * kMpWaves, 0, s>>>(args...);
+}
+
 template <int F, int K, int CUT>
-static void fwd_inst(const MpGeom& mg, const MpFwd& a, hipStream_t s) {
+static void fwd_inst(const MpGeom& mg, const MpFwd& a, hipStream_t s, const ScopedTimer& t) {
     const dim3 grid(cdiv(mg.n, MpShape<F>::APB));
-    if (a.phi_tab) k_message_fwd<F, K, CUT, true><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
-    else k_message_fwd<F, K, CUT, false><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
+    if (a.phi_tab) launch_k(t, k_message_fwd<F, K, CUT, true>, grid, s, mg, a);
+    else launch_k(t, k_message_fwd<F, K, CUT, false>, grid, s, mg, a);
 }
 
 template <int F, int K, int CUT, bool L0>
-static void bwd_inst_l(const MpGeom& mg, const MpBwd& a, bool geo, bool wgrad, hipStream_t s) {
+static void bwd_inst_l(const MpGeom& mg, const MpBwd& a, bool geo, bool wgrad, hipStream_t s,
+                       const ScopedTimer& t) {
     dim3 grid(cdiv(mg.n, MpShape<F>::APB));
     if constexpr (CUT == 1 && F <= 64) {
         // filter weight adjoints exist for the NC embedding only
         if (wgrad) {
-            if (geo) k_message_bwd<F, K, CUT, true, true, L0><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
-            else k_message_bwd<F, K, CUT, false, true, L0><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
+            if (geo) launch_k(t, k_message_bwd<F, K, CUT, true, true, L0>, grid, s, mg, a);
+            else launch_k(t, k_message_bwd<F, K, CUT, false, true, L0>, grid, s, mg, a);
             return;
         }
     } else {
@@ -502,14 +548,14 @@ static void bwd_inst_l(const MpGeom& mg, const MpBwd& a, bool geo, bool wgrad, h
             throw Fail{NNP_EINVAL};
         }
     }
-    if (geo) k_message_bwd<F, K, CUT, true, false, L0><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
-    else k_message_bwd<F, K, CUT, false, false, L0><<<grid, 64 * kMpWaves, 0, s>>>(mg, a);
+    if (geo) launch_k(t, k_message_bwd<F, K, CUT, true, false, L0>, grid, s, mg, a);
+    else launch_k(t, k_message_bwd<F, K, CUT, false, false, L0>, grid, s, mg, a);
 }
 
 template <int F, int K, int CUT>
-static void bwd_inst(const MpGeom& mg, const MpBwd& a, bool geo, bool wgrad, hipStream_t s) {
-    if (a.phi_tab) bwd_inst_l<F, K, CUT, true>(mg, a, geo, wgrad, s);
-    else bwd_inst_l<F, K, CUT, false>(mg, a, geo, wgrad, s);
+static void bwd_inst(const MpGeom& mg, const MpBwd& a, bool geo, bool wgrad, hipStream_t s, const ScopedTimer& t) {
+    if (a.phi_tab) bwd_inst_l<F, K, CUT, true>(mg, a, geo, wgrad, s, t);
+    else bwd_inst_l<F, K, CUT, false>(mg, a, geo, wgrad, s, t);
 }
 
 int mp_blocks(int n, int F) {
@@ -522,16 +568,16 @@ int mp_blocks(int n, int F) {
 
 void launch_message_fwd(int F, int K, int cut, const MpGeom& mg, const MpFwd& a, hipStream_t s) {
     if (mg.n <= 0) return;
-    ScopedTimer timer(cut == 0 ? "message_fwd" : "nc_message_fwd", s);
-    NNP_DISPATCH_MP(128, 16, 0, (fwd_inst<128, 16, 0>(mg, a, s)));
-    NNP_DISPATCH_MP(64, 16, 0, (fwd_inst<64, 16, 0>(mg, a, s)));
-    NNP_DISPATCH_MP(32, 16, 0, (fwd_inst<32, 16, 0>(mg, a, s)));
-    NNP_DISPATCH_MP(16, 16, 0, (fwd_inst<16, 16, 0>(mg, a, s)));
-    NNP_DISPATCH_MP(32, 8, 1, (fwd_inst<32, 8, 1>(mg, a, s)));
-    NNP_DISPATCH_MP(16, 8, 1, (fwd_inst<16, 8, 1>(mg, a, s)));
-    NNP_DISPATCH_MP(64, 8, 1, (fwd_inst<64, 8, 1>(mg, a, s)));
-    NNP_DISPATCH_MP(8, 16, 0, (fwd_inst<8, 16, 0>(mg, a, s)));
-    NNP_DISPATCH_MP(8, 8, 1, (fwd_inst<8, 8, 1>(mg, a, s)));
+    ScopedTimer timer(cut == 0 ? "message_fwd" : "nc_message_fwd", s, true);
+    NNP_DISPATCH_MP(128, 16, 0, (fwd_inst<128, 16, 0>(mg, a, s, timer)));
+    NNP_DISPATCH_MP(64, 16, 0, (fwd_inst<64, 16, 0>(mg, a, s, timer)));
+    NNP_DISPATCH_MP(32, 16, 0, (fwd_inst<32, 16, 0>(mg, a, s, timer)));
+    NNP_DISPATCH_MP(16, 16, 0, (fwd_inst<16, 16, 0>(mg, a, s, timer)));
+    NNP_DISPATCH_MP(32, 8, 1, (fwd_inst<32, 8, 1>(mg, a, s, timer)));
+    NNP_DISPATCH_MP(16, 8, 1, (fwd_inst<16, 8, 1>(mg, a, s, timer)));
+    NNP_DISPATCH_MP(64, 8, 1, (fwd_inst<64, 8, 1>(mg, a, s, timer)));
+    NNP_DISPATCH_MP(8, 16, 0, (fwd_inst<8, 16, 0>(mg, a, s, timer)));
+    NNP_DISPATCH_MP(8, 8, 1, (fwd_inst<8, 8, 1>(mg, a, s, timer)));
     set_error("unsupported message-passing shape");
     throw Fail{NNP_EINVAL};
 }
@@ -539,16 +585,16 @@ void launch_message_fwd(int F, int K, int cut, const MpGeom& mg, const MpFwd& a,
 void launch_message_bwd(int F, int K, int cut, const MpGeom& mg, const MpBwd& a, bool geo, bool wgrad,
                         hipStream_t s) {
     if (mg.n <= 0) return;
-    ScopedTimer timer(cut == 0 ? "message_bwd" : "nc_message_bwd", s);
-    NNP_DISPATCH_MP(128, 16, 0, (bwd_inst<128, 16, 0>(mg, a, geo, wgrad, s)));
-    NNP_DISPATCH_MP(64, 16, 0, (bwd_inst<64, 16, 0>(mg, a, geo, wgrad, s)));
-    NNP_DISPATCH_MP(32, 16, 0, (bwd_inst<32, 16, 0>(mg, a, geo, wgrad, s)));
-    NNP_DISPATCH_MP(16, 16, 0, (bwd_inst<16, 16, 0>(mg, a, geo, wgrad, s)));
-    NNP_DISPATCH_MP(32, 8, 1, (bwd_inst<32, 8, 1>(mg, a, geo, wgrad, s)));
-    NNP_DISPATCH_MP(16, 8, 1, (bwd_inst<16, 8, 1>(mg, a, geo, wgrad, s)));
-    NNP_DISPATCH_MP(64, 8, 1, (bwd_inst<64, 8, 1>(mg, a, geo, wgrad, s)));
-    NNP_DISPATCH_MP(8, 16, 0, (bwd_inst<8, 16, 0>(mg, a, geo, wgrad, s)));
-    NNP_DISPATCH_MP(8, 8, 1, (bwd_inst<8, 8, 1>(mg, a, geo, wgrad, s)));
+    ScopedTimer timer(cut == 0 ? "message_bwd" : "nc_message_bwd", s, true);
+    NNP_DISPATCH_MP(128, 16, 0, (bwd_inst<128, 16, 0>(mg, a, geo, wgrad, s, timer)));
+    NNP_DISPATCH_MP(64, 16, 0, (bwd_inst<64, 16, 0>(mg, a, geo, wgrad, s, timer)));
+    NNP_DISPATCH_MP(32, 16, 0, (bwd_inst<32, 16, 0>(mg, a, geo, wgrad, s, timer)));
+    NNP_DISPATCH_MP(16, 16, 0, (bwd_inst<16, 16, 0>(mg, a, geo, wgrad, s, timer)));
+    NNP_DISPATCH_MP(32, 8, 1, (bwd_inst<32, 8, 1>(mg, a, geo, wgrad, s, timer)));
+    NNP_DISPATCH_MP(16, 8, 1, (bwd_inst<16, 8, 1>(mg, a, geo, wgrad, s, timer)));
+    NNP_DISPATCH_MP(64, 8, 1, (bwd_inst<64, 8, 1>(mg, a, geo, wgrad, s, timer)));
+    NNP_DISPATCH_MP(8, 16, 0, (bwd_inst<8, 16, 0>(mg, a, geo, wgrad, s, timer)));
+    NNP_DISPATCH_MP(8, 8, 1, (bwd_inst<8, 8, 1>(mg, a, geo, wgrad, s, timer)));
     set_error("unsupported message-passing shape");
     throw Fail{NNP_EINVAL};
 }

@@ -395,7 +395,7 @@ void upload_cell_plan(const CellPlan& plan, NbrScratch& s, hipStream_t stream) {
 void launch_build(int n, const double* pos, const RepGeom& geom, const CellPlan& plan, NbrScratch& s,
                   const int* run, double radius, int64_t capacity, int* offsets, int* nbr, int* rev,
                   double* pos_ref, hipStream_t stream) {
-    NNP_HIP(hipMemsetAsync(s.cell_count, 0, sizeof(int) * (plan.n_cells + 1), stream));
+    launch_zero(s.cell_count, plan.n_cells + 1, run, stream);
     k_cell_assign<<<cdiv(n, 256), 256, 0, stream>>>(n, pos, geom, s.grid_m, s.grid_base, run, s.cell_of_atom,
                                                     s.slot_of_atom, s.cell_count, pos_ref);
     k_scan<<<1, 1024, 0, stream>>>(plan.n_cells, s.cell_count, s.cell_start, run);

@@ -21,22 +21,25 @@ std::unordered_map<std::string, Site> g_sites;
 bool g_any = false;
 }  // namespace
 
-ScopedTimer::ScopedTimer(const char* site, hipStream_t s) : name(site), stream(s) {
+ScopedTimer::ScopedTimer(const char* site, hipStream_t s, bool launch_events)
+    : name(site), stream(s), by_launch(launch_events) {
     if (!g_any) return;
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_sites.find(name);
     if (it == g_sites.end() || !it->second.on) return;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
-    if (hipEventRecord(a, stream) != hipSuccess) return;
+    if (!by_launch && hipEventRecord(a, stream) != hipSuccess) return;
     active = true;
 }
 
 ScopedTimer::~ScopedTimer() {
     if (!active) return;
-    (void)hipEventRecord(b, stream);
+    if (!by_launch) (void)hipEventRecord(b, stream);
     std::lock_guard<std::mutex> lk(g_mu);
     g_sites[name].ev.emplace_back(a, b);
 }
+
+bool timers_active() { return g_any; }
 
 }  // namespace nnp
 

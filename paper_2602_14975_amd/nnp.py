@@ -289,8 +289,8 @@ _MODES = {"dmts_nc": _abi.NNP_MODE_DMTS_NC, "sts": _abi.NNP_MODE_STS, "dmts": _a
 
 
 def respa_params(dt_outer, n_inner, temperature=300.0, seed=4000, stream_id=0, mode="dmts_nc", thermostat="langevin",
-                 skin=1.0, check_every=1, rewind_threshold=0.0, save_every=1, sts_after_rewind=0):
+                 skin=1.0, check_every=1, rewind_threshold=0.0, save_every=1, sts_after_rewind=0, graph=True):
     return _abi.RespaParams(float(dt_outer), int(n_inner), _MODES[mode],
                             _abi.NNP_THERMO_FFL if thermostat == "ffl" else _abi.NNP_THERMO_LANGEVIN,
                             int(check_every), float(temperature), int(seed), int(stream_id), float(skin),
-                            float(rewind_threshold), int(save_every), int(sts_after_rewind))
+                            float(rewind_threshold), int(save_every), int(sts_after_rewind), int(bool(graph)))
