@@ -199,6 +199,19 @@ def test_recorded_outer_step_matches_direct_launches(gpu_lib):
     assert np.array_equal(a.positions(), b.positions())
 
 
+def test_split_calls_equal_one_call(gpu_lib):
+    """Resuming from the state a call leaves behind (the checkpoint) gives
+    the trajectory of one uninterrupted call, bit for bit."""
+    a, _ = _traj(gpu_lib, "dmts_nc", 2.0, 4, check_every=2)
+    b, _ = _traj(gpu_lib, "dmts_nc", 2.0, 4, check_every=2)
+    a.respa_step(8)
+    for k in (3, 1, 4):
+        b.respa_step(k)
+    assert a.step_count == b.step_count == 32
+    assert np.array_equal(a.positions(), b.positions()) and np.array_equal(a.velocities(), b.velocities())
+    assert torch.equal(a.f_cons, b.f_cons) and torch.equal(a.f_nc, b.f_nc)
+
+
 def test_rewind_never_tripping_changes_nothing(gpu_lib):
     a, ka = _traj(gpu_lib, "dmts_nc", 2.0, 4)
     b, kb = _traj(gpu_lib, "dmts_nc", 2.0, 4, rewind_threshold=1e9, save_every=2, sts_after_rewind=3)
