@@ -84,20 +84,21 @@ def run_gpu(args):
         traj = nnp.Trajectory(cons, nc if mode == "dmts_nc" else None, system, v0, m, gamma, prm)
         traj.respa_step(max(1, warmup))
         torch.cuda.synchronize()
+        if timer_site:
+            # the kernel's durations over the timed region itself, from HIP
+            # events that its launches timestamp (no host-side records in
+            # between); with timers on, outer steps are launched directly
+            # rather than replayed from a recorded graph
+            lib.nnp_timer_enable(timer_site.encode(), 1)
+            tot, cnt = C.c_double(), C.c_int64()
+            lib.nnp_timer_read(timer_site.encode(), C.byref(tot), C.byref(cnt), 1)
         t0 = time.perf_counter()
         traj.respa_step(steps)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         kt = None
         if timer_site:
-            # kernel durations from HIP events on the launch stream, over a
-            # further stretch of the same run (launch-site timers switch the
-            # recorded outer step off, so they stay out of the timed region)
-            lib.nnp_timer_enable(timer_site.encode(), 1)
             tot, cnt = C.c_double(), C.c_int64()
-            lib.nnp_timer_read(timer_site.encode(), C.byref(tot), C.byref(cnt), 1)
-            traj.respa_step(min(steps, 50))
-            torch.cuda.synchronize()
             lib.nnp_timer_read(timer_site.encode(), C.byref(tot), C.byref(cnt), 1)
             lib.nnp_timer_enable(timer_site.encode(), 0)
             kt = (tot.value, cnt.value)
