@@ -411,7 +411,7 @@ def main():
         avg_s = tot_ms / launches * 1e-3
         flops = message_bwd_flops_per_edge(F, K) * g["n_edges5"]
         achieved = flops / avg_s / 1e12
-        roof = {"bound": "alu", "kernel": "k_message_bwd<128,16,cos>", "achieved": round(achieved, 2),
+        roof = {"bound": "alu", "kernel": "k_message_bwd_mx (F=128, K=16, cosine cutoff)", "achieved": round(achieved, 2),
                 "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
                 "traffic": measured_traffic(), "avg_launch_us": round(avg_s * 1e6, 1), "launches": launches,
                 "edges_per_launch": g["n_edges5"]}

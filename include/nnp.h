@@ -366,6 +366,22 @@ double nnp_server_clock(const nnp_server* server);
 nnp_status nnp_timer_enable(const char* site, int32_t on);
 nnp_status nnp_timer_read(const char* site, double* total_ms, int64_t* launches, int32_t reset);
 
+/* ------------------------------------------------------- kernel choice --
+ * Message kernels of the conservative embedding (the message step
+ * s_i += sum_j a_ij, v_i += sum_j (b_ij v_j + u_ij c_ij) of the models
+ * section above, after the paper's Methods "Model architecture", and its
+ * reverse), chosen process-wide for launches issued after the call:
+ *   NNP_MP_AUTO (0): the matrix-core kernels for the shapes they cover
+ *     (width 128, 16 Bessel functions, cosine cutoff, force evaluation);
+ *     the radial filter runs there as split FP16 products at FP32-equivalent
+ *     precision; the vector kernels elsewhere.
+ *   NNP_MP_VECTOR (1): the vector kernels (plain FP32 filter) everywhere.
+ * Both give results within FP32 rounding of each other; this is for
+ * measuring one against the other.  Other values: NNP_EINVAL. */
+#define NNP_MP_AUTO 0
+#define NNP_MP_VECTOR 1
+nnp_status nnp_set_message_kernels(int32_t mode);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,7 +15,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnnp.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "neighbors.hip", "gemm.hip", "mp.hip", "blocks.hip", "integrator.hip", "server.hip", "timers.hip"]
+SOURCES = [
+    "api.hip", "neighbors.hip", "gemm.hip", "mp.hip", "mp_mx.hip", "blocks.hip", "integrator.hip", "server.hip",
+    "timers.hip",
+]
 ARCH = "gfx950"
 
 

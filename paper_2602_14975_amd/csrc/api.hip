@@ -117,11 +117,13 @@ extern "C" nnp_status nnp_model_create(const nnp_model_desc* desc, nnp_model** o
     if (e == hipSuccess && d.kind == NNP_MODEL_NC && d.width <= 32)
         e = hipMalloc(&m->ncw, sizeof(float) * Model::ncw_count(d.width));
     if (e == hipSuccess) e = hipMalloc(&m->wT, sizeof(float) * m->n_weights);
+    if (e == hipSuccess) e = hipMalloc(&m->mxs, sizeof(float) * 2 * kMaxLayers);
     if (e != hipSuccess) {
         (void)hipFree(m->w);
         if (m->tab) (void)hipFree(m->tab);
         if (m->ncw) (void)hipFree(m->ncw);
         if (m->wT) (void)hipFree(m->wT);
+        if (m->mxs) (void)hipFree(m->mxs);
         delete m;
         set_error(std::string("model set-up: ") + hipGetErrorString(e));
         return NNP_EDEVICE;
@@ -134,6 +136,7 @@ extern "C" nnp_status nnp_model_create(const nnp_model_desc* desc, nnp_model** o
         (void)hipFree(m->tab);
         if (m->ncw) (void)hipFree(m->ncw);
         (void)hipFree(m->wT);
+        (void)hipFree(m->mxs);
         delete m;
         throw;
     }
@@ -148,6 +151,7 @@ extern "C" void nnp_model_destroy(nnp_model* model) {
     if (m->tab) (void)hipFree(m->tab);
     if (m->ncw) (void)hipFree(m->ncw);
     if (m->wT) (void)hipFree(m->wT);
+    if (m->mxs) (void)hipFree(m->mxs);
     delete m;
 }
 
@@ -260,6 +264,11 @@ void carve_model(Arena& a, const Model* m, int64_t n, int64_t E, bool for_wgrad,
         b.gUV = a.take<float>(n * 6 * F);
         b.gphi = a.take<float>(n * 3 * F);
         b.gh1 = a.take<float>(n * F);
+        if (message_mx_shape(int(F), m->desc.n_rbf, 0)) {
+            b.ecnt = a.take<int>(n);
+            b.erec = a.take<EdgeRec>(E);
+            b.ehalf = a.take<uint4>(8 * E);
+        }
     } else {
         const int64_t HC = 2 * int64_t(m->desc.n_s + m->desc.n_l) * m->desc.n_c;
         b.QK = a.take<float>(n * HC);
@@ -299,6 +308,7 @@ void Model::refresh_tables(hipStream_t s) {
     auto tr = [&](int64_t off, int rows, int cols) { launch_transpose(rows, cols, p(off), wT + off, s); };
     for (int l = 0; l < n_layers(); ++l) {
         const LayerOff& ll = loff[l];
+        launch_filter_scale(3 * F * desc.n_rbf, p(ll.Wr), mxs + 2 * l, s);
         tr(ll.W1, F, F);
         tr(ll.W2, 3 * F, F);
         tr(ll.U, 2 * F, F);
@@ -329,6 +339,7 @@ void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, Mode
         MpFwd a{};
         a.Wr = m->p(lo.Wr);
         a.br = m->p(lo.br);
+        a.mx_scale = m->mx_scale(l);
         a.s_out = lb.smid;
         a.v_out = lb.vmid;
         if (l == 0) {
@@ -386,6 +397,7 @@ void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float*
     a.gvm = b.gv;
     a.Wr = m->p(lo.Wr);
     a.br = m->p(lo.br);
+    a.mx_scale = m->mx_scale(l);
     a.gphi = b.gphi;
     a.gv_in = b.gv2;
     a.force = force;
@@ -460,6 +472,13 @@ void cons_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const
     const int n = int(sys.n_atoms);
     const int F = m->desc.width;
     MpGeom mg = make_geom(m, sys, geom, nl);
+    if (b.ecnt && message_mx_active(F, m->desc.n_rbf, 0)) {
+        // the edges within the cutoff, prepared once for all six message launches
+        launch_edge_prep(mg, b.ecnt, b.erec, b.ehalf, s);
+        mg.ecnt = b.ecnt;
+        mg.erec = b.erec;
+        mg.ehalf = b.ehalf;
+    }
     embed_forward(m, sys, mg, b, s);
     const int L = m->n_layers();
     gemm_xwt(n, F, F, b.s[L], F, m->p(m->off_Wo), m->p(m->off_bo), b.zo, F, EPI_SILU, b.ao, F, false, s, m->bf16());

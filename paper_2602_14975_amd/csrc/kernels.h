@@ -90,6 +90,15 @@ void gemm_wgrad(int M, int N, int K, const float* G, int ldg, const float* X, in
 void colsum(int M, int N, const float* G, int ldg, float* db, float* scratch, int chunk, bool accum, hipStream_t s);
 
 // ------------------------------------------------------------ edge kernels
+// One edge within the cutoff, as prepared for the matrix-core message
+// kernels (list order within each atom's row).
+struct EdgeRec {
+    int j, t;       // neighbour, its species (clamped)
+    float fc, dfc;  // f(r), f'(r)
+    float u[3];     // r_ij / r
+    float ir;       // 1 / r
+};
+
 struct MpGeom {
     int n;
     const double* pos;
@@ -99,6 +108,13 @@ struct MpGeom {
     const int* off;
     const int* nbr;
     double rc, rc2, bessel_norm, pi_over_rc, inv_rc;
+    // Prepared edges (launch_edge_prep), or nullptr: per atom i, ecnt[i]
+    // edges within the cutoff at list positions off[i] .. off[i] + ecnt[i],
+    // with records erec[p] and the radial values as FP16 pairs ehalf[p][8]
+    // (e_k f hi, e_k f lo, d/dr hi, d/dr lo; 16 values each).
+    const int* ecnt;
+    const EdgeRec* erec;
+    const uint4* ehalf;
 };
 
 struct MpFwd {
@@ -108,6 +124,7 @@ struct MpFwd {
     const int* species;
     const float* phi_tab;  // [S][3F] or nullptr
     const float* emb;      // [S][F]
+    const float* mx_scale;  // [2] filter-weight scale and its inverse for the matrix-core kernels, or nullptr
 };
 
 struct MpBwd {
@@ -119,9 +136,17 @@ struct MpBwd {
     float* force;       // [3][n] forces -dE/dx (GEO): written, or added to with accum_force
     int accum_force;
     float* wgrad_part;  // [blocks][3F][K + 1] filter weight adjoints (WGRAD)
+    const float* mx_scale;  // [2] filter-weight scale and its inverse for the matrix-core kernels, or nullptr
 };
 
 int mp_blocks(int n, int F);
+// matrix-core message kernels (F = 128, K = 16, cosine cutoff; forces, no weight adjoints)
+bool message_mx_shape(int F, int K, int cut);
+bool message_mx_active(int F, int K, int cut);  // shape covered and not switched off
+void launch_edge_prep(const MpGeom& mg, int* ecnt, EdgeRec* erec, uint4* ehalf, hipStream_t s);
+void launch_message_fwd_mx(const MpGeom& mg, const MpFwd& a, hipStream_t s, const ScopedTimer& t);
+void launch_message_bwd_mx(const MpGeom& mg, const MpBwd& a, hipStream_t s, const ScopedTimer& t);
+void launch_filter_scale(int count, const float* Wr, float* out, hipStream_t s);
 void launch_message_fwd(int F, int K, int cut, const MpGeom& mg, const MpFwd& a, hipStream_t s);
 void launch_message_bwd(int F, int K, int cut, const MpGeom& mg, const MpBwd& a, bool geo, bool wgrad,
                         hipStream_t s);

@@ -41,6 +41,10 @@ struct Model {
     // products run as X W^T with k contiguous in both operands.
     float* wT = nullptr;
     const float* pT(int64_t off) const { return wT + off; }
+    // Per layer: the power-of-two scale of the filter weights used by the
+    // matrix-core message kernels, and its inverse.
+    float* mxs = nullptr;
+    const float* mx_scale(int l) const { return mxs + 2 * l; }
     static int64_t ncw_count(int F) { return 7 * int64_t(F) * F + int64_t(2 * 10 * 8) * F + 2 * int64_t(F); }
     void refresh_tables(hipStream_t s);
 };
@@ -58,6 +62,10 @@ struct ModelBuf {
     float *gs = nullptr, *gs2 = nullptr, *gv = nullptr, *gv2 = nullptr, *gpqo = nullptr, *ga1 = nullptr,
           *gX = nullptr, *gUV = nullptr, *gphi = nullptr, *gh1 = nullptr;
     float *chunk_part = nullptr, *mp_part = nullptr, *filt_sum = nullptr;
+    // prepared edges of the matrix-core message kernels (list capacity E)
+    int* ecnt = nullptr;
+    EdgeRec* erec = nullptr;
+    uint4* ehalf = nullptr;
     // first layer per species: pre-activation, hidden, phi, and adjoints
     float *h1_tab = nullptr, *z_tab = nullptr, *phi_tab = nullptr, *gphi_tab = nullptr, *gh1_tab = nullptr;
 };

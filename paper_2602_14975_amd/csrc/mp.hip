@@ -34,67 +34,15 @@
 //   message is counted by its receiver).
 #include <hip/hip_ext.h>
 
+#include <atomic>
+
 #include "common.h"
 #include "kernels.h"
+#include "mp_edge.h"
 
 namespace nnp {
 
 constexpr int kMpWaves = 4;
-
-template <int K>
-struct EdgeSlot {
-    float ef[K];    // e_k(r) f(r)
-    float def[K];   // d/dr [e_k(r) f(r)]
-    float fc, dfc;  // f(r), f'(r)
-    float u[3];
-    float ir;       // 1 / r
-    int j, t;       // neighbour, neighbour species
-};
-
-// Radial values of one edge: float64 Chebyshev recurrence for sin(k theta)
-// and cos(k theta), theta = pi r / rc.
-template <int K, int CUT, bool DERIV>
-__device__ __forceinline__ void radial(double r, const MpGeom& mg, float* ef, float* def, float& fc, float& dfc) {
-    const double theta = mg.pi_over_rc * r;
-    double sn, cs;
-    sincos(theta, &sn, &cs);
-    double f, df;
-    if (CUT == 0) {
-        f = 0.5 * (cs + 1.0);
-        df = -0.5 * sn * mg.pi_over_rc;
-    } else {
-        const double d = r * mg.inv_rc;
-        const double d2 = d * d, d4 = d2 * d2, d5 = d4 * d;
-        f = 1.0 - 21.0 * d5 + 35.0 * d5 * d - 15.0 * d5 * d2;
-        df = (-105.0 * d4 + 210.0 * d5 - 105.0 * d5 * d) * mg.inv_rc;  // -p(p+1)(p+2)/2 d^4 (1-d)^2 / rc
-    }
-    const double inv_r = 1.0 / r;
-    const double nr = mg.bessel_norm * inv_r;
-    double s_prev = 0.0, s_cur = sn;  // sin(0), sin(theta)
-    double c_prev = 1.0, c_cur = cs;  // cos(0), cos(theta)
-#pragma unroll
-    for (int k = 1; k <= K; ++k) {
-        const double ek = nr * s_cur;
-        ef[k - 1] = float(ek * f);
-        if (DERIV) {
-            // d/dr [sin(k pi r/rc)/r] = (k pi/rc) cos(k theta)/r - sin(k theta)/r^2
-            const double dek = nr * (double(k) * mg.pi_over_rc * c_cur - s_cur * inv_r);
-            def[k - 1] = float(dek * f + ek * df);
-        }
-        const double s_next = 2.0 * cs * s_cur - s_prev;
-        const double c_next = 2.0 * cs * c_cur - c_prev;
-        s_prev = s_cur; s_cur = s_next;
-        c_prev = c_cur; c_cur = c_next;
-    }
-    fc = float(f);
-    dfc = float(df);
-}
-
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
 
 // Stages one batch of edges of atom i (lane l of its group takes entry e)
 // into LDS; returns the number of surviving edges of this group.
@@ -563,12 +511,23 @@ int mp_blocks(int n, int F) {
     return cdiv(n, kMpWaves / (F / G) * (64 / G));
 }
 
+// The matrix-core kernels serve the shapes they cover unless the vector
+// kernels were selected (nnp_set_message_kernels).
+static std::atomic<int> g_mp_mode{NNP_MP_AUTO};
+static bool mx_enabled() { return g_mp_mode.load(std::memory_order_relaxed) == NNP_MP_AUTO; }
+bool message_mx_active(int F, int K, int cut) { return message_mx_shape(F, K, cut) && mx_enabled(); }
+
 #define NNP_DISPATCH_MP(F_, K_, CUT_, CALL)                                          \
     if (F == F_ && K == K_ && cut == CUT_) { CALL; NNP_LAUNCH_CHECK(); return; }
 
 void launch_message_fwd(int F, int K, int cut, const MpGeom& mg, const MpFwd& a, hipStream_t s) {
     if (mg.n <= 0) return;
     ScopedTimer timer(cut == 0 ? "message_fwd" : "nc_message_fwd", s, true);
+    if (mg.ecnt && a.mx_scale && message_mx_active(F, K, cut)) {
+        launch_message_fwd_mx(mg, a, s, timer);
+        NNP_LAUNCH_CHECK();
+        return;
+    }
     NNP_DISPATCH_MP(128, 16, 0, (fwd_inst<128, 16, 0>(mg, a, s, timer)));
     NNP_DISPATCH_MP(64, 16, 0, (fwd_inst<64, 16, 0>(mg, a, s, timer)));
     NNP_DISPATCH_MP(32, 16, 0, (fwd_inst<32, 16, 0>(mg, a, s, timer)));
@@ -586,6 +545,11 @@ void launch_message_bwd(int F, int K, int cut, const MpGeom& mg, const MpBwd& a,
                         hipStream_t s) {
     if (mg.n <= 0) return;
     ScopedTimer timer(cut == 0 ? "message_bwd" : "nc_message_bwd", s, true);
+    if (geo && !wgrad && mg.ecnt && a.mx_scale && message_mx_active(F, K, cut)) {
+        launch_message_bwd_mx(mg, a, s, timer);
+        NNP_LAUNCH_CHECK();
+        return;
+    }
     NNP_DISPATCH_MP(128, 16, 0, (bwd_inst<128, 16, 0>(mg, a, geo, wgrad, s, timer)));
     NNP_DISPATCH_MP(64, 16, 0, (bwd_inst<64, 16, 0>(mg, a, geo, wgrad, s, timer)));
     NNP_DISPATCH_MP(32, 16, 0, (bwd_inst<32, 16, 0>(mg, a, geo, wgrad, s, timer)));
@@ -601,3 +565,9 @@ void launch_message_bwd(int F, int K, int cut, const MpGeom& mg, const MpBwd& a,
 
 
 }  // namespace nnp
+
+extern "C" nnp_status nnp_set_message_kernels(int32_t mode) {
+    if (mode != NNP_MP_AUTO && mode != NNP_MP_VECTOR) return NNP_EINVAL;
+    nnp::g_mp_mode.store(mode, std::memory_order_relaxed);
+    return NNP_OK;
+}

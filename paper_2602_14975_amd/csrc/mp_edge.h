@@ -1,0 +1,65 @@
+// Per-edge staging shared by the message kernels: the LDS slot of one edge
+// and the radial values that fill it.
+#pragma once
+
+#include "common.h"
+#include "kernels.h"
+
+namespace nnp {
+
+template <int K>
+struct EdgeSlot {
+    float ef[K];    // e_k(r) f(r)
+    float def[K];   // d/dr [e_k(r) f(r)]
+    float fc, dfc;  // f(r), f'(r)
+    float u[3];
+    float ir;       // 1 / r
+    int j, t;       // neighbour, neighbour species
+};
+
+// Radial values of one edge: float64 Chebyshev recurrence for sin(k theta)
+// and cos(k theta), theta = pi r / rc.
+template <int K, int CUT, bool DERIV>
+__device__ __forceinline__ void radial(double r, const MpGeom& mg, float* ef, float* def, float& fc, float& dfc) {
+    const double theta = mg.pi_over_rc * r;
+    double sn, cs;
+    sincos(theta, &sn, &cs);
+    double f, df;
+    if (CUT == 0) {
+        f = 0.5 * (cs + 1.0);
+        df = -0.5 * sn * mg.pi_over_rc;
+    } else {
+        const double d = r * mg.inv_rc;
+        const double d2 = d * d, d4 = d2 * d2, d5 = d4 * d;
+        f = 1.0 - 21.0 * d5 + 35.0 * d5 * d - 15.0 * d5 * d2;
+        df = (-105.0 * d4 + 210.0 * d5 - 105.0 * d5 * d) * mg.inv_rc;  // -p(p+1)(p+2)/2 d^4 (1-d)^2 / rc
+    }
+    const double inv_r = 1.0 / r;
+    const double nr = mg.bessel_norm * inv_r;
+    double s_prev = 0.0, s_cur = sn;  // sin(0), sin(theta)
+    double c_prev = 1.0, c_cur = cs;  // cos(0), cos(theta)
+#pragma unroll
+    for (int k = 1; k <= K; ++k) {
+        const double ek = nr * s_cur;
+        ef[k - 1] = float(ek * f);
+        if (DERIV) {
+            // d/dr [sin(k pi r/rc)/r] = (k pi/rc) cos(k theta)/r - sin(k theta)/r^2
+            const double dek = nr * (double(k) * mg.pi_over_rc * c_cur - s_cur * inv_r);
+            def[k - 1] = float(dek * f + ek * df);
+        }
+        const double s_next = 2.0 * cs * s_cur - s_prev;
+        const double c_next = 2.0 * cs * c_cur - c_prev;
+        s_prev = s_cur; s_cur = s_next;
+        c_prev = c_cur; c_cur = c_next;
+    }
+    fc = float(f);
+    dfc = float(df);
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+}  // namespace nnp

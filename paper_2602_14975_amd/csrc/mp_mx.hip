@@ -1,0 +1,538 @@
+// Matrix-core message kernels for width-128 embeddings with 16 Bessel
+// functions and the cosine cutoff (the message step and its reverse), and
+// the edge preparation they share.
+//
+// The radial filter of a batch of edges is a product of the per-edge basis
+// (edges x K) with the filter weights (K x 3F).  It runs on the FP16 matrix
+// cores at FP32-equivalent precision: each FP32 operand x is split into
+// x_hi = fp16(x) and x_lo = fp16(x - x_hi), which together carry 22
+// significant bits, and the products lo*hi, hi*lo and hi*hi are accumulated
+// in FP32 (lo*lo lies below FP32 rounding).  The weights enter scaled by a
+// power of two that puts their largest magnitude in [2^13, 2^14), inside the
+// FP16 range whatever the model; every sum that is linear in the filter is
+// rescaled once per atom, which is exact.
+//
+// Edge preparation (once per force evaluation, shared by the three layers'
+// forward and reverse launches): one wavefront per atom applies the float64
+// pair rule at the model cutoff to the atom's list row, compacts the edges
+// that pass in list order to the front of the row, and stores per edge a
+// record (neighbour, species, f, f', unit vector, 1/r) and the radial values
+// e_k(r) f(r) and their r-derivatives already split into FP16 pairs.
+//
+// Message kernels: blocks take four atoms in turn with four wavefronts, one
+// per block of 32 features; the wavefronts do not synchronise except once
+// per block in the reverse, to add their force shares.  An atom's edges are
+// consumed in batches of fixed size (32 forward, 16 reverse) in list order,
+// so the batch an edge falls into depends only on its rank among the atom's
+// edges within the cutoff: results do not depend on the list radius.
+//
+// In a 32x32x16 product the lane (c, h) = (lane % 32, lane / 32) holds output
+// column c for rows 8j + 4h + i (j, i = 0..3): every lane owns one feature and
+// accumulates over a fixed subset of each batch's edges; the two halves of the
+// wavefront are added at the end of the atom.  Forward: the rows are 32 edges.
+// Reverse: rows 0..15 hold e_k(r) f(r) and rows 16..31 their r-derivatives
+// for the same 16 edges, so one product gives w and dw/dr of an edge in the
+// same lane.  The per-edge work after the filter is that of the vector
+// kernels (same formulas; see the message kernels of mp.hip).
+#include <hip/hip_ext.h>
+
+#include "common.h"
+#include "kernels.h"
+#include "mp_edge.h"
+
+namespace nnp {
+
+namespace {
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef float floatx16_t __attribute__((ext_vector_type(16)));
+
+constexpr int kMxF = 128, kMxK = 16, kMxWaves = 4, kMxAtoms = 4;
+// forward: edges of a lane whose loads are issued together
+constexpr int kFwdGroup = 4;
+// reverse: the same (fewer for the first layer, which then fits three
+// wavefronts per SIMD)
+template <bool L0>
+constexpr int kBwdGroup = L0 ? 4 : 8;
+
+__device__ __forceinline__ void split8(const float* x, half8_t& hi, half8_t& lo) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const _Float16 t = static_cast<_Float16>(x[q]);
+        hi[q] = t;
+        lo[q] = static_cast<_Float16>(x[q] - static_cast<float>(t));
+    }
+}
+
+// A (32 x 16) times B (16 x 32) from the split operands: small terms first
+__device__ __forceinline__ floatx16_t mma3(const half8_t& ah, const half8_t& al, const half8_t& bh,
+                                           const half8_t& bl) {
+    floatx16_t c = {};
+    c = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, c, 0, 0, 0);
+    return c;
+}
+
+__device__ __forceinline__ void load8(const float* p, float* x) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    const float4 b = *reinterpret_cast<const float4*>(p + 4);
+    x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+    x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+}
+
+// This lane's B fragments: rows 8h..8h+7 of column f of the scaled filter
+// weights of each channel, split, and the scaled biases.
+__device__ __forceinline__ void load_filter(const float* Wr, const float* br, float sc, int f, int h, half8_t* bh,
+                                            half8_t* bl, float* bb) {
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        float x[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) x[q] = Wr[(p * kMxF + f) * kMxK + 8 * h + q] * sc;
+        split8(x, bh[p], bl[p]);
+        bb[p] = br[p * kMxF + f] * sc;
+    }
+}
+
+__device__ __forceinline__ half8_t as_half8(const uint4& u) { return __builtin_bit_cast(half8_t, u); }
+
+// ---------------------------------------------------------- edge preparation
+
+__global__ void __launch_bounds__(256) k_edge_prep(MpGeom mg, int* __restrict__ ecnt, EdgeRec* __restrict__ erec,
+                                                   uint4* __restrict__ ehalf) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= mg.n) return;  // whole wavefronts
+    const int n = mg.n;
+    const int start = mg.off[i], end = mg.off[i + 1];
+    double L, inv;
+    mg.geom.get(i, L, inv);
+    const double xi = mg.pos[i], yi = mg.pos[n + i], zi = mg.pos[2 * n + i];
+    int cnt = 0;
+    for (int base = start; base < end; base += 64) {
+        const int e = base + lane;
+        bool ok = false;
+        double dx = 0, dy = 0, dz = 0;
+        int j = -1;
+        if (e < end) {
+            j = mg.nbr[e];
+            ok = pair_rule(xi, yi, zi, mg.pos[j], mg.pos[n + j], mg.pos[2 * n + j], L, inv, mg.rc2, dx, dy, dz);
+        }
+        const uint64_t bal = __ballot(ok);
+        if (ok) {
+            const int p = start + cnt + __popcll(bal & ((1ull << lane) - 1ull));
+            const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+            const double ir = 1.0 / r;
+            float ef[kMxK], def[kMxK], fc, dfc;
+            radial<kMxK, 0, true>(r, mg, ef, def, fc, dfc);
+            EdgeRec rec;
+            rec.j = j;
+            rec.t = mg.species ? min(max(mg.species[j], 0), mg.n_species - 1) : 0;
+            rec.fc = fc;
+            rec.dfc = dfc;
+            rec.u[0] = float(dx * ir);
+            rec.u[1] = float(dy * ir);
+            rec.u[2] = float(dz * ir);
+            rec.ir = float(ir);
+            erec[p] = rec;
+            uint4* dst = ehalf + int64_t(p) * 8;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                half8_t hi, lo;
+                split8(ef + 8 * q, hi, lo);
+                dst[q] = __builtin_bit_cast(uint4, hi);
+                dst[2 + q] = __builtin_bit_cast(uint4, lo);
+                split8(def + 8 * q, hi, lo);
+                dst[4 + q] = __builtin_bit_cast(uint4, hi);
+                dst[6 + q] = __builtin_bit_cast(uint4, lo);
+            }
+        }
+        cnt += __popcll(bal);
+    }
+    if (lane == 0) ecnt[i] = cnt;
+}
+
+// The global loads that start a batch of nb edges at list positions p0..:
+// this lane's A fragment (both FP16 halves of its row; rows past nb are
+// zero) and one 16-byte piece of the batch's edge records.  A batch is
+// fetched while the previous one is processed.
+struct BatchIn {
+    uint4 hi, lo, rec;
+};
+
+template <int BATCH>
+__device__ __forceinline__ BatchIn fetch_batch(const MpGeom& mg, int p0, int nb) {
+    const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
+    BatchIn b{};
+    b.hi = b.lo = b.rec = make_uint4(0, 0, 0, 0);
+    // forward: rows are edges 0..31; reverse: rows 0..15 e_k f, 16..31 d/dr of edges 0..15
+    const int row = BATCH == 32 ? r : (r & 15);
+    const int part = BATCH == 32 ? 0 : 4 * (r >> 4);
+    if (row < nb) {
+        const uint4* src = mg.ehalf + int64_t(p0 + row) * 8 + part;
+        b.hi = src[h];
+        b.lo = src[2 + h];
+    }
+    if (lane < 2 * nb) b.rec = reinterpret_cast<const uint4*>(mg.erec + p0)[lane];
+    return b;
+}
+
+// The batch's records go to the wavefront's own LDS slots.
+__device__ __forceinline__ void stage_records(const BatchIn& in, int nb, EdgeRec* rec) {
+    const int lane = threadIdx.x & 63;
+    if (lane < 2 * nb) reinterpret_cast<uint4*>(rec)[lane] = in.rec;
+    wave_sync_lds();
+}
+
+// ------------------------------------------------------------- forward --
+
+struct FwdAcc {
+    float s, v[3];
+};
+
+// One batch of nb <= 32 edges.  The lane's 16 edges are taken kFwdGroup at
+// a time, the loads of a group issued before its arithmetic (an invalid edge
+// of a partial batch reads the batch's first edge and contributes nothing).
+template <bool L0>
+__device__ __forceinline__ void fwd_batch(const MpFwd& a, const float* ptab, EdgeRec* rec, const BatchIn& in, int nb,
+                                          int f, int h, const half8_t* bh, const half8_t* bl, const float* bb,
+                                          FwdAcc& acc) {
+    constexpr int F = kMxF, E = 16;
+    stage_records(in, nb, rec);
+    const half8_t ah = as_half8(in.hi), al = as_half8(in.lo);
+    const floatx16_t wa = mma3(ah, al, bh[0], bl[0]);
+    floatx16_t wb = {};
+    if (!L0) wb = mma3(ah, al, bh[1], bl[1]);  // the first layer's vector input is zero
+    const floatx16_t wc = mma3(ah, al, bh[2], bl[2]);
+#pragma unroll
+    for (int g0 = 0; g0 < E; g0 += kFwdGroup) {
+        float pa[kFwdGroup], pb[kFwdGroup], pc[kFwdGroup], vj[kFwdGroup][3];
+#pragma unroll
+        for (int g = 0; g < kFwdGroup; ++g) {
+            const int q = g0 + g;
+            const int te = 8 * (q / 4) + 4 * h + q % 4;
+            const EdgeRec& s = rec[te < nb ? te : 0];
+            const float* phj = L0 ? ptab + s.t * 3 * F + f : a.phi + int64_t(s.j) * 3 * F + f;
+            pa[g] = phj[0];
+            pb[g] = phj[F];
+            pc[g] = phj[2 * F];
+            if (!L0) {
+                const float* v = a.v_in + int64_t(s.j) * 3 * F + f;
+                vj[g][0] = v[0];
+                vj[g][1] = v[F];
+                vj[g][2] = v[2 * F];
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < kFwdGroup; ++g) {
+            const int q = g0 + g;
+            const int te = 8 * (q / 4) + 4 * h + q % 4;
+            if (te >= nb) continue;
+            const EdgeRec& s = rec[te];
+            const float fc = s.fc;
+            const float w_a = fmaf(bb[0], fc, wa[q]);
+            const float w_c = fmaf(bb[2], fc, wc[q]);
+            const float c = pc[g] * w_c;
+            acc.s = fmaf(pa[g], w_a, acc.s);
+            if (L0) {
+                acc.v[0] += s.u[0] * c;
+                acc.v[1] += s.u[1] * c;
+                acc.v[2] += s.u[2] * c;
+            } else {
+                const float b = pb[g] * fmaf(bb[1], fc, wb[q]);
+                acc.v[0] += b * vj[g][0] + s.u[0] * c;
+                acc.v[1] += b * vj[g][1] + s.u[1] * c;
+                acc.v[2] += b * vj[g][2] + s.u[2] * c;
+            }
+        }
+    }
+    wave_sync_lds();  // the records are rewritten by the next batch
+}
+
+template <bool L0>
+__global__ void __launch_bounds__(64 * kMxWaves, 2) k_message_fwd_mx(MpGeom mg, MpFwd a) {
+    constexpr int F = kMxF, BATCH = 32;
+    __shared__ __align__(16) EdgeRec rec_all[kMxWaves][BATCH];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int h = lane >> 5, f = w * 32 + (lane & 31);
+    EdgeRec* rec = rec_all[w];
+    const int n = mg.n;
+    // first layer: the species table of phi in LDS
+    __shared__ float ptab_s[L0 ? 8 * 3 * kMxF : 1];
+    if constexpr (L0) {
+        for (int t = threadIdx.x; t < mg.n_species * 3 * F; t += blockDim.x) ptab_s[t] = a.phi_tab[t];
+        __syncthreads();
+    }
+    const float sc = a.mx_scale[0], isc = a.mx_scale[1];
+    half8_t bh[3], bl[3];
+    float bb[3];
+    load_filter(a.Wr, a.br, sc, f, h, bh, bl, bb);
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    for (int ai = 0; ai < kMxAtoms; ++ai) {
+        const int i = blk * kMxAtoms + ai;
+        if (i >= n) break;
+        const int p_start = mg.off[i], cnt = mg.ecnt[i];
+        FwdAcc acc{};
+        BatchIn cur = fetch_batch<BATCH>(mg, p_start, min(BATCH, cnt));
+        for (int b0 = 0; b0 < cnt; b0 += BATCH) {
+            BatchIn nxt = fetch_batch<BATCH>(mg, p_start + b0 + BATCH, min(BATCH, cnt - b0 - BATCH));
+            fwd_batch<L0>(a, ptab_s, rec, cur, min(BATCH, cnt - b0), f, h, bh, bl, bb, acc);
+            cur = nxt;
+        }
+        // both halves of the wavefront hold partial sums of feature f
+        acc.s += __shfl_xor(acc.s, 32, 64);
+#pragma unroll
+        for (int al = 0; al < 3; ++al) acc.v[al] += __shfl_xor(acc.v[al], 32, 64);
+        if (h == 0) {
+            const int ti = L0 ? min(max(a.species[i], 0), mg.n_species - 1) : 0;
+            const float si = L0 ? a.emb[ti * F + f] : a.s_in[int64_t(i) * F + f];
+            a.s_out[int64_t(i) * F + f] = si + acc.s * isc;
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+                const int64_t idx = (int64_t(i) * 3 + al) * F + f;
+                const float vi = L0 ? 0.f : a.v_in[idx];
+                a.v_out[idx] = vi + acc.v[al] * isc;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------- reverse --
+
+struct Owner {
+    float ph[3], v[3], gs, gv[3];
+};
+
+struct BwdAcc {
+    float gph[3], gv[3], fx, fy, fz;
+};
+
+// One batch of nb <= 16 edges; the lane's eight edges are taken kBwdGroup at
+// a time as in the forward batch.
+template <bool L0>
+__device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, EdgeRec* rec, const BatchIn& in, int nb,
+                                          int f, int h, const half8_t* bh, const half8_t* bl, const float* bb,
+                                          const Owner& o, BwdAcc& acc) {
+    constexpr int F = kMxF, E = 8;
+    stage_records(in, nb, rec);
+    const half8_t ah = as_half8(in.hi), al = as_half8(in.lo);
+    const floatx16_t m0 = mma3(ah, al, bh[0], bl[0]);
+    const floatx16_t m1 = mma3(ah, al, bh[1], bl[1]);
+    const floatx16_t m2 = mma3(ah, al, bh[2], bl[2]);
+#pragma unroll
+    for (int g0 = 0; g0 < E; g0 += kBwdGroup<L0>) {
+        constexpr int G = kBwdGroup<L0>;
+        float pa[G], pb[G], pc[G], vn[G][3], gn[G][3], gsn[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int q = g0 + g;
+            const int te = 8 * (q / 4) + 4 * h + q % 4;
+            const EdgeRec& s = rec[te < nb ? te : 0];
+            const int j = s.j;
+            const float* phj = L0 ? ptab + s.t * 3 * F + f : a.phi + int64_t(j) * 3 * F + f;
+            pa[g] = phj[0];
+            pb[g] = phj[F];
+            pc[g] = phj[2 * F];
+            vn[g][0] = vn[g][1] = vn[g][2] = 0.f;
+            if (!L0) {  // the first layer's vector input is zero
+                const float* v = a.v_in + int64_t(j) * 3 * F + f;
+                vn[g][0] = v[0];
+                vn[g][1] = v[F];
+                vn[g][2] = v[2 * F];
+            }
+            const float* gp = a.gvm + int64_t(j) * 3 * F + f;
+            gn[g][0] = gp[0];
+            gn[g][1] = gp[F];
+            gn[g][2] = gp[2 * F];
+            gsn[g] = a.gsm[int64_t(j) * F + f];
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int q = g0 + g;
+            const int te = 8 * (q / 4) + 4 * h + q % 4;
+            if (te >= nb) continue;
+            const EdgeRec& s = rec[te];
+            // w of edge te is row te, dw/dr row 16 + te: accumulator elements q and 8 + q
+            const float fc = s.fc, dfc = s.dfc;
+            const float w[3] = {fmaf(bb[0], fc, m0[q]), fmaf(bb[1], fc, m1[q]), fmaf(bb[2], fc, m2[q])};
+            const float dw[3] = {fmaf(bb[0], dfc, m0[8 + q]), fmaf(bb[1], dfc, m1[8 + q]),
+                                 fmaf(bb[2], dfc, m2[8 + q])};
+            const float u0 = s.u[0], u1 = s.u[1], u2 = s.u[2];
+            const float g0v = gn[g][0], g1v = gn[g][1], g2v = gn[g][2];
+            // projections shared by several terms
+            const float gvo_vn = o.gv[0] * vn[g][0] + o.gv[1] * vn[g][1] + o.gv[2] * vn[g][2];
+            const float gvo_u = o.gv[0] * u0 + o.gv[1] * u1 + o.gv[2] * u2;
+            const float gvn_vo = g0v * o.v[0] + g1v * o.v[1] + g2v * o.v[2];
+            const float gvn_u = g0v * u0 + g1v * u1 + g2v * u2;
+            // message n -> o and message o -> n (unit vector -u): filter adjoints
+            const float gwa = o.gs * pa[g], gwb = pb[g] * gvo_vn, gwc = pc[g] * gvo_u;
+            const float gwa2 = gsn[g] * o.ph[0], gwb2 = o.ph[1] * gvn_vo, gwc2 = -o.ph[2] * gvn_u;
+            const float dr = (gwa + gwa2) * dw[0] + (gwb + gwb2) * dw[1] + (gwc + gwc2) * dw[2];
+            // adjoints of the unit vectors of the two messages
+            const float cA = pc[g] * w[2], cB = o.ph[2] * w[2];
+            const float gu0 = o.gv[0] * cA - g0v * cB;
+            const float gu1 = o.gv[1] * cA - g1v * cB;
+            const float gu2 = o.gv[2] * cA - g2v * cB;
+            // o as the sender of the message o -> n
+            acc.gph[0] = fmaf(gsn[g], w[0], acc.gph[0]);
+            acc.gph[1] = fmaf(w[1], gvn_vo, acc.gph[1]);
+            acc.gph[2] = fmaf(-w[2], gvn_u, acc.gph[2]);
+            const float wbp = w[1] * o.ph[1];
+            acc.gv[0] = fmaf(g0v, wbp, acc.gv[0]);
+            acc.gv[1] = fmaf(g1v, wbp, acc.gv[1]);
+            acc.gv[2] = fmaf(g2v, wbp, acc.gv[2]);
+            // this lane's share of (d_A + d_A') u + P(g_uA - g_uA') / r
+            const float ud = gu0 * u0 + gu1 * u1 + gu2 * u2;
+            acc.fx += dr * u0 + (gu0 - ud * u0) * s.ir;
+            acc.fy += dr * u1 + (gu1 - ud * u1) * s.ir;
+            acc.fz += dr * u2 + (gu2 - ud * u2) * s.ir;
+        }
+    }
+    wave_sync_lds();  // the records are rewritten by the next batch
+}
+
+template <bool L0>
+__global__ void __launch_bounds__(64 * kMxWaves, 2) k_message_bwd_mx(MpGeom mg, MpBwd a) {
+    constexpr int F = kMxF, BATCH = 16;
+    __shared__ __align__(16) EdgeRec rec_all[kMxWaves][BATCH];
+    __shared__ float fpart[kMxAtoms][kMxWaves][3];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int h = lane >> 5, f = w * 32 + (lane & 31);
+    EdgeRec* rec = rec_all[w];
+    const int n = mg.n;
+    // first layer: the species table of phi in LDS
+    __shared__ float ptab_s[L0 ? 8 * 3 * kMxF : 1];
+    if constexpr (L0) {
+        for (int t = threadIdx.x; t < mg.n_species * 3 * F; t += blockDim.x) ptab_s[t] = a.phi_tab[t];
+        __syncthreads();
+    }
+    const float sc = a.mx_scale[0], isc = a.mx_scale[1];
+    half8_t bh[3], bl[3];
+    float bb[3];
+    load_filter(a.Wr, a.br, sc, f, h, bh, bl, bb);
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    for (int ai = 0; ai < kMxAtoms; ++ai) {
+        const int i = blk * kMxAtoms + ai;
+        if (i >= n) break;
+        const int p_start = mg.off[i], cnt = mg.ecnt[i];
+        BatchIn cur = fetch_batch<BATCH>(mg, p_start, min(BATCH, cnt));
+        Owner o{};
+        {
+            const int ti = L0 ? min(max(a.species[i], 0), mg.n_species - 1) : 0;
+            const float* pho = L0 ? ptab_s + ti * 3 * F + f : a.phi + int64_t(i) * 3 * F + f;
+#pragma unroll
+            for (int p = 0; p < 3; ++p) o.ph[p] = pho[p * F];
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+                const int64_t idx = (int64_t(i) * 3 + al) * F + f;
+                if (!L0) o.v[al] = a.v_in[idx];
+                o.gv[al] = a.gvm[idx];
+            }
+            o.gs = a.gsm[int64_t(i) * F + f];
+        }
+        BwdAcc acc{};
+        for (int b0 = 0; b0 < cnt; b0 += BATCH) {
+            BatchIn nxt = fetch_batch<BATCH>(mg, p_start + b0 + BATCH, min(BATCH, cnt - b0 - BATCH));
+            bwd_batch<L0>(a, ptab_s, rec, cur, min(BATCH, cnt - b0), f, h, bh, bl, bb, o, acc);
+            cur = nxt;
+        }
+        // both halves of the wavefront hold partial sums of feature f
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            acc.gph[p] += __shfl_xor(acc.gph[p], 32, 64);
+            acc.gv[p] += __shfl_xor(acc.gv[p], 32, 64);
+        }
+        const float fx = group_sum<64>(acc.fx), fy = group_sum<64>(acc.fy), fz = group_sum<64>(acc.fz);
+        if (lane == 0) {
+            fpart[ai][w][0] = fx;
+            fpart[ai][w][1] = fy;
+            fpart[ai][w][2] = fz;
+        }
+        if (h == 0) {
+            if (a.want_gphi) {
+#pragma unroll
+                for (int p = 0; p < 3; ++p) a.gphi[int64_t(i) * 3 * F + p * F + f] = acc.gph[p] * isc;
+            }
+            if (!L0) {
+#pragma unroll
+                for (int al = 0; al < 3; ++al) {
+                    const int64_t idx = (int64_t(i) * 3 + al) * F + f;
+                    a.gv_in[idx] = o.gv[al] + acc.gv[al] * isc;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // the force on each atom of the block: the feature blocks' shares in a fixed order
+    const int t = threadIdx.x;
+    if (t < 3 * kMxAtoms) {
+        const int ai = t / 3, c = t % 3;
+        const int i = blk * kMxAtoms + ai;
+        if (i < n) {
+            float sum = 0.f;
+            for (int k = 0; k < kMxWaves; ++k) sum += fpart[ai][k][c];
+            sum *= isc;
+            float* fo = a.force + int64_t(c) * n + i;
+            if (a.accum_force) *fo += sum;
+            else *fo = sum;
+        }
+    }
+}
+
+// Scale of the filter weights of one layer for the split products: a power
+// of two s with max |Wr| s in [2^13, 2^14) (s = 1 for all-zero weights), and
+// 1 / s.
+__global__ void __launch_bounds__(256) k_filter_scale(int count, const float* Wr, float* out) {
+    __shared__ float part[256];
+    float m = 0.f;
+    for (int k = threadIdx.x; k < count; k += blockDim.x) m = fmaxf(m, fabsf(Wr[k]));
+    part[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) part[threadIdx.x] = fmaxf(part[threadIdx.x], part[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const float mx = part[0];
+        int e = 0;
+        if (mx > 0.f && isfinite(mx)) (void)frexpf(mx, &e);  // mx < 2^e
+        e = min(max(e, -100), 100);
+        out[0] = ldexpf(1.f, 14 - e);
+        out[1] = ldexpf(1.f, e - 14);
+    }
+}
+
+template <typename Kern, typename Args>
+void launch_mx(const ScopedTimer& t, Kern kern, int n, hipStream_t s, const MpGeom& mg, const Args& a) {
+    const dim3 grid(cdiv(n, kMxAtoms));
+    if (t.active && t.by_launch) hipExtLaunchKernelGGL(kern, grid, dim3(64 * kMxWaves), 0, s, t.a, t.b, 0, mg, a);
+    else kern<<<grid, 64 * kMxWaves, 0, s>>>(mg, a);
+}
+
+}  // namespace
+
+bool message_mx_shape(int F, int K, int cut) { return F == kMxF && K == kMxK && cut == 0; }
+
+void launch_message_fwd_mx(const MpGeom& mg, const MpFwd& a, hipStream_t s, const ScopedTimer& t) {
+    if (a.phi_tab) launch_mx(t, k_message_fwd_mx<true>, mg.n, s, mg, a);
+    else launch_mx(t, k_message_fwd_mx<false>, mg.n, s, mg, a);
+}
+
+void launch_message_bwd_mx(const MpGeom& mg, const MpBwd& a, hipStream_t s, const ScopedTimer& t) {
+    if (a.phi_tab) launch_mx(t, k_message_bwd_mx<true>, mg.n, s, mg, a);
+    else launch_mx(t, k_message_bwd_mx<false>, mg.n, s, mg, a);
+}
+
+void launch_edge_prep(const MpGeom& mg, int* ecnt, EdgeRec* erec, uint4* ehalf, hipStream_t s) {
+    if (mg.n <= 0) return;
+    k_edge_prep<<<cdiv(mg.n, 4), 256, 0, s>>>(mg, ecnt, erec, ehalf);
+    NNP_LAUNCH_CHECK();
+}
+
+void launch_filter_scale(int count, const float* Wr, float* out, hipStream_t s) {
+    k_filter_scale<<<1, 256, 0, s>>>(count, Wr, out);
+    NNP_LAUNCH_CHECK();
+}
+
+}  // namespace nnp

@@ -1,0 +1,108 @@
+"""Matrix-core message kernels (width 128, 16 Bessel functions, cosine
+cutoff): parity with the FP64 oracle and with the vector kernels, filter
+weights far outside the FP16 range, ragged and empty neighbourhoods, dense
+neighbourhoods that wrap the edge ring, and independence of the list radius."""
+
+import numpy as np
+import pytest
+
+import synth
+from synth.weights import ModelSpec, manifest
+from oracle import models as om
+from tests._helpers import FP32_TOL, gpu_list, oracle_list, rel_rmse, small_box
+
+pytestmark = pytest.mark.gpu
+
+SPEC2 = ModelSpec("cons", 128, 2, 16, 5.0)
+
+
+def _set_kernels(nnp, mode):
+    from paper_2602_14975_amd import _abi
+    _abi.check(nnp.lib().nnp_set_message_kernels(mode))
+
+
+def _forces(nnp, spec, w, pos, species, box, list_rc):
+    from paper_2602_14975_amd.nnp import DeviceSystem, workspace
+    m = nnp.Model.from_spec(spec, w)
+    system = DeviceSystem(pos, species, box)
+    nl = gpu_list(nnp, system, list_rc)
+    ws = workspace(m, None, system.n, 1, nl.capacity)
+    e, f = nnp.nnp_cons_energy_forces(m, system, nl, ws)
+    return float(e.cpu()[0]), f.cpu().numpy().T.astype(np.float64)
+
+
+def _oracle(spec, w, pos, species, box):
+    off, nbr = oracle_list(pos, box, spec.cutoff)
+    return om.cons_energy_forces(spec, w, pos, species, box, off, nbr)
+
+
+def _rescaled(spec, w, lam):
+    """The same function with the filter (Wr, br) scaled by lam and the
+    perceptron output (W2, b2) by 1/lam: a = phi w is unchanged."""
+    w = w.copy()
+    off = 0
+    for name, shape, _ in manifest(spec):
+        size = int(np.prod(shape))
+        if name.endswith(".Wr") or name.endswith(".br"):
+            w[off:off + size] *= lam
+        elif name.endswith(".W2") or name.endswith(".b2"):
+            w[off:off + size] /= lam
+        off += size
+    return w
+
+
+def test_matrix_core_and_vector_kernels_agree(gpu_lib):
+    s = synth.water_config(3)
+    spec = synth.CONS_CFG1
+    w = synth.random_weights(spec, 4100)
+    print(f"case water3 n={s.n} width={spec.width}", flush=True)
+    try:
+        _set_kernels(gpu_lib, 1)
+        ev, fv = _forces(gpu_lib, spec, w, s.pos, s.species, s.box, 6.0)
+        _set_kernels(gpu_lib, 0)
+        em, fm = _forces(gpu_lib, spec, w, s.pos, s.species, s.box, 6.0)
+    finally:
+        _set_kernels(gpu_lib, 0)
+    E, F = _oracle(spec, w, s.pos, s.species, s.box)
+    assert rel_rmse(fm, F) <= FP32_TOL and rel_rmse(fv, F) <= FP32_TOL
+    assert rel_rmse(fm, fv) <= 2e-6
+    assert abs(em - ev) <= 1e-6 * abs(E) + 1e-4
+
+
+def test_kernel_mode_rejects_unknown_value(gpu_lib):
+    assert gpu_lib.lib().nnp_set_message_kernels(7) != 0
+
+
+@pytest.mark.parametrize("lam", [2.0 ** 18, 2.0 ** -30])
+def test_filter_weights_outside_fp16_range(gpu_lib, lam):
+    """Scaling the filter by a power of two (and phi by its inverse) leaves
+    the model unchanged; the split FP16 products must give the same forces,
+    bit for bit, although the scaled weights overflow FP16 (2^18) or fall
+    far below its normal range (2^-30)."""
+    pos, species, box = small_box(71, n=101, box=11.5)
+    w = synth.random_weights(SPEC2, 4200)
+    print(f"case lam={lam}", flush=True)
+    e0, f0 = _forces(gpu_lib, SPEC2, w, pos, species, box, 5.0)
+    e1, f1 = _forces(gpu_lib, SPEC2, _rescaled(SPEC2, w, lam), pos, species, box, 5.0)
+    assert np.array_equal(f0, f1) and e0 == e1
+    E, F = _oracle(SPEC2, w, pos, species, box)
+    assert rel_rmse(f1, F) <= FP32_TOL
+
+
+@pytest.mark.parametrize("n,box", [(40, 30.0), (101, 11.5), (400, 11.5)])
+def test_sparse_ragged_and_dense_neighbourhoods(gpu_lib, n, box):
+    """n = 40 in 30 A: most atoms have no or few neighbours (empty and
+    partial batches); n = 400 in 11.5 A: ~140 edges per atom within the
+    cutoff and ~180 list entries at 5.5 A (several staging rounds, the edge
+    ring wraps)."""
+    pos, species, b = small_box(90 + n, n=n, box=box)
+    w = synth.random_weights(SPEC2, 4300 + n)
+    print(f"case n={n} box={box}", flush=True)
+    e, f = _forces(gpu_lib, SPEC2, w, pos, species, b, min(6.0, 0.49 * box))
+    E, F = _oracle(SPEC2, w, pos, species, b)
+    assert abs(e - E) <= 1e-6 * abs(E) + 1e-4
+    assert rel_rmse(f, F) <= FP32_TOL
+    if n == 40:
+        off, _ = oracle_list(pos, b, SPEC2.cutoff)
+        lonely = np.flatnonzero(np.diff(off) == 0)
+        assert lonely.size > 0 and np.all(f[lonely] == 0.0)
