@@ -153,36 +153,64 @@ __global__ void __launch_bounds__(256) k_edge_prep(MpGeom mg, int* __restrict__ 
     if (lane == 0) ecnt[i] = cnt;
 }
 
-// The global loads that start a batch of nb edges at list positions p0..:
-// this lane's A fragment (both FP16 halves of its row; rows past nb are
-// zero) and one 16-byte piece of the batch's edge records.  A batch is
-// fetched while the previous one is processed.
-struct BatchIn {
-    uint4 hi, lo, rec;
+// A batch's prepared edges are loaded once per block: thread t holds one
+// 16-byte piece (radial pieces of the batch's edges, then its records) in a
+// register while the previous batch is processed, and stores it into the
+// batch's LDS buffer (two, alternating) after the barrier that ends that
+// batch's predecessor.  The forward needs only the e_k f pieces of an edge.
+template <int BATCH>
+struct BatchBuf {
+    static constexpr int AP = BATCH == 32 ? 4 : 8;  // radial pieces per edge
+    static constexpr int NA = BATCH * AP, N = NA + 2 * BATCH;
+    uint4 a[BATCH][AP];
+    EdgeRec rec[BATCH];
+};
+
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint4 load_nt(const uint4* p) {
+    const u32x4_t v = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(p));
+    return make_uint4(v[0], v[1], v[2], v[3]);
+}
+
+template <int BATCH>
+__device__ __forceinline__ uint4 fetch_piece(const MpGeom& mg, int p0, int nb) {
+    using B = BatchBuf<BATCH>;
+    const int t = threadIdx.x;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    // read once per evaluation and layer: non-temporal, so that the streamed
+    // edges do not displace the neighbour rows from L2
+    if (t < B::NA) {
+        const int e = t / B::AP, q = t % B::AP;
+        if (e < nb) v = load_nt(mg.ehalf + int64_t(p0 + e) * 8 + q);
+    } else if (t < B::N) {
+        const int u = t - B::NA;
+        if (u < 2 * nb) v = load_nt(reinterpret_cast<const uint4*>(mg.erec + p0) + u);
+    }
+    return v;
+}
+
+template <int BATCH>
+__device__ __forceinline__ void store_piece(BatchBuf<BATCH>& b, const uint4& v) {
+    if (threadIdx.x < BatchBuf<BATCH>::N) reinterpret_cast<uint4*>(&b)[threadIdx.x] = v;
+}
+
+// The block's batches in processing order: atoms i0 .. i0 + kMxAtoms - 1
+// (those below n), each atom's edges in batches of BATCH.  Returns the list
+// position and size of the batch after batch b0 of atom ai (ai = -1: the
+// first batch), or nb = 0 when there is none.
+struct NextBatch {
+    int p0, nb;
 };
 
 template <int BATCH>
-__device__ __forceinline__ BatchIn fetch_batch(const MpGeom& mg, int p0, int nb) {
-    const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
-    BatchIn b{};
-    b.hi = b.lo = b.rec = make_uint4(0, 0, 0, 0);
-    // forward: rows are edges 0..31; reverse: rows 0..15 e_k f, 16..31 d/dr of edges 0..15
-    const int row = BATCH == 32 ? r : (r & 15);
-    const int part = BATCH == 32 ? 0 : 4 * (r >> 4);
-    if (row < nb) {
-        const uint4* src = mg.ehalf + int64_t(p0 + row) * 8 + part;
-        b.hi = src[h];
-        b.lo = src[2 + h];
+__device__ __forceinline__ NextBatch next_batch(const MpGeom& mg, int i0, int ai, int b0, int cnt) {
+    if (ai >= 0 && b0 + BATCH < cnt) return {mg.off[i0 + ai] + b0 + BATCH, min(BATCH, cnt - b0 - BATCH)};
+    for (int a2 = ai + 1; a2 < kMxAtoms && i0 + a2 < mg.n; ++a2) {
+        const int c2 = mg.ecnt[i0 + a2];
+        if (c2 > 0) return {mg.off[i0 + a2], min(BATCH, c2)};
     }
-    if (lane < 2 * nb) b.rec = reinterpret_cast<const uint4*>(mg.erec + p0)[lane];
-    return b;
-}
-
-// The batch's records go to the wavefront's own LDS slots.
-__device__ __forceinline__ void stage_records(const BatchIn& in, int nb, EdgeRec* rec) {
-    const int lane = threadIdx.x & 63;
-    if (lane < 2 * nb) reinterpret_cast<uint4*>(rec)[lane] = in.rec;
-    wave_sync_lds();
+    return {0, 0};
 }
 
 // ------------------------------------------------------------- forward --
@@ -195,12 +223,13 @@ struct FwdAcc {
 // a time, the loads of a group issued before its arithmetic (an invalid edge
 // of a partial batch reads the batch's first edge and contributes nothing).
 template <bool L0>
-__device__ __forceinline__ void fwd_batch(const MpFwd& a, const float* ptab, EdgeRec* rec, const BatchIn& in, int nb,
-                                          int f, int h, const half8_t* bh, const half8_t* bl, const float* bb,
+__device__ __forceinline__ void fwd_batch(const MpFwd& a, const float* ptab, const BatchBuf<32>& buf, int nb, int f,
+                                          int h, const half8_t* bh, const half8_t* bl, const float* bb,
                                           FwdAcc& acc) {
     constexpr int F = kMxF, E = 16;
-    stage_records(in, nb, rec);
-    const half8_t ah = as_half8(in.hi), al = as_half8(in.lo);
+    const EdgeRec* rec = buf.rec;
+    const int r = threadIdx.x & 31;  // A row: edge r (zero past nb)
+    const half8_t ah = as_half8(buf.a[r][h]), al = as_half8(buf.a[r][2 + h]);
     const floatx16_t wa = mma3(ah, al, bh[0], bl[0]);
     floatx16_t wb = {};
     if (!L0) wb = mma3(ah, al, bh[1], bl[1]);  // the first layer's vector input is zero
@@ -247,16 +276,14 @@ __device__ __forceinline__ void fwd_batch(const MpFwd& a, const float* ptab, Edg
             }
         }
     }
-    wave_sync_lds();  // the records are rewritten by the next batch
 }
 
 template <bool L0>
 __global__ void __launch_bounds__(64 * kMxWaves, 2) k_message_fwd_mx(MpGeom mg, MpFwd a) {
     constexpr int F = kMxF, BATCH = 32;
-    __shared__ __align__(16) EdgeRec rec_all[kMxWaves][BATCH];
+    __shared__ __align__(16) BatchBuf<BATCH> buf[2];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int h = lane >> 5, f = w * 32 + (lane & 31);
-    EdgeRec* rec = rec_all[w];
     const int n = mg.n;
     // first layer: the species table of phi in LDS
     __shared__ float ptab_s[L0 ? 8 * 3 * kMxF : 1];
@@ -268,17 +295,22 @@ __global__ void __launch_bounds__(64 * kMxWaves, 2) k_message_fwd_mx(MpGeom mg, 
     half8_t bh[3], bl[3];
     float bb[3];
     load_filter(a.Wr, a.br, sc, f, h, bh, bl, bb);
-    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int i0 = xcd_block(blockIdx.x, gridDim.x) * kMxAtoms;
+    NextBatch nx = next_batch<BATCH>(mg, i0, -1, 0, 0);
+    uint4 piece = fetch_piece<BATCH>(mg, nx.p0, nx.nb);
+    int k = 0;  // batches of the block so far (LDS buffer parity)
     for (int ai = 0; ai < kMxAtoms; ++ai) {
-        const int i = blk * kMxAtoms + ai;
+        const int i = i0 + ai;
         if (i >= n) break;
-        const int p_start = mg.off[i], cnt = mg.ecnt[i];
+        const int cnt = mg.ecnt[i];
         FwdAcc acc{};
-        BatchIn cur = fetch_batch<BATCH>(mg, p_start, min(BATCH, cnt));
-        for (int b0 = 0; b0 < cnt; b0 += BATCH) {
-            BatchIn nxt = fetch_batch<BATCH>(mg, p_start + b0 + BATCH, min(BATCH, cnt - b0 - BATCH));
-            fwd_batch<L0>(a, ptab_s, rec, cur, min(BATCH, cnt - b0), f, h, bh, bl, bb, acc);
-            cur = nxt;
+        for (int b0 = 0; b0 < cnt; b0 += BATCH, ++k) {
+            BatchBuf<BATCH>& b = buf[k & 1];
+            store_piece(b, piece);
+            __syncthreads();  // the batch is staged; the other buffer's batch is done
+            nx = next_batch<BATCH>(mg, i0, ai, b0, cnt);
+            piece = fetch_piece<BATCH>(mg, nx.p0, nx.nb);
+            fwd_batch<L0>(a, ptab_s, b, min(BATCH, cnt - b0), f, h, bh, bl, bb, acc);
         }
         // both halves of the wavefront hold partial sums of feature f
         acc.s += __shfl_xor(acc.s, 32, 64);
@@ -311,12 +343,14 @@ struct BwdAcc {
 // One batch of nb <= 16 edges; the lane's eight edges are taken kBwdGroup at
 // a time as in the forward batch.
 template <bool L0>
-__device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, EdgeRec* rec, const BatchIn& in, int nb,
-                                          int f, int h, const half8_t* bh, const half8_t* bl, const float* bb,
+__device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, const BatchBuf<16>& buf, int nb, int f,
+                                          int h, const half8_t* bh, const half8_t* bl, const float* bb,
                                           const Owner& o, BwdAcc& acc) {
     constexpr int F = kMxF, E = 8;
-    stage_records(in, nb, rec);
-    const half8_t ah = as_half8(in.hi), al = as_half8(in.lo);
+    const EdgeRec* rec = buf.rec;
+    // A rows 0..15: e_k f of edges 0..15, rows 16..31: their r-derivatives (zero past nb)
+    const int r = threadIdx.x & 31, e = r & 15, part = 4 * (r >> 4);
+    const half8_t ah = as_half8(buf.a[e][part + h]), al = as_half8(buf.a[e][part + 2 + h]);
     const floatx16_t m0 = mma3(ah, al, bh[0], bl[0]);
     const floatx16_t m1 = mma3(ah, al, bh[1], bl[1]);
     const floatx16_t m2 = mma3(ah, al, bh[2], bl[2]);
@@ -389,17 +423,15 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, Edg
             acc.fz += dr * u2 + (gu2 - ud * u2) * s.ir;
         }
     }
-    wave_sync_lds();  // the records are rewritten by the next batch
 }
 
 template <bool L0>
 __global__ void __launch_bounds__(64 * kMxWaves, 2) k_message_bwd_mx(MpGeom mg, MpBwd a) {
     constexpr int F = kMxF, BATCH = 16;
-    __shared__ __align__(16) EdgeRec rec_all[kMxWaves][BATCH];
+    __shared__ __align__(16) BatchBuf<BATCH> buf[2];
     __shared__ float fpart[kMxAtoms][kMxWaves][3];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int h = lane >> 5, f = w * 32 + (lane & 31);
-    EdgeRec* rec = rec_all[w];
     const int n = mg.n;
     // first layer: the species table of phi in LDS
     __shared__ float ptab_s[L0 ? 8 * 3 * kMxF : 1];
@@ -412,11 +444,14 @@ __global__ void __launch_bounds__(64 * kMxWaves, 2) k_message_bwd_mx(MpGeom mg, 
     float bb[3];
     load_filter(a.Wr, a.br, sc, f, h, bh, bl, bb);
     const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int i0 = blk * kMxAtoms;
+    NextBatch nx = next_batch<BATCH>(mg, i0, -1, 0, 0);
+    uint4 piece = fetch_piece<BATCH>(mg, nx.p0, nx.nb);
+    int k = 0;  // batches of the block so far (LDS buffer parity)
     for (int ai = 0; ai < kMxAtoms; ++ai) {
-        const int i = blk * kMxAtoms + ai;
+        const int i = i0 + ai;
         if (i >= n) break;
-        const int p_start = mg.off[i], cnt = mg.ecnt[i];
-        BatchIn cur = fetch_batch<BATCH>(mg, p_start, min(BATCH, cnt));
+        const int cnt = mg.ecnt[i];
         Owner o{};
         {
             const int ti = L0 ? min(max(a.species[i], 0), mg.n_species - 1) : 0;
@@ -432,10 +467,13 @@ __global__ void __launch_bounds__(64 * kMxWaves, 2) k_message_bwd_mx(MpGeom mg, 
             o.gs = a.gsm[int64_t(i) * F + f];
         }
         BwdAcc acc{};
-        for (int b0 = 0; b0 < cnt; b0 += BATCH) {
-            BatchIn nxt = fetch_batch<BATCH>(mg, p_start + b0 + BATCH, min(BATCH, cnt - b0 - BATCH));
-            bwd_batch<L0>(a, ptab_s, rec, cur, min(BATCH, cnt - b0), f, h, bh, bl, bb, o, acc);
-            cur = nxt;
+        for (int b0 = 0; b0 < cnt; b0 += BATCH, ++k) {
+            BatchBuf<BATCH>& b = buf[k & 1];
+            store_piece(b, piece);
+            __syncthreads();  // the batch is staged; the other buffer's batch is done
+            nx = next_batch<BATCH>(mg, i0, ai, b0, cnt);
+            piece = fetch_piece<BATCH>(mg, nx.p0, nx.nb);
+            bwd_batch<L0>(a, ptab_s, b, min(BATCH, cnt - b0), f, h, bh, bl, bb, o, acc);
         }
         // both halves of the wavefront hold partial sums of feature f
 #pragma unroll
@@ -468,7 +506,7 @@ __global__ void __launch_bounds__(64 * kMxWaves, 2) k_message_bwd_mx(MpGeom mg, 
     const int t = threadIdx.x;
     if (t < 3 * kMxAtoms) {
         const int ai = t / 3, c = t % 3;
-        const int i = blk * kMxAtoms + ai;
+        const int i = i0 + ai;
         if (i < n) {
             float sum = 0.f;
             for (int k = 0; k < kMxWaves; ++k) sum += fpart[ai][k][c];
