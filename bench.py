@@ -159,7 +159,7 @@ def measured_traffic():
     (two rocprofv3 --pmc passes, calibrated on a plain copy), or None when
     the kernel sources changed after the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "message_bwd_water12288_traffic.md")
+    path = os.path.join(ROOT, "profiles", "message_bwd_mx_water12288_traffic.md")
     try:
         text = open(path).read()
     except OSError:
