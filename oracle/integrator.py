@@ -24,6 +24,13 @@ are given in ps^-1 and used as 1e-3 fs^-1.
   value, or increased by an amount) and the difference is removed from the
   heavy atom it is bonded to, so each molecule keeps its mass.
 * High hydrogen friction: a per-species friction table (diagonal Gamma).
+* NPT virial estimator of one outer step (paper, Methods "Computation of the
+  virial term in NPT"; the reading is that the final estimator is the virial
+  of the slow force F_L = F - F_S at the end of the outer step and the
+  correction is the average, over the inner loop, of the fast force's proxy):
+      W = [W_cons(x_end) - W_S(x_end)] + (1/n) sum_m W_S(x_m)
+  with x_m the positions after inner step m (x_n = x_end).  For a single
+  time step it is W_cons(x_end).
 
 Random numbers: Philox-4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) with key
 (seed, stream) and counter (atom, step, 0, 0); the four 64-bit words give
@@ -229,3 +236,28 @@ def dmts_nc_step(st, cons_fn, nc_fn, prm):
     st.f = cons_fn(st.x)
     st.v = st.v + (0.5 * D) * ACC * (st.f - st.f_nc) / st.m[:, None]
     return st
+
+
+def dmts_nc_step_virial(st, cons_fn, nc_fn, prm, cons_vir, fast_vir):
+    """dmts_nc_step that also returns the step's NPT virial estimator;
+    ``cons_vir(x)`` and ``fast_vir(x)`` give W = -sum_i F_i . q_i of the
+    conservative and the fast force at x."""
+    D, n = prm.dt_outer, prm.n_inner
+    d = D / n
+    if st.first_step or st.f is None or st.f_nc is None:
+        st.f_nc = nc_fn(st.x)
+        st.f = cons_fn(st.x)
+        st.first_step = False
+    st.v = st.v + (0.5 * D) * ACC * (st.f - st.f_nc) / st.m[:, None]
+    inner = []
+    for _ in range(n):
+        _kick(st, st.f_nc, d)
+        st.x = st.x + 0.5 * d * st.v
+        _o_step(st, prm, d)
+        st.x = st.x + 0.5 * d * st.v
+        st.f_nc = nc_fn(st.x)
+        inner.append(fast_vir(st.x))
+        _kick(st, st.f_nc, d)
+    st.f = cons_fn(st.x)
+    st.v = st.v + (0.5 * D) * ACC * (st.f - st.f_nc) / st.m[:, None]
+    return st, (cons_vir(st.x) - inner[-1]) + sum(inner) / n

@@ -38,6 +38,15 @@ Two models are evaluated on a CSR neighbour list (see ``neighbors``):
    The screened nuclear repulsion term is off (its parameters are not
    available); ``nc_forces`` takes no repulsion.
 
+3. Virials for NPT (paper, Methods "Computation of the virial term in NPT"):
+   the quantity W = -sum_i F_i . q_i, written under periodic boundaries
+   through the minimum-image vectors r_ij = q_j - q_i.
+   * Conservative model: W = sum over directed edges of r_e . dE/dr_e, which
+     is dE(lambda)/dlambda at lambda = 1 when every position and the box are
+     scaled by lambda (all minimum-image vectors scale with lambda); taken
+     by autograd in lambda.
+   * NC model: the paper's proxy W = sum_i sum_{j in N(i)} F_ij . r_ij.
+
 Shared pieces:
    Bessel basis  e_k(r) = sqrt(2/rc) sin(k pi r / rc) / r,  k = 1..K
    cosine cutoff fcos(r) = (cos(pi r / rc) + 1) / 2 for r < rc, else 0
@@ -213,6 +222,17 @@ def cons_energy_forces(spec, theta, pos, species, box, offsets, nbr):
     return float(e.detach()), (-g).numpy()
 
 
+def cons_virial(spec, theta, pos, species, box, offsets, nbr):
+    """W = -sum_i F_i . q_i = dE/dlambda under q -> lambda q, L -> lambda L
+    (minimum-image vectors scale with lambda; images fixed), as a float."""
+    lam = torch.tensor(1.0, dtype=_F64, requires_grad=True)
+    x = torch.as_tensor(np.asarray(pos, dtype=np.float64))
+    e = cons_atomic_energies(spec, theta, x * lam, species, torch.as_tensor(box, dtype=_F64) * lam,
+                             offsets, nbr).sum()
+    (g,) = torch.autograd.grad(e, lam)
+    return float(g)
+
+
 # -------------------------------------------------------- non-conservative --
 
 def nc_pair_terms(spec, p, pos, species, box, offsets, nbr):
@@ -244,6 +264,17 @@ def nc_forces(spec, theta, pos, species, box, offsets, nbr):
     x = torch.as_tensor(np.asarray(pos, dtype=np.float64))
     with torch.no_grad():
         return nc_forces_t(spec, theta, x, species, box, offsets, nbr).numpy()
+
+
+def nc_virial_proxy(spec, theta, pos, species, box, offsets, nbr):
+    """The NPT virial proxy sum_i sum_{j in N(i)} F_ij . r_ij (r_ij = q_j - q_i,
+    minimum image), as a float."""
+    p = unpack(spec, theta)
+    x = torch.as_tensor(np.asarray(pos, dtype=np.float64))
+    with torch.no_grad():
+        Fij, i, j = nc_pair_terms(spec, p, x, species, box, offsets, nbr)
+        rvec = edge_vectors(x, box, i, j)
+        return float((Fij * rvec).sum())
 
 
 def nc_weight_grad(spec, theta, pos, species, box, offsets, nbr, dl_df):
