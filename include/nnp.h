@@ -181,6 +181,25 @@ nnp_status nnp_cons_energy_forces(const nnp_model* cons, const nnp_system* sys,
 nnp_status nnp_nc_forces(const nnp_model* nc, const nnp_system* sys, const nnp_nlist* nl,
                          void* ws, size_t ws_bytes, float* forces, void* stream);
 
+/* NPT virials (paper, Methods "Computation of the virial term in NPT"):
+ * W = -sum_i F_i . q_i, written under periodic boundaries through the
+ * minimum-image vectors r_ij = q_j - q_i.  With the kinetic energy K the
+ * pressure is P = (2K - W) / (3V).  virial: device float64 [n_rep].
+ *
+ * nnp_cons_virial: energy (may be NULL) and forces (required) as
+ * nnp_cons_energy_forces, and W = sum over directed edges of r_e . dE/dr_e
+ * (equal to dE/dlambda when positions and box are scaled by lambda),
+ * accumulated from the pair forces of the hand-written reverse pass. */
+nnp_status nnp_cons_virial(const nnp_model* cons, const nnp_system* sys, const nnp_nlist* nl,
+                           void* ws, size_t ws_bytes, double* energy, float* forces, double* virial,
+                           void* stream);
+
+/* nnp_nc_virial: forces as nnp_nc_forces and the paper's proxy
+ * W = sum_i sum_{j in N(i)} F_ij . r_ij of the NC pair terms (equal to
+ * -sum_i F_i . q_i wherever q_i is unambiguous). */
+nnp_status nnp_nc_virial(const nnp_model* nc, const nnp_system* sys, const nnp_nlist* nl,
+                         void* ws, size_t ws_bytes, float* forces, double* virial, void* stream);
+
 /* Weight gradient of the NC model: given dl_df = dL/dF_NC (device float32
  * [3][n_atoms]) writes dL/dtheta (device float32 [n_weights], manifest
  * order), the vector-Jacobian product used to distil the NC model onto
@@ -271,6 +290,8 @@ typedef struct {
     int64_t n_rewinds;     /* out: rewinds performed (accumulates) */
     int64_t n_replays;     /* out: intervals replayed after a list went stale
                               between two predicted rebuilds (accumulates) */
+    double* virial;        /* [n_rep] or NULL: after the call, the NPT virial
+                              estimator W of the last outer step (see below) */
 } respa_state;
 
 /* Advances the state by n_outer outer steps of Algorithm 1 (DMTS-NC, or
@@ -291,7 +312,16 @@ typedef struct {
  * capacity and finiteness; on NNP_ECAPACITY the state is restored to the
  * start of the failing outer step (grow the list buffers and call again);
  * on NNP_EUNSTABLE it is left at the last checked good step.  The sizes of
- * completed steps are reflected in state->step. */
+ * completed steps are reflected in state->step.
+ * Virial estimator (state->virial not NULL; paper, Methods "Computation of
+ * the virial term in NPT"): for an outer step of n inner steps with fast
+ * force F_S (the NC model, or the small conservative model), the virial of
+ * the slow force F_L = F - F_S at the end of the step plus the average over
+ * the inner loop of the fast force's proxy,
+ *   W = [W_cons(x_end) - W_S(x_end)] + (1/n) sum_m W_S(x_m),
+ * x_m the positions after inner step m; a single time step gives
+ * W_cons(x_end).  W_S is the NC proxy (nnp_nc_virial) or the conservative
+ * virial of the small model. */
 nnp_status respa_step(const nnp_model* cons, const nnp_model* nc, respa_state* state,
                       const respa_params* params, int32_t n_outer, void* ws, size_t ws_bytes,
                       void* stream);

@@ -50,7 +50,7 @@ class RespaState(C.Structure):
                 ("f_nc", vp), ("energy", vp), ("pos_ref", vp), ("nl_cons", NList), ("nl_nc", NList),
                 ("step", C.c_uint64), ("first_step", C.c_int32), ("lists_valid", C.c_int32), ("ke", vp),
                 ("n_rebuilds", C.c_int64), ("n_rewinds", C.c_int64),
-                ("n_replays", C.c_int64)]
+                ("n_replays", C.c_int64), ("virial", vp)]
 
 
 class ReplicaDesc(C.Structure):
@@ -76,6 +76,8 @@ PROTOTYPES = {
     "nnp_neighbors": (C.c_int32, [C.POINTER(System), C.POINTER(NList), vp, C.c_size_t, vp]),
     "nnp_cons_energy_forces": (C.c_int32, [vp, C.POINTER(System), C.POINTER(NList), vp, C.c_size_t, vp, vp, vp]),
     "nnp_nc_forces": (C.c_int32, [vp, C.POINTER(System), C.POINTER(NList), vp, C.c_size_t, vp, vp]),
+    "nnp_cons_virial": (C.c_int32, [vp, C.POINTER(System), C.POINTER(NList), vp, C.c_size_t, vp, vp, vp, vp]),
+    "nnp_nc_virial": (C.c_int32, [vp, C.POINTER(System), C.POINTER(NList), vp, C.c_size_t, vp, vp, vp]),
     "nnp_nc_weight_grad": (C.c_int32, [vp, C.POINTER(System), C.POINTER(NList), vp, vp, vp, C.c_size_t, vp]),
     "nnp_force_mse": (C.c_int32, [vp, vp, C.c_int64, vp, vp, vp, C.c_size_t, vp]),
     "nnp_adam_step": (C.c_int32, [vp, vp, vp, vp, C.c_int64, C.c_int64, C.c_double, C.c_double, C.c_double,

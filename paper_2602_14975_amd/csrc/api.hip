@@ -31,7 +31,7 @@ using namespace nnp;
     return NNP_OK;
 
 extern "C" const char* nnp_last_error(void) { return g_err.c_str(); }
-extern "C" int32_t nnp_abi_version(void) { return 1; }
+extern "C" int32_t nnp_abi_version(void) { return 2; }
 
 // ===================================================================== model
 namespace nnp {
@@ -227,6 +227,8 @@ RepGeom upload_tables(const nnp_system& sys, SysTables& t, hipStream_t s, std::v
 void carve_model(Arena& a, const Model* m, int64_t n, int64_t E, bool for_wgrad, ModelBuf& b) {
     const int64_t F = m->desc.width;
     const int L = m->n_layers();
+    b.vir = a.take<float>(n);
+    b.vir_sum = a.take<float>(n);
     for (int l = 0; l <= L; ++l) {
         b.s[l] = a.take<float>(n * F);
         b.v[l] = a.take<float>(n * 3 * F);
@@ -371,7 +373,7 @@ void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, Mode
 // output.  Out: gs, gv = adjoints of the layer input (buffers swapped).
 // With `dtheta`, the weight adjoints of the layer are written too.
 void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float* force, bool accum_force,
-                    float* dtheta, hipStream_t s) {
+                    float* dtheta, hipStream_t s, float* vir = nullptr) {
     const int n = mg.n;
     const int F = m->desc.width, K = m->desc.n_rbf;
     const int cut = m->desc.kind == NNP_MODEL_CONS ? 0 : 1;
@@ -402,6 +404,7 @@ void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float*
     a.gv_in = b.gv2;
     a.force = force;
     a.accum_force = accum_force;
+    a.vir = vir;
     a.wgrad_part = wg ? b.mp_part : nullptr;
     if (l == 0) {
         a.species = mg.species;
@@ -467,8 +470,9 @@ MpGeom make_geom(const Model* m, const nnp_system& sys, const RepGeom& geom, con
     return mg;
 }
 
+// With `vir`, also the per-atom shares of the virial -sum_i F_i . q_i.
 void cons_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const SysTables& t, const nnp_nlist& nl,
-               ModelBuf& b, double* energy, float* forces, hipStream_t s) {
+               ModelBuf& b, double* energy, float* forces, hipStream_t s, float* vir = nullptr) {
     const int n = int(sys.n_atoms);
     const int F = m->desc.width;
     MpGeom mg = make_geom(m, sys, geom, nl);
@@ -488,11 +492,13 @@ void cons_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const
     launch_readout_bwd(n, F, b.ao, m->p(m->off_wo), b.gs2, s);
     gemm_gwt(m, m->off_Wo, n, F, F, b.gs2, F, b.gs, F, EPI_NONE, nullptr, 0, false, s);
     launch_zero(b.gv, int64_t(n) * 3 * F, nullptr, s);
-    for (int l = L - 1; l >= 0; --l) layer_backward(m, l, mg, b, forces, l != L - 1, nullptr, s);
+    for (int l = L - 1; l >= 0; --l) layer_backward(m, l, mg, b, forces, l != L - 1, nullptr, s, vir);
 }
 
+// With vir_set / vir_add, also the per-atom shares of the NPT virial proxy
+// sum_i sum_j F_ij . r_ij, written / added to.
 void nc_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const nnp_nlist& nl, ModelBuf& b,
-             float* forces, hipStream_t s) {
+             float* forces, hipStream_t s, float* vir_set = nullptr, float* vir_add = nullptr) {
     const int n = int(sys.n_atoms);
     const int F = m->desc.width;
     const int HC = 2 * (m->desc.n_s + m->desc.n_l) * m->desc.n_c;
@@ -514,7 +520,7 @@ void nc_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const n
         launch_message_fwd(F, K, 1, mg, a, s);
         NcUpdateArgs u{n, lb.smid, lb.vmid, m->ncw, m->p(lo.m1), m->p(lo.m2), b.QK, b.Vh};
         if (m->ncw && launch_nc_update_proj(u, F, m->bf16(), s)) {
-            launch_head_fwd(mg, b.QK, b.Vh, forces, false, s);
+            launch_head_fwd(mg, b.QK, b.Vh, forces, false, s, vir_set, vir_add);
             return;
         }
     }
@@ -522,7 +528,7 @@ void nc_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const n
     gemm_xwt(n, HC, F, b.s[1], F, m->p(m->off_Wq), nullptr, b.QK, HC, EPI_NONE, nullptr, 0, false, s, m->bf16());
     gemm_xwt(3 * n, m->desc.n_l, F, b.v[1], F, m->p(m->off_WV), nullptr, b.Vh, m->desc.n_l, EPI_NONE, nullptr, 0,
              false, s, m->bf16());
-    launch_head_fwd(mg, b.QK, b.Vh, forces, false, s);
+    launch_head_fwd(mg, b.QK, b.Vh, forces, false, s, vir_set, vir_add);
 }
 
 void nc_wgrad(const Model* m, const nnp_system& sys, const RepGeom& geom, const nnp_nlist& nl, ModelBuf& b,
@@ -664,6 +670,45 @@ extern "C" nnp_status nnp_cons_energy_forces(const nnp_model* cons, const nnp_sy
     std::vector<double> hs;
     RepGeom g = upload_tables(*sys, c.t, s, hs);
     cons_eval(m, *sys, g, c.t, *nl, c.cons, energy, forces, s);
+    NNP_API_END
+}
+
+extern "C" nnp_status nnp_cons_virial(const nnp_model* cons, const nnp_system* sys, const nnp_nlist* nl, void* ws,
+                                      size_t ws_bytes, double* energy, float* forces, double* virial,
+                                      void* stream) {
+    NNP_API_BEGIN
+    NNP_REQUIRE(cons && forces && virial, NNP_EINVAL, "null argument");
+    const Model* m = reinterpret_cast<const Model*>(cons);
+    NNP_REQUIRE(m->desc.kind == NNP_MODEL_CONS, NNP_EINVAL, "not a conservative model");
+    check_system(sys);
+    check_list(nl, sys, m->desc.cutoff);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Arena a(ws, ws_bytes);
+    CallScratch c;
+    carve_all(a, m, nullptr, sys->n_atoms, sys->n_rep, std::max<int64_t>(nl->capacity, 1), false, c);
+    std::vector<double> hs;
+    RepGeom g = upload_tables(*sys, c.t, s, hs);
+    cons_eval(m, *sys, g, c.t, *nl, c.cons, energy, forces, s, c.cons.vir);
+    launch_rep_sum(sys->n_rep, c.t.rep_start, c.cons.vir, virial, s);
+    NNP_API_END
+}
+
+extern "C" nnp_status nnp_nc_virial(const nnp_model* nc, const nnp_system* sys, const nnp_nlist* nl, void* ws,
+                                    size_t ws_bytes, float* forces, double* virial, void* stream) {
+    NNP_API_BEGIN
+    NNP_REQUIRE(nc && forces && virial, NNP_EINVAL, "null argument");
+    const Model* m = reinterpret_cast<const Model*>(nc);
+    NNP_REQUIRE(m->desc.kind == NNP_MODEL_NC, NNP_EINVAL, "not an NC model");
+    check_system(sys);
+    check_list(nl, sys, m->desc.cutoff);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Arena a(ws, ws_bytes);
+    CallScratch c;
+    carve_all(a, nullptr, m, sys->n_atoms, sys->n_rep, std::max<int64_t>(nl->capacity, 1), false, c);
+    std::vector<double> hs;
+    RepGeom g = upload_tables(*sys, c.t, s, hs);
+    nc_eval(m, *sys, g, *nl, c.nc, forces, s, c.nc.vir, nullptr);
+    launch_rep_sum(sys->n_rep, c.t.rep_start, c.nc.vir, virial, s);
     NNP_API_END
 }
 
@@ -947,10 +992,21 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     ba.step_offset = 0;
     ba.step_dev = c.t.o_step;
 
-    auto eval_cons = [&]() { cons_eval(cons, st->sys, g, c.t, lc, c.cons, st->energy, st->f_cons, s); };
+    // NPT virial estimator (state->virial): per-atom shares of W_cons in
+    // c.cons.vir, of the fast force's W_S in c.nc.vir (last evaluation) and
+    // c.nc.vir_sum (summed over the inner loop of the current outer step)
+    const bool want_vir = st->virial != nullptr;
+    auto eval_cons = [&]() {
+        cons_eval(cons, st->sys, g, c.t, lc, c.cons, st->energy, st->f_cons, s, want_vir ? c.cons.vir : nullptr);
+    };
     auto eval_inner = [&]() {
-        if (inner_nc) nc_eval(nc, st->sys, g, ln, c.nc, st->f_nc, s);
-        else cons_eval(nc, st->sys, g, c.t, ln, c.nc, inner_energy, st->f_nc, s);
+        if (inner_nc) {
+            nc_eval(nc, st->sys, g, ln, c.nc, st->f_nc, s, want_vir ? c.nc.vir : nullptr,
+                    want_vir ? c.nc.vir_sum : nullptr);
+        } else {
+            cons_eval(nc, st->sys, g, c.t, ln, c.nc, inner_energy, st->f_nc, s, want_vir ? c.nc.vir : nullptr);
+            if (want_vir) launch_add(n, c.nc.vir, c.nc.vir_sum, s);
+        }
     };
 
     int* hflags = pinned_flags();
@@ -1047,6 +1103,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         launch_baoa(ba, s);
         rebuild_if_flagged();
         eval_cons();
+        if (want_vir) launch_rep_sum(R, c.t.rep_start, c.cons.vir, st->virial, s);
         launch_kick(n, st->vel, st->mass, st->f_cons, nullptr, 0.5 * dt, s, c.t.o_step);
         offset += 1;
         st->step += 1;
@@ -1063,6 +1120,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
             rebuild_if_flagged();
         }
         ba.flag = strict ? trig : stale;
+        if (want_vir) launch_zero(c.nc.vir_sum, n, nullptr, s);
         launch_kick(n, st->vel, st->mass, st->f_cons, st->f_nc, 0.5 * D, s);
         for (int k = 0; k < n_in; ++k) {
             ba.force = st->f_nc;
@@ -1073,6 +1131,10 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
             launch_kick(n, st->vel, st->mass, st->f_nc, nullptr, 0.5 * d, s, c.t.o_step);
         }
         eval_cons();
+        if (want_vir) {
+            launch_virial_combine(n, c.cons.vir, c.nc.vir, c.nc.vir_sum, float(1.0 / n_in), c.cons.vir_sum, s);
+            launch_rep_sum(R, c.t.rep_start, c.cons.vir_sum, st->virial, s);
+        }
         launch_kick(n, st->vel, st->mass, st->f_cons, st->f_nc, 0.5 * D, s);
     };
     // Predictive outer steps can be recorded once as a HIP graph and replayed:

@@ -164,6 +164,7 @@ constexpr int kNs = 8, kNl = 2, kNc = 8, kH = kNs + kNl;
 struct HeadEdge {
     float ef[kNs];  // B_h(r) u(r/rc)
     float u[3];
+    float r;
     int j;
 };
 
@@ -192,6 +193,7 @@ __device__ __forceinline__ bool head_edge(const MpGeom& mg, int i, int e, double
     he.u[0] = float(dx / r);
     he.u[1] = float(dy / r);
     he.u[2] = float(dz / r);
+    he.r = float(r);
     he.j = j;
     return true;
 }
@@ -219,9 +221,10 @@ __device__ __forceinline__ void head_coeffs(const float* qa, const float* kb, fl
 // the row holds or where batch boundaries fall.
 template <int G>
 __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __restrict__ QK,
-                                                  const float* __restrict__ Vh, float* __restrict__ Fout, int accum) {
+                                                  const float* __restrict__ Vh, float* __restrict__ Fout, int accum,
+                                                  float* __restrict__ vir_set, float* __restrict__ vir_add) {
     constexpr int APW = 64 / G;
-    __shared__ float contrib[4][APW][G][3];
+    __shared__ float contrib[4][APW][G][4];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int g = lane / G, l = lane % G;
@@ -246,7 +249,7 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
             for (int h = 0; h < kNl; ++h) Vi[h][a] = Vh[(int64_t(i) * 3 + a) * kNl + h];
     }
     const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (g * G));
-    float fx = 0.f, fy = 0.f, fz = 0.f;  // running sums (first lane of the group)
+    float fx = 0.f, fy = 0.f, fz = 0.f, vr = 0.f;  // running sums (first lane of the group)
     for (int base = 0; __ballot(e0 + base < e1) != 0ull; base += G) {
         const int e = e0 + base + l;
         HeadEdge he;
@@ -266,13 +269,16 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
                 Sji = fmaf(cji[h], he.ef[h], Sji);
             }
             const int pre = __popcll(mine & ((1ull << lane) - 1ull));
+            float fu = 0.f;  // F_ij . u
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const float Dij = he.u[a] + cij[kNs] * Vi[0][a] + cij[kNs + 1] * Vi[1][a];
                 const float Dji = -he.u[a] + cji[kNs] * Vh[(int64_t(j) * 3 + a) * kNl] +
                                   cji[kNs + 1] * Vh[(int64_t(j) * 3 + a) * kNl + 1];
                 contrib[w][g][pre][a] = Sij * Dij - Sji * Dji;
+                fu = fmaf(Sij * Dij, he.u[a], fu);
             }
+            contrib[w][g][pre][3] = fu * he.r;  // F_ij . r_ij
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
@@ -283,6 +289,7 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
                 fx += contrib[w][g][t][0];
                 fy += contrib[w][g][t][1];
                 fz += contrib[w][g][t][2];
+                vr += contrib[w][g][t][3];
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -295,6 +302,8 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
         } else {
             Fout[i] = fx; Fout[n + i] = fy; Fout[2 * n + i] = fz;
         }
+        if (vir_set) vir_set[i] = vr;
+        if (vir_add) vir_add[i] += vr;
     }
 }
 
@@ -610,11 +619,12 @@ void launch_emb_grad(int n, int F, int S, const int* species, const float* gs0, 
     k_emb_grad<<<S, 128, 0, st>>>(n, F, S, species, gs0, gemb);
     NNP_LAUNCH_CHECK();
 }
-void launch_head_fwd(const MpGeom& mg, const float* QK, const float* Vh, float* F, bool accum, hipStream_t st) {
+void launch_head_fwd(const MpGeom& mg, const float* QK, const float* Vh, float* F, bool accum, hipStream_t st,
+                     float* vir_set, float* vir_add) {
     if (mg.n <= 0) return;
     ScopedTimer timer("head_fwd", st);
     // 16 lanes per atom: rows of the 3.5 A list hold about 40 candidates
-    k_head_fwd<16><<<cdiv(mg.n, 16), 256, 0, st>>>(mg, QK, Vh, F, accum);
+    k_head_fwd<16><<<cdiv(mg.n, 16), 256, 0, st>>>(mg, QK, Vh, F, accum, vir_set, vir_add);
     NNP_LAUNCH_CHECK();
 }
 void launch_head_bwd(const MpGeom& mg, const float* QK, const float* Vh, const float* gF, float* gQK, float* gVh,

@@ -182,6 +182,33 @@ void launch_zero(void* p, int64_t words, const int* run, hipStream_t s) {
     NNP_LAUNCH_CHECK();
 }
 
+// NPT virial estimator of an outer step per atom (the per-atom shares of
+// the virial of the slow force at the end of the step plus the inner-loop
+// average of the fast force's proxy): out = w_cons - w_fast_last + inv_n w_fast_sum
+__global__ void k_virial_combine(int n, const float* __restrict__ wc, const float* __restrict__ wl,
+                                 const float* __restrict__ ws, float inv_n, float* __restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[t] = (wc[t] - wl[t]) + ws[t] * inv_n;
+}
+
+void launch_virial_combine(int n, const float* wc, const float* wl, const float* ws, float inv_n, float* out,
+                           hipStream_t s) {
+    if (n <= 0) return;
+    k_virial_combine<<<cdiv(n, 256), 256, 0, s>>>(n, wc, wl, ws, inv_n, out);
+    NNP_LAUNCH_CHECK();
+}
+
+__global__ void k_add(int n, const float* __restrict__ x, float* __restrict__ y) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] += x[t];
+}
+
+void launch_add(int n, const float* x, float* y, hipStream_t s) {
+    if (n <= 0) return;
+    k_add<<<cdiv(n, 256), 256, 0, s>>>(n, x, y);
+    NNP_LAUNCH_CHECK();
+}
+
 void launch_baoa(const BaoaArgs& a, hipStream_t s) {
     ScopedTimer timer("baoa", s);
     k_baoa<<<cdiv(a.n, 256), 256, 0, s>>>(a);

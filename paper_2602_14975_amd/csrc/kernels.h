@@ -136,6 +136,10 @@ struct MpBwd {
     float* force;       // [3][n] forces -dE/dx (GEO): written, or added to with accum_force
     int accum_force;
     float* wgrad_part;  // [blocks][3F][K + 1] filter weight adjoints (WGRAD)
+    // [n] or nullptr (GEO): per owner atom i, 1/2 sum_j r_ij . f_ij of its pair
+    // forces f_ij (its share of the virial -sum F . q), written or added to
+    // with accum_force
+    float* vir;
     const float* mx_scale;  // [2] filter-weight scale and its inverse for the matrix-core kernels, or nullptr
 };
 
@@ -165,7 +169,10 @@ void launch_readout(int n, int F, int S, const float* z, const float* wo, const 
 void launch_readout_bwd(int n, int F, const float* ao, const float* wo, float* gao, hipStream_t st);
 void launch_rep_sum(int n_rep, const int64_t* rep_start, const float* x, double* out, hipStream_t st);
 void launch_emb_grad(int n, int F, int S, const int* species, const float* gs0, float* gemb, hipStream_t st);
-void launch_head_fwd(const MpGeom& mg, const float* QK, const float* Vh, float* F, bool accum, hipStream_t st);
+// vir_set / vir_add ([n] or nullptr): per owner i, sum_j F_ij . r_ij (its
+// share of the NPT virial proxy), written / added to
+void launch_head_fwd(const MpGeom& mg, const float* QK, const float* Vh, float* F, bool accum, hipStream_t st,
+                     float* vir_set = nullptr, float* vir_add = nullptr);
 void launch_head_bwd(const MpGeom& mg, const float* QK, const float* Vh, const float* gF, float* gQK, float* gVh,
                      hipStream_t st);
 
@@ -213,6 +220,9 @@ void launch_kick(int n, double* vel, const double* mass, const float* Fa, const 
 void launch_set_u64(uint64_t* p, uint64_t value, hipStream_t s);
 // zero fill as a kernel (safe inside recorded graphs); with `run`, only when *run != 0
 void launch_zero(void* p, int64_t words, const int* run, hipStream_t s);
+void launch_virial_combine(int n, const float* wc, const float* wl, const float* ws, float inv_n, float* out,
+                           hipStream_t s);
+void launch_add(int n, const float* x, float* y, hipStream_t s);  // y += x
 bool timers_active();
 void launch_baoa(const BaoaArgs& a, hipStream_t s);
 void launch_kinetic(int n_rep, const int64_t* rep_start, int n, const double* pos, const double* vel,

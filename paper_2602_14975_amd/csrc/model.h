@@ -62,6 +62,8 @@ struct ModelBuf {
     float *gs = nullptr, *gs2 = nullptr, *gv = nullptr, *gv2 = nullptr, *gpqo = nullptr, *ga1 = nullptr,
           *gX = nullptr, *gUV = nullptr, *gphi = nullptr, *gh1 = nullptr;
     float *chunk_part = nullptr, *mp_part = nullptr, *filt_sum = nullptr;
+    // per-atom virial shares: of the last evaluation, and a running sum
+    float *vir = nullptr, *vir_sum = nullptr;
     // prepared edges of the matrix-core message kernels (list capacity E)
     int* ecnt = nullptr;
     EdgeRec* erec = nullptr;

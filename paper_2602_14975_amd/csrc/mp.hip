@@ -239,7 +239,7 @@ k_message_bwd(MpGeom mg, MpBwd a) {
     static_assert(!WGRAD || WPA == 1, "filter weight adjoints need one wavefront per atom");
     __shared__ EdgeSlot<K> slots_all[S::SLOT_SETS][APW][G];
     __shared__ int batch_cnt[S::SLOT_SETS];
-    __shared__ float fpart[kMpWaves][APW][3];
+    __shared__ float fpart[kMpWaves][APW][4];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int g = lane / G, l = lane % G;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -263,6 +263,7 @@ k_message_bwd(MpGeom mg, MpBwd a) {
     float ph_o[3][FPL] = {}, v_o[3][FPL] = {}, gs_o[FPL] = {}, gv_o[3][FPL] = {};
     float gph[3][FPL] = {}, gvacc[3][FPL] = {};
     float fx = 0.f, fy = 0.f, fz = 0.f;  // per-lane share of the force on o
+    float vr = 0.f;                      // and of sum_j r_oj . f_oj
     float gwr[WGRAD ? 3 : 1][WGRAD ? FPL : 1][WGRAD ? K : 1] = {};
     float gbr[WGRAD ? 3 : 1][WGRAD ? FPL : 1] = {};
     int start = 0, end = 0;
@@ -391,6 +392,7 @@ k_message_bwd(MpGeom mg, MpBwd a) {
                 fx += dr * u0 + (gu0 - ud * u0) * s.ir;
                 fy += dr * u1 + (gu1 - ud * u1) * s.ir;
                 fz += dr * u2 + (gu2 - ud * u2) * s.ir;
+                if (a.vir) vr += __fdividef(dr, s.ir);  // the projected term is normal to u
             }
         }
         if constexpr (S::SHARED) __syncthreads();  // the slots are restaged next
@@ -400,20 +402,23 @@ k_message_bwd(MpGeom mg, MpBwd a) {
         fx = group_sum<G>(fx);
         fy = group_sum<G>(fy);
         fz = group_sum<G>(fz);
+        vr = group_sum<G>(vr);
         if (WPA > 1) {
             // combine the wavefronts of the atom in a fixed order
             if (l == 0) {
                 fpart[w][g][0] = fx;
                 fpart[w][g][1] = fy;
                 fpart[w][g][2] = fz;
+                fpart[w][g][3] = vr;
             }
             __syncthreads();
             if (w % WPA == 0) {
-                fx = fy = fz = 0.f;
+                fx = fy = fz = vr = 0.f;
                 for (int k = 0; k < WPA; ++k) {
                     fx += fpart[w + k][g][0];
                     fy += fpart[w + k][g][1];
                     fz += fpart[w + k][g][2];
+                    vr += fpart[w + k][g][3];
                 }
             }
         }
@@ -422,6 +427,10 @@ k_message_bwd(MpGeom mg, MpBwd a) {
                 a.force[i] += fx; a.force[n + i] += fy; a.force[2 * n + i] += fz;
             } else {
                 a.force[i] = fx; a.force[n + i] = fy; a.force[2 * n + i] = fz;
+            }
+            if (a.vir) {  // each pair is seen by both of its atoms
+                if (a.accum_force) a.vir[i] += 0.5f * vr;
+                else a.vir[i] = 0.5f * vr;
             }
         }
     }

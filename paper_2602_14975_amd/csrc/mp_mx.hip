@@ -337,12 +337,12 @@ struct Owner {
 };
 
 struct BwdAcc {
-    float gph[3], gv[3], fx, fy, fz;
+    float gph[3], gv[3], fx, fy, fz, vir;
 };
 
 // One batch of nb <= 16 edges; the lane's eight edges are taken kBwdGroup at
 // a time as in the forward batch.
-template <bool L0>
+template <bool L0, bool VIR>
 __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, const BatchBuf<16>& buf, int nb, int f,
                                           int h, const half8_t* bh, const half8_t* bl, const float* bb,
                                           const Owner& o, BwdAcc& acc) {
@@ -421,15 +421,17 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
             acc.fx += dr * u0 + (gu0 - ud * u0) * s.ir;
             acc.fy += dr * u1 + (gu1 - ud * u1) * s.ir;
             acc.fz += dr * u2 + (gu2 - ud * u2) * s.ir;
+            // r_ij . (pair force share): the projected term is normal to u
+            if constexpr (VIR) acc.vir += __fdividef(dr, s.ir);
         }
     }
 }
 
-template <bool L0>
+template <bool L0, bool VIR>
 __global__ void __launch_bounds__(64 * kMxWaves, 2) k_message_bwd_mx(MpGeom mg, MpBwd a) {
     constexpr int F = kMxF, BATCH = 16;
     __shared__ __align__(16) BatchBuf<BATCH> buf[2];
-    __shared__ float fpart[kMxAtoms][kMxWaves][3];
+    __shared__ float fpart[kMxAtoms][kMxWaves][4];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int h = lane >> 5, f = w * 32 + (lane & 31);
     const int n = mg.n;
@@ -473,7 +475,7 @@ __global__ void __launch_bounds__(64 * kMxWaves, 2) k_message_bwd_mx(MpGeom mg, 
             __syncthreads();  // the batch is staged; the other buffer's batch is done
             nx = next_batch<BATCH>(mg, i0, ai, b0, cnt);
             piece = fetch_piece<BATCH>(mg, nx.p0, nx.nb);
-            bwd_batch<L0>(a, ptab_s, b, min(BATCH, cnt - b0), f, h, bh, bl, bb, o, acc);
+            bwd_batch<L0, VIR>(a, ptab_s, b, min(BATCH, cnt - b0), f, h, bh, bl, bb, o, acc);
         }
         // both halves of the wavefront hold partial sums of feature f
 #pragma unroll
@@ -482,10 +484,12 @@ __global__ void __launch_bounds__(64 * kMxWaves, 2) k_message_bwd_mx(MpGeom mg, 
             acc.gv[p] += __shfl_xor(acc.gv[p], 32, 64);
         }
         const float fx = group_sum<64>(acc.fx), fy = group_sum<64>(acc.fy), fz = group_sum<64>(acc.fz);
+        const float vr = VIR ? group_sum<64>(acc.vir) : 0.f;
         if (lane == 0) {
             fpart[ai][w][0] = fx;
             fpart[ai][w][1] = fy;
             fpart[ai][w][2] = fz;
+            fpart[ai][w][3] = vr;
         }
         if (h == 0) {
             if (a.want_gphi) {
@@ -502,16 +506,18 @@ __global__ void __launch_bounds__(64 * kMxWaves, 2) k_message_bwd_mx(MpGeom mg, 
         }
     }
     __syncthreads();
-    // the force on each atom of the block: the feature blocks' shares in a fixed order
+    // the force (and virial share) of each atom of the block: the feature
+    // blocks' shares in a fixed order
     const int t = threadIdx.x;
-    if (t < 3 * kMxAtoms) {
-        const int ai = t / 3, c = t % 3;
+    if (t < 4 * kMxAtoms) {
+        const int ai = t / 4, c = t % 4;
         const int i = i0 + ai;
-        if (i < n) {
+        if (i < n && (c < 3 || VIR)) {
             float sum = 0.f;
             for (int k = 0; k < kMxWaves; ++k) sum += fpart[ai][k][c];
             sum *= isc;
-            float* fo = a.force + int64_t(c) * n + i;
+            float* fo = c < 3 ? a.force + int64_t(c) * n + i : a.vir + i;
+            if (c == 3) sum *= 0.5f;  // each pair is seen by both of its atoms
             if (a.accum_force) *fo += sum;
             else *fo = sum;
         }
@@ -558,8 +564,13 @@ void launch_message_fwd_mx(const MpGeom& mg, const MpFwd& a, hipStream_t s, cons
 }
 
 void launch_message_bwd_mx(const MpGeom& mg, const MpBwd& a, hipStream_t s, const ScopedTimer& t) {
-    if (a.phi_tab) launch_mx(t, k_message_bwd_mx<true>, mg.n, s, mg, a);
-    else launch_mx(t, k_message_bwd_mx<false>, mg.n, s, mg, a);
+    if (a.vir) {
+        if (a.phi_tab) launch_mx(t, k_message_bwd_mx<true, true>, mg.n, s, mg, a);
+        else launch_mx(t, k_message_bwd_mx<false, true>, mg.n, s, mg, a);
+    } else {
+        if (a.phi_tab) launch_mx(t, k_message_bwd_mx<true, false>, mg.n, s, mg, a);
+        else launch_mx(t, k_message_bwd_mx<false, false>, mg.n, s, mg, a);
+    }
 }
 
 void launch_edge_prep(const MpGeom& mg, int* ecnt, EdgeRec* erec, uint4* ehalf, hipStream_t s) {

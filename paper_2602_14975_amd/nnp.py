@@ -170,6 +170,25 @@ def nnp_nc_forces(model, system, nlist, ws, forces=None):
     return forces
 
 
+def nnp_cons_virial(model, system, nlist, ws):
+    """(energy [n_rep], forces [3][n], virial W = -sum F . q [n_rep])."""
+    energy = torch.empty(system.n_rep, dtype=torch.float64, device=DEV)
+    forces = torch.empty(3, system.n, dtype=torch.float32, device=DEV)
+    virial = torch.empty(system.n_rep, dtype=torch.float64, device=DEV)
+    check(lib().nnp_cons_virial(model.handle, C.byref(system.c()), C.byref(nlist.c()), _ptr(ws), ws.numel(),
+                                _ptr(energy), _ptr(forces), _ptr(virial), _stream()))
+    return energy, forces, virial
+
+
+def nnp_nc_virial(model, system, nlist, ws):
+    """(forces [3][n], virial proxy sum F_ij . r_ij [n_rep])."""
+    forces = torch.empty(3, system.n, dtype=torch.float32, device=DEV)
+    virial = torch.empty(system.n_rep, dtype=torch.float64, device=DEV)
+    check(lib().nnp_nc_virial(model.handle, C.byref(system.c()), C.byref(nlist.c()), _ptr(ws), ws.numel(),
+                              _ptr(forces), _ptr(virial), _stream()))
+    return forces, virial
+
+
 def nnp_nc_weight_grad(model, system, nlist, dl_df, ws, out=None):
     out = out if out is not None else torch.empty(model.n_weights, dtype=torch.float32, device=DEV)
     dl_df = dl_df.contiguous()
@@ -206,7 +225,8 @@ def nnp_hmr_masses(bonded_heavy, masses, h_mass=3.0, mode="set"):
 class Trajectory:
     """Device-resident respa_state plus its list buffers and workspace."""
 
-    def __init__(self, cons, nc, system, vel, masses, gamma, params, skin=1.0, capacity_factor=1.4):
+    def __init__(self, cons, nc, system, vel, masses, gamma, params, skin=1.0, capacity_factor=1.4,
+                 virial=False):
         self.cons, self.nc, self.sys = cons, nc, system
         n = system.n
         self.params = params
@@ -218,6 +238,8 @@ class Trajectory:
         self.f_nc = torch.zeros(3, n, dtype=torch.float32, device=DEV)
         self.energy = torch.zeros(system.n_rep, dtype=torch.float64, device=DEV)
         self.pos_ref = torch.zeros(3, n, dtype=torch.float64, device=DEV)
+        # NPT virial estimator of the last outer step, per replica (respa_step)
+        self.virial = torch.zeros(system.n_rep, dtype=torch.float64, device=DEV) if virial else None
         # initial capacity from a list build at the Verlet radius
         ws0 = workspace(None, None, n, system.n_rep, 1)
         rc_c = cons.cutoff + params.skin
@@ -245,7 +267,7 @@ class Trajectory:
                                self.energy.data_ptr(), self.pos_ref.data_ptr(), self.nl_cons.c(), self.nl_nc.c(),
                                self.step_count, self.first_step, self.lists_valid,
                                ke.data_ptr() if ke is not None else None, self.n_rebuilds, self.n_rewinds,
-                               self.n_replays)
+                               self.n_replays, self.virial.data_ptr() if self.virial is not None else None)
 
     def respa_step(self, n_outer, ke=None):
         """Advances by n_outer outer steps (growing list buffers on
