@@ -1239,7 +1239,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
             }
         }
         launch_kinetic(R, c.t.rep_start, n, st->pos, st->vel, st->mass, st->ke ? st->ke + int64_t(o) * R : nullptr,
-                       c.t.rep_bad, s);
+                       c.t.rep_bad, s, st->sys.rep_of_atom);
         if ((o + 1) % check_every == 0 || o + 1 == n_outer) {
             nnp_status e = check(snap_offset, true);
             if (e == NNP_ESTALE_INTERNAL) {

@@ -219,12 +219,13 @@ __device__ __forceinline__ void head_coeffs(const float* qa, const float* kb, fl
 // rule are compacted (ballot) into LDS and added by the group's first lane
 // in row order, so the sum does not depend on how many extra Verlet entries
 // the row holds or where batch boundaries fall.
-template <int G>
+template <int G, bool VIR>
 __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __restrict__ QK,
                                                   const float* __restrict__ Vh, float* __restrict__ Fout, int accum,
                                                   float* __restrict__ vir_set, float* __restrict__ vir_add) {
     constexpr int APW = 64 / G;
-    __shared__ float contrib[4][APW][G][4];
+    constexpr int NC = VIR ? 4 : 3;  // force (and F_ij . r_ij) per staged edge
+    __shared__ float contrib[4][APW][G][NC];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int g = lane / G, l = lane % G;
@@ -275,10 +276,11 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
                 const float Dij = he.u[a] + cij[kNs] * Vi[0][a] + cij[kNs + 1] * Vi[1][a];
                 const float Dji = -he.u[a] + cji[kNs] * Vh[(int64_t(j) * 3 + a) * kNl] +
                                   cji[kNs + 1] * Vh[(int64_t(j) * 3 + a) * kNl + 1];
-                contrib[w][g][pre][a] = Sij * Dij - Sji * Dji;
-                fu = fmaf(Sij * Dij, he.u[a], fu);
+                // one explicit rounding pattern, whether or not the virial is taken
+                contrib[w][g][pre][a] = fmaf(Sij, Dij, -(Sji * Dji));
+                if (VIR) fu = fmaf(Sij * Dij, he.u[a], fu);
             }
-            contrib[w][g][pre][3] = fu * he.r;  // F_ij . r_ij
+            if constexpr (VIR) contrib[w][g][pre][3] = fu * he.r;  // F_ij . r_ij
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
@@ -289,7 +291,7 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
                 fx += contrib[w][g][t][0];
                 fy += contrib[w][g][t][1];
                 fz += contrib[w][g][t][2];
-                vr += contrib[w][g][t][3];
+                if constexpr (VIR) vr += contrib[w][g][t][3];
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -302,8 +304,10 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
         } else {
             Fout[i] = fx; Fout[n + i] = fy; Fout[2 * n + i] = fz;
         }
-        if (vir_set) vir_set[i] = vr;
-        if (vir_add) vir_add[i] += vr;
+        if constexpr (VIR) {
+            if (vir_set) vir_set[i] = vr;
+            if (vir_add) vir_add[i] += vr;
+        }
     }
 }
 
@@ -624,7 +628,8 @@ void launch_head_fwd(const MpGeom& mg, const float* QK, const float* Vh, float* 
     if (mg.n <= 0) return;
     ScopedTimer timer("head_fwd", st);
     // 16 lanes per atom: rows of the 3.5 A list hold about 40 candidates
-    k_head_fwd<16><<<cdiv(mg.n, 16), 256, 0, st>>>(mg, QK, Vh, F, accum, vir_set, vir_add);
+    if (vir_set || vir_add) k_head_fwd<16, true><<<cdiv(mg.n, 16), 256, 0, st>>>(mg, QK, Vh, F, accum, vir_set, vir_add);
+    else k_head_fwd<16, false><<<cdiv(mg.n, 16), 256, 0, st>>>(mg, QK, Vh, F, accum, nullptr, nullptr);
     NNP_LAUNCH_CHECK();
 }
 void launch_head_bwd(const MpGeom& mg, const float* QK, const float* Vh, const float* gF, float* gQK, float* gVh,

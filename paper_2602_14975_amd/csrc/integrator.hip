@@ -153,6 +153,19 @@ __global__ void __launch_bounds__(256) k_kinetic(const int64_t* __restrict__ rep
     if (nonfinite && bad) atomicOr(bad + r, 1);
 }
 
+// The finiteness flags alone (no kinetic energy requested): one thread per
+// atom over the whole grid.
+__global__ void __launch_bounds__(256) k_finite(int n, const int32_t* __restrict__ rep_of_atom,
+                                                const double* __restrict__ pos, const double* __restrict__ vel,
+                                                int* __restrict__ bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool nonfinite = false;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) nonfinite |= !isfinite(vel[c * int64_t(n) + i]) || !isfinite(pos[c * int64_t(n) + i]);
+    if (nonfinite) atomicOr(bad + (rep_of_atom ? rep_of_atom[i] : 0), 1);
+}
+
 // ------------------------------------------------------------------- host --
 void launch_kick(int n, double* vel, const double* mass, const float* Fa, const float* Fb, double half_dt,
                  hipStream_t s, uint64_t* bump) {
@@ -216,8 +229,12 @@ void launch_baoa(const BaoaArgs& a, hipStream_t s) {
 }
 
 void launch_kinetic(int n_rep, const int64_t* rep_start, int n, const double* pos, const double* vel,
-                    const double* mass, double* ke, int* bad, hipStream_t s) {
-    k_kinetic<<<n_rep, 256, 0, s>>>(rep_start, n, pos, vel, mass, ke, bad);
+                    const double* mass, double* ke, int* bad, hipStream_t s, const int32_t* rep_of_atom) {
+    if (!ke && bad && (n_rep == 1 || rep_of_atom)) {
+        if (n > 0) k_finite<<<cdiv(n, 256), 256, 0, s>>>(n, rep_of_atom, pos, vel, bad);
+    } else {
+        k_kinetic<<<n_rep, 256, 0, s>>>(rep_start, n, pos, vel, mass, ke, bad);
+    }
     NNP_LAUNCH_CHECK();
 }
 

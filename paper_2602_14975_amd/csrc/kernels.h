@@ -226,6 +226,7 @@ void launch_add(int n, const float* x, float* y, hipStream_t s);  // y += x
 bool timers_active();
 void launch_baoa(const BaoaArgs& a, hipStream_t s);
 void launch_kinetic(int n_rep, const int64_t* rep_start, int n, const double* pos, const double* vel,
-                    const double* mass, double* ke, int* bad, hipStream_t s);
+                    const double* mass, double* ke, int* bad, hipStream_t s,
+                    const int32_t* rep_of_atom = nullptr);
 
 }  // namespace nnp

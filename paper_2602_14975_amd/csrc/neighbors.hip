@@ -99,7 +99,12 @@ __global__ void k_cell_fill(int n, const int* __restrict__ run, const int* __res
 }
 
 // Iterates over the stencil cells of atom i; calls body(j) for every
-// candidate (lanes split each cell's member list).
+// candidate.  With a cell grid the 27 cells' member lists are taken as one
+// stream: lane k < 27 holds cell k's range, a wavefront prefix sum numbers
+// the candidates, and each lane finds the cell of its candidate by a binary
+// search over the lanes (every lane busy, about (27 x members) / 64 trips
+// instead of 27).  Every candidate is visited once; the order does not
+// matter to the callers (counts; rows sorted by j).
 struct Stencil {
     const int* grid_m;
     const int* grid_base;
@@ -122,21 +127,38 @@ __device__ __forceinline__ void for_candidates(const Stencil& st, int i, int r, 
         }
         return;
     }
-    int local = cell - base;
-    int cx = local / (m * m), cy = (local / m) % m, cz = local % m;
-    for (int dx = -1; dx <= 1; ++dx)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dz = -1; dz <= 1; ++dz) {
-                int ax = (cx + dx + m) % m, ay = (cy + dy + m) % m, az = (cz + dz + m) % m;
-                int c = base + (ax * m + ay) * m + az;
-                int s = st.cell_start[c], e = st.cell_start[c + 1];
-                int cnt = e - s;
-                int trips = (cnt + 63) / 64;
-                for (int k = 0; k < trips; ++k) {
-                    int t = s + k * 64 + lane;
-                    body(t < e ? st.cell_atoms[t] : -1);
-                }
-            }
+    const int local = cell - base;
+    const int cx = local / (m * m), cy = (local / m) % m, cz = local % m;
+    int start = 0, count = 0;
+    if (lane < 27) {
+        const int dx = lane / 9 - 1, dy = (lane / 3) % 3 - 1, dz = lane % 3 - 1;
+        const int ax = (cx + dx + m) % m, ay = (cy + dy + m) % m, az = (cz + dz + m) % m;
+        const int c = base + (ax * m + ay) * m + az;
+        start = st.cell_start[c];
+        count = st.cell_start[c + 1] - start;
+    }
+    int incl = count;  // inclusive prefix sum over lanes 0..26
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    const int excl = incl - count;
+    const int delta = start - excl;  // list position of candidate t of this cell: t + delta
+    const int total = __shfl(incl, 26, 64);
+    for (int t0 = 0; t0 < total; t0 += 64) {
+        const int t = t0 + lane;
+        // the largest cell k with excl_k <= t (empty cells are passed over)
+        int k = 0;
+#pragma unroll
+        for (int step = 16; step >= 1; step >>= 1) {
+            const int cand = k + step;
+            const int e = __shfl(excl, min(cand, 26), 64);
+            if (cand <= 26 && e <= t) k = cand;
+        }
+        const int d = __shfl(delta, k, 64);
+        body(t < total ? st.cell_atoms[t + d] : -1);
+    }
 }
 
 __global__ void __launch_bounds__(64 * kWaves)
