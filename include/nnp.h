@@ -412,6 +412,21 @@ nnp_status nnp_timer_read(const char* site, double* total_ms, int64_t* launches,
 #define NNP_MP_VECTOR 1
 nnp_status nnp_set_message_kernels(int32_t mode);
 
+/* Kernel selection for the per-atom perceptrons and linear maps of FP32
+ * models (every dense product of the models section: phi, the update block's
+ * U, V and mixing perceptron, the readout, the NC projections, and the
+ * input adjoints of each), chosen process-wide for launches issued after the
+ * call:
+ *   NNP_DENSE_AUTO (0): products with K a multiple of 32 and N of 32 run on
+ *     bfloat16 matrix cores with both operands split into three bfloat16
+ *     pieces (the six piece products down to 2^-18, float32 accumulation:
+ *     FP32-equivalent); other shapes on the float32 kernels.
+ *   NNP_DENSE_FP32 (1): float32-operand kernels everywhere.
+ * BF16 models are not affected.  Other values: NNP_EINVAL. */
+#define NNP_DENSE_AUTO 0
+#define NNP_DENSE_FP32 1
+nnp_status nnp_set_dense_kernels(int32_t mode);
+
 #ifdef __cplusplus
 }
 #endif

@@ -98,6 +98,7 @@ PROTOTYPES = {
     "nnp_timer_enable": (C.c_int32, [C.c_char_p, C.c_int32]),
     "nnp_timer_read": (C.c_int32, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]),
     "nnp_set_message_kernels": (C.c_int32, [C.c_int32]),
+    "nnp_set_dense_kernels": (C.c_int32, [C.c_int32]),
 }
 
 _LIB = None

@@ -31,7 +31,7 @@ using namespace nnp;
     return NNP_OK;
 
 extern "C" const char* nnp_last_error(void) { return g_err.c_str(); }
-extern "C" int32_t nnp_abi_version(void) { return 2; }
+extern "C" int32_t nnp_abi_version(void) { return 3; }
 
 // ===================================================================== model
 namespace nnp {
@@ -118,12 +118,14 @@ extern "C" nnp_status nnp_model_create(const nnp_model_desc* desc, nnp_model** o
         e = hipMalloc(&m->ncw, sizeof(float) * Model::ncw_count(d.width));
     if (e == hipSuccess) e = hipMalloc(&m->wT, sizeof(float) * m->n_weights);
     if (e == hipSuccess) e = hipMalloc(&m->mxs, sizeof(float) * 2 * kMaxLayers);
+    if (e == hipSuccess && d.precision != NNP_BF16) e = hipMalloc(&m->wx, sizeof(uint16_t) * 6 * m->wx_stride());
     if (e != hipSuccess) {
         (void)hipFree(m->w);
         if (m->tab) (void)hipFree(m->tab);
         if (m->ncw) (void)hipFree(m->ncw);
         if (m->wT) (void)hipFree(m->wT);
         if (m->mxs) (void)hipFree(m->mxs);
+        if (m->wx) (void)hipFree(m->wx);
         delete m;
         set_error(std::string("model set-up: ") + hipGetErrorString(e));
         return NNP_EDEVICE;
@@ -137,6 +139,7 @@ extern "C" nnp_status nnp_model_create(const nnp_model_desc* desc, nnp_model** o
         if (m->ncw) (void)hipFree(m->ncw);
         (void)hipFree(m->wT);
         (void)hipFree(m->mxs);
+        if (m->wx) (void)hipFree(m->wx);
         delete m;
         throw;
     }
@@ -152,6 +155,7 @@ extern "C" void nnp_model_destroy(nnp_model* model) {
     if (m->ncw) (void)hipFree(m->ncw);
     if (m->wT) (void)hipFree(m->wT);
     if (m->mxs) (void)hipFree(m->mxs);
+    if (m->wx) (void)hipFree(m->wx);
     delete m;
 }
 
@@ -306,8 +310,16 @@ void Model::refresh_tables(hipStream_t s) {
     gemm_xwt(S, F, F, p(off_emb), F, p(lo.W1), p(lo.b1), z_tab(), F, EPI_SILU, h1_tab(), F, false, s, bf16());
     gemm_xwt(S, 3 * F, F, z_tab(), F, p(lo.W2), p(lo.b2), phi_tab(), 3 * F, EPI_NONE, nullptr, 0, false, s, bf16());
     if (ncw) transpose_nc_weights(F, p(lo.U), p(lo.M1), p(lo.M2), p(off_Wq), p(off_WV), bf16(), ncw, s);
-    // transposed mirror of the matrices used as G W
-    auto tr = [&](int64_t off, int rows, int cols) { launch_transpose(rows, cols, p(off), wT + off, s); };
+    // transposed mirror of the matrices used as G W; FP32 models split both
+    // mirrors into bfloat16 pieces
+    auto tr = [&](int64_t off, int rows, int cols) {
+        launch_transpose(rows, cols, p(off), wT + off, s);
+        if (wx) {
+            const int64_t cnt = int64_t(rows) * cols;
+            launch_split3(p(off), cnt, wx + 2 * off, wx_stride(), s);
+            launch_split3(wT + off, cnt, wx + 3 * wx_stride() + 2 * off, wx_stride(), s);
+        }
+    };
     for (int l = 0; l < n_layers(); ++l) {
         const LayerOff& ll = loff[l];
         launch_filter_scale(3 * F * desc.n_rbf, p(ll.Wr), mxs + 2 * l, s);
@@ -328,7 +340,8 @@ void Model::refresh_tables(hipStream_t s) {
 // out[M][K] = G[M][N] W[N][K] through the transposed mirror (X W^T form)
 static void gemm_gwt(const Model* m, int64_t off, int M, int N, int K, const float* G, int ldg, float* out, int ldo,
                      int epi, const float* pre, int ldp, bool accum, hipStream_t s) {
-    gemm_xwt(M, K, N, G, ldg, m->pT(off), nullptr, out, ldo, epi, const_cast<float*>(pre), ldp, accum, s, m->bf16());
+    gemm_xwt(M, K, N, G, ldg, m->pT(off), nullptr, out, ldo, epi, const_cast<float*>(pre), ldp, accum, s, m->bf16(),
+             m->pxT(off), m->wx_stride());
 }
 
 void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, ModelBuf& b, hipStream_t s) {
@@ -350,21 +363,21 @@ void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, Mode
             a.emb = m->p(m->off_emb);
         } else {
             gemm_xwt(n, F, F, b.s[l], F, m->p(lo.W1), m->p(lo.b1), lb.zphi, F, EPI_SILU, lb.h1, F, false, s,
-                     m->bf16());
+                     m->bf16(), m->px(lo.W1), m->wx_stride());
             gemm_xwt(n, 3 * F, F, lb.zphi, F, m->p(lo.W2), m->p(lo.b2), lb.phi, 3 * F, EPI_NONE, nullptr, 0, false,
-                     s, m->bf16());
+                     s, m->bf16(), m->px(lo.W2), m->wx_stride());
             a.s_in = b.s[l];
             a.v_in = b.v[l];
             a.phi = lb.phi;
         }
         launch_message_fwd(F, K, cut, mg, a, s);
         gemm_xwt(3 * n, 2 * F, F, lb.vmid, F, m->p(lo.U), nullptr, lb.UV, 2 * F, EPI_NONE, nullptr, 0, false, s,
-                 m->bf16());
+                 m->bf16(), m->px(lo.U), m->wx_stride());
         launch_build_x(n, F, lb.smid, lb.UV, lb.X, s);
         gemm_xwt(n, F, 2 * F, lb.X, 2 * F, m->p(lo.M1), m->p(lo.m1), lb.z, F, EPI_SILU, lb.a1, F, false, s,
-                 m->bf16());
+                 m->bf16(), m->px(lo.M1), m->wx_stride());
         gemm_xwt(n, 3 * F, F, lb.z, F, m->p(lo.M2), m->p(lo.m2), lb.pqo, 3 * F, EPI_NONE, nullptr, 0, false, s,
-                 m->bf16());
+                 m->bf16(), m->px(lo.M2), m->wx_stride());
         launch_update_combine(n, F, lb.smid, lb.vmid, lb.UV, lb.pqo, b.s[l + 1], b.v[l + 1], s);
     }
 }
@@ -485,7 +498,8 @@ void cons_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const
     }
     embed_forward(m, sys, mg, b, s);
     const int L = m->n_layers();
-    gemm_xwt(n, F, F, b.s[L], F, m->p(m->off_Wo), m->p(m->off_bo), b.zo, F, EPI_SILU, b.ao, F, false, s, m->bf16());
+    gemm_xwt(n, F, F, b.s[L], F, m->p(m->off_Wo), m->p(m->off_bo), b.zo, F, EPI_SILU, b.ao, F, false, s, m->bf16(),
+             m->px(m->off_Wo), m->wx_stride());
     launch_readout(n, F, m->desc.n_species, b.zo, m->p(m->off_wo), m->p(m->off_beta), sys.species, b.Ei, s);
     if (energy) launch_rep_sum(sys.n_rep, t.rep_start, b.Ei, energy, s);
     if (!forces) return;
@@ -525,9 +539,10 @@ void nc_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const n
         }
     }
     embed_forward(m, sys, mg, b, s);
-    gemm_xwt(n, HC, F, b.s[1], F, m->p(m->off_Wq), nullptr, b.QK, HC, EPI_NONE, nullptr, 0, false, s, m->bf16());
+    gemm_xwt(n, HC, F, b.s[1], F, m->p(m->off_Wq), nullptr, b.QK, HC, EPI_NONE, nullptr, 0, false, s, m->bf16(),
+             m->px(m->off_Wq), m->wx_stride());
     gemm_xwt(3 * n, m->desc.n_l, F, b.v[1], F, m->p(m->off_WV), nullptr, b.Vh, m->desc.n_l, EPI_NONE, nullptr, 0,
-             false, s, m->bf16());
+             false, s, m->bf16(), m->px(m->off_WV), m->wx_stride());
     launch_head_fwd(mg, b.QK, b.Vh, forces, false, s, vir_set, vir_add);
 }
 
@@ -539,8 +554,10 @@ void nc_wgrad(const Model* m, const nnp_system& sys, const RepGeom& geom, const 
     const int HC = 2 * (m->desc.n_s + m->desc.n_l) * m->desc.n_c;
     MpGeom mg = make_geom(m, sys, geom, nl);
     embed_forward(m, sys, mg, b, s);
-    gemm_xwt(n, HC, F, b.s[1], F, m->p(m->off_Wq), nullptr, b.QK, HC, EPI_NONE, nullptr, 0, false, s, m->bf16());
-    gemm_xwt(3 * n, nl_, F, b.v[1], F, m->p(m->off_WV), nullptr, b.Vh, nl_, EPI_NONE, nullptr, 0, false, s, m->bf16());
+    gemm_xwt(n, HC, F, b.s[1], F, m->p(m->off_Wq), nullptr, b.QK, HC, EPI_NONE, nullptr, 0, false, s, m->bf16(),
+             m->px(m->off_Wq), m->wx_stride());
+    gemm_xwt(3 * n, nl_, F, b.v[1], F, m->p(m->off_WV), nullptr, b.Vh, nl_, EPI_NONE, nullptr, 0, false, s, m->bf16(),
+             m->px(m->off_WV), m->wx_stride());
     launch_head_bwd(mg, b.QK, b.Vh, dl_df, b.gQK, b.gVh, s);
     gemm_wgrad(n, HC, F, b.gQK, HC, b.s[1], F, dtheta + m->off_Wq, b.chunk_part, kChunk, false, s);
     gemm_gwt(m, m->off_Wq, n, HC, F, b.gQK, HC, b.gs, F, EPI_NONE, nullptr, 0, false, s);

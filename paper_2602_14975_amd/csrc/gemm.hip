@@ -8,6 +8,8 @@
 //
 // Epilogues: SILU stores the pre-activation (for the reverse pass) and
 // writes silu(y); DSILU multiplies by silu'(pre(m, n)); ACCUM adds into C.
+#include <atomic>
+
 #include "common.h"
 #include "kernels.h"
 #include "model.h"
@@ -258,6 +260,210 @@ __global__ void __launch_bounds__(64 * S) k_gemm_rk(GemmArgs g) {
     }
 }
 
+
+// FP32 products on bfloat16 matrix cores.  Each operand is split into three
+// bfloat16 pieces, x = x_h + x_m + x_l (each piece the round-to-nearest of
+// what the previous ones leave), so that x_h carries 8 significant bits,
+// x_h + x_m 16 and x_h + x_m + x_l 24.  Of the nine piece products the six
+// of order >= 2^-18 are accumulated in float32 (hh, hm, mh, hl, lh, mm); the
+// dropped ones are below 2^-26 relative, under float32 rounding itself.
+// The right operand (weights, [N][K]) is split once when the weights change;
+// the left one (activations) on the fly from float32.
+//
+// One block of four wavefronts computes 128 rows x 32T columns over the
+// whole K.  The weight pieces of its columns (3 x 32T rows of K bfloat16)
+// are staged in LDS once, all loads issued together; after that single
+// barrier each wavefront streams its own 32 activation rows in 32-deep
+// chunks straight into registers (a lane reads 16 consecutive k of its
+// row), RING - 1 chunks in flight ahead of the one being multiplied.  MFMA
+// v_mfma_f32_32x32x16_bf16; operand slot i of k-step j in lane half h holds
+// k = 16h + 8j + i of the chunk, for both operands alike, so every product
+// term appears once.  Accumulator layout as in k_gemm.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4_v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split3(const float (&x)[8], bf16x8_t& h, bf16x8_t& m, bf16x8_t& l) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const __bf16 a = __bf16(x[i]);
+        const float r1 = x[i] - float(a);  // exact
+        const __bf16 b = __bf16(r1);
+        const float r2 = r1 - float(b);  // exact
+        h[i] = a;
+        m[i] = b;
+        l[i] = __bf16(r2);
+    }
+}
+
+// The six piece products of one 32-deep chunk: activations av (this lane's
+// 16 k values) against the staged weight pieces; B points at this lane's
+// column (r) and k offset (16 h) of the chunk in piece 0.
+template <int T, int J, int PITCH>
+__device__ __forceinline__ void x3_products(floatx16 (&acc)[J][T], const f32x4_t (&av)[4], const uint16_t* B) {
+    constexpr int PIECE = 32 * T * PITCH;
+#pragma unroll
+    for (int j0 = 0; j0 < 2; j0 += J) {
+        bf16x8_t ah[J], am[J], al[J], bh[J][T], bm[J][T], bl[J][T];
+#pragma unroll
+        for (int jj = 0; jj < J; ++jj) {
+            const int j = j0 + jj;
+            const float x[8] = {av[2 * j].x,     av[2 * j].y,     av[2 * j].z,     av[2 * j].w,
+                                av[2 * j + 1].x, av[2 * j + 1].y, av[2 * j + 1].z, av[2 * j + 1].w};
+            split3(x, ah[jj], am[jj], al[jj]);
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const uint16_t* b = B + 32 * t * PITCH + 8 * j;
+                bh[jj][t] = *reinterpret_cast<const bf16x8_t*>(b);
+                bm[jj][t] = *reinterpret_cast<const bf16x8_t*>(b + PIECE);
+                bl[jj][t] = *reinterpret_cast<const bf16x8_t*>(b + 2 * PIECE);
+            }
+        }
+        // smallest terms first; independent accumulators between dependent ones
+#define NNP_X3_TERM(AX, BX)                                                                                    \
+    _Pragma("unroll") for (int jj = 0; jj < J; ++jj) _Pragma("unroll") for (int t = 0; t < T; ++t) acc[jj][t] = \
+        __builtin_amdgcn_mfma_f32_32x32x16_bf16(AX[jj], BX[jj][t], acc[jj][t], 0, 0, 0);
+        NNP_X3_TERM(al, bh)
+        NNP_X3_TERM(ah, bl)
+        NNP_X3_TERM(am, bm)
+        NNP_X3_TERM(am, bh)
+        NNP_X3_TERM(ah, bm)
+        NNP_X3_TERM(ah, bh)
+#undef NNP_X3_TERM
+    }
+}
+
+template <int T, int KK, int RING>
+__global__ void __launch_bounds__(256) k_gemm_x3(GemmArgs g) {
+    constexpr int BN = 32 * T;
+    constexpr int PITCH = KK + 8;   // bfloat16 per staged row: 4-bank shift per row, conflict-free 16-byte reads
+    constexpr int NCH = KK / 32;    // chunks
+    constexpr int RU = KK / 8;      // 16-byte units per staged row
+    constexpr int UNITS = 3 * BN * RU;
+    constexpr int UPT = UNITS / 256;
+    constexpr int J = T == 1 ? 2 : 1;  // k-steps issued together (independent accumulators for T = 1)
+    static_assert(NCH % RING == 0 && UNITS % 256 == 0, "shape");
+    __shared__ __align__(16) uint16_t Bs[3 * BN * PITCH];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 31, h = lane >> 5;
+    const int NT = g.N / BN;
+    const int L = xcd_block(blockIdx.x, gridDim.x);  // column tiles of a row tile stay on one XCD
+    const int m0 = (L / NT) * 128 + wave * 32, n0 = (L % NT) * BN;
+    // rows past M read row M - 1 (unconditional loads keep the waits exact)
+    // and are never stored
+    const float* arow = g.A + int64_t(min(m0 + r, g.M - 1)) * g.sam + 16 * h;
+
+#define NNP_X3_LOAD_A(DST, C) \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) DST[q] = *reinterpret_cast<const f32x4_t*>(arow + (C) * 32 + 4 * q);
+    f32x4_t ring[RING][4];
+#pragma unroll
+    for (int s = 0; s < RING - 1; ++s) NNP_X3_LOAD_A(ring[s], s)
+    {
+        // weight pieces of the block's columns, all of K: unit idx is piece
+        // idx / (BN RU), column (idx / RU) % BN, k 8 (idx % RU)
+        u32x4_v tmp[UPT];
+#pragma unroll
+        for (int u = 0; u < UPT; ++u) {
+            const int idx = u * 256 + tid;
+            const int p = idx / (BN * RU), col = (idx / RU) % BN, q = idx % RU;
+            tmp[u] = *reinterpret_cast<const u32x4_v*>(g.Bx + p * g.bxs + int64_t(n0 + col) * KK + 8 * q);
+        }
+#pragma unroll
+        for (int u = 0; u < UPT; ++u) {
+            const int idx = u * 256 + tid;
+            const int p = idx / (BN * RU), col = (idx / RU) % BN, q = idx % RU;
+            *reinterpret_cast<u32x4_v*>(&Bs[(p * BN + col) * PITCH + 8 * q]) = tmp[u];
+        }
+    }
+    __syncthreads();
+
+    floatx16 acc[J][T];
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+#pragma unroll
+        for (int t = 0; t < T; ++t) acc[j][t] = floatx16{};
+    const uint16_t* Bl = Bs + r * PITCH + 16 * h;
+    // register sets in rotation: each step loads the chunk RING - 1 ahead
+    // (past the end: the last chunk again, never used) and multiplies one
+    for (int c = 0; c < NCH; c += RING) {
+#pragma unroll
+        for (int s = 0; s < RING; ++s) {
+            NNP_X3_LOAD_A(ring[(s + RING - 1) % RING], min(c + s + RING - 1, NCH - 1))
+            __builtin_amdgcn_sched_barrier(0);
+            x3_products<T, J, PITCH>(acc, ring[s], Bl + (c + s) * 32);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+#undef NNP_X3_LOAD_A
+    if constexpr (J == 2) {
+#pragma unroll
+        for (int t = 0; t < T; ++t) acc[0][t] += acc[1][t];
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int col = n0 + 32 * t + r;
+        const float bias = g.bias ? g.bias[col] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int m = m0 + (i >> 2) * 8 + h * 4 + (i & 3);
+            if (m >= g.M) continue;
+            float y = acc[0][t][i] + bias;
+            const int64_t idx = int64_t(m) * g.ldc + col;
+            if (g.epi == EPI_SILU) {
+                if (g.pre) g.pre[int64_t(m) * g.ldp + col] = y;
+                y = silu(y);
+            } else if (g.epi == EPI_DSILU) {
+                y *= silu_grad(g.pre[int64_t(m) * g.ldp + col]);
+            }
+            if (g.accum) y += g.C[idx];
+            g.C[idx] = y;
+        }
+    }
+}
+
+// Shapes and alignment the split-bfloat16 kernel assumes: k contiguous in A
+// with 16-byte aligned rows, K one of 128, 256, 384, N a multiple of 32, the
+// weight pieces present and 16-byte aligned.
+static bool x3_ok(const GemmArgs& g) {
+    return g.Bx && !g.bf16 && g.chunk_rows == 0 && g.sak == 1 && g.sam % 4 == 0 &&
+           (g.K == 128 || g.K == 256 || g.K == 384) && g.N % 32 == 0 && g.bxs % 8 == 0 &&
+           (reinterpret_cast<uintptr_t>(g.A) & 15) == 0 && (reinterpret_cast<uintptr_t>(g.Bx) & 15) == 0;
+}
+
+static int x3_blocks(const GemmArgs& g, int T) { return cdiv(g.M, 128) * (g.N / (32 * T)); }
+
+static void x3_launch(const GemmArgs& g, hipStream_t stream) {
+    // 64 columns per block where K = 128 (52 KB of staged weights) and that
+    // still gives two blocks per compute unit; 32 otherwise
+    const bool wide = g.K == 128 && g.N % 64 == 0 && x3_blocks(g, 2) >= 512;
+    const dim3 grid(x3_blocks(g, wide ? 2 : 1));
+    if (wide) k_gemm_x3<2, 128, 4><<<grid, 256, 0, stream>>>(g);
+    else if (g.K == 128) k_gemm_x3<1, 128, 4><<<grid, 256, 0, stream>>>(g);
+    else if (g.K == 256) k_gemm_x3<1, 256, 4><<<grid, 256, 0, stream>>>(g);
+    else k_gemm_x3<1, 384, 4><<<grid, 256, 0, stream>>>(g);
+}
+
+__global__ void k_split3(const float* __restrict__ src, int64_t count, __bf16* __restrict__ dst, int64_t ps) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    const float x = src[e];
+    const __bf16 a = __bf16(x);
+    const float r1 = x - float(a);
+    const __bf16 b = __bf16(r1);
+    dst[e] = a;
+    dst[ps + e] = b;
+    dst[2 * ps + e] = __bf16(r1 - float(b));
+}
+
+void launch_split3(const float* src, int64_t count, uint16_t* dst, int64_t piece_stride, hipStream_t s) {
+    if (count <= 0) return;
+    k_split3<<<cdiv(count, 256), 256, 0, s>>>(src, count, reinterpret_cast<__bf16*>(dst), piece_stride);
+    NNP_LAUNCH_CHECK();
+}
+
+static std::atomic<int> g_dense_mode{0};
+void set_dense_mode(int mode) { g_dense_mode.store(mode); }
+
 // Operands qualify for k_gemm_rk when k is contiguous in both, K and the row
 // strides are multiples of 4 and the bases 16-byte aligned.
 static bool rk_ok(const GemmArgs& g) {
@@ -281,7 +487,9 @@ static void gemm_dispatch(const GemmArgs& g, dim3 grid, hipStream_t stream) {
 void launch_gemm(const GemmArgs& g, hipStream_t stream) {
     if (g.M <= 0 || g.N <= 0) return;
     ScopedTimer timer("gemm", stream);
-    if (g.N <= 160 && rk_ok(g)) {
+    if (g_dense_mode.load() == 0 && x3_ok(g)) {
+        x3_launch(g, stream);
+    } else if (g.N <= 160 && rk_ok(g)) {
         // narrow outputs: more, smaller tiles and k split over the block's
         // wavefronts fill the chip better than 64 x 64 tiles
         if (g.K >= 128) rk_launch<1, 4>(g, stream);
@@ -295,13 +503,15 @@ void launch_gemm(const GemmArgs& g, hipStream_t stream) {
 
 // out = X W^T + b (X [M][K] row-major, W [N][K]), optional SiLU (saving pre).
 void gemm_xwt(int M, int N, int K, const float* X, int ldx, const float* W, const float* b, float* out,
-              int ldo, int epi, float* pre, int ldp, bool accum, hipStream_t s, bool bf16) {
+              int ldo, int epi, float* pre, int ldp, bool accum, hipStream_t s, bool bf16, const uint16_t* Wx,
+              int64_t wx_stride) {
     GemmArgs g{};
     g.M = M; g.N = N; g.K = K;
     g.A = X; g.sam = ldx; g.sak = 1;
     g.B = W; g.sbk = 1; g.sbn = K;
     g.C = out; g.ldc = ldo; g.bias = b; g.epi = epi; g.pre = pre; g.ldp = ldp; g.accum = accum;
     g.bf16 = bf16;
+    g.Bx = Wx; g.bxs = wx_stride;
     launch_gemm(g, s);
 }
 
@@ -403,3 +613,9 @@ void launch_split_filter_grad(int rows, int K, const float* sum, float* dWr, flo
     NNP_LAUNCH_CHECK();
 }
 }  // namespace nnp
+
+extern "C" nnp_status nnp_set_dense_kernels(int32_t mode) {
+    if (mode != NNP_DENSE_AUTO && mode != NNP_DENSE_FP32) return NNP_EINVAL;
+    nnp::set_dense_mode(mode);
+    return NNP_OK;
+}

@@ -76,11 +76,22 @@ struct GemmArgs {
     int64_t chunk_rows;    // > 0: split the K range into chunks along grid.z
     int64_t chunk_stride;  // C offset between chunks
     int bf16;              // operands rounded to bfloat16 (float32 accumulation)
+    // B(k, n) = B[n * sbn + k] also as three bfloat16 pieces (hi, mid, lo;
+    // hi + mid + lo = B to within 2^-24 relative), piece p at Bx + p * bxs,
+    // same [N][K] layout; lets FP32 products run on bfloat16 matrix cores
+    const uint16_t* Bx;
+    int64_t bxs;
 };
 
 void launch_gemm(const GemmArgs& g, hipStream_t s);
 void gemm_xwt(int M, int N, int K, const float* X, int ldx, const float* W, const float* b, float* out, int ldo,
-              int epi, float* pre, int ldp, bool accum, hipStream_t s, bool bf16 = false);
+              int epi, float* pre, int ldp, bool accum, hipStream_t s, bool bf16 = false,
+              const uint16_t* Wx = nullptr, int64_t wx_stride = 0);
+// dst[p * piece_stride + e] = piece p (hi, mid, lo) of src[e] as bfloat16
+void launch_split3(const float* src, int64_t count, uint16_t* dst, int64_t piece_stride, hipStream_t s);
+// 0: FP32 products on split-bfloat16 matrix cores where the shapes allow
+// (default); 1: float32-operand kernels only
+void set_dense_mode(int mode);
 // dst[c][r] = src[r][c] for a rows x cols row-major matrix
 void launch_transpose(int rows, int cols, const float* src, float* dst, hipStream_t s);
 void gemm_gw(int M, int N, int K, const float* G, int ldg, const float* W, float* out, int ldo, int epi,

@@ -41,6 +41,16 @@ struct Model {
     // products run as X W^T with k contiguous in both operands.
     float* wT = nullptr;
     const float* pT(int64_t off) const { return wT + off; }
+    // FP32 models: the matrices of both mirrors that X W^T products take as
+    // W, split into three bfloat16 pieces (hi, mid, lo) for the matrix-core
+    // dense kernels.  Piece p of the matrix at offset off starts at element
+    // 2 off of piece array p (16-byte aligned whenever off is a multiple of
+    // 4); arrays of 2 n_weights elements (rounded up to 8), w's three then
+    // wT's three.
+    uint16_t* wx = nullptr;
+    int64_t wx_stride() const { return (2 * n_weights + 7) / 8 * 8; }
+    const uint16_t* px(int64_t off) const { return wx ? wx + 2 * off : nullptr; }
+    const uint16_t* pxT(int64_t off) const { return wx ? wx + 3 * wx_stride() + 2 * off : nullptr; }
     // Per layer: the power-of-two scale of the filter weights used by the
     // matrix-core message kernels, and its inverse.
     float* mxs = nullptr;

@@ -56,10 +56,4 @@ __device__ __forceinline__ void radial(double r, const MpGeom& mg, float* ef, fl
     dfc = float(df);
 }
 
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
 }  // namespace nnp
