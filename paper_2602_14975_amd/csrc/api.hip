@@ -115,7 +115,7 @@ extern "C" nnp_status nnp_model_create(const nnp_model_desc* desc, nnp_model** o
     e = hipMemcpy(m->w, w32.data(), sizeof(float) * m->n_weights, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&m->tab, sizeof(float) * 5 * d.n_species * d.width);
     if (e == hipSuccess && d.kind == NNP_MODEL_NC && d.width <= 32)
-        e = hipMalloc(&m->ncw, sizeof(float) * Model::ncw_count(d.width));
+        e = hipMalloc(&m->ncw, sizeof(float) * nc_image_count(d.width));
     if (e == hipSuccess) e = hipMalloc(&m->wT, sizeof(float) * m->n_weights);
     if (e == hipSuccess) e = hipMalloc(&m->mxs, sizeof(float) * 2 * kMaxLayers);
     if (e == hipSuccess && d.precision != NNP_BF16) e = hipMalloc(&m->wx, sizeof(uint16_t) * 6 * m->wx_stride());
@@ -309,7 +309,7 @@ void Model::refresh_tables(hipStream_t s) {
     const LayerOff& lo = loff[0];
     gemm_xwt(S, F, F, p(off_emb), F, p(lo.W1), p(lo.b1), z_tab(), F, EPI_SILU, h1_tab(), F, false, s, bf16());
     gemm_xwt(S, 3 * F, F, z_tab(), F, p(lo.W2), p(lo.b2), phi_tab(), 3 * F, EPI_NONE, nullptr, 0, false, s, bf16());
-    if (ncw) transpose_nc_weights(F, p(lo.U), p(lo.M1), p(lo.M2), p(off_Wq), p(off_WV), bf16(), ncw, s);
+    if (ncw) pack_nc_weights(F, p(lo.U), p(lo.M1), p(lo.M2), p(off_Wq), p(off_WV), bf16(), ncw, s);
     // transposed mirror of the matrices used as G W; FP32 models split both
     // mirrors into bfloat16 pieces
     auto tr = [&](int64_t off, int rows, int cols) {

@@ -3,6 +3,7 @@
 // F_i = sum_j (F_ij - F_ji)).  The dense contractions around them run in
 // gemm.hip; the edge loops of the embedding in mp.hip.
 #include <algorithm>
+#include <atomic>
 
 #include "common.h"
 #include "kernels.h"
@@ -224,8 +225,8 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
                                                   const float* __restrict__ Vh, float* __restrict__ Fout, int accum,
                                                   float* __restrict__ vir_set, float* __restrict__ vir_add) {
     constexpr int APW = 64 / G;
-    constexpr int NC = VIR ? 4 : 3;  // force (and F_ij . r_ij) per staged edge
-    __shared__ float contrib[4][APW][G][NC];
+    // force (and F_ij . r_ij) per staged edge, one 16-byte slot each
+    __shared__ __align__(16) float contrib[4][APW][G][4];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int g = lane / G, l = lane % G;
@@ -288,10 +289,11 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
         if (l == 0) {
             const int cnt = __popcll(mine);
             for (int t = 0; t < cnt; ++t) {
-                fx += contrib[w][g][t][0];
-                fy += contrib[w][g][t][1];
-                fz += contrib[w][g][t][2];
-                if constexpr (VIR) vr += contrib[w][g][t][3];
+                const float4 c = *reinterpret_cast<const float4*>(&contrib[w][g][t][0]);
+                fx += c.x;
+                fy += c.y;
+                fz += c.z;
+                if constexpr (VIR) vr += c.w;
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -425,11 +427,14 @@ __global__ void __launch_bounds__(64) k_head_bwd(MpGeom mg, const float* __restr
 // ------------------------------------------------- fused NC update block --
 // Update block of the one-layer NC embedding followed by its q/k and vector
 // projections, for widths F <= 32: per atom, one lane per feature column.
-// The model keeps an [in][out] copy of these weights (rounded for BF16
-// models), so staging it into LDS once per block is a straight 16-byte copy;
-// lanes of a group then read consecutive LDS words, and the block walks over
-// groups of atoms.  With BF16, weights and every perceptron input are
-// rounded to bfloat16 and products accumulate in float32, as in the MFMA
+// The model keeps an LDS image of these weights (pack_nc_weights: one row
+// per output, rows padded by four floats, rounded for BF16 models), so
+// staging is a straight 16-byte copy; a lane then reads four consecutive k
+// of its output's row per 16-byte LDS read (the padding puts the rows of
+// neighbouring lanes in different banks), the per-atom inputs as broadcast
+// 16-byte reads, and the block walks over groups of atoms.  Every sum runs
+// over k in increasing order.  With BF16, weights and every perceptron input
+// are rounded to bfloat16 and products accumulate in float32, as in the MFMA
 // GEMMs of the general path.
 __device__ __forceinline__ float bf16_round(float x) {
     uint32_t u = __float_as_uint(x);
@@ -437,25 +442,46 @@ __device__ __forceinline__ float bf16_round(float x) {
     return __uint_as_float(u & 0xFFFF0000u);
 }
 
+// floats of the packed image: rows of U;V (2F), M2 (3F), W_qk (HC) and W_V
+// (n_l) of pitch F + 4, rows of M1 (F) of pitch 2F + 4
+constexpr int64_t nc_image_floats(int F) {
+    return int64_t(5 * F + 2 * kH * kNc + kNl) * (F + 4) + int64_t(F) * (2 * F + 4);
+}
+
 template <int F, bool BF16>
 __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
     constexpr int HC = 2 * kH * kNc;  // q and k outputs
     constexpr int APB = 256 / F;      // atoms per block pass
+    constexpr int P1 = F + 4, P2 = 2 * F + 4;
     extern __shared__ float lds[];
-    float* UVt = lds;                  // [F][2F]   (U; V)^T
-    float* M1t = UVt + 2 * F * F;      // [2F][F]
-    float* M2t = M1t + 2 * F * F;      // [F][3F]
-    float* Qt = M2t + 3 * F * F;       // [F][HC]
-    float* Vt = Qt + F * HC;           // [F][kNl]
-    float* m1 = Vt + F * kNl;          // [F]
+    float* UV = lds;                   // [2F][P1]  outputs of U, then of V
+    float* M1 = UV + 2 * F * P1;       // [F][P2]
+    float* M2 = M1 + F * P2;           // [3F][P1]
+    float* Q = M2 + 3 * F * P1;        // [HC][P1]
+    float* WV = Q + HC * P1;           // [kNl][P1]
+    float* m1 = WV + kNl * P1;         // [F]
     float* m2 = m1 + F;                // [3F]
     float* work = m2 + 3 * F;          // per atom: sm[F], vm[3F], x[2F], z[F], so[F], vo[3F]
     auto rnd = [](float x) { return BF16 ? bf16_round(x) : x; };
-    constexpr int NW = 7 * F * F + HC * F + kNl * F;  // contiguous [in][out] copy, multiple of 4
-    for (int t = threadIdx.x; t < NW / 4; t += 256)
-        reinterpret_cast<float4*>(lds)[t] = reinterpret_cast<const float4*>(a.wt)[t];
-    for (int t = threadIdx.x; t < F; t += 256) m1[t] = a.m1[t];
-    for (int t = threadIdx.x; t < 3 * F; t += 256) m2[t] = a.m2[t];
+    auto rnd4 = [&](float4 v) { return float4{rnd(v.x), rnd(v.y), rnd(v.z), rnd(v.w)}; };
+    constexpr int NW = int(nc_image_floats(F));
+    static_assert(NW % 4 == 0, "image of whole 16-byte units");
+    {
+        // every load issued before the first store: one round trip per block
+        constexpr int U = (NW / 4 + 255) / 256;
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            v[u] = reinterpret_cast<const float4*>(a.wt)[min(int(threadIdx.x) + u * 256, NW / 4 - 1)];
+        const float b1 = a.m1[threadIdx.x % F], b2 = a.m2[threadIdx.x % (3 * F)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = threadIdx.x + u * 256;
+            if (idx < NW / 4) reinterpret_cast<float4*>(lds)[idx] = v[u];
+        }
+        if (threadIdx.x < F) m1[threadIdx.x] = b1;
+        if (threadIdx.x < 3 * F) m2[threadIdx.x] = b2;
+    }
     const int g = threadIdx.x / F, f = threadIdx.x % F;
     float* sm = work + g * 11 * F;
     float* vm = sm + F;
@@ -473,14 +499,25 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
         for (int al = 0; al < 3; ++al) vm[al * F + f] = act ? a.vmid[(int64_t(i) * 3 + al) * F + f] : 0.f;
         __syncthreads();
         float Uv[3] = {}, Vv[3] = {};
-#pragma unroll 8
-        for (int k = 0; k < F; ++k) {
-            const float uw = UVt[k * 2 * F + f], vw = UVt[k * 2 * F + F + f];
+        {
+            const float* ur = UV + f * P1;
+            const float* vr = UV + (F + f) * P1;
+#pragma unroll 2
+            for (int k = 0; k < F; k += 4) {
+                const float4 uw = *reinterpret_cast<const float4*>(ur + k);
+                const float4 vw = *reinterpret_cast<const float4*>(vr + k);
 #pragma unroll
-            for (int al = 0; al < 3; ++al) {
-                const float vk = rnd(vm[al * F + k]);
-                Uv[al] = fmaf(uw, vk, Uv[al]);
-                Vv[al] = fmaf(vw, vk, Vv[al]);
+                for (int al = 0; al < 3; ++al) {
+                    const float4 vk = rnd4(*reinterpret_cast<const float4*>(vm + al * F + k));
+                    Uv[al] = fmaf(uw.x, vk.x, Uv[al]);
+                    Vv[al] = fmaf(vw.x, vk.x, Vv[al]);
+                    Uv[al] = fmaf(uw.y, vk.y, Uv[al]);
+                    Vv[al] = fmaf(vw.y, vk.y, Vv[al]);
+                    Uv[al] = fmaf(uw.z, vk.z, Uv[al]);
+                    Vv[al] = fmaf(vw.z, vk.z, Vv[al]);
+                    Uv[al] = fmaf(uw.w, vk.w, Uv[al]);
+                    Vv[al] = fmaf(vw.w, vk.w, Vv[al]);
+                }
             }
         }
         float nn = 1e-8f;
@@ -490,16 +527,32 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
         x[F + f] = sqrtf(nn);
         __syncthreads();
         float a1 = m1[f];
-#pragma unroll 8
-        for (int k = 0; k < 2 * F; ++k) a1 = fmaf(M1t[k * F + f], rnd(x[k]), a1);
+        {
+            const float* wr = M1 + f * P2;
+#pragma unroll 4
+            for (int k = 0; k < 2 * F; k += 4) {
+                const float4 w = *reinterpret_cast<const float4*>(wr + k);
+                const float4 xv = rnd4(*reinterpret_cast<const float4*>(x + k));
+                a1 = fmaf(w.x, xv.x, a1);
+                a1 = fmaf(w.y, xv.y, a1);
+                a1 = fmaf(w.z, xv.z, a1);
+                a1 = fmaf(w.w, xv.w, a1);
+            }
+        }
         z[f] = silu(a1);
         __syncthreads();
         float pq[3] = {m2[f], m2[F + f], m2[2 * F + f]};
-#pragma unroll 8
-        for (int k = 0; k < F; ++k) {
-            const float zk = rnd(z[k]);
+#pragma unroll 2
+        for (int k = 0; k < F; k += 4) {
+            const float4 zk = rnd4(*reinterpret_cast<const float4*>(z + k));
 #pragma unroll
-            for (int c = 0; c < 3; ++c) pq[c] = fmaf(M2t[k * 3 * F + c * F + f], zk, pq[c]);
+            for (int c = 0; c < 3; ++c) {
+                const float4 w = *reinterpret_cast<const float4*>(M2 + (c * F + f) * P1 + k);
+                pq[c] = fmaf(w.x, zk.x, pq[c]);
+                pq[c] = fmaf(w.y, zk.y, pq[c]);
+                pq[c] = fmaf(w.z, zk.z, pq[c]);
+                pq[c] = fmaf(w.w, zk.w, pq[c]);
+            }
         }
         const float dot = Uv[0] * Vv[0] + Uv[1] * Vv[1] + Uv[2] * Vv[2];
         so[f] = sm[f] + pq[0] + pq[1] * dot;
@@ -508,71 +561,109 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
         __syncthreads();
         if (act) {
             for (int c = f; c < HC; c += F) {
+                const float* wr = Q + c * P1;
                 float acc = 0.f;
-                for (int k = 0; k < F; ++k) acc = fmaf(Qt[k * HC + c], rnd(so[k]), acc);
+#pragma unroll 2
+                for (int k = 0; k < F; k += 4) {
+                    const float4 w = *reinterpret_cast<const float4*>(wr + k);
+                    const float4 sv = rnd4(*reinterpret_cast<const float4*>(so + k));
+                    acc = fmaf(w.x, sv.x, acc);
+                    acc = fmaf(w.y, sv.y, acc);
+                    acc = fmaf(w.z, sv.z, acc);
+                    acc = fmaf(w.w, sv.w, acc);
+                }
                 a.QK[int64_t(i) * HC + c] = acc;
             }
             if (f < 3 * kNl) {
                 const int h = f / 3, al = f % 3;
+                const float* wr = WV + h * P1;
                 float acc = 0.f;
-                for (int k = 0; k < F; ++k) acc = fmaf(Vt[k * kNl + h], rnd(vo[al * F + k]), acc);
+#pragma unroll 2
+                for (int k = 0; k < F; k += 4) {
+                    const float4 w = *reinterpret_cast<const float4*>(wr + k);
+                    const float4 vv = rnd4(*reinterpret_cast<const float4*>(vo + al * F + k));
+                    acc = fmaf(w.x, vv.x, acc);
+                    acc = fmaf(w.y, vv.y, acc);
+                    acc = fmaf(w.z, vv.z, acc);
+                    acc = fmaf(w.w, vv.w, acc);
+                }
                 a.Vh[(int64_t(i) * 3 + al) * kNl + h] = acc;
             }
         }
     }
 }
 
-__global__ void k_transpose_nc(int F, const float* __restrict__ UV, const float* __restrict__ M1,
-                               const float* __restrict__ M2, const float* __restrict__ Wqk,
-                               const float* __restrict__ WV, int bf16, float* __restrict__ out) {
+// The LDS image of k_nc_update_proj, element (row o, column k) of each
+// segment = W[o][k] (zero in the padding), rounded for BF16 models.
+__global__ void k_pack_nc(int F, const float* __restrict__ UV, const float* __restrict__ M1,
+                          const float* __restrict__ M2, const float* __restrict__ Wqk, const float* __restrict__ WV,
+                          int bf16, float* __restrict__ out) {
     constexpr int HC = 2 * kH * kNc;
-    const int64_t total = 7 * int64_t(F) * F + int64_t(HC) * F + kNl * F;
+    const int P1 = F + 4, P2 = 2 * F + 4;
+    const int64_t total = nc_image_floats(F);
     const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (t >= total) return;
-    // segments [F][2F], [2F][F], [F][3F], [F][HC], [F][kNl]: element (k, o) = W[o][k]
     int64_t r = t;
-    float v;
-    if (r < 2 * F * F) {
-        v = UV[(r % (2 * F)) * F + r / (2 * F)];
-    } else if ((r -= 2 * F * F) < 2 * F * F) {
-        v = M1[(r % F) * 2 * F + r / F];
-    } else if ((r -= 2 * F * F) < 3 * F * F) {
-        v = M2[(r % (3 * F)) * F + r / (3 * F)];
-    } else if ((r -= 3 * F * F) < int64_t(HC) * F) {
-        v = Wqk[(r % HC) * F + r / HC];
+    float v = 0.f;
+    if (r < 2 * F * P1) {
+        const int o = int(r / P1), k = int(r % P1);
+        if (k < F) v = UV[int64_t(o) * F + k];
+    } else if ((r -= 2 * F * P1) < int64_t(F) * P2) {
+        const int o = int(r / P2), k = int(r % P2);
+        if (k < 2 * F) v = M1[int64_t(o) * 2 * F + k];
+    } else if ((r -= int64_t(F) * P2) < 3 * F * P1) {
+        const int o = int(r / P1), k = int(r % P1);
+        if (k < F) v = M2[int64_t(o) * F + k];
+    } else if ((r -= 3 * F * P1) < int64_t(HC) * P1) {
+        const int o = int(r / P1), k = int(r % P1);
+        if (k < F) v = Wqk[int64_t(o) * F + k];
     } else {
-        r -= int64_t(HC) * F;
-        v = WV[(r % kNl) * F + r / kNl];
+        r -= int64_t(HC) * P1;
+        const int o = int(r / P1), k = int(r % P1);
+        if (k < F) v = WV[int64_t(o) * F + k];
     }
     out[t] = bf16 ? bf16_round(v) : v;
 }
 
-void transpose_nc_weights(int F, const float* UV, const float* M1, const float* M2, const float* Wqk,
-                          const float* WV, bool bf16, float* out, hipStream_t st) {
-    const int64_t total = 7 * int64_t(F) * F + int64_t(2 * kH * kNc) * F + kNl * F;
-    k_transpose_nc<<<cdiv(total, 256), 256, 0, st>>>(F, UV, M1, M2, Wqk, WV, bf16 ? 1 : 0, out);
+void pack_nc_weights(int F, const float* UV, const float* M1, const float* M2, const float* Wqk, const float* WV,
+                     bool bf16, float* out, hipStream_t st) {
+    const int64_t total = nc_image_floats(F);
+    k_pack_nc<<<cdiv(total, 256), 256, 0, st>>>(F, UV, M1, M2, Wqk, WV, bf16 ? 1 : 0, out);
     NNP_LAUNCH_CHECK();
 }
 
 size_t nc_update_lds_bytes(int F) {
-    const int HC = 2 * kH * kNc;
-    return sizeof(float) * (size_t(7 * F * F + F * HC + F * kNl + F + 3 * F) + size_t(256 / F) * 11 * F);
+    return sizeof(float) * (size_t(nc_image_floats(F)) + size_t(F + 3 * F) + size_t(256 / F) * 11 * F);
 }
+
+int64_t nc_image_count(int F) { return nc_image_floats(F); }
 
 bool launch_nc_update_proj(const NcUpdateArgs& a, int F, bool bf16, hipStream_t st) {
     if (a.n <= 0) return true;
     const size_t lds = nc_update_lds_bytes(F);
     const int blocks = std::min(cdiv(a.n, 256 / F), 512);
     ScopedTimer timer("nc_update", st);
+    // more than 64 KB of dynamic LDS at F = 32: raise each instance's limit
+    // once (flag per width and precision)
+    static std::atomic<bool> raised[6];
+    const int slot = (F == 32 ? 0 : F == 16 ? 1 : 2) * 2 + (bf16 ? 1 : 0);
+    auto launch = [&](void (*kernel)(NcUpdateArgs)) {
+        if (!raised[slot].load()) {
+            NNP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+            raised[slot].store(true);
+        }
+        kernel<<<blocks, 256, lds, st>>>(a);
+    };
     if (F == 32) {
-        if (bf16) k_nc_update_proj<32, true><<<blocks, 256, lds, st>>>(a);
-        else k_nc_update_proj<32, false><<<blocks, 256, lds, st>>>(a);
+        if (bf16) launch(k_nc_update_proj<32, true>);
+        else launch(k_nc_update_proj<32, false>);
     } else if (F == 16) {
-        if (bf16) k_nc_update_proj<16, true><<<blocks, 256, lds, st>>>(a);
-        else k_nc_update_proj<16, false><<<blocks, 256, lds, st>>>(a);
+        if (bf16) launch(k_nc_update_proj<16, true>);
+        else launch(k_nc_update_proj<16, false>);
     } else if (F == 8) {
-        if (bf16) k_nc_update_proj<8, true><<<blocks, 256, lds, st>>>(a);
-        else k_nc_update_proj<8, false><<<blocks, 256, lds, st>>>(a);
+        if (bf16) launch(k_nc_update_proj<8, true>);
+        else launch(k_nc_update_proj<8, false>);
     } else {
         return false;
     }

@@ -139,15 +139,18 @@ void launch_head_bwd(const MpGeom& mg, const float* QK, const float* Vh, const f
 struct NcUpdateArgs {
     int n;
     const float *smid, *vmid;                          // message outputs [n][F], [n][3][F]
-    const float *wt, *m1, *m2;                          // transposed weights (see transpose_nc_weights), biases
+    const float *wt, *m1, *m2;                          // packed weights (pack_nc_weights), biases
     float *QK, *Vh;                                    // [n][2 H n_c], [n][3][n_l]
 };
 // Fused update block + q/k/V projections of the NC embedding (widths <= 32);
 // returns false when the width is not supported by the fused kernel.
 bool launch_nc_update_proj(const NcUpdateArgs& a, int F, bool bf16, hipStream_t st);
-// [in][out] copies of U|V, M1, M2, W_qk and W_V (rounded to bfloat16 when bf16)
-void transpose_nc_weights(int F, const float* UV, const float* M1, const float* M2, const float* Wqk,
-                          const float* WV, bool bf16, float* out, hipStream_t st);
+// LDS image of U|V, M1, M2, W_qk and W_V for k_nc_update_proj: one row per
+// output, rows padded by four floats (rounded to bfloat16 when bf16);
+// nc_image_count(F) floats
+void pack_nc_weights(int F, const float* UV, const float* M1, const float* M2, const float* Wqk, const float* WV,
+                     bool bf16, float* out, hipStream_t st);
+int64_t nc_image_count(int F);
 
 // -------------------------------------------------------------- integrator
 struct BaoaArgs {

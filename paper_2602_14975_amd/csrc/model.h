@@ -33,8 +33,9 @@ struct Model {
     float* z_tab() const { return tab + int64_t(desc.n_species) * desc.width; }
     float* phi_tab() const { return tab + 2 * int64_t(desc.n_species) * desc.width; }
     // NC models of width <= 32: the update-block and projection weights
-    // transposed to [in][out] (UV, M1, M2, W_qk, W_V), BF16-rounded for BF16
-    // models; refreshed with the tables.
+    // (UV, M1, M2, W_qk, W_V) as the LDS image of the fused update kernel
+    // (pack_nc_weights), BF16-rounded for BF16 models; refreshed with the
+    // tables.
     float* ncw = nullptr;
     // A mirror of the weight vector in which every matrix that input adjoints
     // multiply by (out = G W) is stored transposed at its own offset, so those
@@ -55,7 +56,6 @@ struct Model {
     // matrix-core message kernels, and its inverse.
     float* mxs = nullptr;
     const float* mx_scale(int l) const { return mxs + 2 * l; }
-    static int64_t ncw_count(int F) { return 7 * int64_t(F) * F + int64_t(2 * 10 * 8) * F + 2 * int64_t(F); }
     void refresh_tables(hipStream_t s);
 };
 
