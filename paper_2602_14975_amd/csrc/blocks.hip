@@ -227,6 +227,8 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
     constexpr int APW = 64 / G;
     // force (and F_ij . r_ij) per staged edge, one 16-byte slot each
     __shared__ __align__(16) float contrib[4][APW][G][4];
+    // the owner's q and k rows, read by every lane of its group: in LDS
+    __shared__ __align__(16) float qk_s[4][APW][2 * kH * kNc];
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int g = lane / G, l = lane % G;
@@ -235,21 +237,22 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
     const int n = mg.n;
     double L = 1, inv = 1, xi = 0, yi = 0, zi = 0;
     int e0 = 0, e1 = 0;
-    const float* qi = QK;
-    const float* ki = QK;
     float Vi[kNl][3] = {};
     if (active) {
         mg.geom.get(i, L, inv);
         xi = mg.pos[i]; yi = mg.pos[n + i]; zi = mg.pos[2 * n + i];
         e0 = mg.off[i];
         e1 = mg.off[i + 1];
-        qi = QK + int64_t(i) * 2 * kH * kNc;
-        ki = qi + kH * kNc;
+#pragma unroll
+        for (int t = l; t < 2 * kH * kNc; t += G) qk_s[w][g][t] = QK[int64_t(i) * 2 * kH * kNc + t];
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int h = 0; h < kNl; ++h) Vi[h][a] = Vh[(int64_t(i) * 3 + a) * kNl + h];
     }
+    wave_sync_lds();
+    const float* qi = qk_s[w][g];
+    const float* ki = qi + kH * kNc;
     const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << (g * G));
     float fx = 0.f, fy = 0.f, fz = 0.f, vr = 0.f;  // running sums (first lane of the group)
     for (int base = 0; __ballot(e0 + base < e1) != 0ull; base += G) {
