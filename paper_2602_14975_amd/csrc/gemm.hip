@@ -409,14 +409,15 @@ __global__ void __launch_bounds__(256) k_gemm_x3(GemmArgs g) {
             if (m >= g.M) continue;
             float y = acc[0][t][i] + bias;
             const int64_t idx = int64_t(m) * g.ldc + col;
+            // streaming stores: the outputs are not read again by this kernel
             if (g.epi == EPI_SILU) {
-                if (g.pre) g.pre[int64_t(m) * g.ldp + col] = y;
+                if (g.pre) __builtin_nontemporal_store(y, &g.pre[int64_t(m) * g.ldp + col]);
                 y = silu(y);
             } else if (g.epi == EPI_DSILU) {
                 y *= silu_grad(g.pre[int64_t(m) * g.ldp + col]);
             }
             if (g.accum) y += g.C[idx];
-            g.C[idx] = y;
+            __builtin_nontemporal_store(y, &g.C[idx]);
         }
     }
 }
