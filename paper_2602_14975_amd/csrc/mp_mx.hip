@@ -50,10 +50,11 @@ typedef float floatx16_t __attribute__((ext_vector_type(16)));
 constexpr int kMxF = 128, kMxK = 16, kMxWaves = 4, kMxAtoms = 4;
 // forward: edges of a lane whose loads are issued together
 constexpr int kFwdGroup = 4;
-// reverse: the same (fewer for the first layer, which then fits three
-// wavefronts per SIMD)
+// reverse: the same; small groups keep every variant within three
+// wavefronts per SIMD (measured: more gathers in flight per wavefront at
+// two wavefronts per SIMD are 7 % slower than fewer at three)
 template <bool L0>
-constexpr int kBwdGroup = L0 ? 4 : 8;
+constexpr int kBwdGroup = L0 ? 4 : 2;
 
 __device__ __forceinline__ void split8(const float* x, half8_t& hi, half8_t& lo) {
 #pragma unroll
@@ -428,7 +429,7 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
 }
 
 template <bool L0, bool VIR>
-__global__ void __launch_bounds__(64 * kMxWaves, 2) k_message_bwd_mx(MpGeom mg, MpBwd a) {
+__global__ void __launch_bounds__(64 * kMxWaves, 3) k_message_bwd_mx(MpGeom mg, MpBwd a) {
     constexpr int F = kMxF, BATCH = 16;
     __shared__ __align__(16) BatchBuf<BATCH> buf[2];
     __shared__ float fpart[kMxAtoms][kMxWaves][4];
