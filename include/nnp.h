@@ -417,12 +417,15 @@ nnp_status nnp_set_message_kernels(int32_t mode);
  * U, V and mixing perceptron, the readout, the NC projections, and the
  * input adjoints of each), chosen process-wide for launches issued after the
  * call:
- *   NNP_DENSE_AUTO (0): products with K a multiple of 32 and N of 32 run on
- *     bfloat16 matrix cores with both operands split into three bfloat16
- *     pieces (the six piece products down to 2^-18, float32 accumulation:
- *     FP32-equivalent); other shapes on the float32 kernels.
- *   NNP_DENSE_FP32 (1): float32-operand kernels everywhere.
- * BF16 models are not affected.  Other values: NNP_EINVAL. */
+ *   NNP_DENSE_AUTO (0): products with K of 128, 256 or 384 and N a
+ *     multiple of 32 run on the bfloat16 matrix cores of one kernel family:
+ *     for FP32 models with both operands split into three bfloat16 pieces
+ *     (the six piece products down to 2^-18, float32 accumulation:
+ *     FP32-equivalent), for BF16 models with the operands rounded to
+ *     bfloat16; other shapes on the older kernels.
+ *   NNP_DENSE_FP32 (1): the older kernels everywhere (float32 operands for
+ *     FP32 models, bfloat16-rounded operands for BF16 models).
+ * Other values: NNP_EINVAL. */
 #define NNP_DENSE_AUTO 0
 #define NNP_DENSE_FP32 1
 nnp_status nnp_set_dense_kernels(int32_t mode);

@@ -118,7 +118,7 @@ extern "C" nnp_status nnp_model_create(const nnp_model_desc* desc, nnp_model** o
         e = hipMalloc(&m->ncw, sizeof(float) * nc_image_count(d.width));
     if (e == hipSuccess) e = hipMalloc(&m->wT, sizeof(float) * m->n_weights);
     if (e == hipSuccess) e = hipMalloc(&m->mxs, sizeof(float) * 2 * kMaxLayers);
-    if (e == hipSuccess && d.precision != NNP_BF16) e = hipMalloc(&m->wx, sizeof(uint16_t) * 6 * m->wx_stride());
+    if (e == hipSuccess) e = hipMalloc(&m->wx, sizeof(uint16_t) * 6 * m->wx_stride());
     if (e != hipSuccess) {
         (void)hipFree(m->w);
         if (m->tab) (void)hipFree(m->tab);
@@ -310,8 +310,8 @@ void Model::refresh_tables(hipStream_t s) {
     gemm_xwt(S, F, F, p(off_emb), F, p(lo.W1), p(lo.b1), z_tab(), F, EPI_SILU, h1_tab(), F, false, s, bf16());
     gemm_xwt(S, 3 * F, F, z_tab(), F, p(lo.W2), p(lo.b2), phi_tab(), 3 * F, EPI_NONE, nullptr, 0, false, s, bf16());
     if (ncw) pack_nc_weights(F, p(lo.U), p(lo.M1), p(lo.M2), p(off_Wq), p(off_WV), bf16(), ncw, s);
-    // transposed mirror of the matrices used as G W; FP32 models split both
-    // mirrors into bfloat16 pieces
+    // transposed mirror of the matrices used as G W; both mirrors split into
+    // bfloat16 pieces
     auto tr = [&](int64_t off, int rows, int cols) {
         launch_transpose(rows, cols, p(off), wT + off, s);
         if (wx) {

@@ -296,10 +296,12 @@ __device__ __forceinline__ void split3(const float (&x)[8], bf16x8_t& h, bf16x8_
     }
 }
 
-// The six piece products of one 32-deep chunk: activations av (this lane's
-// 16 k values) against the staged weight pieces; B points at this lane's
-// column (r) and k offset (16 h) of the chunk in piece 0.
-template <int T, int J, int PITCH>
+// The piece products of one 32-deep chunk: activations av (this lane's 16 k
+// values) against the staged weight pieces; B points at this lane's column
+// (r) and k offset (16 h) of the chunk in piece 0.  NP = 3: the six products
+// of the split operands (FP32 models); NP = 1: the product of the operands
+// rounded to bfloat16 (BF16 models).
+template <int T, int J, int PITCH, int NP>
 __device__ __forceinline__ void x3_products(floatx16 (&acc)[J][T], const f32x4_t (&av)[4], const uint16_t* B) {
     constexpr int PIECE = 32 * T * PITCH;
 #pragma unroll
@@ -310,40 +312,49 @@ __device__ __forceinline__ void x3_products(floatx16 (&acc)[J][T], const f32x4_t
             const int j = j0 + jj;
             const float x[8] = {av[2 * j].x,     av[2 * j].y,     av[2 * j].z,     av[2 * j].w,
                                 av[2 * j + 1].x, av[2 * j + 1].y, av[2 * j + 1].z, av[2 * j + 1].w};
-            split3(x, ah[jj], am[jj], al[jj]);
+            if constexpr (NP == 3) {
+                split3(x, ah[jj], am[jj], al[jj]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) ah[jj][i] = __bf16(x[i]);
+            }
 #pragma unroll
             for (int t = 0; t < T; ++t) {
                 const uint16_t* b = B + 32 * t * PITCH + 8 * j;
                 bh[jj][t] = *reinterpret_cast<const bf16x8_t*>(b);
-                bm[jj][t] = *reinterpret_cast<const bf16x8_t*>(b + PIECE);
-                bl[jj][t] = *reinterpret_cast<const bf16x8_t*>(b + 2 * PIECE);
+                if constexpr (NP == 3) {
+                    bm[jj][t] = *reinterpret_cast<const bf16x8_t*>(b + PIECE);
+                    bl[jj][t] = *reinterpret_cast<const bf16x8_t*>(b + 2 * PIECE);
+                }
             }
         }
         // smallest terms first; independent accumulators between dependent ones
 #define NNP_X3_TERM(AX, BX)                                                                                    \
     _Pragma("unroll") for (int jj = 0; jj < J; ++jj) _Pragma("unroll") for (int t = 0; t < T; ++t) acc[jj][t] = \
         __builtin_amdgcn_mfma_f32_32x32x16_bf16(AX[jj], BX[jj][t], acc[jj][t], 0, 0, 0);
-        NNP_X3_TERM(al, bh)
-        NNP_X3_TERM(ah, bl)
-        NNP_X3_TERM(am, bm)
-        NNP_X3_TERM(am, bh)
-        NNP_X3_TERM(ah, bm)
+        if constexpr (NP == 3) {
+            NNP_X3_TERM(al, bh)
+            NNP_X3_TERM(ah, bl)
+            NNP_X3_TERM(am, bm)
+            NNP_X3_TERM(am, bh)
+            NNP_X3_TERM(ah, bm)
+        }
         NNP_X3_TERM(ah, bh)
 #undef NNP_X3_TERM
     }
 }
 
-template <int T, int KK, int RING>
+template <int T, int KK, int RING, int NP>
 __global__ void __launch_bounds__(256) k_gemm_x3(GemmArgs g) {
     constexpr int BN = 32 * T;
     constexpr int PITCH = KK + 8;   // bfloat16 per staged row: 4-bank shift per row, conflict-free 16-byte reads
     constexpr int NCH = KK / 32;    // chunks
     constexpr int RU = KK / 8;      // 16-byte units per staged row
-    constexpr int UNITS = 3 * BN * RU;
+    constexpr int UNITS = NP * BN * RU;
     constexpr int UPT = UNITS / 256;
     constexpr int J = T == 1 ? 2 : 1;  // k-steps issued together (independent accumulators for T = 1)
     static_assert(NCH % RING == 0 && UNITS % 256 == 0, "shape");
-    __shared__ __align__(16) uint16_t Bs[3 * BN * PITCH];
+    __shared__ __align__(16) uint16_t Bs[NP * BN * PITCH];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 31, h = lane >> 5;
     const int NT = g.N / BN;
@@ -390,7 +401,7 @@ __global__ void __launch_bounds__(256) k_gemm_x3(GemmArgs g) {
         for (int s = 0; s < RING; ++s) {
             NNP_X3_LOAD_A(ring[(s + RING - 1) % RING], min(c + s + RING - 1, NCH - 1))
             __builtin_amdgcn_sched_barrier(0);
-            x3_products<T, J, PITCH>(acc, ring[s], Bl + (c + s) * 32);
+            x3_products<T, J, PITCH, NP>(acc, ring[s], Bl + (c + s) * 32);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -424,9 +435,10 @@ __global__ void __launch_bounds__(256) k_gemm_x3(GemmArgs g) {
 
 // Shapes and alignment the split-bfloat16 kernel assumes: k contiguous in A
 // with 16-byte aligned rows, K one of 128, 256, 384, N a multiple of 32, the
-// weight pieces present and 16-byte aligned.
+// weight pieces present and 16-byte aligned (for BF16 models only the
+// first piece, the rounded weights, is read).
 static bool x3_ok(const GemmArgs& g) {
-    return g.Bx && !g.bf16 && g.chunk_rows == 0 && g.sak == 1 && g.sam % 4 == 0 &&
+    return g.Bx && g.chunk_rows == 0 && g.sak == 1 && g.sam % 4 == 0 &&
            (g.K == 128 || g.K == 256 || g.K == 384) && g.N % 32 == 0 && g.bxs % 8 == 0 &&
            (reinterpret_cast<uintptr_t>(g.A) & 15) == 0 && (reinterpret_cast<uintptr_t>(g.Bx) & 15) == 0;
 }
@@ -438,10 +450,17 @@ static void x3_launch(const GemmArgs& g, hipStream_t stream) {
     // still gives two blocks per compute unit; 32 otherwise
     const bool wide = g.K == 128 && g.N % 64 == 0 && x3_blocks(g, 2) >= 512;
     const dim3 grid(x3_blocks(g, wide ? 2 : 1));
-    if (wide) k_gemm_x3<2, 128, 4><<<grid, 256, 0, stream>>>(g);
-    else if (g.K == 128) k_gemm_x3<1, 128, 4><<<grid, 256, 0, stream>>>(g);
-    else if (g.K == 256) k_gemm_x3<1, 256, 4><<<grid, 256, 0, stream>>>(g);
-    else k_gemm_x3<1, 384, 4><<<grid, 256, 0, stream>>>(g);
+    if (g.bf16) {  // BF16 models: the rounded operands, one product
+        if (wide) k_gemm_x3<2, 128, 4, 1><<<grid, 256, 0, stream>>>(g);
+        else if (g.K == 128) k_gemm_x3<1, 128, 4, 1><<<grid, 256, 0, stream>>>(g);
+        else if (g.K == 256) k_gemm_x3<1, 256, 4, 1><<<grid, 256, 0, stream>>>(g);
+        else k_gemm_x3<1, 384, 4, 1><<<grid, 256, 0, stream>>>(g);
+    } else {
+        if (wide) k_gemm_x3<2, 128, 4, 3><<<grid, 256, 0, stream>>>(g);
+        else if (g.K == 128) k_gemm_x3<1, 128, 4, 3><<<grid, 256, 0, stream>>>(g);
+        else if (g.K == 256) k_gemm_x3<1, 256, 4, 3><<<grid, 256, 0, stream>>>(g);
+        else k_gemm_x3<1, 384, 4, 3><<<grid, 256, 0, stream>>>(g);
+    }
 }
 
 __global__ void k_split3(const float* __restrict__ src, int64_t count, __bf16* __restrict__ dst, int64_t ps) {

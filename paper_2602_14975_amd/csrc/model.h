@@ -42,9 +42,9 @@ struct Model {
     // products run as X W^T with k contiguous in both operands.
     float* wT = nullptr;
     const float* pT(int64_t off) const { return wT + off; }
-    // FP32 models: the matrices of both mirrors that X W^T products take as
-    // W, split into three bfloat16 pieces (hi, mid, lo) for the matrix-core
-    // dense kernels.  Piece p of the matrix at offset off starts at element
+    // The matrices of both mirrors that X W^T products take as W, split into
+    // three bfloat16 pieces (hi, mid, lo) for the matrix-core dense kernels
+    // (BF16 models read only hi, the weights rounded to bfloat16).  Piece p of the matrix at offset off starts at element
     // 2 off of piece array p (16-byte aligned whenever off is a multiple of
     // 4); arrays of 2 n_weights elements (rounded up to 8), w's three then
     // wT's three.

@@ -71,3 +71,31 @@ def test_ragged_row_tiles(gpu_lib, n, box):
     E, F = _oracle(SPEC2, w, pos, species, b)
     assert abs(e - E) <= 1e-6 * abs(E) + 1e-4
     assert rel_rmse(f, F) <= FP32_TOL
+
+
+def test_bf16_models_on_the_same_kernels(gpu_lib):
+    """BF16 models: the one-piece products (operands rounded to bfloat16,
+    float32 accumulation) against the older BF16 kernels (the same rounding,
+    another summation order) and the FP64 oracle."""
+    from paper_2602_14975_amd import _abi
+    from paper_2602_14975_amd.nnp import DeviceSystem, workspace
+    s = synth.water_config(3)
+    spec = synth.CONS_CFG1
+    w = synth.random_weights(spec, 5300)
+    print(f"case bf16 water3 n={s.n}", flush=True)
+    out = {}
+    try:
+        for mode in (1, 0):
+            _set_dense(gpu_lib, mode)
+            m = gpu_lib.Model.from_spec(spec, w, precision=_abi.NNP_BF16)
+            system = DeviceSystem(s.pos, s.species, s.box)
+            nl = gpu_list(gpu_lib, system, 6.0)
+            ws = workspace(m, None, system.n, 1, nl.capacity)
+            e, f = gpu_lib.nnp_cons_energy_forces(m, system, nl, ws)
+            out[mode] = f.cpu().numpy().T.astype(np.float64)
+    finally:
+        _set_dense(gpu_lib, 0)
+    E, F = _oracle(spec, w, s.pos, s.species, s.box)
+    assert rel_rmse(out[0], F) <= 1e-2 and rel_rmse(out[1], F) <= 1e-2
+    assert rel_rmse(out[0], out[1]) <= 2e-3  # roundings to bfloat16 may differ in rare elements
+    assert not np.array_equal(out[0], out[1])
