@@ -353,7 +353,10 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
     const int r = threadIdx.x & 31, e = r & 15, part = 4 * (r >> 4);
     const half8_t ah = as_half8(buf.a[e][part + h]), al = as_half8(buf.a[e][part + 2 + h]);
     const floatx16_t m0 = mma3(ah, al, bh[0], bl[0]);
-    const floatx16_t m1 = mma3(ah, al, bh[1], bl[1]);
+    // the b channel gates v, zero in the first layer: nothing of it reaches
+    // the forces there
+    floatx16_t m1 = {};
+    if constexpr (!L0) m1 = mma3(ah, al, bh[1], bl[1]);
     const floatx16_t m2 = mma3(ah, al, bh[2], bl[2]);
 #pragma unroll
     for (int g0 = 0; g0 < E; g0 += kBwdGroup<L0>) {
@@ -403,7 +406,8 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
             // message n -> o and message o -> n (unit vector -u): filter adjoints
             const float gwa = o.gs * pa[g], gwb = pb[g] * gvo_vn, gwc = pc[g] * gvo_u;
             const float gwa2 = gsn[g] * o.ph[0], gwb2 = o.ph[1] * gvn_vo, gwc2 = -o.ph[2] * gvn_u;
-            const float dr = (gwa + gwa2) * dw[0] + (gwb + gwb2) * dw[1] + (gwc + gwc2) * dw[2];
+            const float dr = L0 ? (gwa + gwa2) * dw[0] + (gwc + gwc2) * dw[2]
+                                : (gwa + gwa2) * dw[0] + (gwb + gwb2) * dw[1] + (gwc + gwc2) * dw[2];
             // adjoints of the unit vectors of the two messages
             const float cA = pc[g] * w[2], cB = o.ph[2] * w[2];
             const float gu0 = o.gv[0] * cA - g0v * cB;
@@ -411,12 +415,14 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
             const float gu2 = o.gv[2] * cA - g2v * cB;
             // o as the sender of the message o -> n
             acc.gph[0] = fmaf(gsn[g], w[0], acc.gph[0]);
-            acc.gph[1] = fmaf(w[1], gvn_vo, acc.gph[1]);
+            if constexpr (!L0) acc.gph[1] = fmaf(w[1], gvn_vo, acc.gph[1]);
             acc.gph[2] = fmaf(-w[2], gvn_u, acc.gph[2]);
-            const float wbp = w[1] * o.ph[1];
-            acc.gv[0] = fmaf(g0v, wbp, acc.gv[0]);
-            acc.gv[1] = fmaf(g1v, wbp, acc.gv[1]);
-            acc.gv[2] = fmaf(g2v, wbp, acc.gv[2]);
+            if constexpr (!L0) {  // the first layer writes no adjoint of its (zero) vector input
+                const float wbp = w[1] * o.ph[1];
+                acc.gv[0] = fmaf(g0v, wbp, acc.gv[0]);
+                acc.gv[1] = fmaf(g1v, wbp, acc.gv[1]);
+                acc.gv[2] = fmaf(g2v, wbp, acc.gv[2]);
+            }
             // this lane's share of (d_A + d_A') u + P(g_uA - g_uA') / r
             const float ud = gu0 * u0 + gu1 * u1 + gu2 * u2;
             acc.fx += dr * u0 + (gu0 - ud * u0) * s.ir;
