@@ -1,10 +1,14 @@
 // Dense per-atom contractions (the perceptrons of both models).
 //
-// C(m, n) = epi( sum_k A(m, k) B(k, n) + bias(n) ) with strided operands, so
-// one kernel serves the forward products X W^T (B stored [N][K]), the input
-// adjoints G W (B stored [K][N]) and, per chunk of rows, the weight
-// adjoints G^T X.  Tiles of 64 x 64 outputs, 16-deep K slices staged in LDS,
-// 4 x 4 outputs per thread, fp32 accumulation.
+// C(m, n) = epi( sum_k A(m, k) B(k, n) + bias(n) ) with strided operands.
+// Two kernel families:
+//  * k_gemm_x3 (the products X W^T of the force evaluation, K of 128, 256 or
+//    384): bfloat16 matrix cores, FP32 models through operands split into
+//    three bfloat16 pieces, BF16 models through rounded operands;
+//  * k_gemm / k_gemm_rk (other shapes, the weight adjoints G^T X by chunks
+//    of rows, and everything when the older kernels are selected): float32
+//    (or bfloat16-rounded) operands on the matrix cores, LDS-staged 64 x 64
+//    tiles or register-direct 32-wide strips.
 //
 // Epilogues: SILU stores the pre-activation (for the reverse pass) and
 // writes silu(y); DSILU multiplies by silu'(pre(m, n)); ACCUM adds into C.
@@ -268,7 +272,8 @@ __global__ void __launch_bounds__(64 * S) k_gemm_rk(GemmArgs g) {
 // of order >= 2^-18 are accumulated in float32 (hh, hm, mh, hl, lh, mm); the
 // dropped ones are below 2^-26 relative, under float32 rounding itself.
 // The right operand (weights, [N][K]) is split once when the weights change;
-// the left one (activations) on the fly from float32.
+// the left one (activations) on the fly from float32.  BF16 models take the
+// first piece alone (the operands rounded to bfloat16, one product).
 //
 // One block of four wavefronts computes 128 rows x 32T columns over the
 // whole K.  The weight pieces of its columns (3 x 32T rows of K bfloat16)
