@@ -1117,6 +1117,8 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     auto sts_step = [&](double dt) {
         ba.force = st->f_cons;
         ba.dt = dt;
+        ba.step_offset = 0;
+        ba.full_kick = 0;
         launch_baoa(ba, s);
         rebuild_if_flagged();
         eval_cons();
@@ -1139,14 +1141,20 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         ba.flag = strict ? trig : stale;
         if (want_vir) launch_zero(c.nc.vir_sum, n, nullptr, s);
         launch_kick(n, st->vel, st->mass, st->f_cons, st->f_nc, 0.5 * D, s);
+        // inner step k: its opening kick also closes step k - 1 (the same fast
+        // force, nothing reads the velocities in between); its O-step index
+        // is the counter plus k, and the closing kick of the last step
+        // advances the counter past all n_in
         for (int k = 0; k < n_in; ++k) {
             ba.force = st->f_nc;
             ba.dt = d;
+            ba.full_kick = k > 0;
+            ba.step_offset = uint64_t(k);
             launch_baoa(ba, s);
             if (strict) rebuild_if_flagged();
             eval_inner();
-            launch_kick(n, st->vel, st->mass, st->f_nc, nullptr, 0.5 * d, s, c.t.o_step);
         }
+        launch_kick(n, st->vel, st->mass, st->f_nc, nullptr, 0.5 * d, s, c.t.o_step, uint64_t(n_in));
         eval_cons();
         if (want_vir) {
             launch_virial_combine(n, c.cons.vir, c.nc.vir, c.nc.vir_sum, float(1.0 / n_in), c.cons.vir_sum, s);

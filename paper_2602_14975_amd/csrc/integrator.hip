@@ -46,9 +46,9 @@ __device__ __forceinline__ void normals3(uint64_t atom, uint64_t step, uint64_t 
 
 // v += coef * (Fa - Fb) / m   (Fb may be null)
 __global__ void k_kick(int n, double* __restrict__ vel, const double* __restrict__ mass, const float* __restrict__ Fa,
-                       const float* __restrict__ Fb, double coef, uint64_t* bump) {
+                       const float* __restrict__ Fb, double coef, uint64_t* bump, uint64_t bump_by) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (bump && i == 0) *bump += 1;
+    if (bump && i == 0) *bump += bump_by;
     if (i >= n) return;
     const double im = 1.0 / mass[i];
 #pragma unroll
@@ -61,7 +61,8 @@ __global__ void k_kick(int n, double* __restrict__ vel, const double* __restrict
 
 // Fused B(d/2) A(d/2) O(d) A(d/2) with the displacement trigger of the
 // Verlet lists (flag set when an atom moved more than the threshold since
-// the last build, or is not finite).
+// the last build, or is not finite).  With full_kick the opening kick is
+// B(d): the previous step's closing B(d/2) with the same force folded in.
 __global__ void k_baoa(BaoaArgs a) {
     const int n = a.n;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -72,12 +73,13 @@ __global__ void k_baoa(BaoaArgs a) {
         const double m = a.mass[i];
         const double im = 1.0 / m;
         const double hd = 0.5 * a.dt;
+        const double kd = a.full_kick ? a.dt : hd;
         double x[3], v[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             x[c] = a.pos[c * n + i];
             v[c] = a.vel[c * n + i];
-            v[c] += hd * kAcc * double(a.force[c * n + i]) * im;
+            v[c] += kd * kAcc * double(a.force[c * n + i]) * im;
             x[c] += hd * v[c];
         }
         // O step
@@ -168,8 +170,8 @@ __global__ void __launch_bounds__(256) k_finite(int n, const int32_t* __restrict
 
 // ------------------------------------------------------------------- host --
 void launch_kick(int n, double* vel, const double* mass, const float* Fa, const float* Fb, double half_dt,
-                 hipStream_t s, uint64_t* bump) {
-    k_kick<<<cdiv(n, 256), 256, 0, s>>>(n, vel, mass, Fa, Fb, half_dt * kAcc, bump);
+                 hipStream_t s, uint64_t* bump, uint64_t bump_by) {
+    k_kick<<<cdiv(n, 256), 256, 0, s>>>(n, vel, mass, Fa, Fb, half_dt * kAcc, bump, bump_by);
     NNP_LAUNCH_CHECK();
 }
 

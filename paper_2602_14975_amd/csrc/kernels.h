@@ -174,12 +174,15 @@ struct BaoaArgs {
     double disp_thr2;
     int* flag;         // set when an atom moved more than sqrt(disp_thr2) since the last build
     unsigned* maxd2;   // optional: running maximum of the squared displacement (float bits)
+    // 1: the opening kick is B(dt) instead of B(dt/2), standing for the
+    // closing B(dt/2) of the previous step with the same force as well
+    int full_kick;
 };
 
 // v += half_dt * ACC * (Fa - Fb) / m; with `bump`, also advances that O-step
-// counter by one (read by the next k_baoa)
+// counter by bump_by (read by the next k_baoa)
 void launch_kick(int n, double* vel, const double* mass, const float* Fa, const float* Fb, double half_dt,
-                 hipStream_t s, uint64_t* bump = nullptr);
+                 hipStream_t s, uint64_t* bump = nullptr, uint64_t bump_by = 1);
 void launch_set_u64(uint64_t* p, uint64_t value, hipStream_t s);
 // zero fill as a kernel (safe inside recorded graphs); with `run`, only when *run != 0
 void launch_zero(void* p, int64_t words, const int* run, hipStream_t s);
