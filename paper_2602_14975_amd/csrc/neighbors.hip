@@ -64,29 +64,67 @@ __global__ void k_cell_assign(int n, const double* __restrict__ pos, RepGeom geo
 }
 
 // Exclusive scan of in[0..n) into out[0..n] (out[n] = total), one block.
+// Tiles of 1024 x 16 elements pass through LDS so that the global loads and
+// stores are coalesced (element q * 1024 + t of the tile by thread t); in
+// LDS thread t owns 16 consecutive elements: wavefront prefix sums of the
+// thread totals, then the 16 wavefront totals; a carry links the tiles.
 __global__ void __launch_bounds__(1024) k_scan(int n, const int* __restrict__ in,
                                                 int* __restrict__ out, const int* __restrict__ run) {
     if (run && *run == 0) return;
-    __shared__ int partial[1024];
-    int t = threadIdx.x;
-    int per = (n + 1023) / 1024;
-    int lo = t * per, hi = min(n, lo + per);
-    int sum = 0;
-    for (int k = lo; k < hi; ++k) sum += in[k];
-    partial[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int v = t >= off ? partial[t - off] : 0;
+    constexpr int E = 16, TILE = 1024 * E;
+    __shared__ int tile[TILE + TILE / 32];  // one padding word per 32 (thread rows of 16 words)
+    __shared__ int wsum[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    auto at = [](int k) { return k + (k >> 5); };
+    int carry = 0;
+    for (int base = 0; base < n; base += TILE) {
+        int g[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int k = base + q * 1024 + t;
+            g[q] = k < n ? in[min(k, n - 1)] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < E; ++q) tile[at(q * 1024 + t)] = g[q];
         __syncthreads();
-        partial[t] += v;
+        int v[E];
+        int tot = 0;
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            v[k] = tile[at(t * E + k)];
+            tot += v[k];
+        }
+        int inc = tot;  // inclusive prefix of the thread totals within the wavefront
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(inc, off, 64);
+            if (lane >= off) inc += y;
+        }
+        if (lane == 63) wsum[w] = inc;
         __syncthreads();
+        int before = carry, all = carry;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int x = wsum[q];
+            if (q < w) before += x;
+            all += x;
+        }
+        int run_sum = before + inc - tot;
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            tile[at(t * E + k)] = run_sum;
+            run_sum += v[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int k = base + q * 1024 + t;
+            if (k < n) out[k] = tile[at(q * 1024 + t)];
+        }
+        carry = all;
+        __syncthreads();  // tile and wsum are rewritten by the next tile
     }
-    int run_sum = partial[t] - sum;
-    for (int k = lo; k < hi; ++k) {
-        out[k] = run_sum;
-        run_sum += in[k];
-    }
-    if (t == 1023) out[n] = partial[1023];
+    if (t == 0) out[n] = carry;
 }
 
 __global__ void k_cell_fill(int n, const int* __restrict__ run, const int* __restrict__ cell_of_atom,

@@ -84,6 +84,23 @@ def test_packed_replicas(gpu_lib):
         assert np.array_equal(g_nbr[g_off[a0]:g_off[a1]] - a0, nbr)
 
 
+def test_packed_replicas_beyond_one_scan_tile(gpu_lib):
+    """More than 16,384 atoms: the row offsets come from a scan over several
+    tiles (the carry between tiles)."""
+    from paper_2602_14975_amd.nnp import DeviceSystem
+    reps = synth.replica_mix(n_replicas=12, seed_base=770, n_min=1500, n_max=2500, chain_frac=0.0)
+    system = DeviceSystem([r.pos for r in reps], [r.species for r in reps], [r.box for r in reps])
+    print(f"case {system.n} atoms in {len(reps)} replicas", flush=True)
+    assert system.n > 16384
+    nl = gpu_list(gpu_lib, system, 3.5)
+    g_off, g_nbr = nl.rows()
+    for k, r in enumerate(reps):
+        a0, a1 = system.rep_start[k], system.rep_start[k + 1]
+        off, nbr = oracle_list(r.pos, r.box, 3.5)
+        assert np.array_equal(g_off[a0:a1 + 1] - g_off[a0], off)
+        assert np.array_equal(g_nbr[g_off[a0]:g_off[a1]] - a0, nbr)
+
+
 def test_minimal_and_isolated(gpu_lib):
     from paper_2602_14975_amd.nnp import DeviceSystem
     system = DeviceSystem(np.array([[1.0, 1.0, 1.0], [9.0, 9.0, 9.0]]), np.zeros(2, np.int32), 20.0)
