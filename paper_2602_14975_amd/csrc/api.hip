@@ -385,15 +385,17 @@ void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, Mode
 // Reverse of one embedding layer.  In: gs, gv = adjoints of the layer
 // output.  Out: gs, gv = adjoints of the layer input (buffers swapped).
 // With `dtheta`, the weight adjoints of the layer are written too.
+// With gv_zero, the adjoint of the layer's vector output is zero (the last
+// layer of an energy: the readout takes s alone) and b.gv is not read.
 void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float* force, bool accum_force,
-                    float* dtheta, hipStream_t s, float* vir = nullptr) {
+                    float* dtheta, hipStream_t s, float* vir = nullptr, bool gv_zero = false) {
     const int n = mg.n;
     const int F = m->desc.width, K = m->desc.n_rbf;
     const int cut = m->desc.kind == NNP_MODEL_CONS ? 0 : 1;
     const LayerOff& lo = m->loff[l];
     LayerBuf& lb = b.layer[l];
     const bool wg = dtheta != nullptr;
-    launch_update_combine_bwd(n, F, lb.UV, lb.pqo, b.gs, b.gv, b.gpqo, b.gUV, s);
+    launch_update_combine_bwd(n, F, lb.UV, lb.pqo, b.gs, gv_zero ? nullptr : b.gv, b.gpqo, b.gUV, s);
     if (wg) {
         gemm_wgrad(n, 3 * F, F, b.gpqo, 3 * F, lb.z, F, dtheta + lo.M2, b.chunk_part, kChunk, false, s);
         colsum(n, 3 * F, b.gpqo, 3 * F, dtheta + lo.m2, b.chunk_part, kChunk, false, s);
@@ -406,7 +408,7 @@ void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float*
     gemm_gwt(m, lo.M1, n, F, 2 * F, b.ga1, F, b.gX, 2 * F, EPI_NONE, nullptr, 0, false, s);
     launch_norm_bwd(n, F, b.gs, b.gX, lb.X, lb.UV, b.gs2, b.gUV, s);  // gs2 = g_smid
     if (wg) gemm_wgrad(3 * n, 2 * F, F, b.gUV, 2 * F, lb.vmid, F, dtheta + lo.U, b.chunk_part, kChunk, false, s);
-    gemm_gwt(m, lo.U, 3 * n, 2 * F, F, b.gUV, 2 * F, b.gv, F, EPI_NONE, nullptr, 0, true, s);  // gv = g_vmid
+    gemm_gwt(m, lo.U, 3 * n, 2 * F, F, b.gUV, 2 * F, b.gv, F, EPI_NONE, nullptr, 0, !gv_zero, s);  // gv = g_vmid
     MpBwd a{};
     a.gsm = b.gs2;
     a.gvm = b.gv;
@@ -505,8 +507,7 @@ void cons_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const
     if (!forces) return;
     launch_readout_bwd(n, F, b.ao, m->p(m->off_wo), b.gs2, s);
     gemm_gwt(m, m->off_Wo, n, F, F, b.gs2, F, b.gs, F, EPI_NONE, nullptr, 0, false, s);
-    launch_zero(b.gv, int64_t(n) * 3 * F, nullptr, s);
-    for (int l = L - 1; l >= 0; --l) layer_backward(m, l, mg, b, forces, l != L - 1, nullptr, s, vir);
+    for (int l = L - 1; l >= 0; --l) layer_backward(m, l, mg, b, forces, l != L - 1, nullptr, s, vir, l == L - 1);
 }
 
 // With vir_set / vir_add, also the per-atom shares of the NPT virial proxy

@@ -78,7 +78,7 @@ __global__ void k_update_combine_bwd(int n, int F, const float* __restrict__ UV,
     for (int al = 0; al < 3; ++al) {
         const float* row = UV + (int64_t(i) * 3 + al) * 2 * F;
         const float u = row[f], vv = row[F + f];
-        const float gva = gv[(int64_t(i) * 3 + al) * F + f];
+        const float gva = gv ? gv[(int64_t(i) * 3 + al) * F + f] : 0.f;  // nullptr: zero adjoint
         dot = fmaf(u, vv, dot);
         go = fmaf(gva, u, go);
         float* grow = gUV + (int64_t(i) * 3 + al) * 2 * F;
@@ -134,7 +134,16 @@ __global__ void __launch_bounds__(256) k_rep_sum(const int64_t* __restrict__ rep
     int r = blockIdx.x;
     int64_t a0 = rep_start[r], a1 = rep_start[r + 1];
     double s = 0.0;
-    for (int64_t a = a0 + threadIdx.x; a < a1; a += 256) s += double(x[a]);
+    int64_t a = a0 + threadIdx.x;
+    // eight loads in flight, added in the same order as one at a time
+    for (; a + 7 * 256 < a1; a += 8 * 256) {
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = x[a + k * 256];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += double(v[k]);
+    }
+    for (; a < a1; a += 256) s += double(x[a]);
     red[threadIdx.x] = s;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
