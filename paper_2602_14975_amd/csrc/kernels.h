@@ -35,6 +35,7 @@ struct CellPlan {
 struct NbrScratch {
     int *grid_m, *grid_base, *cell_of_atom, *slot_of_atom, *cell_count, *cell_start, *cell_atoms, *counts,
         *tmp_off, *status;
+    double* cell_pos;  // [3][n] positions in cell order
 };
 
 CellPlan plan_cells(const nnp_system& sys, double radius);

@@ -127,17 +127,24 @@ __global__ void __launch_bounds__(1024) k_scan(int n, const int* __restrict__ in
     if (t == 0) out[n] = carry;
 }
 
+// Cell members in cell order, with a copy of their positions in the same
+// order (SoA [3][n]): the candidates of a cell are then read contiguously.
 __global__ void k_cell_fill(int n, const int* __restrict__ run, const int* __restrict__ cell_of_atom,
                             const int* __restrict__ slot_of_atom, const int* __restrict__ cell_start,
-                            int* __restrict__ cell_atoms) {
+                            int* __restrict__ cell_atoms, const double* __restrict__ pos,
+                            double* __restrict__ cell_pos) {
     if (*run == 0) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    cell_atoms[cell_start[cell_of_atom[i]] + slot_of_atom[i]] = i;
+    const int t = cell_start[cell_of_atom[i]] + slot_of_atom[i];
+    cell_atoms[t] = i;
+    cell_pos[t] = pos[i];
+    cell_pos[n + t] = pos[n + i];
+    cell_pos[2 * n + t] = pos[2 * n + i];
 }
 
-// Iterates over the stencil cells of atom i; calls body(j) for every
-// candidate.  With a cell grid the 27 cells' member lists are taken as one
+// Iterates over the stencil cells of atom i; calls body(t) for every
+// candidate, t its position in cell order (-1: none for this lane).  With a cell grid the 27 cells' member lists are taken as one
 // stream: lane k < 27 holds cell k's range, a wavefront prefix sum numbers
 // the candidates, and each lane finds the cell of its candidate by a binary
 // search over the lanes (every lane busy, about (27 x members) / 64 trips
@@ -149,6 +156,7 @@ struct Stencil {
     const int* cell_of_atom;
     const int* cell_start;
     const int* cell_atoms;
+    const double* cell_pos;  // [3][n] positions in cell order
 };
 
 template <class Body>
@@ -161,7 +169,7 @@ __device__ __forceinline__ void for_candidates(const Stencil& st, int i, int r, 
         const int trips = (e - s + 63) / 64;  // uniform across the wavefront
         for (int k = 0; k < trips; ++k) {
             const int t = s + k * 64 + lane;
-            body(t < e ? st.cell_atoms[t] : -1);
+            body(t < e ? t : -1);
         }
         return;
     }
@@ -195,7 +203,7 @@ __device__ __forceinline__ void for_candidates(const Stencil& st, int i, int r, 
             if (cand <= 26 && e <= t) k = cand;
         }
         const int d = __shfl(delta, k, 64);
-        body(t < total ? st.cell_atoms[t + d] : -1);
+        body(t < total ? t + d : -1);
     }
 }
 
@@ -211,10 +219,12 @@ k_nbr_count(int n, const double* __restrict__ pos, RepGeom geom, Stencil st, dou
     geom.get(i, L, inv);
     double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
     int cnt = 0;
-    for_candidates(st, i, r, lane, [&](int j) {
+    for_candidates(st, i, r, lane, [&](int t) {
+        const int j = t >= 0 ? st.cell_atoms[t] : -1;
         if (j >= 0 && j != i) {
             double dx, dy, dz;
-            if (pair_rule(xi, yi, zi, pos[j], pos[n + j], pos[2 * n + j], L, inv, rc2, dx, dy, dz))
+            if (pair_rule(xi, yi, zi, st.cell_pos[t], st.cell_pos[n + t], st.cell_pos[2 * n + t], L, inv, rc2, dx,
+                          dy, dz))
                 ++cnt;
         }
     });
@@ -261,11 +271,13 @@ k_nbr_fill(int n, const double* __restrict__ pos, RepGeom geom, Stencil st, doub
     double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
     int fill = 0;
     int* row = rows[w];
-    for_candidates(st, i, r, lane, [&](int j) {
+    for_candidates(st, i, r, lane, [&](int t) {
+        const int j = t >= 0 ? st.cell_atoms[t] : -1;
         bool ok = false;
         if (j >= 0 && j != i) {
             double dx, dy, dz;
-            ok = pair_rule(xi, yi, zi, pos[j], pos[n + j], pos[2 * n + j], L, inv, rc2, dx, dy, dz);
+            ok = pair_rule(xi, yi, zi, st.cell_pos[t], st.cell_pos[n + t], st.cell_pos[2 * n + t], L, inv, rc2, dx,
+                           dy, dz);
         }
         uint64_t bal = __ballot(ok);
         int pre = __popcll(bal & ((1ull << lane) - 1ull));
@@ -441,6 +453,7 @@ void carve_nbr_scratch(Arena& a, int64_t n, int32_t n_rep, NbrScratch& s) {
     s.cell_count = a.take<int>(C + 1);
     s.cell_start = a.take<int>(C + 1);
     s.cell_atoms = a.take<int>(n);
+    s.cell_pos = a.take<double>(3 * n);
     s.counts = a.take<int>(n);
     s.tmp_off = a.take<int>(n + 1);
     s.status = a.take<int>(8);
@@ -460,8 +473,8 @@ void launch_build(int n, const double* pos, const RepGeom& geom, const CellPlan&
                                                     s.slot_of_atom, s.cell_count, pos_ref);
     k_scan<<<1, 1024, 0, stream>>>(plan.n_cells, s.cell_count, s.cell_start, run);
     k_cell_fill<<<cdiv(n, 256), 256, 0, stream>>>(n, run, s.cell_of_atom, s.slot_of_atom, s.cell_start,
-                                                  s.cell_atoms);
-    Stencil st{s.grid_m, s.grid_base, s.cell_of_atom, s.cell_start, s.cell_atoms};
+                                                  s.cell_atoms, pos, s.cell_pos);
+    Stencil st{s.grid_m, s.grid_base, s.cell_of_atom, s.cell_start, s.cell_atoms, s.cell_pos};
     double rc2 = radius * radius;
     k_nbr_count<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, pos, geom, st, rc2, run, s.counts, s.status);
     k_scan<<<1, 1024, 0, stream>>>(n, s.counts, s.tmp_off, run);
