@@ -274,6 +274,7 @@ void carve_model(Arena& a, const Model* m, int64_t n, int64_t E, bool for_wgrad,
             b.ecnt = a.take<int>(n);
             b.erec = a.take<EdgeRec>(E);
             b.ehalf = a.take<uint4>(8 * E);
+            for (int l = 1; l < L; ++l) b.layer[l].pv = a.take<float>(n * 3 * F);
         }
     } else {
         const int64_t HC = 2 * int64_t(m->desc.n_s + m->desc.n_l) * m->desc.n_c;
@@ -369,6 +370,7 @@ void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, Mode
             a.s_in = b.s[l];
             a.v_in = b.v[l];
             a.phi = lb.phi;
+            a.pv = lb.pv;
         }
         launch_message_fwd(F, K, cut, mg, a, s);
         gemm_xwt(3 * n, 2 * F, F, lb.vmid, F, m->p(lo.U), nullptr, lb.UV, 2 * F, EPI_NONE, nullptr, 0, false, s,
@@ -428,6 +430,7 @@ void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float*
     } else {
         a.v_in = b.v[l];
         a.phi = lb.phi;
+        a.pv = lb.pv;
         a.want_gphi = 1;
     }
     launch_message_bwd(F, K, cut, mg, a, force != nullptr, wg, s);

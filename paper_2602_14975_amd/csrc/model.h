@@ -61,6 +61,7 @@ struct Model {
 
 struct LayerBuf {
     float *h1, *zphi, *phi, *smid, *vmid, *UV, *X, *a1, *z, *pqo;
+    float* pv = nullptr;  // phi_b * v_in (matrix-core message kernels, layers past the first)
 };
 
 struct ModelBuf {

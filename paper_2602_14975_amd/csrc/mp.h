@@ -41,6 +41,11 @@ struct MpFwd {
     const float* phi_tab;  // [S][3F] or nullptr
     const float* emb;      // [S][F]
     const float* mx_scale;  // [2] filter-weight scale and its inverse for the matrix-core kernels, or nullptr
+    // [n][3][F] products phi_b * v_in per atom (phi_b: the second third of
+    // phi, which gates the neighbour's vector features): written by the
+    // matrix-core forward of layers past the first, read there and by the
+    // reverse in place of phi_b and v_in; ignored elsewhere
+    float* pv;
 };
 
 struct MpBwd {
@@ -57,6 +62,7 @@ struct MpBwd {
     // with accum_force
     float* vir;
     const float* mx_scale;  // [2] filter-weight scale and its inverse for the matrix-core kernels, or nullptr
+    const float* pv;        // phi_b * v_in as written by the matrix-core forward (layers past the first)
 };
 
 }  // namespace nnp

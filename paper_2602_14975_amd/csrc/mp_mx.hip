@@ -237,7 +237,8 @@ __device__ __forceinline__ void fwd_batch(const MpFwd& a, const float* ptab, con
     const floatx16_t wc = mma3(ah, al, bh[2], bl[2]);
 #pragma unroll
     for (int g0 = 0; g0 < E; g0 += kFwdGroup) {
-        float pa[kFwdGroup], pb[kFwdGroup], pc[kFwdGroup], vj[kFwdGroup][3];
+        // the b channel enters only as phi_b v_j, read as one product
+        float pa[kFwdGroup], pc[kFwdGroup], pv[kFwdGroup][3];
 #pragma unroll
         for (int g = 0; g < kFwdGroup; ++g) {
             const int q = g0 + g;
@@ -245,13 +246,12 @@ __device__ __forceinline__ void fwd_batch(const MpFwd& a, const float* ptab, con
             const EdgeRec& s = rec[te < nb ? te : 0];
             const float* phj = L0 ? ptab + s.t * 3 * F + f : a.phi + int64_t(s.j) * 3 * F + f;
             pa[g] = phj[0];
-            pb[g] = phj[F];
             pc[g] = phj[2 * F];
             if (!L0) {
-                const float* v = a.v_in + int64_t(s.j) * 3 * F + f;
-                vj[g][0] = v[0];
-                vj[g][1] = v[F];
-                vj[g][2] = v[2 * F];
+                const float* v = a.pv + int64_t(s.j) * 3 * F + f;
+                pv[g][0] = v[0];
+                pv[g][1] = v[F];
+                pv[g][2] = v[2 * F];
             }
         }
 #pragma unroll
@@ -270,10 +270,10 @@ __device__ __forceinline__ void fwd_batch(const MpFwd& a, const float* ptab, con
                 acc.v[1] += s.u[1] * c;
                 acc.v[2] += s.u[2] * c;
             } else {
-                const float b = pb[g] * fmaf(bb[1], fc, wb[q]);
-                acc.v[0] += b * vj[g][0] + s.u[0] * c;
-                acc.v[1] += b * vj[g][1] + s.u[1] * c;
-                acc.v[2] += b * vj[g][2] + s.u[2] * c;
+                const float b = fmaf(bb[1], fc, wb[q]);
+                acc.v[0] += b * pv[g][0] + s.u[0] * c;
+                acc.v[1] += b * pv[g][1] + s.u[1] * c;
+                acc.v[2] += b * pv[g][2] + s.u[2] * c;
             }
         }
     }
@@ -361,7 +361,8 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
 #pragma unroll
     for (int g0 = 0; g0 < E; g0 += kBwdGroup<L0>) {
         constexpr int G = kBwdGroup<L0>;
-        float pa[G], pb[G], pc[G], vn[G][3], gn[G][3], gsn[G];
+        // phi_b of the neighbour enters only as phi_b v_n, read as one product
+        float pa[G], pc[G], pvn[G][3], gn[G][3], gsn[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int q = g0 + g;
@@ -370,14 +371,13 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
             const int j = s.j;
             const float* phj = L0 ? ptab + s.t * 3 * F + f : a.phi + int64_t(j) * 3 * F + f;
             pa[g] = phj[0];
-            pb[g] = phj[F];
             pc[g] = phj[2 * F];
-            vn[g][0] = vn[g][1] = vn[g][2] = 0.f;
+            pvn[g][0] = pvn[g][1] = pvn[g][2] = 0.f;
             if (!L0) {  // the first layer's vector input is zero
-                const float* v = a.v_in + int64_t(j) * 3 * F + f;
-                vn[g][0] = v[0];
-                vn[g][1] = v[F];
-                vn[g][2] = v[2 * F];
+                const float* v = a.pv + int64_t(j) * 3 * F + f;
+                pvn[g][0] = v[0];
+                pvn[g][1] = v[F];
+                pvn[g][2] = v[2 * F];
             }
             const float* gp = a.gvm + int64_t(j) * 3 * F + f;
             gn[g][0] = gp[0];
@@ -399,12 +399,12 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
             const float u0 = s.u[0], u1 = s.u[1], u2 = s.u[2];
             const float g0v = gn[g][0], g1v = gn[g][1], g2v = gn[g][2];
             // projections shared by several terms
-            const float gvo_vn = o.gv[0] * vn[g][0] + o.gv[1] * vn[g][1] + o.gv[2] * vn[g][2];
+            const float gvo_pvn = o.gv[0] * pvn[g][0] + o.gv[1] * pvn[g][1] + o.gv[2] * pvn[g][2];
             const float gvo_u = o.gv[0] * u0 + o.gv[1] * u1 + o.gv[2] * u2;
             const float gvn_vo = g0v * o.v[0] + g1v * o.v[1] + g2v * o.v[2];
             const float gvn_u = g0v * u0 + g1v * u1 + g2v * u2;
             // message n -> o and message o -> n (unit vector -u): filter adjoints
-            const float gwa = o.gs * pa[g], gwb = pb[g] * gvo_vn, gwc = pc[g] * gvo_u;
+            const float gwa = o.gs * pa[g], gwb = gvo_pvn, gwc = pc[g] * gvo_u;
             const float gwa2 = gsn[g] * o.ph[0], gwb2 = o.ph[1] * gvn_vo, gwc2 = -o.ph[2] * gvn_u;
             const float dr = L0 ? (gwa + gwa2) * dw[0] + (gwc + gwc2) * dw[2]
                                 : (gwa + gwa2) * dw[0] + (gwb + gwb2) * dw[1] + (gwc + gwc2) * dw[2];
@@ -554,6 +554,24 @@ __global__ void __launch_bounds__(256) k_filter_scale(int count, const float* Wr
     }
 }
 
+// pv[i][al][f] = phi[i][F + f] * v[i][al][f]: one thread per four features
+// of an atom.
+__global__ void __launch_bounds__(256) k_phib_v(int n, const float* __restrict__ phi, const float* __restrict__ v,
+                                                float* __restrict__ pv) {
+    constexpr int F = kMxF, C = F / 4;
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= int64_t(n) * C) return;
+    const int64_t i = t / C;
+    const int c = int(t % C);
+    const float4 b = reinterpret_cast<const float4*>(phi + i * 3 * F + F)[c];
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+        const int64_t row = (i * 3 + al) * F;
+        const float4 x = reinterpret_cast<const float4*>(v + row)[c];
+        reinterpret_cast<float4*>(pv + row)[c] = make_float4(b.x * x.x, b.y * x.y, b.z * x.z, b.w * x.w);
+    }
+}
+
 template <typename Kern, typename Args>
 void launch_mx(const ScopedTimer& t, Kern kern, int n, hipStream_t s, const MpGeom& mg, const Args& a) {
     const dim3 grid(cdiv(n, kMxAtoms));
@@ -566,11 +584,23 @@ void launch_mx(const ScopedTimer& t, Kern kern, int n, hipStream_t s, const MpGe
 bool message_mx_shape(int F, int K, int cut) { return F == kMxF && K == kMxK && cut == 0; }
 
 void launch_message_fwd_mx(const MpGeom& mg, const MpFwd& a, hipStream_t s, const ScopedTimer& t) {
-    if (a.phi_tab) launch_mx(t, k_message_fwd_mx<true>, mg.n, s, mg, a);
-    else launch_mx(t, k_message_fwd_mx<false>, mg.n, s, mg, a);
+    if (a.phi_tab) {
+        launch_mx(t, k_message_fwd_mx<true>, mg.n, s, mg, a);
+        return;
+    }
+    if (!a.pv) {
+        set_error("matrix-core message step: no phi_b * v buffer");
+        throw Fail{NNP_EINVAL};
+    }
+    k_phib_v<<<cdiv(int64_t(mg.n) * (kMxF / 4), 256), 256, 0, s>>>(mg.n, a.phi, a.v_in, a.pv);
+    launch_mx(t, k_message_fwd_mx<false>, mg.n, s, mg, a);
 }
 
 void launch_message_bwd_mx(const MpGeom& mg, const MpBwd& a, hipStream_t s, const ScopedTimer& t) {
+    if (!a.phi_tab && !a.pv) {
+        set_error("matrix-core message reverse: no phi_b * v buffer");
+        throw Fail{NNP_EINVAL};
+    }
     if (a.vir) {
         if (a.phi_tab) launch_mx(t, k_message_bwd_mx<true, true>, mg.n, s, mg, a);
         else launch_mx(t, k_message_bwd_mx<false, true>, mg.n, s, mg, a);
