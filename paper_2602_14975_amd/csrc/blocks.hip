@@ -7,6 +7,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "mp_edge.h"
 
 namespace nnp {
 
@@ -184,26 +185,15 @@ __device__ __forceinline__ bool head_edge(const MpGeom& mg, int i, int e, double
     const int j = mg.nbr[e];
     double dx, dy, dz;
     if (!pair_rule(xi, yi, zi, mg.pos[j], mg.pos[n + j], mg.pos[2 * n + j], L, inv, mg.rc2, dx, dy, dz)) return false;
-    const double r = sqrt((dx * dx + dy * dy) + dz * dz);
-    const double rc = mg.rc;
-    const double theta = M_PI * r / rc;
-    double sn, cs;
-    sincos(theta, &sn, &cs);
-    const double d = r / rc, d2 = d * d, d5 = d2 * d2 * d;
-    const double env = 1.0 - 21.0 * d5 + 35.0 * d5 * d - 15.0 * d5 * d2;
-    const double pre = mg.bessel_norm / r * env;
-    double s_prev = 0.0, s_cur = sn;
-#pragma unroll
-    for (int h = 0; h < kNs; ++h) {
-        he.ef[h] = float(pre * s_cur);
-        const double s_next = 2.0 * cs * s_cur - s_prev;
-        s_prev = s_cur;
-        s_cur = s_next;
-    }
-    he.u[0] = float(dx / r);
-    he.u[1] = float(dy / r);
-    he.u[2] = float(dz / r);
-    he.r = float(r);
+    // radial values in float32 (the pair rule above decides in float64)
+    const float r = sqrtf(float((dx * dx + dy * dy) + dz * dz));
+    const float ir = 1.f / r;
+    float env;
+    radial_poly_f32<kNs>(r * float(mg.inv_rc), float(mg.bessel_norm) * ir, he.ef, env);
+    he.u[0] = float(dx) * ir;
+    he.u[1] = float(dy) * ir;
+    he.u[2] = float(dz) * ir;
+    he.r = r;
     he.j = j;
     return true;
 }

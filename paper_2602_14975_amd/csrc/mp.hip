@@ -63,14 +63,26 @@ __device__ __forceinline__ int stage_batch(const MpGeom& mg, bool active, int e,
     const uint64_t mine = bal & gmask;
     const int pre = __popcll(mine & ((1ull << (g * G + l)) - 1ull));
     if (ok) {
-        const double r = sqrt((dx * dx + dy * dy) + dz * dz);
-        const double ir = 1.0 / r;
         EdgeSlot<K>& s = slots[pre];
-        radial<K, CUT, DERIV>(r, mg, s.ef, s.def, s.fc, s.dfc);
-        s.u[0] = float(dx * ir);
-        s.u[1] = float(dy * ir);
-        s.u[2] = float(dz * ir);
-        s.ir = float(ir);
+        if constexpr (CUT == 1 && !DERIV) {
+            // NC forward: radial values in float32
+            const float r = sqrtf(float((dx * dx + dy * dy) + dz * dz));
+            const float ir = 1.f / r;
+            radial_poly_f32<K>(r * float(mg.inv_rc), float(mg.bessel_norm) * ir, s.ef, s.fc);
+            s.dfc = 0.f;
+            s.u[0] = float(dx) * ir;
+            s.u[1] = float(dy) * ir;
+            s.u[2] = float(dz) * ir;
+            s.ir = ir;
+        } else {
+            const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+            const double ir = 1.0 / r;
+            radial<K, CUT, DERIV>(r, mg, s.ef, s.def, s.fc, s.dfc);
+            s.u[0] = float(dx * ir);
+            s.u[1] = float(dy * ir);
+            s.u[2] = float(dz * ir);
+            s.ir = float(ir);
+        }
         s.j = j;
         s.t = species ? min(max(species[j], 0), mg.n_species - 1) : 0;
     }

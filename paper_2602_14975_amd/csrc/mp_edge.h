@@ -56,4 +56,31 @@ __device__ __forceinline__ void radial(double r, const MpGeom& mg, float* ef, fl
     dfc = float(df);
 }
 
+// Forward radial values of the polynomial envelope (the NC model) in
+// float32; the pair rule and the displacement stay in float64 upstream.
+// d = r / rc, nr = bessel_norm / r.  sin(k pi d) follows the Chebyshev
+// recurrence from sincospi(d); the envelope 1 - 21 d^5 + 35 d^6 - 15 d^7 is
+// evaluated in its factored form (1 - d)^3 (1 + 3d + 6d^2 + 10d^3 + 15d^4),
+// which keeps full relative precision as d approaches 1 (1 - d is exact for
+// d >= 1/2).
+template <int K>
+__device__ __forceinline__ void radial_poly_f32(float d, float nr, float* ef, float& fc) {
+    float sn, cs;
+    sincospif(d, &sn, &cs);
+    const float e = 1.f - d;
+    const float q = fmaf(d, fmaf(d, fmaf(d, fmaf(d, 15.f, 10.f), 6.f), 3.f), 1.f);
+    const float f = e * e * e * q;
+    const float nf = nr * f;
+    float s_prev = 0.f, s_cur = sn;
+    const float c2 = 2.f * cs;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        ef[k] = nf * s_cur;
+        const float s_next = fmaf(c2, s_cur, -s_prev);
+        s_prev = s_cur;
+        s_cur = s_next;
+    }
+    fc = f;
+}
+
 }  // namespace nnp
