@@ -428,7 +428,8 @@ __global__ void __launch_bounds__(64) k_head_bwd(MpGeom mg, const float* __restr
 
 // ------------------------------------------------- fused NC update block --
 // Update block of the one-layer NC embedding followed by its q/k and vector
-// projections, for widths F <= 32: per atom, one lane per feature column.
+// projections, for widths F <= 32: one lane per feature column of two atoms
+// (each weight read from LDS serves both).
 // The model keeps an LDS image of these weights (pack_nc_weights: one row
 // per output, rows padded by four floats, rounded for BF16 models), so
 // staging is a straight 16-byte copy; a lane then reads four consecutive k
@@ -446,6 +447,9 @@ __device__ __forceinline__ float bf16_round(float x) {
 
 // floats of the packed image: rows of U;V (2F), M2 (3F), W_qk (HC) and W_V
 // (n_l) of pitch F + 4, rows of M1 (F) of pitch 2F + 4
+// atoms per lane and block pass of k_nc_update_proj
+constexpr int kNcAtomsPerLane = 2;
+
 constexpr int64_t nc_image_floats(int F) {
     return int64_t(5 * F + 2 * kH * kNc + kNl) * (F + 4) + int64_t(F) * (2 * F + 4);
 }
@@ -453,7 +457,11 @@ constexpr int64_t nc_image_floats(int F) {
 template <int F, bool BF16>
 __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
     constexpr int HC = 2 * kH * kNc;  // q and k outputs
-    constexpr int APB = 256 / F;      // atoms per block pass
+    constexpr int GPB = 256 / F;      // lane groups per block
+    constexpr int NA = kNcAtomsPerLane;
+    constexpr int APB = NA * GPB;     // atoms per block pass
+    constexpr int QPL = HC / F;       // q/k outputs per lane
+    static_assert(HC % F == 0, "q/k outputs split evenly over the lanes of an atom");
     constexpr int P1 = F + 4, P2 = 2 * F + 4;
     extern __shared__ float lds[];
     float* UV = lds;                   // [2F][P1]  outputs of U, then of V
@@ -466,6 +474,7 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
     float* work = m2 + 3 * F;          // per atom: sm[F], vm[3F], x[2F], z[F], so[F], vo[3F]
     auto rnd = [](float x) { return BF16 ? bf16_round(x) : x; };
     auto rnd4 = [&](float4 v) { return float4{rnd(v.x), rnd(v.y), rnd(v.z), rnd(v.w)}; };
+    auto ld4 = [](const float* p) { return *reinterpret_cast<const float4*>(p); };
     constexpr int NW = int(nc_image_floats(F));
     static_assert(NW % 4 == 0, "image of whole 16-byte units");
     {
@@ -484,112 +493,165 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
         if (threadIdx.x < F) m1[threadIdx.x] = b1;
         if (threadIdx.x < 3 * F) m2[threadIdx.x] = b2;
     }
+    // lane (g, f) takes feature f of atoms base + g + u GPB, u < NA: every
+    // weight read from LDS serves NA atoms
     const int g = threadIdx.x / F, f = threadIdx.x % F;
-    float* sm = work + g * 11 * F;
-    float* vm = sm + F;
-    float* x = vm + 3 * F;
-    float* z = x + 2 * F;
-    float* so = z + F;
-    float* vo = so + F;
+    float *sm[NA], *vm[NA], *x[NA], *z[NA], *so[NA], *vo[NA];
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+        sm[u] = work + (g + u * GPB) * 11 * F;
+        vm[u] = sm[u] + F;
+        x[u] = vm[u] + 3 * F;
+        z[u] = x[u] + 2 * F;
+        so[u] = z[u] + F;
+        vo[u] = so[u] + F;
+    }
     const int n = a.n;
     for (int base = blockIdx.x * APB; base < n; base += gridDim.x * APB) {
-        const int i = base + g;
-        const bool act = i < n;
         __syncthreads();  // weights staged / previous pass done with the work rows
-        sm[f] = act ? a.smid[int64_t(i) * F + f] : 0.f;
 #pragma unroll
-        for (int al = 0; al < 3; ++al) vm[al * F + f] = act ? a.vmid[(int64_t(i) * 3 + al) * F + f] : 0.f;
+        for (int u = 0; u < NA; ++u) {
+            const int i = base + g + u * GPB;
+            const bool act = i < n;
+            sm[u][f] = act ? a.smid[int64_t(i) * F + f] : 0.f;
+#pragma unroll
+            for (int al = 0; al < 3; ++al) vm[u][al * F + f] = act ? a.vmid[(int64_t(i) * 3 + al) * F + f] : 0.f;
+        }
         __syncthreads();
-        float Uv[3] = {}, Vv[3] = {};
+        float Uv[NA][3] = {}, Vv[NA][3] = {};
         {
             const float* ur = UV + f * P1;
             const float* vr = UV + (F + f) * P1;
 #pragma unroll 2
             for (int k = 0; k < F; k += 4) {
-                const float4 uw = *reinterpret_cast<const float4*>(ur + k);
-                const float4 vw = *reinterpret_cast<const float4*>(vr + k);
+                const float4 uw = ld4(ur + k);
+                const float4 vw = ld4(vr + k);
 #pragma unroll
-                for (int al = 0; al < 3; ++al) {
-                    const float4 vk = rnd4(*reinterpret_cast<const float4*>(vm + al * F + k));
-                    Uv[al] = fmaf(uw.x, vk.x, Uv[al]);
-                    Vv[al] = fmaf(vw.x, vk.x, Vv[al]);
-                    Uv[al] = fmaf(uw.y, vk.y, Uv[al]);
-                    Vv[al] = fmaf(vw.y, vk.y, Vv[al]);
-                    Uv[al] = fmaf(uw.z, vk.z, Uv[al]);
-                    Vv[al] = fmaf(vw.z, vk.z, Vv[al]);
-                    Uv[al] = fmaf(uw.w, vk.w, Uv[al]);
-                    Vv[al] = fmaf(vw.w, vk.w, Vv[al]);
-                }
+                for (int u = 0; u < NA; ++u)
+#pragma unroll
+                    for (int al = 0; al < 3; ++al) {
+                        const float4 vk = rnd4(ld4(vm[u] + al * F + k));
+                        Uv[u][al] = fmaf(uw.x, vk.x, Uv[u][al]);
+                        Vv[u][al] = fmaf(vw.x, vk.x, Vv[u][al]);
+                        Uv[u][al] = fmaf(uw.y, vk.y, Uv[u][al]);
+                        Vv[u][al] = fmaf(vw.y, vk.y, Vv[u][al]);
+                        Uv[u][al] = fmaf(uw.z, vk.z, Uv[u][al]);
+                        Vv[u][al] = fmaf(vw.z, vk.z, Vv[u][al]);
+                        Uv[u][al] = fmaf(uw.w, vk.w, Uv[u][al]);
+                        Vv[u][al] = fmaf(vw.w, vk.w, Vv[u][al]);
+                    }
             }
         }
-        float nn = 1e-8f;
 #pragma unroll
-        for (int al = 0; al < 3; ++al) nn = fmaf(Vv[al], Vv[al], nn);
-        x[f] = sm[f];
-        x[F + f] = sqrtf(nn);
+        for (int u = 0; u < NA; ++u) {
+            float nn = 1e-8f;
+#pragma unroll
+            for (int al = 0; al < 3; ++al) nn = fmaf(Vv[u][al], Vv[u][al], nn);
+            x[u][f] = sm[u][f];
+            x[u][F + f] = sqrtf(nn);
+        }
         __syncthreads();
-        float a1 = m1[f];
         {
+            float a1[NA];
+#pragma unroll
+            for (int u = 0; u < NA; ++u) a1[u] = m1[f];
             const float* wr = M1 + f * P2;
 #pragma unroll 4
             for (int k = 0; k < 2 * F; k += 4) {
-                const float4 w = *reinterpret_cast<const float4*>(wr + k);
-                const float4 xv = rnd4(*reinterpret_cast<const float4*>(x + k));
-                a1 = fmaf(w.x, xv.x, a1);
-                a1 = fmaf(w.y, xv.y, a1);
-                a1 = fmaf(w.z, xv.z, a1);
-                a1 = fmaf(w.w, xv.w, a1);
+                const float4 w = ld4(wr + k);
+#pragma unroll
+                for (int u = 0; u < NA; ++u) {
+                    const float4 xv = rnd4(ld4(x[u] + k));
+                    a1[u] = fmaf(w.x, xv.x, a1[u]);
+                    a1[u] = fmaf(w.y, xv.y, a1[u]);
+                    a1[u] = fmaf(w.z, xv.z, a1[u]);
+                    a1[u] = fmaf(w.w, xv.w, a1[u]);
+                }
             }
+#pragma unroll
+            for (int u = 0; u < NA; ++u) z[u][f] = silu(a1[u]);
         }
-        z[f] = silu(a1);
         __syncthreads();
-        float pq[3] = {m2[f], m2[F + f], m2[2 * F + f]};
+        float pq[NA][3];
+#pragma unroll
+        for (int u = 0; u < NA; ++u)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pq[u][c] = m2[c * F + f];
 #pragma unroll 2
         for (int k = 0; k < F; k += 4) {
-            const float4 zk = rnd4(*reinterpret_cast<const float4*>(z + k));
+            float4 zk[NA];
+#pragma unroll
+            for (int u = 0; u < NA; ++u) zk[u] = rnd4(ld4(z[u] + k));
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const float4 w = *reinterpret_cast<const float4*>(M2 + (c * F + f) * P1 + k);
-                pq[c] = fmaf(w.x, zk.x, pq[c]);
-                pq[c] = fmaf(w.y, zk.y, pq[c]);
-                pq[c] = fmaf(w.z, zk.z, pq[c]);
-                pq[c] = fmaf(w.w, zk.w, pq[c]);
+                const float4 w = ld4(M2 + (c * F + f) * P1 + k);
+#pragma unroll
+                for (int u = 0; u < NA; ++u) {
+                    pq[u][c] = fmaf(w.x, zk[u].x, pq[u][c]);
+                    pq[u][c] = fmaf(w.y, zk[u].y, pq[u][c]);
+                    pq[u][c] = fmaf(w.z, zk[u].z, pq[u][c]);
+                    pq[u][c] = fmaf(w.w, zk[u].w, pq[u][c]);
+                }
             }
         }
-        const float dot = Uv[0] * Vv[0] + Uv[1] * Vv[1] + Uv[2] * Vv[2];
-        so[f] = sm[f] + pq[0] + pq[1] * dot;
 #pragma unroll
-        for (int al = 0; al < 3; ++al) vo[al * F + f] = vm[al * F + f] + pq[2] * Uv[al];
+        for (int u = 0; u < NA; ++u) {
+            const float dot = Uv[u][0] * Vv[u][0] + Uv[u][1] * Vv[u][1] + Uv[u][2] * Vv[u][2];
+            so[u][f] = sm[u][f] + pq[u][0] + pq[u][1] * dot;
+#pragma unroll
+            for (int al = 0; al < 3; ++al) vo[u][al * F + f] = vm[u][al * F + f] + pq[u][2] * Uv[u][al];
+        }
         __syncthreads();
-        if (act) {
-            for (int c = f; c < HC; c += F) {
-                const float* wr = Q + c * P1;
-                float acc = 0.f;
+        {
+            // q/k outputs f + q F, q < QPL, of every atom of the lane: one
+            // read of each input chunk serves all of them
+            float acc[NA][QPL] = {};
 #pragma unroll 2
-                for (int k = 0; k < F; k += 4) {
-                    const float4 w = *reinterpret_cast<const float4*>(wr + k);
-                    const float4 sv = rnd4(*reinterpret_cast<const float4*>(so + k));
-                    acc = fmaf(w.x, sv.x, acc);
-                    acc = fmaf(w.y, sv.y, acc);
-                    acc = fmaf(w.z, sv.z, acc);
-                    acc = fmaf(w.w, sv.w, acc);
+            for (int k = 0; k < F; k += 4) {
+                float4 sv[NA];
+#pragma unroll
+                for (int u = 0; u < NA; ++u) sv[u] = rnd4(ld4(so[u] + k));
+#pragma unroll
+                for (int q = 0; q < QPL; ++q) {
+                    const float4 w = ld4(Q + (f + q * F) * P1 + k);
+#pragma unroll
+                    for (int u = 0; u < NA; ++u) {
+                        acc[u][q] = fmaf(w.x, sv[u].x, acc[u][q]);
+                        acc[u][q] = fmaf(w.y, sv[u].y, acc[u][q]);
+                        acc[u][q] = fmaf(w.z, sv[u].z, acc[u][q]);
+                        acc[u][q] = fmaf(w.w, sv[u].w, acc[u][q]);
+                    }
                 }
-                a.QK[int64_t(i) * HC + c] = acc;
             }
-            if (f < 3 * kNl) {
-                const int h = f / 3, al = f % 3;
-                const float* wr = WV + h * P1;
-                float acc = 0.f;
-#pragma unroll 2
-                for (int k = 0; k < F; k += 4) {
-                    const float4 w = *reinterpret_cast<const float4*>(wr + k);
-                    const float4 vv = rnd4(*reinterpret_cast<const float4*>(vo + al * F + k));
-                    acc = fmaf(w.x, vv.x, acc);
-                    acc = fmaf(w.y, vv.y, acc);
-                    acc = fmaf(w.z, vv.z, acc);
-                    acc = fmaf(w.w, vv.w, acc);
+#pragma unroll
+            for (int u = 0; u < NA; ++u) {
+                const int i = base + g + u * GPB;
+                if (i < n) {
+#pragma unroll
+                    for (int q = 0; q < QPL; ++q) a.QK[int64_t(i) * HC + f + q * F] = acc[u][q];
                 }
-                a.Vh[(int64_t(i) * 3 + al) * kNl + h] = acc;
+            }
+        }
+        if (f < 3 * kNl) {
+            const int h = f / 3, al = f % 3;
+            const float* wr = WV + h * P1;
+            float acc[NA] = {};
+#pragma unroll 2
+            for (int k = 0; k < F; k += 4) {
+                const float4 w = ld4(wr + k);
+#pragma unroll
+                for (int u = 0; u < NA; ++u) {
+                    const float4 vv = rnd4(ld4(vo[u] + al * F + k));
+                    acc[u] = fmaf(w.x, vv.x, acc[u]);
+                    acc[u] = fmaf(w.y, vv.y, acc[u]);
+                    acc[u] = fmaf(w.z, vv.z, acc[u]);
+                    acc[u] = fmaf(w.w, vv.w, acc[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < NA; ++u) {
+                const int i = base + g + u * GPB;
+                if (i < n) a.Vh[(int64_t(i) * 3 + al) * kNl + h] = acc[u];
             }
         }
     }
@@ -635,7 +697,8 @@ void pack_nc_weights(int F, const float* UV, const float* M1, const float* M2, c
 }
 
 size_t nc_update_lds_bytes(int F) {
-    return sizeof(float) * (size_t(nc_image_floats(F)) + size_t(F + 3 * F) + size_t(256 / F) * 11 * F);
+    return sizeof(float) *
+           (size_t(nc_image_floats(F)) + size_t(F + 3 * F) + size_t(kNcAtomsPerLane) * size_t(256 / F) * 11 * F);
 }
 
 int64_t nc_image_count(int F) { return nc_image_floats(F); }
@@ -643,7 +706,7 @@ int64_t nc_image_count(int F) { return nc_image_floats(F); }
 bool launch_nc_update_proj(const NcUpdateArgs& a, int F, bool bf16, hipStream_t st) {
     if (a.n <= 0) return true;
     const size_t lds = nc_update_lds_bytes(F);
-    const int blocks = std::min(cdiv(a.n, 256 / F), 512);
+    const int blocks = std::min(cdiv(a.n, kNcAtomsPerLane * (256 / F)), 512);
     ScopedTimer timer("nc_update", st);
     // more than 64 KB of dynamic LDS at F = 32: raise each instance's limit
     // once (flag per width and precision)
