@@ -128,10 +128,11 @@ def test_nc_forces_water(gpu_lib, which, spec):
     assert np.linalg.norm(f.sum(0)) <= 1e-5 * np.abs(f).sum()
 
 
-@pytest.mark.parametrize("width", [8, 64])
+@pytest.mark.parametrize("width", [8, 16, 32, 64])
 def test_nc_other_widths_ragged(gpu_lib, width):
-    """Width 8 takes the fused update/projection kernel, width 64 the
-    general GEMM sequence."""
+    """Widths 8, 16 and 32 take the fused update/projection kernel (101
+    atoms: a partial last pass of 64, 32 or 16 atoms per block), width 64
+    the general GEMM sequence."""
     from paper_2602_14975_amd.nnp import DeviceSystem, workspace
     spec = ModelSpec("nc", width, 1, 8, 3.5)
     pos, species, box = small_box(11 + width, n=101, box=11.5)
