@@ -100,7 +100,7 @@ __device__ __forceinline__ half8_t as_half8(const uint4& u) { return __builtin_b
 
 // ---------------------------------------------------------- edge preparation
 
-__global__ void __launch_bounds__(256) k_edge_prep(MpGeom mg, int* __restrict__ ecnt, EdgeRec* __restrict__ erec,
+__global__ void __launch_bounds__(256, 3) k_edge_prep(MpGeom mg, int* __restrict__ ecnt, EdgeRec* __restrict__ erec,
                                                    uint4* __restrict__ ehalf) {
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
