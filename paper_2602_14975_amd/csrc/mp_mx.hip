@@ -48,8 +48,9 @@ typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef float floatx16_t __attribute__((ext_vector_type(16)));
 
 constexpr int kMxF = 128, kMxK = 16, kMxWaves = 4, kMxAtoms = 4;
-// forward: edges of a lane whose loads are issued together
-constexpr int kFwdGroup = 4;
+// forward: edges of a lane whose loads are issued together (eight: 40
+// loads in flight per lane, within three wavefronts per SIMD)
+constexpr int kFwdGroup = 8;
 // reverse: the same; small groups keep every variant within three
 // wavefronts per SIMD (measured: more gathers in flight per wavefront at
 // two wavefronts per SIMD are 7 % slower than fewer at three)
