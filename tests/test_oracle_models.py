@@ -67,6 +67,26 @@ def test_polynomial_envelope(p):
     assert abs(float(g2[-1])) < 1e-9
 
 
+def test_polynomial_envelope_factored_form():
+    """The GPU's float32 NC edge values evaluate the p = 5 envelope as
+    (1 - d)^3 (1 + 3d + 6d^2 + 10d^3 + 15d^4): the same polynomial as the
+    oracle's expanded form (coefficients compared exactly), and in float32
+    it keeps its relative precision as d approaches 1."""
+    rc = 3.5
+    expanded = np.polynomial.Polynomial([1, 0, 0, 0, 0, -21, 35, -15])
+    factored = np.polynomial.Polynomial([1, -1]) ** 3 * np.polynomial.Polynomial([1, 3, 6, 10, 15])
+    np.testing.assert_array_equal(factored.coef, expanded.coef)
+    d = np.linspace(0.0, 1.0, 257)
+    u = om.poly_envelope(torch.tensor(d * rc, dtype=torch.float64), rc, 5).numpy()
+    np.testing.assert_allclose(factored(d), u, rtol=1e-12, atol=1e-14)  # the expanded form cancels near d = 1
+    d32 = np.float32(1.0) - np.float32(2.0) ** -np.arange(2, 20, dtype=np.float32)  # d close to 1
+    e = np.float32(1.0) - d32
+    q = ((((np.float32(15) * d32 + 10) * d32 + 6) * d32 + 3) * d32 + 1).astype(np.float32)
+    f32 = (e * e * e * q).astype(np.float64)
+    exact = factored(d32.astype(np.float64))
+    assert np.all(np.abs(f32 / exact - 1) < 1e-6)
+
+
 def test_cosine_cutoff():
     rc = 5.0
     r = torch.tensor([0.0, rc / 2, rc, rc + 1], dtype=torch.float64, requires_grad=True)
