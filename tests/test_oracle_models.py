@@ -83,7 +83,8 @@ def test_polynomial_envelope_factored_form():
     e = np.float32(1.0) - d32
     q = ((((np.float32(15) * d32 + 10) * d32 + 6) * d32 + 3) * d32 + 1).astype(np.float32)
     f32 = (e * e * e * q).astype(np.float64)
-    exact = factored(d32.astype(np.float64))
+    d64 = d32.astype(np.float64)
+    exact = (1.0 - d64) ** 3 * (1 + 3 * d64 + 6 * d64**2 + 10 * d64**3 + 15 * d64**4)  # factored, in float64
     assert np.all(np.abs(f32 / exact - 1) < 1e-6)
 
 
