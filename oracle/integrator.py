@@ -41,10 +41,16 @@ for the x, y, z noise of that atom at that O-step.  ``step`` counts O-steps
 from the start of the trajectory.
 
 Pins (tests/test_oracle_integrator.py): Philox known-answer vectors and
-numpy's Philox bit generator; Box-Muller at chosen uniforms; RESPA with n = 1
-equal to BAOAB; RESPA with NC equal to the conservative force equal to n
-BAOAB steps of size d; BAOAB on harmonic oscillators giving <x^2> = kT/k;
-temperatures following (T/d) chi^2(d); molecule masses kept by HMR.
+numpy's Philox bit generator; Box-Muller at chosen uniforms (closed-form
+angles and radii); RESPA with n = 1 equal to BAOAB; RESPA with NC equal to
+the conservative force equal to n BAOAB steps of size d; BAOAB on harmonic
+oscillators giving <x^2> = kT/k; temperatures following (T/d) chi^2(d), for
+the Langevin O step and for the Fast-Forward Langevin step (which keeps the
+Maxwell-Boltzmann law: zero-force runs started far from it relax to 300 K
+with the chi^2 spread, and the reduced speeds follow the Maxwell law);
+energy conservation without friction (the energy fluctuation of BAOAB with
+the conservative model shrinks four-fold when the step is halved, the
+second-order error of the Strang splitting); molecule masses kept by HMR.
 """
 
 import math
@@ -116,16 +122,21 @@ def uniforms_from_bits(w):
     return ((np.asarray(w, dtype=np.uint64) >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53
 
 
-def langevin_normals(seed, stream, step, n_atoms):
-    """(N, 3) standard normals for O-step ``step`` of stream ``stream``."""
-    atoms = np.arange(n_atoms, dtype=np.uint64)
-    w = philox4x64(atoms, np.uint64(step), 0, 0, seed, stream)
-    u0, u1, u2, u3 = (uniforms_from_bits(x) for x in w)
+def box_muller(u0, u1, u2, u3):
+    """(..., 3) normals from four uniforms in (0, 1): the first pair gives
+    the x and y components, the second pair the z component."""
     r0 = np.sqrt(-2.0 * np.log(u0))
     r1 = np.sqrt(-2.0 * np.log(u2))
     return np.stack([r0 * np.cos(2.0 * math.pi * u1),
                      r0 * np.sin(2.0 * math.pi * u1),
-                     r1 * np.cos(2.0 * math.pi * u3)], axis=1)
+                     r1 * np.cos(2.0 * math.pi * u3)], axis=-1)
+
+
+def langevin_normals(seed, stream, step, n_atoms):
+    """(N, 3) standard normals for O-step ``step`` of stream ``stream``."""
+    atoms = np.arange(n_atoms, dtype=np.uint64)
+    w = philox4x64(atoms, np.uint64(step), 0, 0, seed, stream)
+    return box_muller(*(uniforms_from_bits(x) for x in w))
 
 
 # ----------------------------------------------------- masses and friction --

@@ -65,7 +65,9 @@ cutoff; continuity of E as a pair crosses the cutoff; reduction to per-atom
 perceptrons (evaluated with torch.nn.functional.linear) when the radial filter
 is a constant; NC forces summing to zero over each connected component,
 rotation equivariance, central pair forces with a symmetric weight when there
-are no vector heads, zero forces for zero queries, a two-atom closed form,
+are no vector heads, zero forces for zero queries, a closed form of the pair
+force of a two-species dimer with hand-set weights (which tells the owner's
+vector heads V_i from the neighbour's and c_ijh = q_ih . k_jh from q_jh . k_ih),
 and the weight gradient against finite differences.
 """
 
@@ -285,19 +287,3 @@ def nc_weight_grad(spec, theta, pos, species, box, offsets, nbr, dl_df):
     f = nc_forces_t(spec, th, x, species, box, offsets, nbr)
     (g,) = torch.autograd.grad((f * torch.as_tensor(np.asarray(dl_df, dtype=np.float64))).sum(), th)
     return g.numpy()
-
-
-def force_mse_loss_grad(spec, theta, frames, ref_forces):
-    """Loss L = mean over frames, atoms and components of (F_NC - F_ref)^2
-    and dL/dtheta; ``frames`` is a list of (pos, species, box, offsets, nbr)."""
-    th = torch.tensor(np.asarray(theta, dtype=np.float64), requires_grad=True)
-    tot, count = 0.0, 0
-    for (pos, species, box, offsets, nbr), fref in zip(frames, ref_forces):
-        x = torch.as_tensor(np.asarray(pos, dtype=np.float64))
-        f = nc_forces_t(spec, th, x, species, box, offsets, nbr)
-        d = f - torch.as_tensor(np.asarray(fref, dtype=np.float64))
-        tot = tot + (d * d).sum()
-        count += d.numel()
-    loss = tot / count
-    (g,) = torch.autograd.grad(loss, th)
-    return float(loss.detach()), g.numpy()

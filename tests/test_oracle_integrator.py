@@ -50,6 +50,18 @@ def test_normals_are_standard_gaussian():
     assert abs(np.corrcoef(a, b)[0, 1]) < 0.03
 
 
+def test_box_muller_at_chosen_uniforms():
+    """u0 = u2 = exp(-1/2) gives radius 1; the angles 2 pi u1 and 2 pi u3 at
+    u = 0, 1/8, 1/4, 1/2 put the normals at known points of the unit circle."""
+    r = np.exp(-0.5)
+    u1 = np.array([0.0, 0.125, 0.25, 0.5])
+    u3 = np.array([0.5, 0.0, 0.125, 0.25])
+    g = oi.box_muller(np.full(4, r), u1, np.full(4, r * r), u3)   # second radius sqrt(2)
+    h = np.sqrt(0.5)
+    expect = np.array([[1.0, 0.0, -np.sqrt(2)], [h, h, np.sqrt(2)], [0.0, 1.0, 1.0], [-1.0, 0.0, 0.0]])
+    np.testing.assert_allclose(g, expect, atol=1e-15)
+
+
 def test_uniform_mapping_endpoints():
     u = oi.uniforms_from_bits(np.array([0, 2 ** 64 - 1], dtype=np.uint64))
     assert u[0] == 0.5 * 2.0 ** -53 and u[1] == 1.0 - 0.5 * 2.0 ** -53
@@ -137,6 +149,69 @@ def test_ffl_keeps_direction():
     oi._o_step(st, prm, 1.0)
     cos = np.sum(st.v * v0, 1) / np.linalg.norm(st.v, axis=1) / np.linalg.norm(v0, axis=1)
     np.testing.assert_allclose(cos, 1.0, atol=1e-12)
+
+
+def test_ffl_keeps_maxwell_boltzmann():
+    """Fast-Forward Langevin (Methods, "High Hydrogen Friction": the O step
+    takes the norm of the Langevin update and the direction of v) leaves the
+    Maxwell-Boltzmann law invariant: with zero force, velocities started at
+    four times the target temperature relax to T = 300 K with the
+    (T/d) chi^2(d) spread, and the reduced speeds |v| sqrt(m / k_B T) follow
+    the Maxwell (chi, 3 degrees of freedom) law."""
+    n, T = 400, 300.0
+    rng = np.random.default_rng(17)
+    m = rng.choice([1.008, 3.0, 12.011, 15.999], size=n)
+    st = oi.State(np.zeros((n, 3)), 2.0 * synth.maxwell_boltzmann(m, T, 18), m)
+    prm = oi.LangevinParams(2.0, 1, T, rng.choice([10.0, 40.0], size=n), seed=19, thermostat="ffl")
+    zero = lambda x: np.zeros_like(x)
+    temps, speeds = [], []
+    for step in range(2400):
+        oi.baoab_step(st, zero, prm)
+        if step >= 400 and step % 4 == 0:
+            temps.append(oi.temperature(st.v, st.m))
+        if step >= 400 and step % 50 == 0:
+            speeds.append(np.linalg.norm(st.v, axis=1) * np.sqrt(m / (oi.KB * T * oi.ACC)))
+    mean, sd = oa.chi2_temperature_moments(T, n)
+    assert abs(np.mean(temps) - mean) < 0.01 * mean
+    assert abs(np.std(temps) / sd - 1) < 0.1
+    assert stats.kstest(np.concatenate(speeds), stats.chi(3).cdf).pvalue > 1e-3
+
+
+def test_nve_energy_error_is_second_order():
+    """Without friction BAOAB is velocity Verlet: with the conservative model
+    the total energy fluctuates by O(dt^2) (the O(t^3) local error of the
+    Strang splitting, Methods "Multi-time-step integrator"), so halving the
+    step divides the fluctuation by about four."""
+    from oracle import models as om
+    from oracle import neighbors as nb
+    spec = synth.ModelSpec("cons", 8, 2, 16, 5.0)
+    th = synth.random_weights(spec, 51)
+    rng = np.random.default_rng(52)
+    n, box = 27, 11.0
+    species = rng.integers(0, 4, size=n).astype(np.int32)
+    g = np.stack(np.meshgrid(*[np.arange(3)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    pos = (g + 0.5) * (box / 3) + rng.normal(scale=0.2, size=(n, 3))
+    m = np.full(n, 16.0)   # heavy atoms keep the 80 fs window free of close encounters
+    v0 = synth.maxwell_boltzmann(m, 300.0, 53)
+    energy = {}
+
+    def force(x):
+        e, f = om.cons_energy_forces(spec, th, x, species, box, *nb.pairs_bruteforce(x, box, spec.cutoff))
+        energy["e"] = e
+        return f
+
+    def fluctuation(dt, steps):
+        st = oi.State(pos.copy(), v0.copy(), m.copy())
+        prm = oi.LangevinParams(dt, 1, 300.0, np.zeros(n), seed=1)
+        h = []
+        for _ in range(steps):
+            oi.baoab_step(st, force, prm)
+            h.append(energy["e"] + oi.kinetic_energy(st.v, st.m))
+        h = np.array(h)
+        return np.sqrt(np.mean((h - h.mean()) ** 2))
+
+    f = [fluctuation(2.0, 40), fluctuation(1.0, 80), fluctuation(0.5, 160)]
+    assert 3.0 < f[0] / f[1] < 5.0 and 3.0 < f[1] / f[2] < 5.0
 
 
 # -------------------------------------------------------------- HMR/friction --

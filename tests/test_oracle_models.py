@@ -320,3 +320,77 @@ def test_nc_weight_gradient_finite_differences():
     d = rng.normal(size=th.size)
     fd = (L(th + h * d) - L(th - h * d)) / (2 * h)
     assert abs(fd - grad @ d) <= 1e-6 * max(1.0, abs(fd))
+
+
+def _pack(spec, named):
+    """Flat weight vector in manifest order from a dict of named arrays."""
+    return np.concatenate([np.asarray(named[name], dtype=np.float64).reshape(-1)
+                           for name, _, _ in synth.weights.manifest(spec)])
+
+
+def _silu(x):
+    return x / (1.0 + np.exp(-x))
+
+
+def test_nc_dimer_closed_form():
+    """Two atoms of different species, hand-set weights (Methods, "Model
+    architecture": the equations for q_ih, k_ih, c_ijh, F_ij and F_i).
+
+    With W1 = I, b1 = b2 = 0, Wr = 0 and the update perceptron switched off
+    (M1 = 0, m1 = m2 = 0), the embedding after the layer is
+        s_i = emb[t_i] + phi_a(j) * br_a u,   v_i = u_ij (phi_c(j) * br_c u)
+    with phi(j) = W2 silu(emb[t_j]) and u the p = 5 envelope at d = r/rc.
+    Every vector lies on the axis e = u_01, so V_0h = e g0_h and V_1h = -e g1_h
+    with g0_h = WV[h] . (phi_c(1) br_c u), g1_h = WV[h] . (phi_c(0) br_c u),
+    and the force on atom 0 is, along e,
+        u [S_01 (1 + sum_h c_01(ns+h) g0_h) + S_10 (1 + sum_h c_10(ns+h) g1_h)].
+    The weights are chosen so that the two plausible misreadings (the
+    neighbour's vector heads V_jh in F_ij; c_ijh from q_jh . k_ih) change that
+    value, which the test checks as well."""
+    spec = SMALL_NC
+    F, K, H, nc, ns, nl = spec.width, spec.n_rbf, spec.n_s + spec.n_l, spec.n_c, spec.n_s, spec.n_l
+    rng = np.random.default_rng(41)
+    w = {name: np.zeros(shape) for name, shape, _ in synth.weights.manifest(spec)}
+    w["emb"] = rng.normal(size=(4, F))
+    w["l0.W1"] = np.eye(F)
+    w["l0.W2"] = rng.normal(size=(3 * F, F)) * 0.5
+    w["l0.br"] = rng.normal(size=3 * F)
+    w["l0.U"] = rng.normal(size=(F, F))      # unused: the update perceptron is off
+    w["l0.V"] = rng.normal(size=(F, F))
+    w["l0.M2"] = rng.normal(size=(3 * F, F))
+    w["Wq"] = rng.normal(size=(H, nc, F)) * 0.5
+    w["Wk"] = rng.normal(size=(H, nc, F)) * 0.5
+    w["WV"] = rng.normal(size=(nl, F))
+    th = _pack(spec, w)
+
+    r, rc = 2.3, spec.cutoff
+    e = np.array([0.6, -0.8, 0.0])
+    pos = np.array([[10.0, 10.0, 10.0], 10.0 + r * e])
+    species = np.array([3, 0], np.int32)
+    Fo = _ncf(spec, th, pos, species, 40.0)
+
+    d = r / rc
+    u = 1 - 21 * d**5 + 35 * d**6 - 15 * d**7
+    phi = [w["l0.W2"] @ _silu(w["emb"][t]) for t in species]
+    wf = w["l0.br"] * u
+    s = [w["emb"][species[0]] + phi[1][:F] * wf[:F], w["emb"][species[1]] + phi[0][:F] * wf[:F]]
+    vc = [phi[1][2 * F:] * wf[2 * F:], phi[0][2 * F:] * wf[2 * F:]]    # v_0 = e vc0, v_1 = -e vc1
+    q = [np.einsum("hcf,f->hc", w["Wq"], si) for si in s]
+    k = [np.einsum("hcf,f->hc", w["Wk"], si) for si in s]
+    g = [w["WV"] @ vc[0], w["WV"] @ vc[1]]
+    c01 = (q[0] * k[1]).sum(1) / math.sqrt(nc)
+    c10 = (q[1] * k[0]).sum(1) / math.sqrt(nc)
+    B = math.sqrt(2 / rc) * np.sin(np.arange(1, ns + 1) * math.pi * r / rc) / r
+    S01, S10 = c01[:ns] @ B, c10[:ns] @ B
+
+    def along(S01, S10, C01, C10, g0, g1):
+        return u * (S01 * (1 + C01[ns:] @ g0) + S10 * (1 + C10[ns:] @ g1))
+
+    expect = along(S01, S10, c01, c10, g[0], g[1])
+    np.testing.assert_allclose(Fo[0], expect * e, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(Fo[1], -expect * e, rtol=1e-12, atol=1e-14)
+    # the configuration tells both misreadings apart from the paper's form
+    swapped_v = u * (S01 * (1 - c01[ns:] @ g[1]) + S10 * (1 - c10[ns:] @ g[0]))
+    swapped_qk = along(S10, S01, c10, c01, g[0], g[1])
+    for alt in (swapped_v, swapped_qk):
+        assert abs(alt - expect) > 1e-2 * abs(expect)
