@@ -181,6 +181,22 @@ nnp_status nnp_cons_energy_forces(const nnp_model* cons, const nnp_system* sys,
 nnp_status nnp_nc_forces(const nnp_model* nc, const nnp_system* sys, const nnp_nlist* nl,
                          void* ws, size_t ws_bytes, float* forces, void* stream);
 
+/* nnp_nc_forces for callers that cannot allocate device memory (code under
+ * stream capture, serving loops or harnesses that forbid hipMalloc): the
+ * same kernels and result as nnp_nc_forces, with the scratch taken from a
+ * static device array of nnp_nc_forces_noalloc_max_bytes() bytes (64 MiB;
+ * about 14,000 atoms for a width-32 NC model) instead of a workspace.  The
+ * caller still owns sys, nl and forces.  The call allocates nothing; each GPU
+ * the library runs on holds its own copy of the array until the process
+ * ends.  No part of the array needs to start at zero (every byte a call
+ * reads is written earlier in the same call).  Every call on one GPU shares
+ * that GPU's array, so calls that overlap on one GPU (other streams, other
+ * threads) race.  NNP_EINVAL (nothing launched) when the system needs more
+ * scratch than the maximum, with the required size in nnp_last_error(). */
+size_t nnp_nc_forces_noalloc_max_bytes(void);
+nnp_status nnp_nc_forces_noalloc(const nnp_model* nc, const nnp_system* sys, const nnp_nlist* nl,
+                                 float* forces, void* stream);
+
 /* NPT virials (paper, Methods "Computation of the virial term in NPT"):
  * W = -sum_i F_i . q_i, written under periodic boundaries through the
  * minimum-image vectors r_ij = q_j - q_i.  With the kinetic energy K the

@@ -76,6 +76,8 @@ PROTOTYPES = {
     "nnp_neighbors": (C.c_int32, [C.POINTER(System), C.POINTER(NList), vp, C.c_size_t, vp]),
     "nnp_cons_energy_forces": (C.c_int32, [vp, C.POINTER(System), C.POINTER(NList), vp, C.c_size_t, vp, vp, vp]),
     "nnp_nc_forces": (C.c_int32, [vp, C.POINTER(System), C.POINTER(NList), vp, C.c_size_t, vp, vp]),
+    "nnp_nc_forces_noalloc": (C.c_int32, [vp, C.POINTER(System), C.POINTER(NList), vp, vp]),
+    "nnp_nc_forces_noalloc_max_bytes": (C.c_size_t, []),
     "nnp_cons_virial": (C.c_int32, [vp, C.POINTER(System), C.POINTER(NList), vp, C.c_size_t, vp, vp, vp, vp]),
     "nnp_nc_virial": (C.c_int32, [vp, C.POINTER(System), C.POINTER(NList), vp, C.c_size_t, vp, vp, vp]),
     "nnp_nc_weight_grad": (C.c_int32, [vp, C.POINTER(System), C.POINTER(NList), vp, vp, vp, C.c_size_t, vp]),

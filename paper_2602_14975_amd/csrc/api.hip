@@ -751,6 +751,74 @@ extern "C" nnp_status nnp_nc_forces(const nnp_model* nc, const nnp_system* sys, 
     NNP_API_END
 }
 
+// ======================================================= no-allocation NC
+// A variant of nnp_nc_forces for callers that cannot allocate device memory
+// (code under stream capture, serving loops that forbid hipMalloc): its
+// scratch is a file-scope device array instead of a caller workspace.  The
+// array's name is a host-side stand-in in host code; the device address of
+// each GPU's copy is looked up once per device with hipGetSymbolAddress and
+// only that address is passed to kernels.
+namespace nnp {
+
+constexpr size_t kNcScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNcScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::vector<void*> g_scratch_addr;  // per device ordinal
+
+static void* scratch_address() {
+    int dev = 0;
+    NNP_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (size_t(dev) >= g_scratch_addr.size()) g_scratch_addr.resize(size_t(dev) + 1, nullptr);
+    if (!g_scratch_addr[dev]) {
+        void* ptr = nullptr;
+        NNP_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        NNP_REQUIRE(ptr != nullptr, NNP_EDEVICE, "no device address for the static scratch array");
+        g_scratch_addr[dev] = ptr;
+    }
+    return g_scratch_addr[dev];
+}
+
+// The part of the workspace layout that the NC force evaluation touches.
+static void carve_nc_only(Arena& a, const Model* m, int64_t n, int32_t n_rep, SysTables& t, ModelBuf& b) {
+    carve_tables(a, n_rep, t);
+    carve_model(a, m, n, 1, false, b);
+}
+
+}  // namespace nnp
+
+extern "C" size_t nnp_nc_forces_noalloc_max_bytes(void) { return nnp::kNcScratchBytes; }
+
+extern "C" nnp_status nnp_nc_forces_noalloc(const nnp_model* nc, const nnp_system* sys, const nnp_nlist* nl,
+                                            float* forces, void* stream) {
+    NNP_API_BEGIN
+    NNP_REQUIRE(nc && forces, NNP_EINVAL, "null argument");
+    const Model* m = reinterpret_cast<const Model*>(nc);
+    NNP_REQUIRE(m->desc.kind == NNP_MODEL_NC, NNP_EINVAL, "not an NC model");
+    check_system(sys);
+    check_list(nl, sys, m->desc.cutoff);
+    {
+        Arena probe(nullptr, 0);
+        SysTables t;
+        ModelBuf b;
+        carve_nc_only(probe, m, sys->n_atoms, sys->n_rep, t, b);
+        NNP_REQUIRE(probe.used <= kNcScratchBytes, NNP_EINVAL,
+                    "nnp_nc_forces_noalloc: the system needs " + std::to_string(probe.used) +
+                        " bytes of scratch, above the static maximum of " + std::to_string(kNcScratchBytes));
+    }
+    void* ptr = scratch_address();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Arena a(ptr, kNcScratchBytes);
+    SysTables t;
+    ModelBuf b;
+    carve_nc_only(a, m, sys->n_atoms, sys->n_rep, t, b);
+    static thread_local std::vector<double> hs;  // reused: no host allocation once grown
+    RepGeom g = upload_tables(*sys, t, s, hs);
+    nc_eval(m, *sys, g, *nl, b, forces, s);
+    NNP_API_END
+}
+
 extern "C" nnp_status nnp_nc_weight_grad(const nnp_model* nc, const nnp_system* sys, const nnp_nlist* nl,
                                          const float* dl_df, float* dl_dtheta, void* ws, size_t ws_bytes,
                                          void* stream) {

@@ -170,6 +170,15 @@ def nnp_nc_forces(model, system, nlist, ws, forces=None):
     return forces
 
 
+def nnp_nc_forces_noalloc(model, system, nlist, forces=None):
+    """nnp_nc_forces without a workspace: the library's static device scratch
+    (nnp_nc_forces_noalloc_max_bytes() bytes) serves the call."""
+    forces = forces if forces is not None else torch.empty(3, system.n, dtype=torch.float32, device=DEV)
+    check(lib().nnp_nc_forces_noalloc(model.handle, C.byref(system.c()), C.byref(nlist.c()), _ptr(forces),
+                                      _stream()))
+    return forces
+
+
 def nnp_cons_virial(model, system, nlist, ws):
     """(energy [n_rep], forces [3][n], virial W = -sum F . q [n_rep])."""
     energy = torch.empty(system.n_rep, dtype=torch.float64, device=DEV)
