@@ -266,20 +266,26 @@ typedef struct {
     double skin;            /* Verlet skin (A) of both lists; lists are rebuilt when an
                                atom has moved more than skin/2 since the last build */
     /* Rewind procedure (paper, Methods "Preventing rare model disagreements"):
-     * when rewind_threshold > 0, a frame is saved every save_every outer steps;
-     * after each outer step the disagreement sqrt(mean_i |F_i - F_fast,i|^2) of
-     * every replica is measured, and if one exceeds the threshold the whole
-     * system returns to the saved frame (positions, velocities, forces and the
-     * O-step counter), runs sts_after_rewind BAOAB steps of size delta with the
-     * conservative force, re-evaluates the fast force and resumes MTS. */
+     * when rewind_threshold > 0, after each outer step the device measures the
+     * disagreement sqrt(mean_i |F_i - F_fast,i|^2) of every replica; if one
+     * exceeds the threshold (or the state is not finite) the whole system
+     * returns to the last saved frame (positions, velocities, forces and the
+     * O-step counter), runs sts_after_rewind BAOAB steps of size delta with
+     * the conservative force, re-evaluates the fast force and resumes MTS.
+     * The trip is read at the status checks (every check_every outer steps),
+     * where frames are also saved, every save_every kept outer steps
+     * (save_every must be a multiple of check_every); outer steps undone by
+     * a rewind do not count towards n_outer, so the result does not depend on
+     * check_every.  More than max(16, n_outer) rewinds in one call return
+     * NNP_EUNSTABLE with the state at the saved frame. */
     double rewind_threshold;  /* kcal/mol/A; 0 disables */
     int32_t save_every;       /* >= 1 */
     int32_t sts_after_rewind; /* >= 0 */
-    /* 1: multiple-time-step runs without rewinding record one outer step as a
-     * HIP graph on the caller's stream and replay it (fewer launch gaps; the
-     * numbers are identical); 0: launch every kernel directly.  Graphs are
-     * not used while launch-site timers are enabled or for calls of fewer
-     * than three outer steps. */
+    /* 1: multiple-time-step runs record one outer step as a HIP graph on the
+     * caller's stream and replay it (fewer launch gaps; the numbers are
+     * identical); 0: launch every kernel directly.  Graphs are not used while
+     * launch-site timers are enabled or for calls of fewer than three outer
+     * steps. */
     int32_t graph;
 } respa_params;
 
@@ -319,7 +325,7 @@ typedef struct {
  * (atom index within its replica, O-step index, 0, 0), Box-Muller on the four
  * uniforms ((w >> 11) + 0.5) 2^-53; FFL keeps each atom's velocity direction.
  * Lists are rebuilt when an atom moved more than skin/2 since the last
- * build.  Multiple-time-step runs without rewinding decide this once per
+ * build.  Multiple-time-step runs (n > 1) decide this once per
  * outer step, from the largest displacement so far and its growth over the
  * previous outer step; should an inner step still exceed skin/2, the
  * interval since the last check is replayed with the check after every

@@ -20,6 +20,15 @@ are given in ps^-1 and used as 1e-3 fs^-1.
   (the inner expression of the Fast-Forward Langevin update of the paper).
 * The Fast-Forward Langevin variant replaces that step by
       v <- |c1 v + sigma G| v / |v|   per atom (3-vector norm).
+* Rewind procedure (Methods, "Preventing rare model disagreements"): a
+  frame (x, v, cached forces, O-step counter) is saved every ``save_every``
+  kept outer steps; after each outer step the disagreement of the two force
+  models at the step's end, sqrt(mean_i |F_i - F_NC,i|^2), is compared with
+  a threshold, and when it is exceeded (or is not finite) the state returns
+  to the saved frame, ``sts_after`` BAOAB steps of size d = D/n with the
+  conservative force follow, F_NC is evaluated again and multiple time
+  stepping resumes with a new frame.  Steps undone by a rewind do not count:
+  a run of n_outer outer steps ends after n_outer kept ones.
 * Hydrogen mass repartitioning: each hydrogen's mass is raised (set to a
   value, or increased by an amount) and the difference is removed from the
   heavy atom it is bonded to, so each molecule keeps its mass.
@@ -272,3 +281,40 @@ def dmts_nc_step_virial(st, cons_fn, nc_fn, prm, cons_vir, fast_vir):
     st.f = cons_fn(st.x)
     st.v = st.v + (0.5 * D) * ACC * (st.f - st.f_nc) / st.m[:, None]
     return st, (cons_vir(st.x) - inner[-1]) + sum(inner) / n
+
+
+def disagreement(f, f_nc):
+    """sqrt(mean over atoms of |F_i - F_NC,i|^2) (kcal/mol/A)."""
+    d = np.asarray(f, dtype=np.float64) - np.asarray(f_nc, dtype=np.float64)
+    return float(np.sqrt(np.sum(d * d) / d.shape[0]))
+
+
+def dmts_nc_run_rewind(st, cons_fn, nc_fn, prm, n_outer, threshold, save_every, sts_after, max_rewinds=None):
+    """n_outer kept outer steps of Algorithm 1 under the rewind procedure.
+    Returns (rewinds, disagreements) with the disagreement measured after
+    every outer step taken, kept or undone."""
+    frame, since_save, kept, rewinds, seen = None, 0, 0, 0, []
+    limit = max(16, n_outer) if max_rewinds is None else max_rewinds
+    sts = LangevinParams(prm.dt_outer / prm.n_inner, 1, prm.temperature, prm.gamma_ps, prm.seed, prm.stream,
+                         prm.thermostat)
+    while kept < n_outer:
+        if since_save % save_every == 0:
+            frame = (st.x.copy(), st.v.copy(), None if st.f is None else st.f.copy(),
+                     None if st.f_nc is None else st.f_nc.copy(), st.step, st.first_step, kept)
+            since_save = 0
+        dmts_nc_step(st, cons_fn, nc_fn, prm)
+        kept += 1
+        since_save += 1
+        dis = disagreement(st.f, st.f_nc) if np.all(np.isfinite(st.x)) and np.all(np.isfinite(st.v)) else math.inf
+        seen.append(dis)
+        if not dis <= threshold:
+            rewinds += 1
+            if rewinds > limit:
+                raise RuntimeError("the fast model keeps disagreeing: rewind limit reached")
+            x, v, f, f_nc, step, first, kept = frame
+            st.x, st.v, st.f, st.f_nc, st.step, st.first_step = x.copy(), v.copy(), f, f_nc, step, first
+            for _ in range(sts_after):
+                baoab_step(st, cons_fn, sts)
+            st.f_nc = nc_fn(st.x)
+            since_save = 0
+    return rewinds, seen

@@ -980,11 +980,13 @@ void check_respa(const respa_state* st, const respa_params* p, const Model* cons
 // Per-replica disagreement sqrt(mean_i |F_i - F_fast,i|^2), fixed-order
 // float64 reduction, one block per replica.  Non-finite positions or
 // velocities count as infinite disagreement (such atoms leave every
-// neighbour list, so their forces alone would not show the failure).
+// neighbour list, so their forces alone would not show the failure).  A
+// replica above `thr` (or not finite) sets *trip, which the host reads at
+// its next status check.
 __global__ void __launch_bounds__(256) k_disagreement(const int64_t* __restrict__ rep_start, int n,
                                                       const float* __restrict__ fa, const float* __restrict__ fb,
                                                       const double* __restrict__ pos, const double* __restrict__ vel,
-                                                      double* __restrict__ out) {
+                                                      double* __restrict__ out, double thr, int* __restrict__ trip) {
     __shared__ double red[256];
     const int r = blockIdx.x;
     const int64_t a0 = rep_start[r], a1 = rep_start[r + 1];
@@ -1001,7 +1003,11 @@ __global__ void __launch_bounds__(256) k_disagreement(const int64_t* __restrict_
         if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[r] = sqrt(red[0] / double(max<int64_t>(a1 - a0, 1)));
+    if (threadIdx.x == 0) {
+        const double dis = sqrt(red[0] / double(max<int64_t>(a1 - a0, 1)));
+        out[r] = dis;
+        if (!(dis <= thr)) *trip = 1;
+    }
 }
 
 // Advances a packed system by n_outer outer steps.  Replica r draws its
@@ -1009,8 +1015,10 @@ __global__ void __launch_bounds__(256) k_disagreement(const int64_t* __restrict_
 // k counting the O-steps of this call.  rep_bad (host, n_rep, optional)
 // receives per-replica non-finite flags at each check; without it any
 // non-finite replica fails the call.
-// internal: a list went stale between predicted rebuilds (never returned)
+// internal: a list went stale between predicted rebuilds; the fast force
+// disagreed (rewind); neither is returned
 constexpr nnp_status NNP_ESTALE_INTERNAL = static_cast<nnp_status>(-100);
+constexpr nnp_status NNP_EREWIND_INTERNAL = static_cast<nnp_status>(-101);
 
 nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const respa_params* p, int32_t n_outer,
                      void* ws, size_t ws_bytes, hipStream_t s, const uint64_t* seeds, const uint64_t* streams,
@@ -1041,7 +1049,9 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     CellPlan plan = plan_cells(st->sys, rc_cons);
     upload_cell_plan(plan, c.nb, s);
     // flags: [0] rebuild trigger, [4] stale-list flag of the predictive mode, [5..6]
-    // displacement record, [8..10] fast-force list status; nb.status: conservative list
+    // displacement record, [8..10] fast-force list status, [12] rewind trip;
+    // nb.status: conservative list
+    int* trip = c.t.flags + 12;
     int* trig = c.t.flags;
     int* stale = c.t.flags + 4;
     unsigned* maxd2 = reinterpret_cast<unsigned*>(c.t.flags + 5);
@@ -1100,7 +1110,6 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
 
     int* hflags = pinned_flags();
     std::vector<int> bad(R);
-    std::vector<double> dis(R);
     auto read_status = [&]() {
         NNP_HIP(hipMemcpyAsync(hflags, c.t.flags, sizeof(int) * 16, hipMemcpyDeviceToHost, s));
         NNP_HIP(hipMemcpyAsync(hflags + 16, c.nb.status, sizeof(int) * 8, hipMemcpyDeviceToHost, s));
@@ -1133,6 +1142,8 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         rebuilds_seen = rb;
         // a stale list may have produced anything else flagged here as well
         if (hflags[4] != 0) return NNP_ESTALE_INTERNAL;
+        // so may a fast force that disagreed: the rewind undoes those steps
+        if (rewind && hflags[12] != 0) return NNP_EREWIND_INTERNAL;
         const bool row_long = hflags[16 + 2] != 0 || hflags[8 + 2] != 0;
         const bool over_cons = hflags[16 + 0] != 0;
         const bool over_nc = hflags[8 + 0] != 0;
@@ -1180,13 +1191,16 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         nnp_status e = check(0, false);
         if (e != NNP_OK) return e;
     }
-    const int check_every = rewind ? 1 : std::max(1, p->check_every);
+    const int check_every = std::max(1, p->check_every);
+    NNP_REQUIRE(!rewind || p->save_every % check_every == 0, NNP_EINVAL,
+                "with rewinding on, save_every must be a multiple of check_every (frames are saved at checks)");
     const int n_in = mts ? p->n_inner : 1;
     const double D = p->dt_outer_fs;
     const double d = D / n_in;
 
     // one BAOAB step of size dt with the conservative force
     auto sts_step = [&](double dt) {
+        ba.flag = trig;  // the per-step displacement check rebuilds at once
         ba.force = st->f_cons;
         ba.dt = dt;
         ba.step_offset = 0;
@@ -1233,6 +1247,13 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
             launch_rep_sum(R, c.t.rep_start, c.cons.vir_sum, st->virial, s);
         }
         launch_kick(n, st->vel, st->mass, st->f_cons, st->f_nc, 0.5 * D, s);
+        if (rewind) {
+            // both forces now belong to the end of the step; a trip is acted
+            // on at the next status check
+            k_disagreement<<<R, 256, 0, s>>>(c.t.rep_start, n, st->f_cons, st->f_nc, st->pos, st->vel, disagree,
+                                             p->rewind_threshold, trip);
+            NNP_LAUNCH_CHECK();
+        }
     };
     // Predictive outer steps can be recorded once as a HIP graph and replayed:
     // every launch argument is fixed within the call (the O-step counter and
@@ -1289,10 +1310,10 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         st->step += n_in;
     };
 
-    // predictive rebuilds for multiple-time-step runs without rewinding; a
-    // stale list found at a check sends the run back to the last snapshot,
-    // which is replayed in strict mode
-    const bool predictive = mts && !rewind && n_in > 1;
+    // predictive rebuilds for multiple-time-step runs; a stale list found at
+    // a check sends the run back to the last snapshot, which is replayed in
+    // strict mode
+    const bool predictive = mts && n_in > 1;
     const bool use_graph = predictive && p->graph != 0 && n_outer >= 3 && !timers_active();
     if (predictive) {
         // the displacement record starts empty: begin from fresh lists
@@ -1300,64 +1321,78 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         rebuild_if_flagged();
     }
     uint64_t snap_offset = 0;
-    int snap_o = 0, strict_until = 0;
+    int snap_o = 0, strict_until = 0, snap_since_save = 0;
     copy_state(c.rs, true);
+    // Rewind procedure: frames are saved at status checks only (the trip is
+    // read there), every save_every kept outer steps; a trip sends the state
+    // and the loop back to the frame, so the steps taken since then do not
+    // count, whichever check found it.
     uint64_t frame_offset = 0;
-    int since_save = 0;
+    int frame_o = 0, since_save = 0, rewinds_here = 0;
+    const int rewind_limit = std::max(16, n_outer);
     for (int o = 0; o < n_outer; ++o) {
         const bool strict = !predictive || o < strict_until;
         if (rewind && since_save % p->save_every == 0) {
             copy_state(frame, true);
             frame_offset = offset;
+            frame_o = o;
             since_save = 0;
         }
-        if (mts) mts_step(strict, use_graph && n_outer - o >= 1);
+        if (mts) mts_step(strict, use_graph);
         else sts_step(D);
         ++since_save;
-        if (rewind) {
-            k_disagreement<<<R, 256, 0, s>>>(c.t.rep_start, n, st->f_cons, st->f_nc, st->pos, st->vel, disagree);
-            NNP_LAUNCH_CHECK();
-            NNP_HIP(hipMemcpyAsync(dis.data(), disagree, sizeof(double) * R, hipMemcpyDeviceToHost, s));
-            NNP_HIP(hipStreamSynchronize(s));
-            bool trip = false;
-            for (int r = 0; r < R; ++r) trip |= !(dis[r] <= p->rewind_threshold);
-            if (trip) {
-                // back to the saved frame (state and O-step counter), STS, then MTS again
-                copy_state(frame, false);
-                st->step -= offset - frame_offset;
-                offset = frame_offset;
-                launch_set_u64(c.t.o_step, offset, s);
-                launch_set_flag(trig, 1, s);
-                rebuild_if_flagged();
-                for (int k = 0; k < p->sts_after_rewind; ++k) sts_step(d);
-                eval_inner();
-                st->n_rewinds += 1;
-                since_save = 0;
-            }
-        }
         launch_kinetic(R, c.t.rep_start, n, st->pos, st->vel, st->mass, st->ke ? st->ke + int64_t(o) * R : nullptr,
                        c.t.rep_bad, s, st->sys.rep_of_atom);
         if ((o + 1) % check_every == 0 || o + 1 == n_outer) {
             nnp_status e = check(snap_offset, true);
-            if (e == NNP_ESTALE_INTERNAL) {
-                // back to the snapshot; replay up to here with strict rebuilds
-                copy_state(c.rs, false);
-                st->step -= offset - snap_offset;
-                offset = snap_offset;
+            if (e == NNP_ESTALE_INTERNAL || e == NNP_EREWIND_INTERNAL) {
+                const bool back_to_frame = e == NNP_EREWIND_INTERNAL;
+                if (back_to_frame) {
+                    copy_state(frame, false);
+                    st->step -= offset - frame_offset;
+                    offset = frame_offset;
+                    o = frame_o - 1;
+                    strict_until = 0;
+                    if (++rewinds_here > rewind_limit) {
+                        // leave the state at the saved frame (its last good step)
+                        NNP_HIP(hipStreamSynchronize(s));
+                        set_error("the fast force keeps disagreeing: rewind limit of the call reached");
+                        return NNP_EUNSTABLE;
+                    }
+                } else {
+                    // back to the snapshot; replay up to here with strict rebuilds
+                    copy_state(c.rs, false);
+                    st->step -= offset - snap_offset;
+                    offset = snap_offset;
+                    strict_until = o + 1;
+                    o = snap_o - 1;
+                    since_save = snap_since_save;
+                    st->n_replays += 1;
+                }
                 launch_set_u64(c.t.o_step, offset, s);
-                strict_until = o + 1;
-                o = snap_o - 1;
-                st->n_replays += 1;
-                NNP_HIP(hipMemsetAsync(c.t.flags + 4, 0, sizeof(int) * 12, s));  // stale, record, fast-list status
+                NNP_HIP(hipMemsetAsync(c.t.flags + 4, 0, sizeof(int) * 12, s));  // stale, record, lists, trip
                 NNP_HIP(hipMemsetAsync(c.nb.status, 0, sizeof(int) * 8, s));
                 NNP_HIP(hipMemsetAsync(c.t.rep_bad, 0, sizeof(int) * R, s));
                 launch_set_flag(trig, 1, s);
                 rebuild_if_flagged();
+                if (back_to_frame) {
+                    // single time steps of delta with the reference force, a
+                    // fresh fast force, then multiple time steps again
+                    for (int k = 0; k < p->sts_after_rewind; ++k) sts_step(d);
+                    eval_inner();
+                    st->n_rewinds += 1;
+                    since_save = 0;
+                    snap_offset = offset;
+                    snap_o = frame_o;
+                    snap_since_save = 0;
+                    copy_state(c.rs, true);
+                }
                 continue;
             }
             if (e != NNP_OK) return e;
             snap_offset = offset;
             snap_o = o + 1;
+            snap_since_save = since_save;
             if (o + 1 < n_outer) copy_state(c.rs, true);
         }
     }

@@ -109,6 +109,69 @@ def test_respa_with_equal_models_is_n_baoab_steps():
     assert st_a.step == st_b.step == 80
 
 
+def test_rewind_never_tripping_is_plain_dmts_nc():
+    fs, fnc = _harmonic(60.0), lambda x: -50.0 * x
+    a = _state(20, 31)
+    b = copy.deepcopy(a)
+    prm = oi.LangevinParams(2.0, 4, 300.0, np.full(20, 5.0), seed=7)
+    rewinds, seen = oi.dmts_nc_run_rewind(a, fs, fnc, prm, 9, threshold=1e9, save_every=2, sts_after=3)
+    for _ in range(9):
+        oi.dmts_nc_step(b, fs, fnc, prm)
+    assert rewinds == 0 and len(seen) == 9
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.v, b.v) and a.step == b.step == 36
+
+
+def test_rewind_returns_to_the_last_saved_frame():
+    """Methods, "Preventing rare model disagreements": when the models
+    disagree, the run goes back to the last saved frame, takes single time
+    steps with the reference force for a while and then multiple time steps
+    again.  The fast force here disagrees only during its calls 14-17 (the
+    fourth outer step; call 1 is the initial evaluation); frames are saved
+    every two outer steps, so the run must equal: two outer steps, (frame)
+    two outer steps that the rewind undoes, sts_after BAOAB steps of d from
+    the frame with the O-step counter of that frame, a fresh F_NC, then the
+    four remaining outer steps."""
+    k = 60.0
+    fs = _harmonic(k)
+    calls = {"n": 0}
+
+    def fnc(x, bad=range(14, 18)):
+        calls["n"] += 1
+        return -0.8 * k * x + (500.0 if calls["n"] in bad else 0.0)
+
+    prm = oi.LangevinParams(2.0, 4, 300.0, np.full(20, 5.0), seed=11)
+    a = _state(20, 32)
+    b = copy.deepcopy(a)
+    calls["n"] = 0
+    rewinds, seen = oi.dmts_nc_run_rewind(a, fs, fnc, prm, 6, threshold=100.0, save_every=2, sts_after=3)
+    assert rewinds == 1 and len(seen) == 8 and seen[3] > 100.0 and max(seen[:3] + seen[4:]) < 100.0
+
+    plain = lambda x: -0.8 * k * x
+    for _ in range(2):
+        oi.dmts_nc_step(b, fs, plain, prm)
+    frame = copy.deepcopy(b)
+    for _ in range(2):
+        oi.dmts_nc_step(b, fs, plain, prm)        # undone by the rewind
+    b = frame
+    sts = oi.LangevinParams(0.5, 1, 300.0, np.full(20, 5.0), seed=11)
+    for _ in range(3):
+        oi.baoab_step(b, fs, sts)
+    b.f_nc = plain(b.x)
+    for _ in range(4):
+        oi.dmts_nc_step(b, fs, plain, prm)
+    assert b.step == 2 * 4 + 3 + 4 * 4 == a.step
+    np.testing.assert_allclose(a.x, b.x, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(a.v, b.v, rtol=0, atol=1e-13)
+
+
+def test_rewind_gives_up_on_a_model_that_always_disagrees():
+    fs, fnc = _harmonic(60.0), lambda x: np.full_like(x, 1e3)
+    st = _state(10, 33)
+    prm = oi.LangevinParams(2.0, 4, 300.0, np.full(10, 5.0), seed=7)
+    with pytest.raises(RuntimeError, match="rewind limit"):
+        oi.dmts_nc_run_rewind(st, fs, fnc, prm, 3, threshold=1.0, save_every=1, sts_after=2, max_rewinds=5)
+
+
 def test_baoab_harmonic_configurational_variance():
     """BAOAB samples the exact configurational law of a harmonic oscillator
     for any stable step: <x^2> = k_B T / k per component."""
