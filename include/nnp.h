@@ -348,6 +348,38 @@ nnp_status respa_step(const nnp_model* cons, const nnp_model* nc, respa_state* s
                       const respa_params* params, int32_t n_outer, void* ws, size_t ws_bytes,
                       void* stream);
 
+/* Barostat (paper, Methods "Computation of the virial term in NPT": NPT
+ * runs with Bussi's stochastic barostat fed by the virial estimator of the
+ * multiple-time-step outer step).  Isotropic stochastic cell rescaling, one
+ * Euler-Maruyama step in eps = ln V per replica:
+ *   P_int = (2K - W) / (3V),  K the kinetic energy of the state, W =
+ *   state->virial[r] (the estimator of the last outer step of respa_step);
+ *   d eps = -(beta_T / tau_p)(P_0 - P_int) dt_b
+ *           + sqrt(2 k_B T beta_T dt_b / (V tau_p)) g;
+ * positions scaled by mu = exp(d eps / 3), velocities by 1/mu, the box edge
+ * by mu (the rescaling of the velocities makes a k_B T / V drift term
+ * unnecessary: the ideal gas samples <V> = (N + 1) k_B T / P_0).  g is the
+ * first Box-Muller normal of the Philox-4x64-10 block with key
+ * (seed, stream_id + r) and counter (0, barostat_step, 1, 0).  1 bar =
+ * 1e5 N_A 1e-30 / 4184 kcal/mol/A^3. */
+typedef struct {
+    double pressure_bar;             /* P_0 */
+    double compressibility_per_bar;  /* beta_T */
+    double tau_fs;                   /* tau_p */
+    double dt_fs;                    /* time since the previous barostat step */
+    double temperature_K;
+    uint64_t seed;
+    uint64_t stream_id;              /* replica r uses stream_id + r */
+} nnp_barostat_params;
+
+/* Applies the step to the state in place, writes the new box edges to
+ * box_host (the system's host array, required) and box_dev (its device
+ * array; NULL allowed for one replica), marks the lists invalid and sets
+ * first_step (the cached forces belong to the old cell).  Synchronises
+ * `stream`.  ws: a workspace of nnp_workspace_size for the system. */
+nnp_status nnp_barostat_scr(respa_state* state, const nnp_barostat_params* params, uint64_t barostat_step,
+                            double* box_host, double* box_dev, void* ws, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------ serving
  * Continuous batching of independent replicas.  Replicas are submitted at
  * any time, admitted at outer-step boundaries when a slot is free and their

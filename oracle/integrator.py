@@ -29,6 +29,20 @@ are given in ps^-1 and used as 1e-3 fs^-1.
   conservative force follow, F_NC is evaluated again and multiple time
   stepping resumes with a new frame.  Steps undone by a rewind do not count:
   a run of n_outer outer steps ends after n_outer kept ones.
+* Barostat (Methods, "Computation of the virial term in NPT", which runs
+  NPT with Bussi's stochastic barostat and the virial estimator below;
+  the paper gives no barostat equations).  Isotropic stochastic cell
+  rescaling in eps = ln V, one Euler-Maruyama step of length dt_b:
+      P_int = (2K - W) / (3V)
+      d eps = -(beta_T / tau_p)(P_0 - P_int) dt_b
+              + sqrt(2 k_B T beta_T dt_b / (V tau_p)) R
+  positions scaled by mu = exp(d eps / 3), velocities by 1/mu, box by mu;
+  W is the outer step's virial estimator and K the kinetic energy after it.
+  With the velocities rescaled with the cell no k_B T / V drift term is
+  needed: the ideal gas then samples <V> = (N + 1) k_B T / P_0, the
+  isothermal-isobaric law (pinned).  R is the first Box-Muller normal of the
+  Philox block with key (seed, stream) and counter (0, barostat step, 1, 0)
+  (word 2 = 1 keeps it apart from the O-step normals).
 * Hydrogen mass repartitioning: each hydrogen's mass is raised (set to a
   value, or increased by an amount) and the difference is removed from the
   heavy atom it is bonded to, so each molecule keeps its mass.
@@ -318,3 +332,42 @@ def dmts_nc_run_rewind(st, cons_fn, nc_fn, prm, n_outer, threshold, save_every, 
             st.f_nc = nc_fn(st.x)
             since_save = 0
     return rewinds, seen
+
+
+BAR = 1e5 * 6.02214076e23 * 1e-30 / 4184.0      # one bar in kcal/mol/A^3
+
+
+@dataclass
+class BarostatParams:
+    pressure_bar: float
+    compressibility_per_bar: float   # beta_T
+    tau_fs: float                    # tau_p
+    dt_fs: float                     # time between barostat steps
+    temperature: float               # K
+    seed: int
+    stream: int = 0
+
+
+def barostat_normal(seed, stream, step):
+    w = philox4x64_scalar([0, step, 1, 0], [seed, stream])
+    u0, u1 = (uniforms_from_bits(np.uint64(x)) for x in w[:2])
+    return float(math.sqrt(-2.0 * math.log(u0)) * math.cos(2.0 * math.pi * u1))
+
+
+def scr_barostat_step(st, box, virial, prm, step):
+    """One stochastic cell rescaling step; returns the new box edge.  The
+    cached forces no longer belong to the scaled positions: the state is
+    marked for a fresh evaluation."""
+    V = box ** 3
+    K = kinetic_energy(st.v, st.m)
+    p_int = (2.0 * K - virial) / (3.0 * V)
+    beta = prm.compressibility_per_bar / BAR
+    kT = KB * prm.temperature
+    g = barostat_normal(prm.seed, prm.stream, step)
+    de = (-(beta / prm.tau_fs) * (prm.pressure_bar * BAR - p_int) * prm.dt_fs
+          + math.sqrt(2.0 * kT * beta * prm.dt_fs / (V * prm.tau_fs)) * g)
+    mu = math.exp(de / 3.0)
+    st.x = st.x * mu
+    st.v = st.v / mu
+    st.first_step = True
+    return box * mu

@@ -45,6 +45,12 @@ class RespaParams(C.Structure):
                 ("graph", C.c_int32)]
 
 
+class BarostatParams(C.Structure):
+    _fields_ = [("pressure_bar", C.c_double), ("compressibility_per_bar", C.c_double), ("tau_fs", C.c_double),
+                ("dt_fs", C.c_double), ("temperature_K", C.c_double), ("seed", C.c_uint64),
+                ("stream_id", C.c_uint64)]
+
+
 class RespaState(C.Structure):
     _fields_ = [("sys", System), ("pos", vp), ("vel", vp), ("mass", vp), ("gamma", vp), ("f_cons", vp),
                 ("f_nc", vp), ("energy", vp), ("pos_ref", vp), ("nl_cons", NList), ("nl_nc", NList),
@@ -86,6 +92,8 @@ PROTOTYPES = {
                                   C.c_double, vp]),
     "nnp_hmr_masses": (C.c_int32, [C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_double,
                                    C.c_int32, C.POINTER(C.c_double)]),
+    "nnp_barostat_scr": (C.c_int32, [C.POINTER(RespaState), C.POINTER(BarostatParams), C.c_uint64, vp, vp, vp,
+                                     C.c_size_t, vp]),
     "respa_step": (C.c_int32, [vp, vp, C.POINTER(RespaState), C.POINTER(RespaParams), C.c_int32, vp, C.c_size_t,
                                vp]),
     "nnp_server_create": (C.c_int32, [vp, vp, C.POINTER(RespaParams), C.c_size_t, C.c_int32, C.POINTER(vp)]),

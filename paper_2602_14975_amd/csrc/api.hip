@@ -1401,6 +1401,44 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
 
 }  // namespace nnp
 
+extern "C" nnp_status nnp_barostat_scr(respa_state* st, const nnp_barostat_params* p, uint64_t barostat_step,
+                                       double* box_host, double* box_dev, void* ws, size_t ws_bytes, void* stream) {
+    NNP_API_BEGIN
+    NNP_REQUIRE(st && p && box_host, NNP_EINVAL, "null argument");
+    NNP_REQUIRE(st->virial, NNP_EINVAL, "the barostat needs state->virial (the last outer step's estimator)");
+    NNP_REQUIRE(st->pos && st->vel && st->mass && st->sys.pos == st->pos, NNP_EINVAL, "incomplete state");
+    NNP_REQUIRE(p->tau_fs > 0 && p->dt_fs > 0 && p->compressibility_per_bar >= 0 && p->temperature_K >= 0 &&
+                    std::isfinite(p->pressure_bar),
+                NNP_EINVAL, "bad barostat parameters");
+    check_system(&st->sys);
+    NNP_REQUIRE(box_host == st->sys.box, NNP_EINVAL, "box_host must be the system's host box array");
+    NNP_REQUIRE(st->sys.n_rep == 1 || box_dev == st->sys.box_dev, NNP_EINVAL,
+                "box_dev must be the system's device box array");
+    const int n = int(st->sys.n_atoms), R = st->sys.n_rep;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Arena a(ws, ws_bytes);
+    SysTables t;
+    carve_tables(a, R, t);
+    double* ke = a.take<double>(R);
+    double* mu = a.take<double>(R);
+    std::vector<double> hs;
+    upload_tables(st->sys, t, s, hs);
+    launch_kinetic(R, t.rep_start, n, st->pos, st->vel, st->mass, ke, nullptr, s, st->sys.rep_of_atom);
+    const double bar = 1e5 * 6.02214076e23 * 1e-30 / 4184.0;  // kcal/mol/A^3
+    ScrArgs sa{p->pressure_bar * bar, p->compressibility_per_bar / bar, p->tau_fs, p->dt_fs, p->temperature_K,
+               p->seed, p->stream_id, barostat_step};
+    launch_scr(R, ke, st->virial, t.box, mu, sa, s);
+    launch_scale(n, R > 1 ? st->sys.rep_of_atom : nullptr, mu, st->pos, st->vel, s);
+    if (box_dev) NNP_HIP(hipMemcpyAsync(box_dev, t.box, sizeof(double) * R, hipMemcpyDeviceToDevice, s));
+    std::vector<double> nb(R);
+    NNP_HIP(hipMemcpyAsync(nb.data(), t.box, sizeof(double) * R, hipMemcpyDeviceToHost, s));
+    NNP_HIP(hipStreamSynchronize(s));
+    for (int r = 0; r < R; ++r) box_host[r] = nb[r];
+    st->lists_valid = 0;
+    st->first_step = 1;
+    NNP_API_END
+}
+
 extern "C" nnp_status respa_step(const nnp_model* cons_h, const nnp_model* nc_h, respa_state* st,
                                  const respa_params* p, int32_t n_outer, void* ws, size_t ws_bytes, void* stream) {
     NNP_API_BEGIN

@@ -230,6 +230,50 @@ void launch_baoa(const BaoaArgs& a, hipStream_t s) {
     NNP_LAUNCH_CHECK();
 }
 
+// Stochastic cell rescaling, one thread per replica: P = (2K - W) / (3V),
+// d eps = -(beta/tau)(P0 - P) dt + sqrt(2 kT beta dt / (V tau)) g with g the
+// first Box-Muller normal of the Philox block at counter (0, step, 1, 0);
+// mu = exp(d eps / 3) and the box edge becomes L mu.
+__global__ void k_scr(int n_rep, const double* __restrict__ ke, const double* __restrict__ virial,
+                      double* __restrict__ box, double* __restrict__ mu, ScrArgs a) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rep) return;
+    const double L = box[r];
+    const double V = L * L * L;
+    const double p_int = (2.0 * ke[r] - virial[r]) / (3.0 * V);
+    uint64_t c0 = 0, c1 = a.step, c2 = 1, c3 = 0;
+    philox4x64_10(c0, c1, c2, c3, a.seed, a.stream + uint64_t(r));
+    const double g = sqrt(-2.0 * log(u01(c0))) * cos(2.0 * M_PI * u01(c1));
+    const double kT = kKb * a.temperature;
+    const double de = -(a.beta / a.tau) * (a.p0 - p_int) * a.dt + sqrt(2.0 * kT * a.beta * a.dt / (V * a.tau)) * g;
+    const double m = exp(de / 3.0);
+    mu[r] = m;
+    box[r] = L * m;
+}
+
+__global__ void k_scale(int n, const int32_t* __restrict__ rep_of_atom, const double* __restrict__ mu,
+                        double* __restrict__ pos, double* __restrict__ vel) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double m = mu[rep_of_atom ? rep_of_atom[i] : 0];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        pos[c * int64_t(n) + i] *= m;
+        vel[c * int64_t(n) + i] /= m;
+    }
+}
+
+void launch_scr(int n_rep, const double* ke, const double* virial, double* box, double* mu, const ScrArgs& a,
+                hipStream_t s) {
+    k_scr<<<cdiv(n_rep, 64), 64, 0, s>>>(n_rep, ke, virial, box, mu, a);
+    NNP_LAUNCH_CHECK();
+}
+
+void launch_scale(int n, const int32_t* rep_of_atom, const double* mu, double* pos, double* vel, hipStream_t s) {
+    if (n > 0) k_scale<<<cdiv(n, 256), 256, 0, s>>>(n, rep_of_atom, mu, pos, vel);
+    NNP_LAUNCH_CHECK();
+}
+
 void launch_kinetic(int n_rep, const int64_t* rep_start, int n, const double* pos, const double* vel,
                     const double* mass, double* ke, int* bad, hipStream_t s, const int32_t* rep_of_atom) {
     if (!ke && bad && (n_rep == 1 || rep_of_atom)) {

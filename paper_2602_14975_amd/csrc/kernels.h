@@ -192,6 +192,14 @@ void launch_virial_combine(int n, const float* wc, const float* wl, const float*
 void launch_add(int n, const float* x, float* y, hipStream_t s);  // y += x
 bool timers_active();
 void launch_baoa(const BaoaArgs& a, hipStream_t s);
+// stochastic cell rescaling (pressures in kcal/mol/A^3, beta in their inverse)
+struct ScrArgs {
+    double p0, beta, tau, dt, temperature;
+    uint64_t seed, stream, step;
+};
+void launch_scr(int n_rep, const double* ke, const double* virial, double* box, double* mu, const ScrArgs& a,
+                hipStream_t s);
+void launch_scale(int n, const int32_t* rep_of_atom, const double* mu, double* pos, double* vel, hipStream_t s);
 void launch_kinetic(int n_rep, const int64_t* rep_start, int n, const double* pos, const double* vel,
                     const double* mass, double* ke, int* bad, hipStream_t s,
                     const int32_t* rep_of_atom = nullptr);

@@ -309,6 +309,21 @@ class Trajectory:
             return
         raise RuntimeError("respa_step kept running out of list capacity")
 
+    def barostat(self, params, step):
+        """One stochastic cell rescaling step (nnp_barostat_scr) fed by the
+        virial estimator of the last outer step; updates the system's box
+        edges in place.  Needs virial=True."""
+        if self.virial is None:
+            raise ValueError("the barostat needs a trajectory created with virial=True")
+        st = self._state(None)
+        box_dev = self.sys.box_dev.data_ptr()
+        check(lib().nnp_barostat_scr(C.byref(st), C.byref(params), int(step),
+                                     self.sys.box.ctypes.data_as(C.c_void_p), box_dev, _ptr(self.ws),
+                                     self.ws.numel(), _stream()))
+        self.first_step = int(st.first_step)
+        self.lists_valid = int(st.lists_valid)
+        return self.sys.box.copy()
+
     def positions(self):
         return self.sys.pos.T.cpu().numpy()
 
@@ -317,6 +332,12 @@ class Trajectory:
 
 
 _MODES = {"dmts_nc": _abi.NNP_MODE_DMTS_NC, "sts": _abi.NNP_MODE_STS, "dmts": _abi.NNP_MODE_DMTS}
+
+
+def barostat_params(pressure_bar=1.0, compressibility_per_bar=4.5e-5, tau_fs=100.0, dt_fs=4.0, temperature=300.0,
+                    seed=6000, stream_id=0):
+    return _abi.BarostatParams(float(pressure_bar), float(compressibility_per_bar), float(tau_fs), float(dt_fs),
+                               float(temperature), int(seed), int(stream_id))
 
 
 def respa_params(dt_outer, n_inner, temperature=300.0, seed=4000, stream_id=0, mode="dmts_nc", thermostat="langevin",

@@ -56,7 +56,7 @@ def test_structure_layouts_match_the_header(tmp_path):
         pytest.skip("gcc not available")
     structs = {"nnp_model_desc": _abi.ModelDesc, "nnp_system": _abi.System, "nnp_nlist": _abi.NList,
                "respa_params": _abi.RespaParams, "respa_state": _abi.RespaState, "replica_desc": _abi.ReplicaDesc,
-               "replica_status": _abi.ReplicaStatus}
+               "replica_status": _abi.ReplicaStatus, "nnp_barostat_params": _abi.BarostatParams}
     lines = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

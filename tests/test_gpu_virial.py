@@ -146,3 +146,59 @@ def test_respa_virial_estimator_sts(gpu_lib):
     W, ref = _estimator_pair(gpu_lib, "sts", 0.5, 1, 4)
     print(f"estimator gpu {W:.8g} oracle {ref:.8g}", flush=True)
     assert abs(W - ref) <= 1e-4 * abs(ref)
+
+
+def test_npt_barostat_matches_oracle(gpu_lib):
+    """Stochastic cell rescaling fed by the outer step's virial estimator
+    (Methods, "Computation of the virial term in NPT"): six barostat steps,
+    each after two DMTS-NC outer steps, on the 192-atom workload.  Box edges
+    follow the oracle's within 1e-9 relative, positions within 2e-6 A."""
+    nnp = gpu_lib
+    s = synth.water_config(0)
+    masses = s.standard_masses()
+    gamma = np.ones(s.n)
+    cons_spec, nc_spec = synth.CONS_CFG0, synth.NC_CFG0
+    cw = synth.random_weights(cons_spec, 2000)
+    nw = synth.random_weights(nc_spec, 3000)
+    v0 = synth.maxwell_boltzmann(masses, 300.0, 5000)
+    system = nnp.DeviceSystem(s.pos, s.species, s.box)
+    prm = nnp.respa_params(2.0, 4, 300.0, seed=4000)
+    traj = nnp.Trajectory(nnp.Model.from_spec(cons_spec, cw), nnp.Model.from_spec(nc_spec, nw), system, v0,
+                          masses, gamma, prm, virial=True)
+    bp_gpu = nnp.barostat_params(1.0, 4.5e-5, 100.0, 4.0, 300.0, seed=6000)
+    boxes_gpu = []
+    for k in range(6):
+        traj.respa_step(2)
+        boxes_gpu.append(float(traj.barostat(bp_gpu, k)[0]))
+
+    box = {"L": s.box}
+
+    def lists(x, rc):
+        return onb.pairs_bruteforce(x, box["L"], rc)
+
+    def cons_fn(x):
+        return om.cons_energy_forces(cons_spec, cw, x, s.species, box["L"], *lists(x, cons_spec.cutoff))[1]
+
+    def nc_fn(x):
+        return om.nc_forces(nc_spec, nw, x, s.species, box["L"], *lists(x, nc_spec.cutoff))
+
+    def cons_vir(x):
+        return om.cons_virial(cons_spec, cw, x, s.species, box["L"], *lists(x, cons_spec.cutoff))
+
+    def nc_vir(x):
+        return om.nc_virial_proxy(nc_spec, nw, x, s.species, box["L"], *lists(x, nc_spec.cutoff))
+
+    st = oi.State(s.pos.copy(), v0.copy(), masses.copy())
+    p = oi.LangevinParams(2.0, 4, 300.0, gamma, seed=4000)
+    bp = oi.BarostatParams(1.0, 4.5e-5, 100.0, 4.0, 300.0, seed=6000)
+    boxes = []
+    for k in range(6):
+        for _ in range(2):
+            st, W = oi.dmts_nc_step_virial(st, cons_fn, nc_fn, p, cons_vir, nc_vir)
+        box["L"] = oi.scr_barostat_step(st, box["L"], W, bp, k)
+        boxes.append(box["L"])
+    print("boxes gpu", boxes_gpu, "oracle", boxes, flush=True)
+    assert abs(boxes[-1] / s.box - 1) > 1e-4          # the cell moved
+    np.testing.assert_allclose(boxes_gpu, boxes, rtol=1e-9, atol=0)
+    assert np.max(np.abs(traj.positions() - st.x)) <= 2e-6
+    assert np.max(np.abs(traj.velocities() - st.v)) <= 1e-5 * np.max(np.abs(st.v))

@@ -277,6 +277,42 @@ def test_nve_energy_error_is_second_order():
     assert 3.0 < f[0] / f[1] < 5.0 and 3.0 < f[1] / f[2] < 5.0
 
 
+def test_cell_rescaling_samples_ideal_gas_volume_law():
+    """Stochastic cell rescaling with the Langevin thermostat on an ideal gas
+    (zero force, W = 0) samples the isothermal-isobaric law
+    p(V) ~ V^N exp(-P V / k_B T): <V> = (N + 1) k_B T / P_0 and
+    var(V) = (N + 1) (k_B T / P_0)^2.  With N = 4 a k_B T / V drift term in
+    d eps would shift <V> by a quarter and a wrong velocity scaling by more."""
+    n, T = 4, 300.0
+    kT = oi.KB * T
+    bp = oi.BarostatParams(1000.0, 4.5e-4, 20.0, 2.0, T, seed=21)
+    unit = kT / (bp.pressure_bar * oi.BAR)
+    m = np.full(n, 16.0)
+    st = oi.State(np.zeros((n, 3)), synth.maxwell_boltzmann(m, T, 22), m)
+    prm = oi.LangevinParams(2.0, 1, T, np.full(n, 20.0), seed=23)
+    zero = lambda x: np.zeros_like(x)
+    box, vols = ((n + 1) * unit) ** (1.0 / 3.0), []
+    for step in range(20000):
+        oi.baoab_step(st, zero, prm)
+        box = oi.scr_barostat_step(st, box, 0.0, bp, step)
+        if step >= 500:
+            vols.append(box ** 3 / unit)
+    vols = np.array(vols)
+    assert abs(vols.mean() / (n + 1) - 1) < 0.05
+    assert abs(vols.var() / (n + 1) - 1) < 0.2
+
+
+def test_cell_rescaling_scales_positions_and_velocities_oppositely():
+    st = _state(6, 41)
+    x0, v0 = st.x.copy(), st.v.copy()
+    bp = oi.BarostatParams(1.0, 4.5e-5, 100.0, 4.0, 300.0, seed=5)
+    box = oi.scr_barostat_step(st, 20.0, -35.0, bp, 3)
+    mu = box / 20.0
+    assert mu != 1.0 and st.first_step
+    np.testing.assert_allclose(st.x, x0 * mu, rtol=1e-15)
+    np.testing.assert_allclose(st.v, v0 / mu, rtol=1e-15)
+
+
 # -------------------------------------------------------------- HMR/friction --
 
 def test_hmr_keeps_molecule_mass():
