@@ -386,8 +386,15 @@ nnp_status nnp_barostat_scr(respa_state* state, const nnp_barostat_params* param
  * device footprint fits the HBM budget, advanced together in fused launches
  * (one packed system, block-diagonal neighbour lists, per-replica boxes,
  * Philox keys and step counters), and retired when they reach their step
- * count.  All their state stays on the device while resident.  Results do
- * not depend on which other replicas share the launches. */
+ * count.  The budget is reserved once at creation; it holds two banks of
+ * packed state, a staging bank for admissions, and the lists and scratch of
+ * the resident set.  An admitted replica is uploaded once, its lists built
+ * and F and F_NC evaluated in the staging bank; when the resident set
+ * changes, a gather kernel moves the resident replicas (with their cached
+ * forces) and the admitted ones into the other bank, so resident state
+ * never leaves the device and nothing is evaluated twice; only a retiring
+ * replica's final state is copied to the host.  Results do not depend on
+ * which other replicas share the launches. */
 typedef struct nnp_server nnp_server;
 
 nnp_status nnp_server_create(const nnp_model* cons, const nnp_model* nc,
@@ -426,12 +433,18 @@ nnp_status replica_submit(nnp_server* server, const replica_desc* desc, uint64_t
  * NULL) receive the final state. */
 nnp_status replica_poll(nnp_server* server, uint64_t ticket, replica_status* out,
                         double* pos_out, double* vel_out);
-/* Runs up to max_outer_steps fused outer steps, admitting and retiring at
- * each boundary; returns after the first step boundary at which nothing is
- * resident or queued.  *n_resident receives the resident count. */
+/* Advances the resident set by up to max_outer_steps outer steps.  A
+ * boundary (retirement, admission, repacking) comes at the start of the
+ * call and whenever a resident replica reaches its step count; between
+ * boundaries the steps run as one integrator call (recorded outer steps
+ * replayed as a graph, one status check at its end), so the step count of
+ * a call bounds the wait of replicas queued meanwhile.  Returns early when
+ * nothing is resident.  *n_resident receives the resident count. */
 nnp_status nnp_server_progress(nnp_server* server, int32_t max_outer_steps, int32_t* n_resident);
 /* Copies up to cap per-replica step latencies (seconds between consecutive
- * outer-step completions of a replica; the first from its admission). */
+ * outer-step completions of a replica, the first from its admission, on the
+ * device's constant-rate wall clock: every outer step ends with a
+ * timestamp). */
 nnp_status nnp_server_step_latencies(nnp_server* server, double* out, int64_t cap, int64_t* n_out);
 /* Device bytes that one replica of n atoms in a box of edge `box` occupies
  * when resident alone (state, neighbour lists and scratch); a resident set

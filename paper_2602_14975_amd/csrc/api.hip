@@ -1022,7 +1022,7 @@ constexpr nnp_status NNP_EREWIND_INTERNAL = static_cast<nnp_status>(-101);
 
 nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const respa_params* p, int32_t n_outer,
                      void* ws, size_t ws_bytes, hipStream_t s, const uint64_t* seeds, const uint64_t* streams,
-                     const uint64_t* step_base, int* rep_bad) {
+                     const uint64_t* step_base, int* rep_bad, uint64_t* stamps) {
     check_respa(st, p, cons, nc);
     check_system(&st->sys);
     NNP_REQUIRE(n_outer >= 0, NNP_EINVAL, "n_outer must be >= 0");
@@ -1173,6 +1173,11 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         return NNP_OK;
     };
 
+    // work at entry that can fail (a list build, the first evaluation) is
+    // checked before the first step; a call that starts from valid lists and
+    // cached forces goes straight on
+    bool entry_work = false;
+    const bool built_at_entry = !st->lists_valid;
     if (!st->lists_valid) {
         // empty rows until the first build succeeds, so a failed build never
         // leaves uninitialised offsets behind
@@ -1181,13 +1186,15 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         launch_set_flag(trig, 1, s);
         rebuild_if_flagged();
         st->lists_valid = 1;
+        entry_work = true;
     }
     if (st->first_step) {
         if (mts) eval_inner();
         eval_cons();
         st->first_step = 0;
+        entry_work = true;
     }
-    {
+    if (entry_work) {
         nnp_status e = check(0, false);
         if (e != NNP_OK) return e;
     }
@@ -1315,10 +1322,11 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     // strict mode
     const bool predictive = mts && n_in > 1;
     const bool use_graph = predictive && p->graph != 0 && n_outer >= 3 && !timers_active();
-    if (predictive) {
-        // the displacement record starts empty: begin from fresh lists
-        launch_set_flag(trig, 1, s);
-        rebuild_if_flagged();
+    if (predictive && !built_at_entry) {
+        // lists from an earlier call: rebuild the displacement record from
+        // pos_ref, taking its growth over the previous outer step to be all
+        // of it (an over-estimate: at worst an early rebuild)
+        launch_disp_record(n, st->pos, st->pos_ref, maxd2, s);
     }
     uint64_t snap_offset = 0;
     int snap_o = 0, strict_until = 0, snap_since_save = 0;
@@ -1343,6 +1351,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         ++since_save;
         launch_kinetic(R, c.t.rep_start, n, st->pos, st->vel, st->mass, st->ke ? st->ke + int64_t(o) * R : nullptr,
                        c.t.rep_bad, s, st->sys.rep_of_atom);
+        if (stamps) launch_stamp(stamps + o, s);
         if ((o + 1) % check_every == 0 || o + 1 == n_outer) {
             nnp_status e = check(snap_offset, true);
             if (e == NNP_ESTALE_INTERNAL || e == NNP_EREWIND_INTERNAL) {

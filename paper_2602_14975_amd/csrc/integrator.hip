@@ -123,6 +123,39 @@ __global__ void k_baoa(BaoaArgs a) {
     }
 }
 
+// Largest squared displacement since the last list build, into the record
+// that k_baoa keeps (for calls that start with valid lists).
+__global__ void k_disp_record(int n, const double* __restrict__ pos, const double* __restrict__ pos_ref,
+                              unsigned* __restrict__ maxd2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    float dmax = 0.f;
+    if (i < n) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double d = pos[c * n + i] - pos_ref[c * n + i];
+            d2 += d * d;
+        }
+        dmax = !(d2 <= 3.0e38) ? 3.0e38f : float(d2);
+    }
+    for (int o = 32; o > 0; o >>= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(maxd2, __float_as_uint(dmax));
+}
+
+__global__ void k_stamp(uint64_t* out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out = uint64_t(wall_clock64());
+}
+
+void launch_disp_record(int n, const double* pos, const double* pos_ref, unsigned* maxd2, hipStream_t s) {
+    if (n > 0) k_disp_record<<<cdiv(n, 256), 256, 0, s>>>(n, pos, pos_ref, maxd2);
+    NNP_LAUNCH_CHECK();
+}
+
+void launch_stamp(uint64_t* out, hipStream_t s) {
+    k_stamp<<<1, 64, 0, s>>>(out);
+    NNP_LAUNCH_CHECK();
+}
+
 // Per-replica kinetic energy (fixed-order float64 reduction, one block per
 // replica) and a per-replica finiteness flag of positions and velocities.
 __global__ void __launch_bounds__(256) k_kinetic(const int64_t* __restrict__ rep_start, int n,

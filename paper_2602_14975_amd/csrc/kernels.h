@@ -185,6 +185,9 @@ struct BaoaArgs {
 void launch_kick(int n, double* vel, const double* mass, const float* Fa, const float* Fb, double half_dt,
                  hipStream_t s, uint64_t* bump = nullptr, uint64_t bump_by = 1);
 void launch_set_u64(uint64_t* p, uint64_t value, hipStream_t s);
+void launch_disp_record(int n, const double* pos, const double* pos_ref, unsigned* maxd2, hipStream_t s);
+// device wall-clock ticks (hipDeviceAttributeWallClockRate) written once the stream reaches it
+void launch_stamp(uint64_t* out, hipStream_t s);
 // zero fill as a kernel (safe inside recorded graphs); with `run`, only when *run != 0
 void launch_zero(void* p, int64_t words, const int* run, hipStream_t s);
 void launch_virial_combine(int n, const float* wc, const float* wl, const float* ws, float inv_n, float* out,

@@ -107,7 +107,7 @@ size_t call_scratch_bytes(const Model* cons, const Model* nc, int64_t n, int32_t
 void check_system(const nnp_system* sys);
 nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const respa_params* p, int32_t n_outer,
                      void* ws, size_t ws_bytes, hipStream_t s, const uint64_t* seeds, const uint64_t* streams,
-                     const uint64_t* step_base, int* rep_bad);
+                     const uint64_t* step_base, int* rep_bad, uint64_t* stamps = nullptr);
 void launch_split_filter_grad(int rows, int K, const float* sum, float* dWr, float* dbr, hipStream_t s);
 
 }  // namespace nnp

@@ -69,30 +69,60 @@ class Server:
             self.h = None
 
 
-def run(server, replicas, arrivals, n_steps, dt_fs, vel_seed_base=5000, gamma_fn=None, mass_fn=None):
-    """Submits replica k at server time arrivals[k] (seconds after start)
-    while driving the server one outer step at a time.  Returns a report."""
+def _submit_replica(server, r, k, n_steps, vel_seed_base, gamma_fn, mass_fn):
     import synth
+    m = mass_fn(r) if mass_fn else r.standard_masses()
+    g = gamma_fn(r) if gamma_fn else np.ones(r.n)
+    v = synth.maxwell_boltzmann(m, 300.0, vel_seed_base + k)
+    return server.replica_submit(r.pos, v, m, g, r.species, r.box, 4000 + k, k, n_steps)
+
+
+def saturated_rate(server, replicas, n_steps, steps_per_call=4, vel_seed_base=5000):
+    """Closed-loop throughput: every replica submitted at once, the server
+    driven until all are done.  Returns atom-steps per second (the whole
+    run, including the tail where the queue has emptied)."""
+    t0 = server.clock()
+    tickets = [_submit_replica(server, r, k, n_steps, vel_seed_base, None, None) for k, r in enumerate(replicas)]
+    while server.progress(steps_per_call) > 0:
+        pass
+    wall = server.clock() - t0
+    states = [server.replica_poll(t)[0] for t in tickets]
+    atom_steps = sum(st.steps_done * r.n for st, r in zip(states, replicas))
+    return atom_steps / wall, wall
+
+
+def run(server, replicas, arrivals, n_steps, dt_fs, steps_per_call=2, vel_seed_base=5000, gamma_fn=None,
+        mass_fn=None, log=None, log_every_s=15.0):
+    """Submits replica k at server time arrivals[k] (seconds after start)
+    while driving the server `steps_per_call` outer steps per call (each call
+    ends at a boundary, where waiting replicas are admitted).  `log`, when
+    given, receives a status line every log_every_s seconds.  Returns a
+    report."""
     order = np.argsort(arrivals)
     t0 = server.clock()
     tickets = {}
     nxt = 0
     n_total = len(replicas)
+    resident_time, last_t, max_res = 0.0, 0.0, 0
+    next_log = log_every_s
     while True:
         now = server.clock() - t0
         while nxt < n_total and arrivals[order[nxt]] <= now:
             k = int(order[nxt])
-            r = replicas[k]
-            m = mass_fn(r) if mass_fn else r.standard_masses()
-            g = gamma_fn(r) if gamma_fn else np.ones(r.n)
-            v = synth.maxwell_boltzmann(m, 300.0, vel_seed_base + k)
-            tickets[k] = server.replica_submit(r.pos, v, m, g, r.species, r.box, 4000 + k, k, n_steps)
+            tickets[k] = _submit_replica(server, replicas[k], k, n_steps, vel_seed_base, gamma_fn, mass_fn)
             nxt += 1
-        nres = server.progress(1)
+        nres = server.progress(steps_per_call)
+        t = server.clock() - t0
+        resident_time += nres * (t - last_t)
+        last_t = t
+        max_res = max(max_res, nres)
+        if log and t >= next_log:
+            log(f"serving: t = {t:.0f} s, {nxt} of {n_total} submitted, {nres} resident")
+            next_log += log_every_s
         if nres == 0:
             if nxt >= n_total:
                 # every replica submitted; finished when all are done
-                done = all(server.replica_poll(t)[0].state in (2, 3) for t in tickets.values())
+                done = all(server.replica_poll(tk)[0].state in (2, 3) for tk in tickets.values())
                 if done:
                     break
             else:
@@ -110,4 +140,6 @@ def run(server, replicas, arrivals, n_steps, dt_fs, vel_seed_base=5000, gamma_fn
         "latency_p50_ms": float(np.percentile(lat, 50) * 1e3), "latency_p99_ms": float(np.percentile(lat, 99) * 1e3),
         "latency_samples": int(lat.size), "queue_delay_mean_s": float(queue.mean()),
         "queue_delay_p99_s": float(np.percentile(queue, 99)),
+        "replicas_waiting_over_1s": int((queue > 1.0).sum()),
+        "resident_mean": resident_time / max(wall, 1e-9), "resident_max": int(max_res),
     }
