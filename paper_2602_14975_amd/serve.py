@@ -78,15 +78,19 @@ def _submit_replica(server, r, k, n_steps, vel_seed_base, gamma_fn, mass_fn):
 
 
 def saturated_rate(server, replicas, n_steps, steps_per_call=4, vel_seed_base=5000):
-    """Closed-loop throughput: every replica submitted at once, the server
-    driven until all are done.  Returns atom-steps per second (the whole
-    run, including the tail where the queue has emptied)."""
+    """Closed-loop throughput: every replica submitted at once and the server
+    driven while some still wait for admission, i.e. while the budget (or
+    the slots) hold the resident set at its limit.  Returns (atom-steps per
+    second over that interval, its length in seconds); replicas still
+    resident at its end are left to the caller (destroy the server)."""
     t0 = server.clock()
     tickets = [_submit_replica(server, r, k, n_steps, vel_seed_base, None, None) for k, r in enumerate(replicas)]
-    while server.progress(steps_per_call) > 0:
-        pass
+    while True:
+        nres = server.progress(steps_per_call)
+        states = [server.replica_poll(t)[0] for t in tickets]
+        if nres == 0 or all(st.state != 0 for st in states):
+            break
     wall = server.clock() - t0
-    states = [server.replica_poll(t)[0] for t in tickets]
     atom_steps = sum(st.steps_done * r.n for st, r in zip(states, replicas))
     return atom_steps / wall, wall
 
