@@ -99,6 +99,13 @@ __device__ __forceinline__ void load_filter(const float* Wr, const float* br, fl
 
 __device__ __forceinline__ half8_t as_half8(const uint4& u) { return __builtin_bit_cast(half8_t, u); }
 
+// A float at a 32-bit byte offset from a wavefront-uniform base: the
+// neighbour-row gathers then take one 32-bit multiply-add per edge for
+// their address, and the quantities of a row differ by immediate offsets.
+__device__ __forceinline__ float ld_off(const float* base, uint32_t byte_off) {
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
 // ---------------------------------------------------------- edge preparation
 
 __global__ void __launch_bounds__(256, 3) k_edge_prep(MpGeom mg, int* __restrict__ ecnt, EdgeRec* __restrict__ erec,
@@ -236,23 +243,28 @@ __device__ __forceinline__ void fwd_batch(const MpFwd& a, const float* ptab, con
     floatx16_t wb = {};
     if (!L0) wb = mma3(ah, al, bh[1], bl[1]);  // the first layer's vector input is zero
     const floatx16_t wc = mma3(ah, al, bh[2], bl[2]);
+    const uint32_t fo = uint32_t(f) * 4u;
 #pragma unroll
     for (int g0 = 0; g0 < E; g0 += kFwdGroup) {
-        // the b channel enters only as phi_b v_j, read as one product
+        // the b channel enters only as phi_b v_j, read as one product; rows
+        // of phi and pv are 3F floats: one byte offset per edge serves both
         float pa[kFwdGroup], pc[kFwdGroup], pv[kFwdGroup][3];
 #pragma unroll
         for (int g = 0; g < kFwdGroup; ++g) {
             const int q = g0 + g;
             const int te = 8 * (q / 4) + 4 * h + q % 4;
             const EdgeRec& s = rec[te < nb ? te : 0];
-            const float* phj = L0 ? ptab + s.t * 3 * F + f : a.phi + int64_t(s.j) * 3 * F + f;
-            pa[g] = phj[0];
-            pc[g] = phj[2 * F];
-            if (!L0) {
-                const float* v = a.pv + int64_t(s.j) * 3 * F + f;
-                pv[g][0] = v[0];
-                pv[g][1] = v[F];
-                pv[g][2] = v[2 * F];
+            if (L0) {
+                const float* phj = ptab + s.t * 3 * F + f;
+                pa[g] = phj[0];
+                pc[g] = phj[2 * F];
+            } else {
+                const uint32_t off = uint32_t(s.j) * (3u * F * 4u) + fo;
+                pa[g] = ld_off(a.phi, off);
+                pc[g] = ld_off(a.phi, off + 2 * F * 4);
+                pv[g][0] = ld_off(a.pv, off);
+                pv[g][1] = ld_off(a.pv, off + F * 4);
+                pv[g][2] = ld_off(a.pv, off + 2 * F * 4);
             }
         }
 #pragma unroll
@@ -267,14 +279,14 @@ __device__ __forceinline__ void fwd_batch(const MpFwd& a, const float* ptab, con
             const float c = pc[g] * w_c;
             acc.s = fmaf(pa[g], w_a, acc.s);
             if (L0) {
-                acc.v[0] += s.u[0] * c;
-                acc.v[1] += s.u[1] * c;
-                acc.v[2] += s.u[2] * c;
+                acc.v[0] = fmaf(s.u[0], c, acc.v[0]);
+                acc.v[1] = fmaf(s.u[1], c, acc.v[1]);
+                acc.v[2] = fmaf(s.u[2], c, acc.v[2]);
             } else {
                 const float b = fmaf(bb[1], fc, wb[q]);
-                acc.v[0] += b * pv[g][0] + s.u[0] * c;
-                acc.v[1] += b * pv[g][1] + s.u[1] * c;
-                acc.v[2] += b * pv[g][2] + s.u[2] * c;
+                acc.v[0] = fmaf(s.u[0], c, fmaf(b, pv[g][0], acc.v[0]));
+                acc.v[1] = fmaf(s.u[1], c, fmaf(b, pv[g][1], acc.v[1]));
+                acc.v[2] = fmaf(s.u[2], c, fmaf(b, pv[g][2], acc.v[2]));
             }
         }
     }
@@ -338,8 +350,16 @@ struct Owner {
     float ph[3], v[3], gs, gv[3];
 };
 
+// Per-lane sums of the reverse over the lane's edges (feature f):
+//   gph0 = sum gs_n w_a,  gph2 = -sum w_c (g_vn . u),  GV = sum w_b g_vn
+//   (phi_b adjoint o.v . GV and v adjoint o.ph_b GV at the end),
+// and the lane's share of the force on the owner,
+//   sum_e [dr u + (g_u - (g_u . u) u) / r]
+//     = S1 + o.gv T1 - o.ph_c T2,  g_u = pc w_c o.gv - o.ph_c w_c g_vn,
+//   S1 = sum (dr - (g_u . u) / r) u,  T1 = sum pc w_c / r,  T2 = sum w_c g_vn / r,
+// which keeps the owner's factors out of the per-edge work.
 struct BwdAcc {
-    float gph[3], gv[3], fx, fy, fz, vir;
+    float gph0, gph2, GV[3], S1[3], T1, T2[3], vir;
 };
 
 // One batch of nb <= 16 edges; the lane's eight edges are taken kBwdGroup at
@@ -359,32 +379,36 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
     floatx16_t m1 = {};
     if constexpr (!L0) m1 = mma3(ah, al, bh[1], bl[1]);
     const floatx16_t m2 = mma3(ah, al, bh[2], bl[2]);
+    const uint32_t fo = uint32_t(f) * 4u;
 #pragma unroll
     for (int g0 = 0; g0 < E; g0 += kBwdGroup<L0>) {
         constexpr int G = kBwdGroup<L0>;
-        // phi_b of the neighbour enters only as phi_b v_n, read as one product
+        // phi_b of the neighbour enters only as phi_b v_n, read as one
+        // product; phi, pv and the vector adjoints have rows of 3F floats
+        // (one byte offset per edge), the scalar adjoints rows of F
         float pa[G], pc[G], pvn[G][3], gn[G][3], gsn[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int q = g0 + g;
             const int te = 8 * (q / 4) + 4 * h + q % 4;
             const EdgeRec& s = rec[te < nb ? te : 0];
-            const int j = s.j;
-            const float* phj = L0 ? ptab + s.t * 3 * F + f : a.phi + int64_t(j) * 3 * F + f;
-            pa[g] = phj[0];
-            pc[g] = phj[2 * F];
-            pvn[g][0] = pvn[g][1] = pvn[g][2] = 0.f;
-            if (!L0) {  // the first layer's vector input is zero
-                const float* v = a.pv + int64_t(j) * 3 * F + f;
-                pvn[g][0] = v[0];
-                pvn[g][1] = v[F];
-                pvn[g][2] = v[2 * F];
+            const uint32_t j = uint32_t(s.j);
+            const uint32_t off3 = j * (3u * F * 4u) + fo;
+            if (L0) {
+                const float* phj = ptab + s.t * 3 * F + f;
+                pa[g] = phj[0];
+                pc[g] = phj[2 * F];
+            } else {
+                pa[g] = ld_off(a.phi, off3);
+                pc[g] = ld_off(a.phi, off3 + 2 * F * 4);
+                pvn[g][0] = ld_off(a.pv, off3);
+                pvn[g][1] = ld_off(a.pv, off3 + F * 4);
+                pvn[g][2] = ld_off(a.pv, off3 + 2 * F * 4);
             }
-            const float* gp = a.gvm + int64_t(j) * 3 * F + f;
-            gn[g][0] = gp[0];
-            gn[g][1] = gp[F];
-            gn[g][2] = gp[2 * F];
-            gsn[g] = a.gsm[int64_t(j) * F + f];
+            gn[g][0] = ld_off(a.gvm, off3);
+            gn[g][1] = ld_off(a.gvm, off3 + F * 4);
+            gn[g][2] = ld_off(a.gvm, off3 + 2 * F * 4);
+            gsn[g] = ld_off(a.gsm, j * (F * 4u) + fo);
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -393,44 +417,47 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
             if (te >= nb) continue;
             const EdgeRec& s = rec[te];
             // w of edge te is row te, dw/dr row 16 + te: accumulator elements q and 8 + q
-            const float fc = s.fc, dfc = s.dfc;
-            const float w[3] = {fmaf(bb[0], fc, m0[q]), fmaf(bb[1], fc, m1[q]), fmaf(bb[2], fc, m2[q])};
-            const float dw[3] = {fmaf(bb[0], dfc, m0[8 + q]), fmaf(bb[1], dfc, m1[8 + q]),
-                                 fmaf(bb[2], dfc, m2[8 + q])};
+            const float fc = s.fc, dfc = s.dfc, ir = s.ir;
+            const float w0 = fmaf(bb[0], fc, m0[q]), w2 = fmaf(bb[2], fc, m2[q]);
+            const float dw0 = fmaf(bb[0], dfc, m0[8 + q]), dw2 = fmaf(bb[2], dfc, m2[8 + q]);
             const float u0 = s.u[0], u1 = s.u[1], u2 = s.u[2];
             const float g0v = gn[g][0], g1v = gn[g][1], g2v = gn[g][2];
-            // projections shared by several terms
-            const float gvo_pvn = o.gv[0] * pvn[g][0] + o.gv[1] * pvn[g][1] + o.gv[2] * pvn[g][2];
-            const float gvo_u = o.gv[0] * u0 + o.gv[1] * u1 + o.gv[2] * u2;
-            const float gvn_vo = g0v * o.v[0] + g1v * o.v[1] + g2v * o.v[2];
-            const float gvn_u = g0v * u0 + g1v * u1 + g2v * u2;
-            // message n -> o and message o -> n (unit vector -u): filter adjoints
-            const float gwa = o.gs * pa[g], gwb = gvo_pvn, gwc = pc[g] * gvo_u;
-            const float gwa2 = gsn[g] * o.ph[0], gwb2 = o.ph[1] * gvn_vo, gwc2 = -o.ph[2] * gvn_u;
-            const float dr = L0 ? (gwa + gwa2) * dw[0] + (gwc + gwc2) * dw[2]
-                                : (gwa + gwa2) * dw[0] + (gwb + gwb2) * dw[1] + (gwc + gwc2) * dw[2];
-            // adjoints of the unit vectors of the two messages
-            const float cA = pc[g] * w[2], cB = o.ph[2] * w[2];
-            const float gu0 = o.gv[0] * cA - g0v * cB;
-            const float gu1 = o.gv[1] * cA - g1v * cB;
-            const float gu2 = o.gv[2] * cA - g2v * cB;
-            // o as the sender of the message o -> n
-            acc.gph[0] = fmaf(gsn[g], w[0], acc.gph[0]);
-            if constexpr (!L0) acc.gph[1] = fmaf(w[1], gvn_vo, acc.gph[1]);
-            acc.gph[2] = fmaf(-w[2], gvn_u, acc.gph[2]);
-            if constexpr (!L0) {  // the first layer writes no adjoint of its (zero) vector input
-                const float wbp = w[1] * o.ph[1];
-                acc.gv[0] = fmaf(g0v, wbp, acc.gv[0]);
-                acc.gv[1] = fmaf(g1v, wbp, acc.gv[1]);
-                acc.gv[2] = fmaf(g2v, wbp, acc.gv[2]);
+            const float gvn_u = fmaf(g2v, u2, fmaf(g1v, u1, g0v * u0));
+            const float gvo_u = fmaf(o.gv[2], u2, fmaf(o.gv[1], u1, o.gv[0] * u0));
+            // filter adjoints of both messages of the pair (n -> o and o -> n),
+            // contracted with dw/dr
+            const float A = fmaf(o.gs, pa[g], o.ph[0] * gsn[g]);
+            const float C = fmaf(pc[g], gvo_u, -(o.ph[2] * gvn_u));
+            float dr;
+            if constexpr (L0) {
+                dr = fmaf(A, dw0, C * dw2);
+            } else {
+                const float w1 = fmaf(bb[1], fc, m1[q]), dw1 = fmaf(bb[1], dfc, m1[8 + q]);
+                const float gvn_vo = fmaf(g2v, o.v[2], fmaf(g1v, o.v[1], g0v * o.v[0]));
+                const float gvo_pvn = fmaf(o.gv[2], pvn[g][2], fmaf(o.gv[1], pvn[g][1], o.gv[0] * pvn[g][0]));
+                const float B = fmaf(o.ph[1], gvn_vo, gvo_pvn);
+                dr = fmaf(A, dw0, fmaf(B, dw1, C * dw2));
+                acc.GV[0] = fmaf(w1, g0v, acc.GV[0]);
+                acc.GV[1] = fmaf(w1, g1v, acc.GV[1]);
+                acc.GV[2] = fmaf(w1, g2v, acc.GV[2]);
             }
-            // this lane's share of (d_A + d_A') u + P(g_uA - g_uA') / r
-            const float ud = gu0 * u0 + gu1 * u1 + gu2 * u2;
-            acc.fx += dr * u0 + (gu0 - ud * u0) * s.ir;
-            acc.fy += dr * u1 + (gu1 - ud * u1) * s.ir;
-            acc.fz += dr * u2 + (gu2 - ud * u2) * s.ir;
+            // g_u . u of the unit-vector adjoints, from the projections above
+            const float cA = pc[g] * w2;
+            const float ud = fmaf(cA, gvo_u, -((o.ph[2] * w2) * gvn_u));
+            const float sv = fmaf(-ud, ir, dr);
+            acc.S1[0] = fmaf(sv, u0, acc.S1[0]);
+            acc.S1[1] = fmaf(sv, u1, acc.S1[1]);
+            acc.S1[2] = fmaf(sv, u2, acc.S1[2]);
+            acc.T1 = fmaf(cA, ir, acc.T1);
+            const float w2ir = w2 * ir;
+            acc.T2[0] = fmaf(w2ir, g0v, acc.T2[0]);
+            acc.T2[1] = fmaf(w2ir, g1v, acc.T2[1]);
+            acc.T2[2] = fmaf(w2ir, g2v, acc.T2[2]);
+            // o as the sender of the message o -> n
+            acc.gph0 = fmaf(gsn[g], w0, acc.gph0);
+            acc.gph2 = fmaf(-w2, gvn_u, acc.gph2);
             // r_ij . (pair force share): the projected term is normal to u
-            if constexpr (VIR) acc.vir += __fdividef(dr, s.ir);
+            if constexpr (VIR) acc.vir += __fdividef(dr, ir);
         }
     }
 }
@@ -485,13 +512,18 @@ __global__ void __launch_bounds__(64 * kMxWaves, 3) k_message_bwd_mx(MpGeom mg, 
             piece = fetch_piece<BATCH>(mg, nx.p0, nx.nb);
             bwd_batch<L0, VIR>(a, ptab_s, b, min(BATCH, cnt - b0), f, h, bh, bl, bb, o, acc);
         }
-        // both halves of the wavefront hold partial sums of feature f
+        // the lane's force share, then both halves of the wavefront (partial
+        // sums of feature f) and the features of the wavefront
+        float fs[3];
 #pragma unroll
-        for (int p = 0; p < 3; ++p) {
-            acc.gph[p] += __shfl_xor(acc.gph[p], 32, 64);
-            acc.gv[p] += __shfl_xor(acc.gv[p], 32, 64);
-        }
-        const float fx = group_sum<64>(acc.fx), fy = group_sum<64>(acc.fy), fz = group_sum<64>(acc.fz);
+        for (int al = 0; al < 3; ++al) fs[al] = fmaf(o.gv[al], acc.T1, fmaf(-o.ph[2], acc.T2[al], acc.S1[al]));
+        acc.gph0 += __shfl_xor(acc.gph0, 32, 64);
+        acc.gph2 += __shfl_xor(acc.gph2, 32, 64);
+#pragma unroll
+        for (int p = 0; p < 3; ++p) acc.GV[p] += __shfl_xor(acc.GV[p], 32, 64);
+        const float gph[3] = {acc.gph0, fmaf(o.v[2], acc.GV[2], fmaf(o.v[1], acc.GV[1], o.v[0] * acc.GV[0])),
+                              acc.gph2};
+        const float fx = group_sum<64>(fs[0]), fy = group_sum<64>(fs[1]), fz = group_sum<64>(fs[2]);
         const float vr = VIR ? group_sum<64>(acc.vir) : 0.f;
         if (lane == 0) {
             fpart[ai][w][0] = fx;
@@ -502,13 +534,13 @@ __global__ void __launch_bounds__(64 * kMxWaves, 3) k_message_bwd_mx(MpGeom mg, 
         if (h == 0) {
             if (a.want_gphi) {
 #pragma unroll
-                for (int p = 0; p < 3; ++p) a.gphi[int64_t(i) * 3 * F + p * F + f] = acc.gph[p] * isc;
+                for (int p = 0; p < 3; ++p) a.gphi[int64_t(i) * 3 * F + p * F + f] = gph[p] * isc;
             }
             if (!L0) {
 #pragma unroll
                 for (int al = 0; al < 3; ++al) {
                     const int64_t idx = (int64_t(i) * 3 + al) * F + f;
-                    a.gv_in[idx] = o.gv[al] + acc.gv[al] * isc;
+                    a.gv_in[idx] = o.gv[al] + (o.ph[1] * acc.GV[al]) * isc;
                 }
             }
         }
