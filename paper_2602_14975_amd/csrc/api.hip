@@ -323,7 +323,7 @@ void Model::refresh_tables(hipStream_t s) {
     };
     for (int l = 0; l < n_layers(); ++l) {
         const LayerOff& ll = loff[l];
-        launch_filter_scale(3 * F * desc.n_rbf, p(ll.Wr), mxs + 2 * l, s);
+        launch_filter_scale(3 * F * (desc.n_rbf + 1), p(ll.Wr), mxs + 2 * l, s);  // Wr, then br
         tr(ll.W1, F, F);
         tr(ll.W2, 3 * F, F);
         tr(ll.U, 2 * F, F);

@@ -45,6 +45,7 @@ namespace nnp {
 namespace {
 
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef float floatx16_t __attribute__((ext_vector_type(16)));
 
 constexpr int kMxF = 128, kMxK = 16, kMxWaves = 4, kMxAtoms = 4;
@@ -66,10 +67,13 @@ __device__ __forceinline__ void split8(const float* x, half8_t& hi, half8_t& lo)
     }
 }
 
-// A (32 x 16) times B (16 x 32) from the split operands: small terms first
-__device__ __forceinline__ floatx16_t mma3(const half8_t& ah, const half8_t& al, const half8_t& bh,
-                                           const half8_t& bl) {
+// The bias product (rows ab, bias operand bb), then A (32 x 16) times
+// B (16 x 32) from the split operands, small terms first
+template <bool BIAS = true>
+__device__ __forceinline__ floatx16_t mma3(const half4_t& ab, const half4_t& bb, const half8_t& ah,
+                                           const half8_t& al, const half8_t& bh, const half8_t& bl) {
     floatx16_t c = {};
+    if constexpr (BIAS) c = __builtin_amdgcn_mfma_f32_32x32x8f16(ab, bb, c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh, c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl, c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, c, 0, 0, 0);
@@ -84,17 +88,43 @@ __device__ __forceinline__ void load8(const float* p, float* x) {
 }
 
 // This lane's B fragments: rows 8h..8h+7 of column f of the scaled filter
-// weights of each channel, split, and the scaled biases.
+// weights of each channel, split; and the bias operand of each channel (a
+// 32x32x8 product): rows 0..2 of column f hold (b_hi, b_hi, b_lo) of the
+// scaled bias, the other rows zero, so that with A rows (c_hi, c_lo, c_hi,
+// 0, ...) of a per-edge factor c one product gives c b at FP32-equivalent
+// precision.
 __device__ __forceinline__ void load_filter(const float* Wr, const float* br, float sc, int f, int h, half8_t* bh,
-                                            half8_t* bl, float* bb) {
+                                            half8_t* bl, half4_t* bb) {
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
         float x[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) x[q] = Wr[(p * kMxF + f) * kMxK + 8 * h + q] * sc;
         split8(x, bh[p], bl[p]);
-        bb[p] = br[p * kMxF + f] * sc;
+        const float b = br[p * kMxF + f] * sc;
+        const _Float16 b_hi = static_cast<_Float16>(b);
+        const _Float16 b_lo = static_cast<_Float16>(b - static_cast<float>(b_hi));
+        bb[p] = half4_t{};
+        if (h == 0) {
+            bb[p][0] = b_hi;
+            bb[p][1] = b_hi;
+            bb[p][2] = b_lo;
+        }
     }
+}
+
+// The A operand of the bias product for a row whose per-edge factor is c
+// (the cutoff f or its derivative): (c_hi, c_lo, c_hi, 0, ...) in the lanes
+// of the first half, zero in the second.
+__device__ __forceinline__ half4_t bias_rows(float c, int h) {
+    half4_t a = {};
+    if (h == 0) {
+        const _Float16 c_hi = static_cast<_Float16>(c);
+        a[0] = c_hi;
+        a[1] = static_cast<_Float16>(c - static_cast<float>(c_hi));
+        a[2] = c_hi;
+    }
+    return a;
 }
 
 __device__ __forceinline__ half8_t as_half8(const uint4& u) { return __builtin_bit_cast(half8_t, u); }
@@ -233,16 +263,18 @@ struct FwdAcc {
 // of a partial batch reads the batch's first edge and contributes nothing).
 template <bool L0>
 __device__ __forceinline__ void fwd_batch(const MpFwd& a, const float* ptab, const BatchBuf<32>& buf, int nb, int f,
-                                          int h, const half8_t* bh, const half8_t* bl, const float* bb,
+                                          int h, const half8_t* bh, const half8_t* bl, const half4_t* bb,
                                           FwdAcc& acc) {
     constexpr int F = kMxF, E = 16;
     const EdgeRec* rec = buf.rec;
-    const int r = threadIdx.x & 31;  // A row: edge r (zero past nb)
+    const int r = threadIdx.x & 31;  // A row: edge r (zero past nb: staged as zeros)
     const half8_t ah = as_half8(buf.a[r][h]), al = as_half8(buf.a[r][2 + h]);
-    const floatx16_t wa = mma3(ah, al, bh[0], bl[0]);
+    const half4_t ab = bias_rows(rec[r].fc, h);
+    // w = Wr (e f) + b f of every channel
+    const floatx16_t wa = mma3(ab, bb[0], ah, al, bh[0], bl[0]);
     floatx16_t wb = {};
-    if (!L0) wb = mma3(ah, al, bh[1], bl[1]);  // the first layer's vector input is zero
-    const floatx16_t wc = mma3(ah, al, bh[2], bl[2]);
+    if (!L0) wb = mma3(ab, bb[1], ah, al, bh[1], bl[1]);  // the first layer's vector input is zero
+    const floatx16_t wc = mma3(ab, bb[2], ah, al, bh[2], bl[2]);
     const uint32_t fo = uint32_t(f) * 4u;
 #pragma unroll
     for (int g0 = 0; g0 < E; g0 += kFwdGroup) {
@@ -273,17 +305,15 @@ __device__ __forceinline__ void fwd_batch(const MpFwd& a, const float* ptab, con
             const int te = 8 * (q / 4) + 4 * h + q % 4;
             if (te >= nb) continue;
             const EdgeRec& s = rec[te];
-            const float fc = s.fc;
-            const float w_a = fmaf(bb[0], fc, wa[q]);
-            const float w_c = fmaf(bb[2], fc, wc[q]);
-            const float c = pc[g] * w_c;
+            const float w_a = wa[q];
+            const float c = pc[g] * wc[q];
             acc.s = fmaf(pa[g], w_a, acc.s);
             if (L0) {
                 acc.v[0] = fmaf(s.u[0], c, acc.v[0]);
                 acc.v[1] = fmaf(s.u[1], c, acc.v[1]);
                 acc.v[2] = fmaf(s.u[2], c, acc.v[2]);
             } else {
-                const float b = fmaf(bb[1], fc, wb[q]);
+                const float b = wb[q];
                 acc.v[0] = fmaf(s.u[0], c, fmaf(b, pv[g][0], acc.v[0]));
                 acc.v[1] = fmaf(s.u[1], c, fmaf(b, pv[g][1], acc.v[1]));
                 acc.v[2] = fmaf(s.u[2], c, fmaf(b, pv[g][2], acc.v[2]));
@@ -307,7 +337,7 @@ __global__ void __launch_bounds__(64 * kMxWaves, 2) k_message_fwd_mx(MpGeom mg, 
     }
     const float sc = a.mx_scale[0], isc = a.mx_scale[1];
     half8_t bh[3], bl[3];
-    float bb[3];
+    half4_t bb[3];
     load_filter(a.Wr, a.br, sc, f, h, bh, bl, bb);
     const int i0 = xcd_block(blockIdx.x, gridDim.x) * kMxAtoms;
     NextBatch nx = next_batch<BATCH>(mg, i0, -1, 0, 0);
@@ -366,19 +396,23 @@ struct BwdAcc {
 // a time as in the forward batch.
 template <bool L0, bool VIR>
 __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, const BatchBuf<16>& buf, int nb, int f,
-                                          int h, const half8_t* bh, const half8_t* bl, const float* bb,
-                                          const Owner& o, BwdAcc& acc) {
+                                          int h, const half8_t* bh, const half8_t* bl, const half4_t* bb,
+                                          const float* b0, const Owner& o, BwdAcc& acc) {
     constexpr int F = kMxF, E = 8;
     const EdgeRec* rec = buf.rec;
-    // A rows 0..15: e_k f of edges 0..15, rows 16..31: their r-derivatives (zero past nb)
+    // A rows 0..15: e_k f of edges 0..15, rows 16..31: their r-derivatives
+    // (zero past nb: staged as zeros), and the bias rows f or f'
     const int r = threadIdx.x & 31, e = r & 15, part = 4 * (r >> 4);
     const half8_t ah = as_half8(buf.a[e][part + h]), al = as_half8(buf.a[e][part + 2 + h]);
-    const floatx16_t m0 = mma3(ah, al, bh[0], bl[0]);
+    // the first layer adds the biases in the per-edge work instead: the
+    // bias operands would cost it the registers of a fourth wavefront per SIMD
+    const half4_t ab = L0 ? half4_t{} : bias_rows(part ? rec[e].dfc : rec[e].fc, h);
+    const floatx16_t m0 = mma3<!L0>(ab, bb[0], ah, al, bh[0], bl[0]);
     // the b channel gates v, zero in the first layer: nothing of it reaches
     // the forces there
     floatx16_t m1 = {};
-    if constexpr (!L0) m1 = mma3(ah, al, bh[1], bl[1]);
-    const floatx16_t m2 = mma3(ah, al, bh[2], bl[2]);
+    if constexpr (!L0) m1 = mma3(ab, bb[1], ah, al, bh[1], bl[1]);
+    const floatx16_t m2 = mma3<!L0>(ab, bb[2], ah, al, bh[2], bl[2]);
     const uint32_t fo = uint32_t(f) * 4u;
 #pragma unroll
     for (int g0 = 0; g0 < E; g0 += kBwdGroup<L0>) {
@@ -417,9 +451,14 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
             if (te >= nb) continue;
             const EdgeRec& s = rec[te];
             // w of edge te is row te, dw/dr row 16 + te: accumulator elements q and 8 + q
-            const float fc = s.fc, dfc = s.dfc, ir = s.ir;
-            const float w0 = fmaf(bb[0], fc, m0[q]), w2 = fmaf(bb[2], fc, m2[q]);
-            const float dw0 = fmaf(bb[0], dfc, m0[8 + q]), dw2 = fmaf(bb[2], dfc, m2[8 + q]);
+            const float ir = s.ir;
+            float w0 = m0[q], w2 = m2[q], dw0 = m0[8 + q], dw2 = m2[8 + q];
+            if constexpr (L0) {
+                w0 = fmaf(b0[0], s.fc, w0);
+                w2 = fmaf(b0[2], s.fc, w2);
+                dw0 = fmaf(b0[0], s.dfc, dw0);
+                dw2 = fmaf(b0[2], s.dfc, dw2);
+            }
             const float u0 = s.u[0], u1 = s.u[1], u2 = s.u[2];
             const float g0v = gn[g][0], g1v = gn[g][1], g2v = gn[g][2];
             const float gvn_u = fmaf(g2v, u2, fmaf(g1v, u1, g0v * u0));
@@ -432,7 +471,7 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
             if constexpr (L0) {
                 dr = fmaf(A, dw0, C * dw2);
             } else {
-                const float w1 = fmaf(bb[1], fc, m1[q]), dw1 = fmaf(bb[1], dfc, m1[8 + q]);
+                const float w1 = m1[q], dw1 = m1[8 + q];
                 const float gvn_vo = fmaf(g2v, o.v[2], fmaf(g1v, o.v[1], g0v * o.v[0]));
                 const float gvo_pvn = fmaf(o.gv[2], pvn[g][2], fmaf(o.gv[1], pvn[g][1], o.gv[0] * pvn[g][0]));
                 const float B = fmaf(o.ph[1], gvn_vo, gvo_pvn);
@@ -478,8 +517,13 @@ __global__ void __launch_bounds__(64 * kMxWaves, 3) k_message_bwd_mx(MpGeom mg, 
     }
     const float sc = a.mx_scale[0], isc = a.mx_scale[1];
     half8_t bh[3], bl[3];
-    float bb[3];
+    half4_t bb[3];
     load_filter(a.Wr, a.br, sc, f, h, bh, bl, bb);
+    float bf[3] = {};  // the scaled biases, for the first layer's per-edge work
+    if constexpr (L0) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) bf[p] = a.br[p * F + f] * sc;
+    }
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int i0 = blk * kMxAtoms;
     NextBatch nx = next_batch<BATCH>(mg, i0, -1, 0, 0);
@@ -510,7 +554,7 @@ __global__ void __launch_bounds__(64 * kMxWaves, 3) k_message_bwd_mx(MpGeom mg, 
             __syncthreads();  // the batch is staged; the other buffer's batch is done
             nx = next_batch<BATCH>(mg, i0, ai, b0, cnt);
             piece = fetch_piece<BATCH>(mg, nx.p0, nx.nb);
-            bwd_batch<L0, VIR>(a, ptab_s, b, min(BATCH, cnt - b0), f, h, bh, bl, bb, o, acc);
+            bwd_batch<L0, VIR>(a, ptab_s, b, min(BATCH, cnt - b0), f, h, bh, bl, bb, bf, o, acc);
         }
         // the lane's force share, then both halves of the wavefront (partial
         // sums of feature f) and the features of the wavefront
@@ -564,9 +608,9 @@ __global__ void __launch_bounds__(64 * kMxWaves, 3) k_message_bwd_mx(MpGeom mg, 
     }
 }
 
-// Scale of the filter weights of one layer for the split products: a power
-// of two s with max |Wr| s in [2^13, 2^14) (s = 1 for all-zero weights), and
-// 1 / s.
+// Scale of the filter weights and biases of one layer for the split
+// products: a power of two s with max(|Wr|, |br|) s in [2^13, 2^14) (s = 1
+// when all are zero), and 1 / s.  Wr and br are contiguous in the weights.
 __global__ void __launch_bounds__(256) k_filter_scale(int count, const float* Wr, float* out) {
     __shared__ float part[256];
     float m = 0.f;
