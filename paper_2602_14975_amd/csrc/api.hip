@@ -280,6 +280,11 @@ void carve_model(Arena& a, const Model* m, int64_t n, int64_t E, bool for_wgrad,
         const int64_t HC = 2 * int64_t(m->desc.n_s + m->desc.n_l) * m->desc.n_c;
         b.QK = a.take<float>(n * HC);
         b.Vh = a.take<float>(n * 3 * m->desc.n_l);
+        if (E > 1) {
+            b.nc_edges = a.take<NcEdge>(E);
+            b.nc_ecnt = a.take<int>(n);
+            b.nc_edge_cap = E;
+        }
         if (for_wgrad) {
             b.gQK = a.take<float>(n * HC);
             b.gVh = a.take<float>(n * 3 * m->desc.n_l);
@@ -535,10 +540,17 @@ void nc_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const n
         a.species = sys.species;
         a.phi_tab = b.phi_tab;
         a.emb = m->p(m->off_emb);
+        // the pair head then reads the edges as records (no second pair rule)
+        const bool records = b.nc_edges && nl.capacity <= b.nc_edge_cap && K == 8 && m->desc.n_s == 8;
+        if (records) {
+            a.edge_out = b.nc_edges;
+            a.edge_cnt = b.nc_ecnt;
+        }
         launch_message_fwd(F, K, 1, mg, a, s);
         NcUpdateArgs u{n, lb.smid, lb.vmid, m->ncw, m->p(lo.m1), m->p(lo.m2), b.QK, b.Vh};
         if (m->ncw && launch_nc_update_proj(u, F, m->bf16(), s)) {
-            launch_head_fwd(mg, b.QK, b.Vh, forces, false, s, vir_set, vir_add);
+            if (records) launch_head_fwd_rec(mg, b.nc_ecnt, b.nc_edges, b.QK, b.Vh, forces, false, s, vir_set, vir_add);
+            else launch_head_fwd(mg, b.QK, b.Vh, forces, false, s, vir_set, vir_add);
             return;
         }
     }

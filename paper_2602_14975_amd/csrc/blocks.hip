@@ -315,6 +315,144 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
     }
 }
 
+// The same head over the records the NC message step left (edges within the
+// cutoff in list order, B_h u, u and r in float32): no pair rule or radial
+// values here.  One wavefront per owner atom, four edges at a time: lane
+// 16 e + h takes head h (h < 10) of edge e, so that the neighbour's q and k
+// rows are read as 32-byte pieces per lane, contiguous across the heads of
+// an edge.  The coefficients come to the edge's first lane, which forms the
+// pair contribution with the sums in the order of the kernel above; the
+// owner's first lane adds the four contributions in record order.  The
+// result is therefore the same, bit for bit, as that kernel's.
+template <bool VIR>
+__global__ void __launch_bounds__(256) k_head_fwd_rec(int n, const int* __restrict__ off,
+                                                      const int* __restrict__ cnt_in, const NcEdge* __restrict__ rec,
+                                                      const float* __restrict__ QK, const float* __restrict__ Vh,
+                                                      float* __restrict__ Fout, int accum, float* __restrict__ vir_set,
+                                                      float* __restrict__ vir_add) {
+    constexpr int HC = 2 * kH * kNc;
+    const int lane = threadIdx.x & 63;
+    const int e = lane >> 4, h = lane & 15;
+    const int i = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;  // whole wavefronts
+    const int e0 = off[i], cnt = cnt_in[i];
+    const int hh = h < kH ? h : 0;
+    float qi[kNc], ki[kNc];
+    {
+        const float4* q4 = reinterpret_cast<const float4*>(QK + int64_t(i) * HC + hh * kNc);
+        const float4* k4 = reinterpret_cast<const float4*>(QK + int64_t(i) * HC + (kH + hh) * kNc);
+        const float4 a0 = q4[0], a1 = q4[1], b0 = k4[0], b1 = k4[1];
+        qi[0] = a0.x; qi[1] = a0.y; qi[2] = a0.z; qi[3] = a0.w; qi[4] = a1.x; qi[5] = a1.y; qi[6] = a1.z; qi[7] = a1.w;
+        ki[0] = b0.x; ki[1] = b0.y; ki[2] = b0.z; ki[3] = b0.w; ki[4] = b1.x; ki[5] = b1.y; ki[6] = b1.z; ki[7] = b1.w;
+    }
+    float Vi[kNl][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int l = 0; l < kNl; ++l) Vi[l][a] = Vh[(int64_t(i) * 3 + a) * kNl + l];
+    const float scale = 0.35355339059327373f;  // 1/sqrt(n_c), n_c = 8
+    // q_a . k_b over the channels in the order of head_coeffs
+    auto dot8 = [](const float* a, const float4& b0, const float4& b1) {
+        float acc = a[0] * b0.x;
+        acc = fmaf(a[1], b0.y, acc); acc = fmaf(a[2], b0.z, acc); acc = fmaf(a[3], b0.w, acc);
+        acc = fmaf(a[4], b1.x, acc); acc = fmaf(a[5], b1.y, acc); acc = fmaf(a[6], b1.z, acc);
+        acc = fmaf(a[7], b1.w, acc);
+        return acc;
+    };
+    auto dot8r = [](const float4& a0, const float4& a1, const float* b) {
+        float acc = a0.x * b[0];
+        acc = fmaf(a0.y, b[1], acc); acc = fmaf(a0.z, b[2], acc); acc = fmaf(a0.w, b[3], acc);
+        acc = fmaf(a1.x, b[4], acc); acc = fmaf(a1.y, b[5], acc); acc = fmaf(a1.z, b[6], acc);
+        acc = fmaf(a1.w, b[7], acc);
+        return acc;
+    };
+    float fx = 0.f, fy = 0.f, fz = 0.f, vr = 0.f;  // running sums (lane 0)
+    // the neighbours of the first 64 edges, one per lane, read up front; the
+    // rows of the next four edges are requested before the current four are
+    // reduced
+    const int jl = lane < cnt ? rec[e0 + lane].j : 0;
+    auto neighbour = [&](int ee) {
+        const int jj = __shfl(jl, ee & 63, 64);  // by every lane: no divergent shuffle
+        return ee < 64 ? jj : rec[e0 + ee].j;
+    };
+    auto fetch = [&](int j, float4* r) {
+        if (h < kH) {
+            const float4* q4 = reinterpret_cast<const float4*>(QK + int64_t(j) * HC + h * kNc);
+            const float4* k4 = reinterpret_cast<const float4*>(QK + int64_t(j) * HC + (kH + h) * kNc);
+            r[0] = q4[0]; r[1] = q4[1]; r[2] = k4[0]; r[3] = k4[1];
+        }
+    };
+    float4 cur[4] = {}, nxt[4] = {};
+    int jc = neighbour(e < cnt ? e : 0);
+    fetch(jc, cur);
+    for (int base = 0; base < cnt; base += 4) {
+        const int ee = base + e;
+        const bool ok = ee < cnt;
+        const NcEdge& he = rec[e0 + (ok ? ee : 0)];
+        const int j = jc;
+        if (base + 4 < cnt) {
+            jc = neighbour(base + 4 + e < cnt ? base + 4 + e : base + 4);
+            fetch(jc, nxt);
+        }
+        float cij = 0.f, cji = 0.f;
+        if (h < kH) {
+            cij = dot8(qi, cur[2], cur[3]) * scale;   // q_i . k_j
+            cji = dot8r(cur[0], cur[1], ki) * scale;  // q_j . k_i
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) cur[t] = nxt[t];
+        // the coefficients of every head at the edge's first lane
+        float ci[kH], cj[kH];
+#pragma unroll
+        for (int t = 0; t < kH; ++t) {
+            ci[t] = __shfl(cij, 16 * e + t, 64);
+            cj[t] = __shfl(cji, 16 * e + t, 64);
+        }
+        float c[4] = {0.f, 0.f, 0.f, 0.f};
+        if (h == 0 && ok) {
+            float Sij = 0.f, Sji = 0.f;
+#pragma unroll
+            for (int t = 0; t < kNs; ++t) {
+                Sij = fmaf(ci[t], he.ef[t], Sij);
+                Sji = fmaf(cj[t], he.ef[t], Sji);
+            }
+            float fu = 0.f;  // F_ij . u
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const float Dij = he.u[a] + ci[kNs] * Vi[0][a] + ci[kNs + 1] * Vi[1][a];
+                const float Dji = -he.u[a] + cj[kNs] * Vh[(int64_t(j) * 3 + a) * kNl] +
+                                  cj[kNs + 1] * Vh[(int64_t(j) * 3 + a) * kNl + 1];
+                c[a] = fmaf(Sij, Dij, -(Sji * Dji));
+                if (VIR) fu = fmaf(Sij * Dij, he.u[a], fu);
+            }
+            if constexpr (VIR) c[3] = fu * he.r;  // F_ij . r_ij
+        }
+        // the owner's sums, edge by edge in record order
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float cx = __shfl(c[0], 16 * t, 64), cy = __shfl(c[1], 16 * t, 64),
+                        cz = __shfl(c[2], 16 * t, 64), cw = VIR ? __shfl(c[3], 16 * t, 64) : 0.f;
+            if (base + t < cnt) {
+                fx += cx;
+                fy += cy;
+                fz += cz;
+                if constexpr (VIR) vr += cw;
+            }
+        }
+    }
+    if (lane == 0) {
+        if (accum) {
+            Fout[i] += fx; Fout[n + i] += fy; Fout[2 * n + i] += fz;
+        } else {
+            Fout[i] = fx; Fout[n + i] = fy; Fout[2 * n + i] = fz;
+        }
+        if constexpr (VIR) {
+            if (vir_set) vir_set[i] = vr;
+            if (vir_add) vir_add[i] += vr;
+        }
+    }
+}
+
 // Reverse of the head for a loss with dL/dF_i = gF_i: each directed edge
 // (i, j) carries a_ij = gF_i - gF_j as the adjoint of F_ij.  The owner i
 // accumulates only its own adjoints, so no atomics are needed: q_i and V_i
@@ -786,6 +924,18 @@ void launch_head_fwd(const MpGeom& mg, const float* QK, const float* Vh, float* 
     // 16 lanes per atom: rows of the 3.5 A list hold about 40 candidates
     if (vir_set || vir_add) k_head_fwd<16, true><<<cdiv(mg.n, 16), 256, 0, st>>>(mg, QK, Vh, F, accum, vir_set, vir_add);
     else k_head_fwd<16, false><<<cdiv(mg.n, 16), 256, 0, st>>>(mg, QK, Vh, F, accum, nullptr, nullptr);
+    NNP_LAUNCH_CHECK();
+}
+void launch_head_fwd_rec(const MpGeom& mg, const int* cnt, const NcEdge* rec, const float* QK, const float* Vh,
+                         float* F, bool accum, hipStream_t st, float* vir_set, float* vir_add) {
+    if (mg.n <= 0) return;
+    ScopedTimer timer("head_fwd", st);
+    // one wavefront per owner atom
+    if (vir_set || vir_add)
+        k_head_fwd_rec<true><<<cdiv(mg.n, 4), 256, 0, st>>>(mg.n, mg.off, cnt, rec, QK, Vh, F, accum, vir_set, vir_add);
+    else
+        k_head_fwd_rec<false><<<cdiv(mg.n, 4), 256, 0, st>>>(mg.n, mg.off, cnt, rec, QK, Vh, F, accum, nullptr,
+                                                              nullptr);
     NNP_LAUNCH_CHECK();
 }
 void launch_head_bwd(const MpGeom& mg, const float* QK, const float* Vh, const float* gF, float* gQK, float* gVh,

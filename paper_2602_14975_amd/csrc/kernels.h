@@ -132,6 +132,8 @@ void launch_rep_sum(int n_rep, const int64_t* rep_start, const float* x, double*
 void launch_emb_grad(int n, int F, int S, const int* species, const float* gs0, float* gemb, hipStream_t st);
 // vir_set / vir_add ([n] or nullptr): per owner i, sum_j F_ij . r_ij (its
 // share of the NPT virial proxy), written / added to
+void launch_head_fwd_rec(const MpGeom& mg, const int* cnt, const NcEdge* rec, const float* QK, const float* Vh,
+                         float* F, bool accum, hipStream_t st, float* vir_set, float* vir_add);
 void launch_head_fwd(const MpGeom& mg, const float* QK, const float* Vh, float* F, bool accum, hipStream_t st,
                      float* vir_set = nullptr, float* vir_add = nullptr);
 void launch_head_bwd(const MpGeom& mg, const float* QK, const float* Vh, const float* gF, float* gQK, float* gVh,

@@ -75,6 +75,11 @@ struct ModelBuf {
     float *chunk_part = nullptr, *mp_part = nullptr, *filt_sum = nullptr;
     // per-atom virial shares: of the last evaluation, and a running sum
     float *vir = nullptr, *vir_sum = nullptr;
+    // NC models: the edges within the cutoff as records for the pair head
+    // (list capacity E), and their count per atom; null when not carved
+    NcEdge* nc_edges = nullptr;
+    int* nc_ecnt = nullptr;
+    int64_t nc_edge_cap = 0;
     // prepared edges of the matrix-core message kernels (list capacity E)
     int* ecnt = nullptr;
     EdgeRec* erec = nullptr;

@@ -15,6 +15,17 @@ struct EdgeRec {
     float ir;       // 1 / r
 };
 
+// One NC edge within the cutoff as the NC message step leaves it for the
+// pair head (list order within each owner's row): neighbour, r, unit vector
+// and the envelope-weighted Bessel values B_h(r) u(r / rc), float32.
+struct NcEdge {
+    int j;
+    float r;
+    float u[3];
+    float pad[3];
+    float ef[8];
+};
+
 struct MpGeom {
     int n;
     const double* pos;
@@ -46,6 +57,11 @@ struct MpFwd {
     // matrix-core forward of layers past the first, read there and by the
     // reverse in place of phi_b and v_in; ignored elsewhere
     float* pv;
+    // NC forward (vector kernel, F <= 64): when set, the edges within the
+    // cutoff are also written as records at off[i] + rank (rank among the
+    // atom's edges within the cutoff), with their count per atom
+    NcEdge* edge_out;
+    int* edge_cnt;
 };
 
 struct MpBwd {

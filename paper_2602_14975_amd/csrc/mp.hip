@@ -74,6 +74,7 @@ __device__ __forceinline__ int stage_batch(const MpGeom& mg, bool active, int e,
             s.u[1] = float(dy) * ir;
             s.u[2] = float(dz) * ir;
             s.ir = ir;
+            s.r = r;
         } else {
             const double r = sqrt((dx * dx + dy * dy) + dz * dz);
             const double ir = 1.0 / r;
@@ -162,7 +163,7 @@ k_message_fwd(MpGeom mg, MpFwd a) {
             bb[p][q] = a.br[row];
         }
     float sacc[FPL] = {}, vacc[3][FPL] = {};
-    int start = 0, end = 0;
+    int start = 0, end = 0, emitted = 0;
     double xi = 0, yi = 0, zi = 0, L = 1, inv = 1;
     if (active) {
         start = mg.off[i];
@@ -185,6 +186,23 @@ k_message_fwd(MpGeom mg, MpFwd a) {
         } else {
             cnt = stage_batch<G, K, CUT, false>(mg, active, start + base + l, end, l, g, xi, yi, zi, L, inv, slots,
                                               L0 ? a.species : nullptr);
+            if constexpr (CUT == 1 && K == 8) {
+                // the NC pair head reads the same edges as records
+                if (a.edge_out && l < cnt) {
+                    const EdgeSlot<K>& s = slots[l];
+                    NcEdge rec;
+                    rec.j = s.j;
+                    rec.r = s.r;
+                    rec.u[0] = s.u[0];
+                    rec.u[1] = s.u[1];
+                    rec.u[2] = s.u[2];
+                    rec.pad[0] = rec.pad[1] = rec.pad[2] = 0.f;
+#pragma unroll
+                    for (int k = 0; k < K; ++k) rec.ef[k] = s.ef[k];
+                    a.edge_out[start + emitted + l] = rec;
+                }
+                emitted += cnt;
+            }
         }
 #pragma unroll 1
         for (int t = 0; t < cnt; ++t) {
@@ -223,6 +241,9 @@ k_message_fwd(MpGeom mg, MpFwd a) {
         }
         if constexpr (S::SHARED) __syncthreads();  // the slots are restaged next
         else wave_sync_lds();
+    }
+    if constexpr (CUT == 1 && K == 8 && !S::SHARED) {
+        if (a.edge_cnt && active && l == 0) a.edge_cnt[i] = emitted;
     }
     if (active) {
         float out[FPL];

@@ -14,6 +14,7 @@ struct EdgeSlot {
     float fc, dfc;  // f(r), f'(r)
     float u[3];
     float ir;       // 1 / r
+    float r;        // NC forward only: r in float32
     int j, t;       // neighbour, neighbour species
 };
 
