@@ -587,6 +587,9 @@ void nc_wgrad(const Model* m, const nnp_system& sys, const RepGeom& geom, const 
 // ============================================================== workspace
 namespace nnp {
 
+// atoms per block of the disagreement reduction
+constexpr int kDisChunk = 2048;
+
 struct CallScratch {
     SysTables t;
     NbrScratch nb;
@@ -595,6 +598,7 @@ struct CallScratch {
     RespaBuf frame;    // saved frame of the rewind procedure
     double* inner_energy = nullptr;
     double* disagree = nullptr;
+    double* ke_part = nullptr;
 };
 
 // One layout serves every entry point: tables, neighbour scratch, the
@@ -616,7 +620,8 @@ void carve_all(Arena& a, const Model* cons, const Model* nc, int64_t n, int32_t 
     c.frame.f_nc = a.take<float>(3 * n);
     c.frame.energy = a.take<double>(n_rep);
     c.inner_energy = a.take<double>(n_rep);
-    c.disagree = a.take<double>(n_rep);
+    c.disagree = a.take<double>(int64_t(n_rep) * (cdiv(n, kDisChunk) + 1));
+    c.ke_part = a.take<double>(int64_t(n_rep) * cdiv(n, kKeChunk));
     if (cons) carve_model(a, cons, n, E, false, c.cons);
     if (nc) carve_model(a, nc, n, E, wgrad, c.nc);
 }
@@ -989,19 +994,21 @@ void check_respa(const respa_state* st, const respa_params* p, const Model* cons
     NNP_REQUIRE(st->nl_cons.n_atoms == st->sys.n_atoms, NNP_EINVAL, "list rows must equal n_atoms");
 }
 
-// Per-replica disagreement sqrt(mean_i |F_i - F_fast,i|^2), fixed-order
-// float64 reduction, one block per replica.  Non-finite positions or
-// velocities count as infinite disagreement (such atoms leave every
-// neighbour list, so their forces alone would not show the failure).  A
-// replica above `thr` (or not finite) sets *trip, which the host reads at
-// its next status check.
-__global__ void __launch_bounds__(256) k_disagreement(const int64_t* __restrict__ rep_start, int n,
-                                                      const float* __restrict__ fa, const float* __restrict__ fb,
-                                                      const double* __restrict__ pos, const double* __restrict__ vel,
-                                                      double* __restrict__ out, double thr, int* __restrict__ trip) {
+// Per-replica disagreement sqrt(mean_i |F_i - F_fast,i|^2) in two fixed-order
+// float64 reductions: block (c, r) sums chunk c (kDisChunk atoms) of replica
+// r into part[r * chunks + c], then one wavefront per replica adds its
+// chunks in order.  Non-finite positions or velocities count as infinite
+// disagreement (such atoms leave every neighbour list, so their forces alone
+// would not show the failure).  A replica above `thr` (or not finite) sets
+// *trip, which the host reads at its next status check.
+__global__ void __launch_bounds__(256) k_disagreement_part(const int64_t* __restrict__ rep_start, int n, int chunks,
+                                                           const float* __restrict__ fa, const float* __restrict__ fb,
+                                                           const double* __restrict__ pos,
+                                                           const double* __restrict__ vel, double* __restrict__ part) {
     __shared__ double red[256];
-    const int r = blockIdx.x;
-    const int64_t a0 = rep_start[r], a1 = rep_start[r + 1];
+    const int r = blockIdx.y, ch = blockIdx.x;
+    const int64_t a0 = rep_start[r] + int64_t(ch) * kDisChunk;
+    const int64_t a1 = min(rep_start[r + 1], a0 + kDisChunk);
     double acc = 0.0;
     for (int64_t i = a0 + threadIdx.x; i < a1; i += 256)
         for (int c = 0; c < 3; ++c) {
@@ -1015,11 +1022,20 @@ __global__ void __launch_bounds__(256) k_disagreement(const int64_t* __restrict_
         if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const double dis = sqrt(red[0] / double(max<int64_t>(a1 - a0, 1)));
-        out[r] = dis;
-        if (!(dis <= thr)) *trip = 1;
-    }
+    if (threadIdx.x == 0) part[int64_t(r) * chunks + ch] = red[0];
+}
+
+__global__ void k_disagreement_final(const int64_t* __restrict__ rep_start, int chunks, const double* __restrict__ part,
+                                     double* __restrict__ out, double thr, int* __restrict__ trip) {
+    const int r = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    const int64_t na = rep_start[r + 1] - rep_start[r];
+    const int nc = int((na + kDisChunk - 1) / kDisChunk);
+    double acc = 0.0;
+    for (int c = 0; c < nc; ++c) acc += part[int64_t(r) * chunks + c];
+    const double dis = sqrt(acc / double(max<int64_t>(na, 1)));
+    out[r] = dis;
+    if (!(dis <= thr)) *trip = 1;
 }
 
 // Advances a packed system by n_outer outer steps.  Replica r draws its
@@ -1048,7 +1064,13 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     const int64_t E = std::max<int64_t>({st->nl_cons.capacity, mts ? st->nl_nc.capacity : 0, int64_t(1)});
     carve_all(a, cons, mts ? nc : nullptr, n, R, E, false, c);
     RespaBuf& frame = c.frame;
-    double* disagree = c.disagree;
+    int ke_chunks = 1;
+    for (int r = 0; r < R; ++r)
+        ke_chunks = std::max<int>(ke_chunks, cdiv(st->sys.rep_start[r + 1] - st->sys.rep_start[r], kKeChunk));
+    double* disagree = c.disagree;  // [R] results, then [R][dis_chunks] partial sums
+    int dis_chunks = 1;
+    for (int r = 0; r < R; ++r)
+        dis_chunks = std::max<int>(dis_chunks, cdiv(st->sys.rep_start[r + 1] - st->sys.rep_start[r], kDisChunk));
     double* inner_energy = c.inner_energy;
     std::vector<double> hs;
     RepGeom g = upload_tables(st->sys, c.t, s, hs);
@@ -1269,8 +1291,10 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         if (rewind) {
             // both forces now belong to the end of the step; a trip is acted
             // on at the next status check
-            k_disagreement<<<R, 256, 0, s>>>(c.t.rep_start, n, st->f_cons, st->f_nc, st->pos, st->vel, disagree,
-                                             p->rewind_threshold, trip);
+            k_disagreement_part<<<dim3(dis_chunks, R), 256, 0, s>>>(c.t.rep_start, n, dis_chunks, st->f_cons,
+                                                                   st->f_nc, st->pos, st->vel, disagree + R);
+            k_disagreement_final<<<R, 64, 0, s>>>(c.t.rep_start, dis_chunks, disagree + R, disagree,
+                                                  p->rewind_threshold, trip);
             NNP_LAUNCH_CHECK();
         }
     };
@@ -1362,7 +1386,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         else sts_step(D);
         ++since_save;
         launch_kinetic(R, c.t.rep_start, n, st->pos, st->vel, st->mass, st->ke ? st->ke + int64_t(o) * R : nullptr,
-                       c.t.rep_bad, s, st->sys.rep_of_atom);
+                       c.t.rep_bad, s, st->sys.rep_of_atom, c.ke_part, ke_chunks);
         if (stamps) launch_stamp(stamps + o, s);
         if ((o + 1) % check_every == 0 || o + 1 == n_outer) {
             nnp_status e = check(snap_offset, true);
@@ -1442,9 +1466,13 @@ extern "C" nnp_status nnp_barostat_scr(respa_state* st, const nnp_barostat_param
     carve_tables(a, R, t);
     double* ke = a.take<double>(R);
     double* mu = a.take<double>(R);
+    int chunks = 1;
+    for (int r = 0; r < R; ++r)
+        chunks = std::max<int>(chunks, cdiv(st->sys.rep_start[r + 1] - st->sys.rep_start[r], kKeChunk));
+    double* part = a.take<double>(int64_t(R) * chunks);
     std::vector<double> hs;
     upload_tables(st->sys, t, s, hs);
-    launch_kinetic(R, t.rep_start, n, st->pos, st->vel, st->mass, ke, nullptr, s, st->sys.rep_of_atom);
+    launch_kinetic(R, t.rep_start, n, st->pos, st->vel, st->mass, ke, nullptr, s, st->sys.rep_of_atom, part, chunks);
     const double bar = 1e5 * 6.02214076e23 * 1e-30 / 4184.0;  // kcal/mol/A^3
     ScrArgs sa{p->pressure_bar * bar, p->compressibility_per_bar / bar, p->tau_fs, p->dt_fs, p->temperature_K,
                p->seed, p->stream_id, barostat_step};

@@ -188,6 +188,51 @@ __global__ void __launch_bounds__(256) k_kinetic(const int64_t* __restrict__ rep
     if (nonfinite && bad) atomicOr(bad + r, 1);
 }
 
+// The same over chunks of kKeChunk atoms: block (c, r) writes the partial
+// sum of chunk c of replica r to part[r * chunks + c], then one lane per
+// replica adds its chunks in order.
+__global__ void __launch_bounds__(256) k_kinetic_part(const int64_t* __restrict__ rep_start, int n, int chunks,
+                                                      const double* __restrict__ pos, const double* __restrict__ vel,
+                                                      const double* __restrict__ mass, double* __restrict__ part,
+                                                      int* __restrict__ bad) {
+    __shared__ double red[256];
+    const int r = blockIdx.y, ch = blockIdx.x;
+    const int64_t a0 = rep_start[r] + int64_t(ch) * kKeChunk;
+    const int64_t a1 = min(rep_start[r + 1], a0 + kKeChunk);
+    double s = 0.0;
+    bool nonfinite = false;
+    for (int64_t i = a0 + threadIdx.x; i < a1; i += 256) {
+        double v2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double v = vel[c * int64_t(n) + i];
+            const double x = pos[c * int64_t(n) + i];
+            v2 += v * v;
+            nonfinite |= !isfinite(v) || !isfinite(x);
+        }
+        s += mass[i] * v2;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[int64_t(r) * chunks + ch] = red[0];
+    if (nonfinite && bad) atomicOr(bad + r, 1);
+}
+
+__global__ void k_kinetic_final(const int64_t* __restrict__ rep_start, int chunks, const double* __restrict__ part,
+                                double* __restrict__ ke) {
+    const int r = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    const int64_t na = rep_start[r + 1] - rep_start[r];
+    const int nc = int((na + kKeChunk - 1) / kKeChunk);
+    double acc = 0.0;
+    for (int c = 0; c < nc; ++c) acc += part[int64_t(r) * chunks + c];
+    ke[r] = 0.5 * acc / kAcc;
+}
+
 // The finiteness flags alone (no kinetic energy requested): one thread per
 // atom over the whole grid.
 __global__ void __launch_bounds__(256) k_finite(int n, const int32_t* __restrict__ rep_of_atom,
@@ -308,9 +353,13 @@ void launch_scale(int n, const int32_t* rep_of_atom, const double* mu, double* p
 }
 
 void launch_kinetic(int n_rep, const int64_t* rep_start, int n, const double* pos, const double* vel,
-                    const double* mass, double* ke, int* bad, hipStream_t s, const int32_t* rep_of_atom) {
+                    const double* mass, double* ke, int* bad, hipStream_t s, const int32_t* rep_of_atom,
+                    double* part, int chunks) {
     if (!ke && bad && (n_rep == 1 || rep_of_atom)) {
         if (n > 0) k_finite<<<cdiv(n, 256), 256, 0, s>>>(n, rep_of_atom, pos, vel, bad);
+    } else if (part && chunks > 1) {
+        k_kinetic_part<<<dim3(chunks, n_rep), 256, 0, s>>>(rep_start, n, chunks, pos, vel, mass, part, bad);
+        if (ke) k_kinetic_final<<<n_rep, 64, 0, s>>>(rep_start, chunks, part, ke);
     } else {
         k_kinetic<<<n_rep, 256, 0, s>>>(rep_start, n, pos, vel, mass, ke, bad);
     }

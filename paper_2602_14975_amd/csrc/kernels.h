@@ -205,8 +205,12 @@ struct ScrArgs {
 void launch_scr(int n_rep, const double* ke, const double* virial, double* box, double* mu, const ScrArgs& a,
                 hipStream_t s);
 void launch_scale(int n, const int32_t* rep_of_atom, const double* mu, double* pos, double* vel, hipStream_t s);
+// atoms per block of the chunked kinetic-energy reduction; part: scratch of
+// n_rep * chunks doubles, chunks = the largest replica's atom count over
+// kKeChunk, rounded up (without it, one block per replica)
+constexpr int kKeChunk = 2048;
 void launch_kinetic(int n_rep, const int64_t* rep_start, int n, const double* pos, const double* vel,
                     const double* mass, double* ke, int* bad, hipStream_t s,
-                    const int32_t* rep_of_atom = nullptr);
+                    const int32_t* rep_of_atom = nullptr, double* part = nullptr, int chunks = 0);
 
 }  // namespace nnp
