@@ -75,6 +75,15 @@ __device__ __forceinline__ int stage_batch(const MpGeom& mg, bool active, int e,
             s.u[2] = float(dz) * ir;
             s.ir = ir;
             s.r = r;
+        } else if constexpr (CUT == 0) {
+            // conservative model: radial values in float32
+            const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+            const double ir = 1.0 / r;
+            radial_cos_f32<K>(float(r), mg, s.ef, s.def, s.fc, s.dfc);
+            s.u[0] = float(dx * ir);
+            s.u[1] = float(dy * ir);
+            s.u[2] = float(dz * ir);
+            s.ir = float(ir);
         } else {
             const double r = sqrt((dx * dx + dy * dy) + dz * dz);
             const double ir = 1.0 / r;

@@ -57,6 +57,38 @@ __device__ __forceinline__ void radial(double r, const MpGeom& mg, float* ef, fl
     dfc = float(df);
 }
 
+// Radial values of the cosine cutoff (the conservative model) in float32,
+// with their r-derivatives; the pair rule and the displacement stay in
+// float64 upstream.  sin(k theta) and cos(k theta), theta = pi r / rc, come
+// from sincospi(r / rc) and the rotation by theta (angle addition), whose
+// rounding errors grow only linearly with k.
+template <int K>
+__device__ __forceinline__ void radial_cos_f32(float r, const MpGeom& mg, float* ef, float* def, float& fc,
+                                               float& dfc) {
+    const float inv_rc = float(mg.inv_rc), k_pi = float(mg.pi_over_rc);
+    float sn, cs;
+    sincospif(r * inv_rc, &sn, &cs);
+    const float f = 0.5f * (cs + 1.f);
+    const float df = -0.5f * sn * k_pi;
+    const float ir = 1.f / r;
+    const float nr = float(mg.bessel_norm) * ir;
+    float s = sn, c = cs;  // sin(k theta), cos(k theta) for k = 1
+#pragma unroll
+    for (int k = 1; k <= K; ++k) {
+        const float ek = nr * s;
+        ef[k - 1] = ek * f;
+        // d/dr [sin(k pi r/rc)/r] = (k pi/rc) cos(k theta)/r - sin(k theta)/r^2
+        const float dek = nr * fmaf(float(k) * k_pi, c, -s * ir);
+        def[k - 1] = fmaf(dek, f, ek * df);
+        const float s_next = fmaf(s, cs, c * sn);
+        const float c_next = fmaf(c, cs, -(s * sn));
+        s = s_next;
+        c = c_next;
+    }
+    fc = f;
+    dfc = df;
+}
+
 // Forward radial values of the polynomial envelope (the NC model) in
 // float32; the pair rule and the displacement stay in float64 upstream.
 // d = r / rc, nr = bessel_norm / r.  sin(k pi d) follows the Chebyshev

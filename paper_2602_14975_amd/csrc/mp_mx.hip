@@ -17,7 +17,8 @@
 // pair rule at the model cutoff to the atom's list row, compacts the edges
 // that pass in list order to the front of the row, and stores per edge a
 // record (neighbour, species, f, f', unit vector, 1/r) and the radial values
-// e_k(r) f(r) and their r-derivatives already split into FP16 pairs.
+// e_k(r) f(r) and their r-derivatives (float32) already split into FP16
+// pairs.
 //
 // Message kernels: blocks take four atoms in turn with four wavefronts, one
 // per block of 32 features; the wavefronts do not synchronise except once
@@ -164,7 +165,7 @@ __global__ void __launch_bounds__(256, 3) k_edge_prep(MpGeom mg, int* __restrict
             const double r = sqrt((dx * dx + dy * dy) + dz * dz);
             const double ir = 1.0 / r;
             float ef[kMxK], def[kMxK], fc, dfc;
-            radial<kMxK, 0, true>(r, mg, ef, def, fc, dfc);
+            radial_cos_f32<kMxK>(float(r), mg, ef, def, fc, dfc);
             EdgeRec rec;
             rec.j = j;
             rec.t = mg.species ? min(max(mg.species[j], 0), mg.n_species - 1) : 0;
