@@ -46,7 +46,11 @@ enum {
     NNP_ECAPACITY = -3,  /* a neighbour list did not fit its buffer */
     NNP_EDEVICE = -4,    /* a HIP runtime call failed */
     NNP_EUNSTABLE = -5,  /* non-finite positions or velocities detected */
-    NNP_ENOTFOUND = -6   /* unknown ticket */
+    NNP_ENOTFOUND = -6,  /* unknown ticket */
+    NNP_EROWLIMIT = -7   /* an atom has more than 1024 list entries: the
+                            builder sorts each row in LDS, so a larger list
+                            buffer cannot fix it (a denser system than the
+                            models are meant for, or a collapsing one) */
 };
 
 const char* nnp_last_error(void);
@@ -162,7 +166,8 @@ nnp_status nnp_workspace_size(const nnp_model* cons, const nnp_model* nc, int64_
  * list with a 27-cell stencil where a replica has >= 3 cells per side, all
  * atoms of the replica otherwise).  Synchronises `stream` to learn the edge
  * count.  NNP_ECAPACITY: nl->n_edges holds the required capacity and the
- * buffers are unchanged; NNP_EINVAL: cutoff >= L/2 or bad sizes. */
+ * buffers are unchanged; NNP_EROWLIMIT: a row is longer than 1024 entries
+ * (buffers unchanged); NNP_EINVAL: cutoff >= L/2 or bad sizes. */
 nnp_status nnp_neighbors(const nnp_system* sys, nnp_nlist* nl, void* ws, size_t ws_bytes,
                          void* stream);
 
@@ -333,6 +338,7 @@ typedef struct {
  * Every `check_every` outer steps the call synchronises and checks list
  * capacity and finiteness; on NNP_ECAPACITY the state is restored to the
  * start of the failing outer step (grow the list buffers and call again);
+ * NNP_EROWLIMIT restores it the same way, but is not recoverable by growing;
  * on NNP_EUNSTABLE it is left at the last checked good step.  The sizes of
  * completed steps are reflected in state->step.
  * Virial estimator (state->virial not NULL; paper, Methods "Computation of

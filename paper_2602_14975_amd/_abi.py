@@ -7,6 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnnp.so")
 
 NNP_OK, NNP_EINVAL, NNP_ENOMEM, NNP_ECAPACITY, NNP_EDEVICE, NNP_EUNSTABLE, NNP_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
+NNP_EROWLIMIT = -7
 NNP_MODEL_CONS, NNP_MODEL_NC = 0, 1
 NNP_FP32, NNP_BF16 = 0, 1
 NNP_MODE_DMTS_NC, NNP_MODE_STS, NNP_MODE_DMTS = 0, 1, 2
@@ -14,7 +15,7 @@ NNP_THERMO_LANGEVIN, NNP_THERMO_FFL = 0, 1
 REPLICA_QUEUED, REPLICA_RUNNING, REPLICA_DONE, REPLICA_FAILED = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "NNP_OK", -1: "NNP_EINVAL", -2: "NNP_ENOMEM", -3: "NNP_ECAPACITY", -4: "NNP_EDEVICE",
-                -5: "NNP_EUNSTABLE", -6: "NNP_ENOTFOUND"}
+                -5: "NNP_EUNSTABLE", -6: "NNP_ENOTFOUND", -7: "NNP_EROWLIMIT"}
 
 vp = C.c_void_p
 

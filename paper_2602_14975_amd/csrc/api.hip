@@ -674,7 +674,7 @@ extern "C" nnp_status nnp_neighbors(const nnp_system* sys, nnp_nlist* nl, void* 
     NNP_HIP(hipMemcpyAsync(&total, nb.tmp_off + sys->n_atoms, sizeof(int), hipMemcpyDeviceToHost, s));
     NNP_HIP(hipStreamSynchronize(s));
     nl->n_edges = total;
-    NNP_REQUIRE(host_status[2] == 0, NNP_ECAPACITY, "a neighbour row exceeds the 1024-entry limit of the builder");
+    NNP_REQUIRE(host_status[2] == 0, NNP_EROWLIMIT, "a neighbour row exceeds the 1024-entry limit of the builder");
     NNP_REQUIRE(host_status[0] == 0, NNP_ECAPACITY,
                 "neighbour list needs " + std::to_string(total) + " entries, capacity " +
                     std::to_string(nl->capacity));
@@ -1193,7 +1193,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
             st->lists_valid = 0;
             set_error(row_long ? "a neighbour row exceeds the 1024-entry limit of the builder"
                                : "neighbour list capacity exceeded; grow the buffer to n_edges and call again");
-            return NNP_ECAPACITY;
+            return row_long ? NNP_EROWLIMIT : NNP_ECAPACITY;
         }
         bool any_bad = false;
         for (int r = 0; r < R; ++r) {

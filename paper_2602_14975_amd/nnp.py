@@ -279,8 +279,11 @@ class Trajectory:
                                self.n_replays, self.virial.data_ptr() if self.virial is not None else None)
 
     def respa_step(self, n_outer, ke=None):
-        """Advances by n_outer outer steps (growing list buffers on
-        NNP_ECAPACITY).  ke: optional float64 [n_outer][n_rep] tensor."""
+        """Advances by n_outer outer steps, growing the list buffers on
+        NNP_ECAPACITY (each retry resumes at the failed outer step; growth is
+        by 1.3x the reported need, so a second retry means the lists kept
+        growing).  NNP_EROWLIMIT and every other error raise at once.
+        ke: optional float64 [n_outer][n_rep] tensor."""
         for _ in range(8):
             st = self._state(ke)
             code = lib().respa_step(self.cons.handle, self.nc.handle if self.nc else None, C.byref(st),
@@ -307,7 +310,8 @@ class Trajectory:
                 continue
             check(code)
             return
-        raise RuntimeError("respa_step kept running out of list capacity")
+        raise RuntimeError("respa_step: list capacity was exceeded 8 times in a row although each retry grew "
+                           "the buffers to 1.3x the reported need; the system is probably collapsing")
 
     def barostat(self, params, step):
         """One stochastic cell rescaling step (nnp_barostat_scr) fed by the

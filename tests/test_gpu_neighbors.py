@@ -126,6 +126,29 @@ def test_capacity_overflow_reports_size(gpu_lib):
     assert bool((nl.nbr == sentinel).all())
 
 
+def test_row_limit_has_its_own_status(gpu_lib):
+    """2,400 atoms in a 10.5 A box give about 1,090 neighbours per atom at
+    5 A, beyond the builder's 1,024-entry rows: NNP_EROWLIMIT (not the
+    growable NNP_ECAPACITY) with the buffers untouched, and the binding
+    raises instead of growing."""
+    import ctypes as C
+    from paper_2602_14975_amd import _abi
+    from paper_2602_14975_amd.nnp import DeviceSystem, NeighborList, lib, workspace, _ptr, _stream
+    rng = np.random.default_rng(77)
+    n = 2400
+    system = DeviceSystem(rng.uniform(0.0, 10.5, (n, 3)), np.zeros(n, np.int32), 10.5)
+    nl = NeighborList(n, 5.0, 4 << 20)
+    sentinel = nl.nbr[:4096].clone()
+    ws = workspace(None, None, n, 1, 1)
+    cl = nl.c()
+    code = lib().nnp_neighbors(C.byref(system.c()), C.byref(cl), _ptr(ws), ws.numel(), _stream())
+    assert code == _abi.NNP_EROWLIMIT
+    assert bool((nl.nbr[:4096] == sentinel).all())
+    with pytest.raises(_abi.NnpError) as e:
+        gpu_lib.nnp_neighbors(system, nl, ws)
+    assert e.value.code == _abi.NNP_EROWLIMIT and nl.capacity == 4 << 20
+
+
 def test_rejects_cutoff_above_half_box(gpu_lib):
     from paper_2602_14975_amd import _abi
     from paper_2602_14975_amd.nnp import DeviceSystem, NeighborList, workspace
