@@ -68,7 +68,7 @@ def message_counts(F, K, n_atoms, n_edges, reverse):
     return flops, nbytes
 
 
-TIMER_SITES = ("message_bwd", "message_fwd", "nc_message_fwd", "head_fwd", "gemm")
+TIMER_SITES = ("message_bwd", "message_fwd", "nc_message_fwd", "nc_update", "head_fwd", "baoa", "gemm")
 
 
 def run_gpu(args):
@@ -511,7 +511,7 @@ def main():
         flops, nbytes = message_counts(F, K, s.n, g["n_edges5"], reverse=False)
         kernels["message_fwd"] = roofline_entry("k_message_fwd_mx (conservative message forward)",
                                                 *kt["message_fwd"], flops, nbytes)
-    for site in ("nc_message_fwd", "head_fwd", "gemm"):
+    for site in ("nc_message_fwd", "nc_update", "head_fwd", "baoa", "gemm"):
         if kt.get(site, (0, 0))[1] > 0:
             tot, cnt = kt[site]
             kernels[site] = {"avg_launch_us": round(tot / cnt * 1e3, 2), "launches": cnt,

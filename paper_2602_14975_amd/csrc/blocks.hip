@@ -214,6 +214,38 @@ __device__ __forceinline__ void head_coeffs(const float* qa, const float* kb, fl
     }
 }
 
+// S = sum_h c_h B_h(r) u(r/rc) over the n_s Bessel heads in one fixed
+// order, ((p0 + p4) + (p2 + p6)) + ((p1 + p5) + (p3 + p7)) with rounded
+// products p_h: the order a butterfly over eight lanes produces, so that
+// the record kernel below, which spreads the heads over lanes, gives the
+// same sums bit for bit.
+__device__ __forceinline__ float head_sum(const float* c, const float* ef) {
+    float p[kNs];
+#pragma unroll
+    for (int h = 0; h < kNs; ++h) p[h] = __fmul_rn(c[h], ef[h]);
+    return ((p[0] + p[4]) + (p[2] + p[6])) + ((p[1] + p[5]) + (p[3] + p[7]));
+}
+
+// The contribution of edge (i, j) to F_i: F_ij - F_ji = S_ij D_ij - S_ji D_ji
+// with D_ij = u + c_ij,s V_i,0 + c_ij,s+1 V_i,1 and D_ji = -u + c_ji,s V_j,0 +
+// c_ji,s+1 V_j,1 (s = n_s), and with VIR its share F_ij . r_ij of the virial
+// proxy in out[3].  Vi, Vj: [n_l][3].  Explicit fused operations fix the
+// rounding.
+template <bool VIR>
+__device__ __forceinline__ void head_pair(float Sij, float Sji, float ci8, float ci9, float cj8, float cj9,
+                                          const float* u, float r, const float (*Vi)[3], const float (*Vj)[3],
+                                          float* out) {
+    float fu = 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float Dij = fmaf(ci9, Vi[1][a], fmaf(ci8, Vi[0][a], u[a]));
+        const float Dji = fmaf(cj9, Vj[1][a], fmaf(cj8, Vj[0][a], -u[a]));
+        out[a] = fmaf(Sij, Dij, -(Sji * Dji));
+        if (VIR) fu = fmaf(Sij * Dij, u[a], fu);
+    }
+    out[3] = VIR ? fu * r : 0.f;
+}
+
 // A group of G lanes per owner atom (64 / G atoms per wavefront); lanes take
 // one CSR entry each.  The contributions of the entries that pass the pair
 // rule are compacted (ballot) into LDS and added by the group's first lane
@@ -266,24 +298,16 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
             float cij[kH], cji[kH];
             head_coeffs(qi, kj, cij);
             head_coeffs(qj, ki, cji);
-            float Sij = 0.f, Sji = 0.f;
+            float Vj[kNl][3];
 #pragma unroll
-            for (int h = 0; h < kNs; ++h) {
-                Sij = fmaf(cij[h], he.ef[h], Sij);
-                Sji = fmaf(cji[h], he.ef[h], Sji);
-            }
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int h = 0; h < kNl; ++h) Vj[h][a] = Vh[(int64_t(j) * 3 + a) * kNl + h];
             const int pre = __popcll(mine & ((1ull << lane) - 1ull));
-            float fu = 0.f;  // F_ij . u
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const float Dij = he.u[a] + cij[kNs] * Vi[0][a] + cij[kNs + 1] * Vi[1][a];
-                const float Dji = -he.u[a] + cji[kNs] * Vh[(int64_t(j) * 3 + a) * kNl] +
-                                  cji[kNs + 1] * Vh[(int64_t(j) * 3 + a) * kNl + 1];
-                // one explicit rounding pattern, whether or not the virial is taken
-                contrib[w][g][pre][a] = fmaf(Sij, Dij, -(Sji * Dji));
-                if (VIR) fu = fmaf(Sij * Dij, he.u[a], fu);
-            }
-            if constexpr (VIR) contrib[w][g][pre][3] = fu * he.r;  // F_ij . r_ij
+            float c[4];
+            head_pair<VIR>(head_sum(cij, he.ef), head_sum(cji, he.ef), cij[kNs], cij[kNs + 1], cji[kNs],
+                           cji[kNs + 1], he.u, he.r, Vi, Vj, c);
+            *reinterpret_cast<float4*>(&contrib[w][g][pre][0]) = make_float4(c[0], c[1], c[2], c[3]);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
@@ -317,13 +341,17 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
 
 // The same head over the records the NC message step left (edges within the
 // cutoff in list order, B_h u, u and r in float32): no pair rule or radial
-// values here.  One wavefront per owner atom, four edges at a time: lane
-// 16 e + h takes head h (h < 10) of edge e, so that the neighbour's q and k
-// rows are read as 32-byte pieces per lane, contiguous across the heads of
-// an edge.  The coefficients come to the edge's first lane, which forms the
-// pair contribution with the sums in the order of the kernel above; the
-// owner's first lane adds the four contributions in record order.  The
-// result is therefore the same, bit for bit, as that kernel's.
+// values here.  One wavefront per four owner atoms, lanes 16 e .. 16 e + 15
+// for owner e, which they walk one edge at a time in record order: lane
+// 16 e + h takes head h (h < 10), so that the neighbour's q and k rows are
+// read as 32-byte pieces per lane, contiguous across the heads of an edge.
+// Everything an edge needs is requested one step ahead: lanes h < 8 read
+// B_h u of the record, lane 8 its u and r and the neighbour's V rows (the
+// first 32 neighbours of each owner are read up front, two per lane).  The
+// head sums S come from a butterfly over lanes 0..7 (the order of
+// head_sum), and lane 8 forms the pair contribution (head_pair) and adds it
+// to the owner's sums: the result is the same, bit for bit, as that of the
+// kernel above.
 template <bool VIR>
 __global__ void __launch_bounds__(256) k_head_fwd_rec(int n, const int* __restrict__ off,
                                                       const int* __restrict__ cnt_in, const NcEdge* __restrict__ rec,
@@ -333,23 +361,29 @@ __global__ void __launch_bounds__(256) k_head_fwd_rec(int n, const int* __restri
     constexpr int HC = 2 * kH * kNc;
     const int lane = threadIdx.x & 63;
     const int e = lane >> 4, h = lane & 15;
-    const int i = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
-    if (i >= n) return;  // whole wavefronts
-    const int e0 = off[i], cnt = cnt_in[i];
+    const int iw = (xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6)) * 4;
+    if (iw >= n) return;  // whole wavefronts
+    const int i = iw + e;
+    const bool own = i < n;
+    const int e0 = own ? off[i] : 0, cnt = own ? cnt_in[i] : 0;
     const int hh = h < kH ? h : 0;
-    float qi[kNc], ki[kNc];
-    {
+    float qi[kNc] = {}, ki[kNc] = {};
+    float Vi[kNl][3] = {};
+    if (own) {
         const float4* q4 = reinterpret_cast<const float4*>(QK + int64_t(i) * HC + hh * kNc);
         const float4* k4 = reinterpret_cast<const float4*>(QK + int64_t(i) * HC + (kH + hh) * kNc);
         const float4 a0 = q4[0], a1 = q4[1], b0 = k4[0], b1 = k4[1];
         qi[0] = a0.x; qi[1] = a0.y; qi[2] = a0.z; qi[3] = a0.w; qi[4] = a1.x; qi[5] = a1.y; qi[6] = a1.z; qi[7] = a1.w;
         ki[0] = b0.x; ki[1] = b0.y; ki[2] = b0.z; ki[3] = b0.w; ki[4] = b1.x; ki[5] = b1.y; ki[6] = b1.z; ki[7] = b1.w;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int l = 0; l < kNl; ++l) Vi[l][a] = Vh[(int64_t(i) * 3 + a) * kNl + l];
     }
-    float Vi[kNl][3];
+    // the longest row of the four
+    int steps = cnt;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int l = 0; l < kNl; ++l) Vi[l][a] = Vh[(int64_t(i) * 3 + a) * kNl + l];
+    for (int m = 16; m <= 32; m <<= 1) steps = max(steps, __shfl_xor(steps, m, 64));
     const float scale = 0.35355339059327373f;  // 1/sqrt(n_c), n_c = 8
     // q_a . k_b over the channels in the order of head_coeffs
     auto dot8 = [](const float* a, const float4& b0, const float4& b1) {
@@ -366,81 +400,69 @@ __global__ void __launch_bounds__(256) k_head_fwd_rec(int n, const int* __restri
         acc = fmaf(a1.w, b[7], acc);
         return acc;
     };
-    float fx = 0.f, fy = 0.f, fz = 0.f, vr = 0.f;  // running sums (lane 0)
-    // the neighbours of the first 64 edges, one per lane, read up front; the
-    // rows of the next four edges are requested before the current four are
-    // reduced
-    const int jl = lane < cnt ? rec[e0 + lane].j : 0;
-    auto neighbour = [&](int ee) {
-        const int jj = __shfl(jl, ee & 63, 64);  // by every lane: no divergent shuffle
-        return ee < 64 ? jj : rec[e0 + ee].j;
+    // what one lane holds of an edge: its head's q and k rows of the
+    // neighbour; B_h u (h < 8); u, r and the neighbour's V (h = 8)
+    struct Pre {
+        float4 q0, q1, k0, k1;
+        float ef, u[3], r;
+        float2 vj[3];
     };
-    auto fetch = [&](int j, float4* r) {
+    // neighbours of the owner's first 32 edges: lane 16 e + h holds those of
+    // edges h and 16 + h
+    const int jl0 = h < cnt ? rec[e0 + h].j : 0;
+    const int jl1 = 16 + h < cnt ? rec[e0 + 16 + h].j : 0;
+    // edge t of this lane's owner (t < cnt); every lane takes part in the shuffles
+    auto fetch = [&](int t, Pre& p) {
+        const int tt = t & 15;
+        const int a0 = __shfl(jl0, 16 * e + tt, 64), a1 = __shfl(jl1, 16 * e + tt, 64);
+        if (t >= cnt) return;
+        const int j = t < 16 ? a0 : t < 32 ? a1 : rec[e0 + t].j;
+        const NcEdge* re = rec + e0 + t;
         if (h < kH) {
             const float4* q4 = reinterpret_cast<const float4*>(QK + int64_t(j) * HC + h * kNc);
             const float4* k4 = reinterpret_cast<const float4*>(QK + int64_t(j) * HC + (kH + h) * kNc);
-            r[0] = q4[0]; r[1] = q4[1]; r[2] = k4[0]; r[3] = k4[1];
+            p.q0 = q4[0]; p.q1 = q4[1]; p.k0 = k4[0]; p.k1 = k4[1];
+        }
+        if (h < kNs) p.ef = re->ef[h];
+        if (h == kNs) {
+            p.u[0] = re->u[0]; p.u[1] = re->u[1]; p.u[2] = re->u[2];
+            p.r = re->r;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) p.vj[a] = *reinterpret_cast<const float2*>(Vh + (int64_t(j) * 3 + a) * kNl);
         }
     };
-    float4 cur[4] = {}, nxt[4] = {};
-    int jc = neighbour(e < cnt ? e : 0);
-    fetch(jc, cur);
-    for (int base = 0; base < cnt; base += 4) {
-        const int ee = base + e;
-        const bool ok = ee < cnt;
-        const NcEdge& he = rec[e0 + (ok ? ee : 0)];
-        const int j = jc;
-        if (base + 4 < cnt) {
-            jc = neighbour(base + 4 + e < cnt ? base + 4 + e : base + 4);
-            fetch(jc, nxt);
-        }
+    float fx = 0.f, fy = 0.f, fz = 0.f, vr = 0.f;  // the owner's sums (lane 16 e + 8)
+    Pre cur{}, nxt{};
+    fetch(0, cur);
+    for (int t = 0; t < steps; ++t) {
+        if (t + 1 < steps) fetch(t + 1, nxt);
         float cij = 0.f, cji = 0.f;
         if (h < kH) {
-            cij = dot8(qi, cur[2], cur[3]) * scale;   // q_i . k_j
-            cji = dot8r(cur[0], cur[1], ki) * scale;  // q_j . k_i
+            cij = dot8(qi, cur.k0, cur.k1) * scale;   // q_i . k_j
+            cji = dot8r(cur.q0, cur.q1, ki) * scale;  // q_j . k_i
         }
+        // S over lanes 0..7 of the owner (butterfly 4, 2, 1)
+        float pij = h < kNs ? __fmul_rn(cij, cur.ef) : 0.f;
+        float pji = h < kNs ? __fmul_rn(cji, cur.ef) : 0.f;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) cur[t] = nxt[t];
-        // the coefficients of every head at the edge's first lane
-        float ci[kH], cj[kH];
-#pragma unroll
-        for (int t = 0; t < kH; ++t) {
-            ci[t] = __shfl(cij, 16 * e + t, 64);
-            cj[t] = __shfl(cji, 16 * e + t, 64);
+        for (int m = 4; m >= 1; m >>= 1) {
+            pij += __shfl_xor(pij, m, 64);
+            pji += __shfl_xor(pji, m, 64);
         }
-        float c[4] = {0.f, 0.f, 0.f, 0.f};
-        if (h == 0 && ok) {
-            float Sij = 0.f, Sji = 0.f;
-#pragma unroll
-            for (int t = 0; t < kNs; ++t) {
-                Sij = fmaf(ci[t], he.ef[t], Sij);
-                Sji = fmaf(cj[t], he.ef[t], Sji);
-            }
-            float fu = 0.f;  // F_ij . u
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const float Dij = he.u[a] + ci[kNs] * Vi[0][a] + ci[kNs + 1] * Vi[1][a];
-                const float Dji = -he.u[a] + cj[kNs] * Vh[(int64_t(j) * 3 + a) * kNl] +
-                                  cj[kNs + 1] * Vh[(int64_t(j) * 3 + a) * kNl + 1];
-                c[a] = fmaf(Sij, Dij, -(Sji * Dji));
-                if (VIR) fu = fmaf(Sij * Dij, he.u[a], fu);
-            }
-            if constexpr (VIR) c[3] = fu * he.r;  // F_ij . r_ij
+        const float Sij = __shfl(pij, 16 * e, 64), Sji = __shfl(pji, 16 * e, 64);
+        const float ci9 = __shfl(cij, 16 * e + kNs + 1, 64), cj9 = __shfl(cji, 16 * e + kNs + 1, 64);
+        if (h == kNs && t < cnt) {
+            const float Vj[kNl][3] = {{cur.vj[0].x, cur.vj[1].x, cur.vj[2].x}, {cur.vj[0].y, cur.vj[1].y, cur.vj[2].y}};
+            float c[4];
+            head_pair<VIR>(Sij, Sji, cij, ci9, cji, cj9, cur.u, cur.r, Vi, Vj, c);
+            fx += c[0];
+            fy += c[1];
+            fz += c[2];
+            if constexpr (VIR) vr += c[3];
         }
-        // the owner's sums, edge by edge in record order
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const float cx = __shfl(c[0], 16 * t, 64), cy = __shfl(c[1], 16 * t, 64),
-                        cz = __shfl(c[2], 16 * t, 64), cw = VIR ? __shfl(c[3], 16 * t, 64) : 0.f;
-            if (base + t < cnt) {
-                fx += cx;
-                fy += cy;
-                fz += cz;
-                if constexpr (VIR) vr += cw;
-            }
-        }
+        cur = nxt;
     }
-    if (lane == 0) {
+    if (own && h == kNs) {
         if (accum) {
             Fout[i] += fx; Fout[n + i] += fy; Fout[2 * n + i] += fz;
         } else {
@@ -932,9 +954,9 @@ void launch_head_fwd_rec(const MpGeom& mg, const int* cnt, const NcEdge* rec, co
     ScopedTimer timer("head_fwd", st);
     // one wavefront per owner atom
     if (vir_set || vir_add)
-        k_head_fwd_rec<true><<<cdiv(mg.n, 4), 256, 0, st>>>(mg.n, mg.off, cnt, rec, QK, Vh, F, accum, vir_set, vir_add);
+        k_head_fwd_rec<true><<<cdiv(mg.n, 16), 256, 0, st>>>(mg.n, mg.off, cnt, rec, QK, Vh, F, accum, vir_set, vir_add);
     else
-        k_head_fwd_rec<false><<<cdiv(mg.n, 4), 256, 0, st>>>(mg.n, mg.off, cnt, rec, QK, Vh, F, accum, nullptr,
+        k_head_fwd_rec<false><<<cdiv(mg.n, 16), 256, 0, st>>>(mg.n, mg.off, cnt, rec, QK, Vh, F, accum, nullptr,
                                                               nullptr);
     NNP_LAUNCH_CHECK();
 }
