@@ -218,3 +218,32 @@ def test_bf16_forces_within_bound(gpu_lib, which):
     assert err_c > 1e-6  # the BF16 path is really taken
     f64 = f.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(f64.sum(1)) <= 1e-5 * np.abs(f64).sum()
+
+
+def test_chain_workload_forces_fp32_and_bf16(gpu_lib):
+    """The 600-heavy-atom chain of the solvated-chain workload (its seed and
+    composition) in 3,500 waters (12,043 atoms; the workload has 30,000):
+    FP32 and BF16 conservative and NC forces against the oracle, with the
+    workload's model widths."""
+    from paper_2602_14975_amd import _abi
+    from paper_2602_14975_amd.nnp import DeviceSystem, workspace
+    s = synth.solvated_chain(600, 3500, seed=1002)
+    print(f"case chain workload n={s.n}", flush=True)
+    cw = synth.random_weights(synth.CONS_CFG1, 2004)
+    nw = synth.random_weights(synth.NC_CFG1, 3004)
+    off, nbr = oracle_list(s.pos, s.box, 5.0)
+    E, F = om.cons_energy_forces(synth.CONS_CFG1, cw, s.pos, s.species, s.box, off, nbr)
+    off3, nbr3 = oracle_list(s.pos, s.box, 3.5)
+    Fn = om.nc_forces(synth.NC_CFG1, nw, s.pos, s.species, s.box, off3, nbr3)
+    system = DeviceSystem(s.pos, s.species, s.box)
+    nl = gpu_list(gpu_lib, system, 5.0)
+    for prec, tol in ((_abi.NNP_FP32, FP32_TOL), (_abi.NNP_BF16, BF16_TOL)):
+        cons = gpu_lib.Model.from_spec(synth.CONS_CFG1, cw, precision=prec)
+        nc = gpu_lib.Model.from_spec(synth.NC_CFG1, nw, precision=prec)
+        ws = workspace(cons, nc, system.n, 1, nl.capacity)
+        e, f = gpu_lib.nnp_cons_energy_forces(cons, system, nl, ws)
+        fn = gpu_lib.nnp_nc_forces(nc, system, nl, ws)
+        err_c = rel_rmse(f.cpu().numpy().T, F)
+        err_n = rel_rmse(fn.cpu().numpy().T, Fn)
+        print(f"chain workload precision {prec}: force rel RMSE cons {err_c:.2e} nc {err_n:.2e}", flush=True)
+        assert err_c <= tol and err_n <= tol
