@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <map>
 #include <mutex>
 
 #include "common.h"
@@ -1048,6 +1049,34 @@ __global__ void k_disagreement_final(const int64_t* __restrict__ rep_start, int 
 constexpr nnp_status NNP_ESTALE_INTERNAL = static_cast<nnp_status>(-100);
 constexpr nnp_status NNP_EREWIND_INTERNAL = static_cast<nnp_status>(-101);
 
+// A second stream of the calling host thread on the current device, with a
+// fork and a join event (created on first use, kept until the process ends;
+// default priority).  The conservative evaluation at the end of an outer
+// step runs there beside the last inner evaluation.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+static const SideStream* side_stream() {
+    thread_local std::map<int, SideStream> per_device;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    auto it = per_device.find(dev);
+    if (it == per_device.end()) {
+        SideStream x;
+        const bool ok = hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking) == hipSuccess &&
+                        hipEventCreateWithFlags(&x.fork, hipEventDisableTiming) == hipSuccess &&
+                        hipEventCreateWithFlags(&x.join, hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        it = per_device.emplace(dev, x).first;
+    }
+    return &it->second;
+}
+
 nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const respa_params* p, int32_t n_outer,
                      void* ws, size_t ws_bytes, hipStream_t s, const uint64_t* seeds, const uint64_t* streams,
                      const uint64_t* step_base, int* rep_bad, uint64_t* stamps) {
@@ -1260,6 +1289,24 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     // whose displacement check fires.  Both give the same numbers whenever
     // no stale flag is raised (results do not depend on when lists are built).
     // (launches only; the caller advances offset and st->step by n_in)
+    // The conservative evaluation at the end of the outer step reads the
+    // positions the last inner BAOA fixed and writes only its own buffers:
+    // it runs on the side stream beside the last inner evaluation and the
+    // closing kick, and is joined before the outer kick.
+    const SideStream* side = mts ? side_stream() : nullptr;
+    auto eval_cons_beside = [&]() {
+        NNP_HIP(hipEventRecord(side->fork, s));
+        NNP_HIP(hipStreamWaitEvent(side->s, side->fork, 0));
+        const hipStream_t main = s;
+        struct Restore {
+            hipStream_t& ref;
+            hipStream_t v;
+            ~Restore() { ref = v; }
+        } restore{s, main};
+        s = side->s;
+        eval_cons();
+        NNP_HIP(hipEventRecord(side->join, side->s));
+    };
     auto mts_launches = [&](bool strict) {
         if (!strict) {
             launch_predict_rebuild(maxd2, disp_thr, trig, s);
@@ -1279,10 +1326,12 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
             ba.step_offset = uint64_t(k);
             launch_baoa(ba, s);
             if (strict) rebuild_if_flagged();
+            if (side && k == n_in - 1) eval_cons_beside();
             eval_inner();
         }
         launch_kick(n, st->vel, st->mass, st->f_nc, nullptr, 0.5 * d, s, c.t.o_step, uint64_t(n_in));
-        eval_cons();
+        if (side) NNP_HIP(hipStreamWaitEvent(s, side->join, 0));
+        else eval_cons();
         if (want_vir) {
             launch_virial_combine(n, c.cons.vir, c.nc.vir, c.nc.vir_sum, float(1.0 / n_in), c.cons.vir_sum, s);
             launch_rep_sum(R, c.t.rep_start, c.cons.vir_sum, st->virial, s);
