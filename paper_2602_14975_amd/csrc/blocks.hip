@@ -220,9 +220,10 @@ __device__ __forceinline__ void head_coeffs(const float* qa, const float* kb, fl
 // the record kernel below, which spreads the heads over lanes, gives the
 // same sums bit for bit.
 __device__ __forceinline__ float head_sum(const float* c, const float* ef) {
+#pragma clang fp contract(off)  // rounded products: no product may fuse into the sums
     float p[kNs];
 #pragma unroll
-    for (int h = 0; h < kNs; ++h) p[h] = __fmul_rn(c[h], ef[h]);
+    for (int h = 0; h < kNs; ++h) p[h] = c[h] * ef[h];
     return ((p[0] + p[4]) + (p[2] + p[6])) + ((p[1] + p[5]) + (p[3] + p[7]));
 }
 
@@ -441,13 +442,18 @@ __global__ void __launch_bounds__(256) k_head_fwd_rec(int n, const int* __restri
             cij = dot8(qi, cur.k0, cur.k1) * scale;   // q_i . k_j
             cji = dot8r(cur.q0, cur.q1, ki) * scale;  // q_j . k_i
         }
-        // S over lanes 0..7 of the owner (butterfly 4, 2, 1)
-        float pij = h < kNs ? __fmul_rn(cij, cur.ef) : 0.f;
-        float pji = h < kNs ? __fmul_rn(cji, cur.ef) : 0.f;
+        // S over lanes 0..7 of the owner (butterfly 4, 2, 1; rounded products
+        // as in head_sum)
+        float pij, pji;
+        {
+#pragma clang fp contract(off)
+            pij = h < kNs ? cij * cur.ef : 0.f;
+            pji = h < kNs ? cji * cur.ef : 0.f;
 #pragma unroll
-        for (int m = 4; m >= 1; m >>= 1) {
-            pij += __shfl_xor(pij, m, 64);
-            pji += __shfl_xor(pji, m, 64);
+            for (int m = 4; m >= 1; m >>= 1) {
+                pij += __shfl_xor(pij, m, 64);
+                pji += __shfl_xor(pji, m, 64);
+            }
         }
         const float Sij = __shfl(pij, 16 * e, 64), Sji = __shfl(pji, 16 * e, 64);
         const float ci9 = __shfl(cij, 16 * e + kNs + 1, 64), cj9 = __shfl(cji, 16 * e + kNs + 1, 64);
