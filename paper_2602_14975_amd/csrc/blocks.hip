@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
 // for owner e, which they walk one edge at a time in record order: lane
 // 16 e + h takes head h (h < 10), so that the neighbour's q and k rows are
 // read as 32-byte pieces per lane, contiguous across the heads of an edge.
-// Everything an edge needs is requested one step ahead: lanes h < 8 read
+// Everything an edge needs is requested three edges ahead: lanes h < 8 read
 // B_h u of the record, lane 8 its u and r and the neighbour's V rows (the
 // first 32 neighbours of each owner are read up front, two per lane).  The
 // head sums S come from a butterfly over lanes 0..7 (the order of
@@ -433,10 +433,8 @@ __global__ void __launch_bounds__(256) k_head_fwd_rec(int n, const int* __restri
         }
     };
     float fx = 0.f, fy = 0.f, fz = 0.f, vr = 0.f;  // the owner's sums (lane 16 e + 8)
-    Pre cur{}, nxt{};
-    fetch(0, cur);
-    for (int t = 0; t < steps; ++t) {
-        if (t + 1 < steps) fetch(t + 1, nxt);
+    // edge t with its operands in `cur`
+    auto edge_step = [&](int t, const Pre& cur) {
         float cij = 0.f, cji = 0.f;
         if (h < kH) {
             cij = dot8(qi, cur.k0, cur.k1) * scale;   // q_i . k_j
@@ -466,7 +464,24 @@ __global__ void __launch_bounds__(256) k_head_fwd_rec(int n, const int* __restri
             fz += c[2];
             if constexpr (VIR) vr += c[3];
         }
-        cur = nxt;
+    };
+    // three edges in flight: the operands of edge t + 3 are requested as
+    // soon as edge t is done with its stage
+    Pre p0{}, p1{}, p2{};
+    fetch(0, p0);
+    if (1 < steps) fetch(1, p1);
+    if (2 < steps) fetch(2, p2);
+    for (int t = 0; t < steps; t += 3) {
+        edge_step(t, p0);
+        if (t + 3 < steps) fetch(t + 3, p0);
+        if (t + 1 < steps) {
+            edge_step(t + 1, p1);
+            if (t + 4 < steps) fetch(t + 4, p1);
+        }
+        if (t + 2 < steps) {
+            edge_step(t + 2, p2);
+            if (t + 5 < steps) fetch(t + 5, p2);
+        }
     }
     if (own && h == kNs) {
         if (accum) {
