@@ -654,7 +654,6 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
     float* m2 = m1 + F;                // [3F]
     float* work = m2 + 3 * F;          // per atom: sm[F], vm[3F], x[2F], z[F], so[F], vo[3F]
     auto rnd = [](float x) { return BF16 ? bf16_round(x) : x; };
-    auto rnd4 = [&](float4 v) { return float4{rnd(v.x), rnd(v.y), rnd(v.z), rnd(v.w)}; };
     auto ld4 = [](const float* p) { return *reinterpret_cast<const float4*>(p); };
     constexpr int NW = int(nc_image_floats(F));
     static_assert(NW % 4 == 0, "image of whole 16-byte units");
@@ -690,13 +689,21 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
     const int n = a.n;
     for (int base = blockIdx.x * APB; base < n; base += gridDim.x * APB) {
         __syncthreads();  // weights staged / previous pass done with the work rows
+        // the work rows hold perceptron inputs as the products read them
+        // (rounded once here for BF16 models); the lane keeps its own
+        // columns of s and v unrounded for the residual sums
+        float s_own[NA], v_own[NA][3];
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
             const int i = base + g + u * GPB;
             const bool act = i < n;
-            sm[u][f] = act ? a.smid[int64_t(i) * F + f] : 0.f;
+            s_own[u] = act ? a.smid[int64_t(i) * F + f] : 0.f;
+            sm[u][f] = rnd(s_own[u]);
 #pragma unroll
-            for (int al = 0; al < 3; ++al) vm[u][al * F + f] = act ? a.vmid[(int64_t(i) * 3 + al) * F + f] : 0.f;
+            for (int al = 0; al < 3; ++al) {
+                v_own[u][al] = act ? a.vmid[(int64_t(i) * 3 + al) * F + f] : 0.f;
+                vm[u][al * F + f] = rnd(v_own[u][al]);
+            }
         }
         __syncthreads();
         float Uv[NA][3] = {}, Vv[NA][3] = {};
@@ -711,7 +718,7 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
                 for (int u = 0; u < NA; ++u)
 #pragma unroll
                     for (int al = 0; al < 3; ++al) {
-                        const float4 vk = rnd4(ld4(vm[u] + al * F + k));
+                        const float4 vk = ld4(vm[u] + al * F + k);
                         Uv[u][al] = fmaf(uw.x, vk.x, Uv[u][al]);
                         Vv[u][al] = fmaf(vw.x, vk.x, Vv[u][al]);
                         Uv[u][al] = fmaf(uw.y, vk.y, Uv[u][al]);
@@ -729,7 +736,7 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
 #pragma unroll
             for (int al = 0; al < 3; ++al) nn = fmaf(Vv[u][al], Vv[u][al], nn);
             x[u][f] = sm[u][f];
-            x[u][F + f] = sqrtf(nn);
+            x[u][F + f] = rnd(sqrtf(nn));
         }
         __syncthreads();
         {
@@ -742,7 +749,7 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
                 const float4 w = ld4(wr + k);
 #pragma unroll
                 for (int u = 0; u < NA; ++u) {
-                    const float4 xv = rnd4(ld4(x[u] + k));
+                    const float4 xv = ld4(x[u] + k);
                     a1[u] = fmaf(w.x, xv.x, a1[u]);
                     a1[u] = fmaf(w.y, xv.y, a1[u]);
                     a1[u] = fmaf(w.z, xv.z, a1[u]);
@@ -750,7 +757,7 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
                 }
             }
 #pragma unroll
-            for (int u = 0; u < NA; ++u) z[u][f] = silu(a1[u]);
+            for (int u = 0; u < NA; ++u) z[u][f] = rnd(silu(a1[u]));
         }
         __syncthreads();
         float pq[NA][3];
@@ -762,7 +769,7 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
         for (int k = 0; k < F; k += 4) {
             float4 zk[NA];
 #pragma unroll
-            for (int u = 0; u < NA; ++u) zk[u] = rnd4(ld4(z[u] + k));
+            for (int u = 0; u < NA; ++u) zk[u] = ld4(z[u] + k);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const float4 w = ld4(M2 + (c * F + f) * P1 + k);
@@ -778,9 +785,9 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
 #pragma unroll
         for (int u = 0; u < NA; ++u) {
             const float dot = Uv[u][0] * Vv[u][0] + Uv[u][1] * Vv[u][1] + Uv[u][2] * Vv[u][2];
-            so[u][f] = sm[u][f] + pq[u][0] + pq[u][1] * dot;
+            so[u][f] = rnd(s_own[u] + pq[u][0] + pq[u][1] * dot);
 #pragma unroll
-            for (int al = 0; al < 3; ++al) vo[u][al * F + f] = vm[u][al * F + f] + pq[u][2] * Uv[u][al];
+            for (int al = 0; al < 3; ++al) vo[u][al * F + f] = rnd(v_own[u][al] + pq[u][2] * Uv[u][al]);
         }
         __syncthreads();
         {
@@ -791,7 +798,7 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
             for (int k = 0; k < F; k += 4) {
                 float4 sv[NA];
 #pragma unroll
-                for (int u = 0; u < NA; ++u) sv[u] = rnd4(ld4(so[u] + k));
+                for (int u = 0; u < NA; ++u) sv[u] = ld4(so[u] + k);
 #pragma unroll
                 for (int q = 0; q < QPL; ++q) {
                     const float4 w = ld4(Q + (f + q * F) * P1 + k);
@@ -822,7 +829,7 @@ __global__ void __launch_bounds__(256) k_nc_update_proj(NcUpdateArgs a) {
                 const float4 w = ld4(wr + k);
 #pragma unroll
                 for (int u = 0; u < NA; ++u) {
-                    const float4 vv = rnd4(ld4(vo[u] + al * F + k));
+                    const float4 vv = ld4(vo[u] + al * F + k);
                     acc[u] = fmaf(w.x, vv.x, acc[u]);
                     acc[u] = fmaf(w.y, vv.y, acc[u]);
                     acc[u] = fmaf(w.z, vv.z, acc[u]);
