@@ -393,13 +393,52 @@ struct BwdAcc {
     float gph0, gph2, GV[3], S1[3], T1, T2[3], vir;
 };
 
-// One batch of nb <= 16 edges; the lane's eight edges are taken kBwdGroup at
-// a time as in the forward batch.
+// The split filter operands of a lane in LDS: pieces bh[0..2], bl[0..2],
+// then bb[0], bb[1] and bb[2] (8 bytes each) in pieces 6 and 7, each piece
+// at stride 64 (one lane's) so that a wavefront reads 1 KB contiguously.
+constexpr int kFiltPieces = 8;
+
+__device__ __forceinline__ void store_filter(uint4* fl, const half8_t* bh, const half8_t* bl, const half4_t* bb) {
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        fl[p * 64] = __builtin_bit_cast(uint4, bh[p]);
+        fl[(3 + p) * 64] = __builtin_bit_cast(uint4, bl[p]);
+    }
+    const uint2 b0 = __builtin_bit_cast(uint2, bb[0]), b1 = __builtin_bit_cast(uint2, bb[1]),
+                b2 = __builtin_bit_cast(uint2, bb[2]);
+    fl[6 * 64] = make_uint4(b0.x, b0.y, b1.x, b1.y);
+    fl[7 * 64] = make_uint4(b2.x, b2.y, 0u, 0u);
+}
+
+__device__ __forceinline__ void load_channel(const uint4* fl, int p, half8_t& bh, half8_t& bl, half4_t& bb) {
+    bh = as_half8(fl[p * 64]);
+    bl = as_half8(fl[(3 + p) * 64]);
+    const uint4 q = fl[(6 + p / 2) * 64];
+    bb = __builtin_bit_cast(half4_t, p % 2 == 0 ? make_uint2(q.x, q.y) : make_uint2(q.z, q.w));
+}
+
+// The neighbour rows one group of edges needs (phi_b of the neighbour
+// enters only as phi_b v_n, read as one product; phi, pv and the vector
+// adjoints have rows of 3F floats, one byte offset per edge serves them,
+// the scalar adjoints rows of F).
+template <int G>
+struct BwdGather {
+    float pa[G], pc[G], pvn[G][3], gn[G][3], gsn[G];
+};
+
+// One batch of nb <= 16 edges.  The lane's eight edges are taken kBwdGroup
+// at a time (an invalid edge of a partial batch reads the batch's first
+// edge and contributes nothing).  Past the first layer the rows of the next
+// group are requested before the current one is reduced, and the filter
+// operands come from LDS (fl) for the products only, which keeps their
+// registers free for the second group; the first layer, with fewer rows per
+// edge and room for a fourth wavefront per SIMD, keeps its operands in
+// registers (bhr, blr, bbr) and takes the groups one after the other.
 template <bool L0, bool VIR>
 __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, const BatchBuf<16>& buf, int nb, int f,
-                                          int h, const half8_t* bh, const half8_t* bl, const half4_t* bb,
-                                          const float* b0, const Owner& o, BwdAcc& acc) {
-    constexpr int F = kMxF, E = 8;
+                                          int h, const uint4* fl, const half8_t* bhr, const half8_t* blr,
+                                          const half4_t* bbr, const float* b0, const Owner& o, BwdAcc& acc) {
+    constexpr int F = kMxF, E = 8, G = kBwdGroup<L0>;
     const EdgeRec* rec = buf.rec;
     // A rows 0..15: e_k f of edges 0..15, rows 16..31: their r-derivatives
     // (zero past nb: staged as zeros), and the bias rows f or f'
@@ -408,20 +447,24 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
     // the first layer adds the biases in the per-edge work instead: the
     // bias operands would cost it the registers of a fourth wavefront per SIMD
     const half4_t ab = L0 ? half4_t{} : bias_rows(part ? rec[e].dfc : rec[e].fc, h);
-    const floatx16_t m0 = mma3<!L0>(ab, bb[0], ah, al, bh[0], bl[0]);
-    // the b channel gates v, zero in the first layer: nothing of it reaches
-    // the forces there
-    floatx16_t m1 = {};
-    if constexpr (!L0) m1 = mma3(ab, bb[1], ah, al, bh[1], bl[1]);
-    const floatx16_t m2 = mma3<!L0>(ab, bb[2], ah, al, bh[2], bl[2]);
+    floatx16_t m0, m1 = {}, m2;
+    if constexpr (L0) {
+        // the b channel gates v, zero in the first layer: nothing of it
+        // reaches the forces there
+        m0 = mma3<false>(ab, bbr[0], ah, al, bhr[0], blr[0]);
+        m2 = mma3<false>(ab, bbr[2], ah, al, bhr[2], blr[2]);
+    } else {
+        half8_t bh, bl;
+        half4_t bb;
+        load_channel(fl, 0, bh, bl, bb);
+        m0 = mma3(ab, bb, ah, al, bh, bl);
+        load_channel(fl, 1, bh, bl, bb);
+        m1 = mma3(ab, bb, ah, al, bh, bl);
+        load_channel(fl, 2, bh, bl, bb);
+        m2 = mma3(ab, bb, ah, al, bh, bl);
+    }
     const uint32_t fo = uint32_t(f) * 4u;
-#pragma unroll
-    for (int g0 = 0; g0 < E; g0 += kBwdGroup<L0>) {
-        constexpr int G = kBwdGroup<L0>;
-        // phi_b of the neighbour enters only as phi_b v_n, read as one
-        // product; phi, pv and the vector adjoints have rows of 3F floats
-        // (one byte offset per edge), the scalar adjoints rows of F
-        float pa[G], pc[G], pvn[G][3], gn[G][3], gsn[G];
+    auto gather = [&](int g0, BwdGather<G>& d) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int q = g0 + g;
@@ -431,20 +474,22 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
             const uint32_t off3 = j * (3u * F * 4u) + fo;
             if (L0) {
                 const float* phj = ptab + s.t * 3 * F + f;
-                pa[g] = phj[0];
-                pc[g] = phj[2 * F];
+                d.pa[g] = phj[0];
+                d.pc[g] = phj[2 * F];
             } else {
-                pa[g] = ld_off(a.phi, off3);
-                pc[g] = ld_off(a.phi, off3 + 2 * F * 4);
-                pvn[g][0] = ld_off(a.pv, off3);
-                pvn[g][1] = ld_off(a.pv, off3 + F * 4);
-                pvn[g][2] = ld_off(a.pv, off3 + 2 * F * 4);
+                d.pa[g] = ld_off(a.phi, off3);
+                d.pc[g] = ld_off(a.phi, off3 + 2 * F * 4);
+                d.pvn[g][0] = ld_off(a.pv, off3);
+                d.pvn[g][1] = ld_off(a.pv, off3 + F * 4);
+                d.pvn[g][2] = ld_off(a.pv, off3 + 2 * F * 4);
             }
-            gn[g][0] = ld_off(a.gvm, off3);
-            gn[g][1] = ld_off(a.gvm, off3 + F * 4);
-            gn[g][2] = ld_off(a.gvm, off3 + 2 * F * 4);
-            gsn[g] = ld_off(a.gsm, j * (F * 4u) + fo);
+            d.gn[g][0] = ld_off(a.gvm, off3);
+            d.gn[g][1] = ld_off(a.gvm, off3 + F * 4);
+            d.gn[g][2] = ld_off(a.gvm, off3 + 2 * F * 4);
+            d.gsn[g] = ld_off(a.gsm, j * (F * 4u) + fo);
         }
+    };
+    auto reduce = [&](int g0, const BwdGather<G>& d) {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int q = g0 + g;
@@ -461,20 +506,21 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
                 dw2 = fmaf(b0[2], s.dfc, dw2);
             }
             const float u0 = s.u[0], u1 = s.u[1], u2 = s.u[2];
-            const float g0v = gn[g][0], g1v = gn[g][1], g2v = gn[g][2];
+            const float g0v = d.gn[g][0], g1v = d.gn[g][1], g2v = d.gn[g][2];
             const float gvn_u = fmaf(g2v, u2, fmaf(g1v, u1, g0v * u0));
             const float gvo_u = fmaf(o.gv[2], u2, fmaf(o.gv[1], u1, o.gv[0] * u0));
             // filter adjoints of both messages of the pair (n -> o and o -> n),
             // contracted with dw/dr
-            const float A = fmaf(o.gs, pa[g], o.ph[0] * gsn[g]);
-            const float C = fmaf(pc[g], gvo_u, -(o.ph[2] * gvn_u));
+            const float A = fmaf(o.gs, d.pa[g], o.ph[0] * d.gsn[g]);
+            const float C = fmaf(d.pc[g], gvo_u, -(o.ph[2] * gvn_u));
             float dr;
             if constexpr (L0) {
                 dr = fmaf(A, dw0, C * dw2);
             } else {
                 const float w1 = m1[q], dw1 = m1[8 + q];
                 const float gvn_vo = fmaf(g2v, o.v[2], fmaf(g1v, o.v[1], g0v * o.v[0]));
-                const float gvo_pvn = fmaf(o.gv[2], pvn[g][2], fmaf(o.gv[1], pvn[g][1], o.gv[0] * pvn[g][0]));
+                const float gvo_pvn =
+                    fmaf(o.gv[2], d.pvn[g][2], fmaf(o.gv[1], d.pvn[g][1], o.gv[0] * d.pvn[g][0]));
                 const float B = fmaf(o.ph[1], gvn_vo, gvo_pvn);
                 dr = fmaf(A, dw0, fmaf(B, dw1, C * dw2));
                 acc.GV[0] = fmaf(w1, g0v, acc.GV[0]);
@@ -482,7 +528,7 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
                 acc.GV[2] = fmaf(w1, g2v, acc.GV[2]);
             }
             // g_u . u of the unit-vector adjoints, from the projections above
-            const float cA = pc[g] * w2;
+            const float cA = d.pc[g] * w2;
             const float ud = fmaf(cA, gvo_u, -((o.ph[2] * w2) * gvn_u));
             const float sv = fmaf(-ud, ir, dr);
             acc.S1[0] = fmaf(sv, u0, acc.S1[0]);
@@ -494,10 +540,30 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
             acc.T2[1] = fmaf(w2ir, g1v, acc.T2[1]);
             acc.T2[2] = fmaf(w2ir, g2v, acc.T2[2]);
             // o as the sender of the message o -> n
-            acc.gph0 = fmaf(gsn[g], w0, acc.gph0);
+            acc.gph0 = fmaf(d.gsn[g], w0, acc.gph0);
             acc.gph2 = fmaf(-w2, gvn_u, acc.gph2);
             // r_ij . (pair force share): the projected term is normal to u
             if constexpr (VIR) acc.vir += __fdividef(dr, ir);
+        }
+    };
+    if constexpr (L0) {
+#pragma unroll
+        for (int g0 = 0; g0 < E; g0 += G) {
+            BwdGather<G> d;
+            gather(g0, d);
+            reduce(g0, d);
+        }
+    } else {
+        BwdGather<G> d0, d1;
+        gather(0, d0);
+#pragma unroll
+        for (int g0 = 0; g0 < E; g0 += 2 * G) {
+            if (g0 + G < E) gather(g0 + G, d1);
+            reduce(g0, d0);
+            if (g0 + G < E) {
+                if (g0 + 2 * G < E) gather(g0 + 2 * G, d0);
+                reduce(g0 + G, d1);
+            }
         }
     }
 }
@@ -517,9 +583,17 @@ __global__ void __launch_bounds__(64 * kMxWaves, 3) k_message_bwd_mx(MpGeom mg, 
         __syncthreads();
     }
     const float sc = a.mx_scale[0], isc = a.mx_scale[1];
+    // this lane's split filter operands: past the first layer kept in LDS
+    // between the batches, in the first layer in registers
+    __shared__ __align__(16) uint4 filt_s[L0 ? 1 : kMxWaves][L0 ? 1 : kFiltPieces][64];
+    uint4* fl = L0 ? nullptr : &filt_s[L0 ? 0 : w][0][lane];
     half8_t bh[3], bl[3];
     half4_t bb[3];
     load_filter(a.Wr, a.br, sc, f, h, bh, bl, bb);
+    if constexpr (!L0) {
+        store_filter(fl, bh, bl, bb);
+        wave_sync_lds();
+    }
     float bf[3] = {};  // the scaled biases, for the first layer's per-edge work
     if constexpr (L0) {
 #pragma unroll
@@ -555,7 +629,7 @@ __global__ void __launch_bounds__(64 * kMxWaves, 3) k_message_bwd_mx(MpGeom mg, 
             __syncthreads();  // the batch is staged; the other buffer's batch is done
             nx = next_batch<BATCH>(mg, i0, ai, b0, cnt);
             piece = fetch_piece<BATCH>(mg, nx.p0, nx.nb);
-            bwd_batch<L0, VIR>(a, ptab_s, b, min(BATCH, cnt - b0), f, h, bh, bl, bb, bf, o, acc);
+            bwd_batch<L0, VIR>(a, ptab_s, b, min(BATCH, cnt - b0), f, h, fl, bh, bl, bb, bf, o, acc);
         }
         // the lane's force share, then both halves of the wavefront (partial
         // sums of feature f) and the features of the wavefront
