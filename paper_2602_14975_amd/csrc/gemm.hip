@@ -288,17 +288,38 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4_v __attribute__((ext_vector_type(4)));
 
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// Two floats rounded to nearest bfloat16, packed (element 0 in the low half).
+__device__ __forceinline__ uint32_t pack_bf16(f32x2_t x) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(x, bf16x2_t));
+}
+
+// The float values of a packed pair: a bfloat16 is the high half of its float.
+__device__ __forceinline__ f32x2_t unpack_bf16(uint32_t p) {
+    return f32x2_t{__uint_as_float(p << 16), __uint_as_float(p & 0xFFFF0000u)};
+}
+
+// Pairs of elements are rounded with one packed conversion and taken back
+// apart with a shift and a mask, so each piece costs half a conversion, one
+// bit operation and one subtraction per element.
 __device__ __forceinline__ void split3(const float (&x)[8], bf16x8_t& h, bf16x8_t& m, bf16x8_t& l) {
+    u32x4_v hw, mw, lw;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const __bf16 a = __bf16(x[i]);
-        const float r1 = x[i] - float(a);  // exact
-        const __bf16 b = __bf16(r1);
-        const float r2 = r1 - float(b);  // exact
-        h[i] = a;
-        m[i] = b;
-        l[i] = __bf16(r2);
+    for (int p = 0; p < 4; ++p) {
+        const f32x2_t a{x[2 * p], x[2 * p + 1]};
+        const uint32_t ph = pack_bf16(a);
+        const f32x2_t r1 = a - unpack_bf16(ph);  // exact
+        const uint32_t pm = pack_bf16(r1);
+        const f32x2_t r2 = r1 - unpack_bf16(pm);  // exact
+        hw[p] = ph;
+        mw[p] = pm;
+        lw[p] = pack_bf16(r2);
     }
+    h = __builtin_bit_cast(bf16x8_t, hw);
+    m = __builtin_bit_cast(bf16x8_t, mw);
+    l = __builtin_bit_cast(bf16x8_t, lw);
 }
 
 // The piece products of one 32-deep chunk: activations av (this lane's 16 k
