@@ -319,6 +319,19 @@ typedef struct {
                               between two predicted rebuilds (accumulates) */
     double* virial;        /* [n_rep] or NULL: after the call, the NPT virial
                               estimator W of the last outer step (see below) */
+    int32_t* order;        /* [2 n] or NULL.  Non-NULL: the model evaluations
+                              keep their per-atom rows in the cell order of the
+                              last list build (atoms that are close in space
+                              are close in memory, whatever the caller's
+                              numbering); order[p] is the caller's index of row
+                              p, order[n + i] the row of atom i.  Written at
+                              each list build, read by later calls while
+                              lists_valid is 1; nl_cons and nl_nc then hold
+                              rows and entries in that order.  Each row lists
+                              its neighbours in ascending caller index, so
+                              every per-atom sum runs in the same order as
+                              with NULL and the results are the same bits.
+                              NULL: rows in the caller's order. */
 } respa_state;
 
 /* Advances the state by n_outer outer steps of Algorithm 1 (DMTS-NC, or

@@ -57,7 +57,7 @@ class RespaState(C.Structure):
                 ("f_nc", vp), ("energy", vp), ("pos_ref", vp), ("nl_cons", NList), ("nl_nc", NList),
                 ("step", C.c_uint64), ("first_step", C.c_int32), ("lists_valid", C.c_int32), ("ke", vp),
                 ("n_rebuilds", C.c_int64), ("n_rewinds", C.c_int64),
-                ("n_replays", C.c_int64), ("virial", vp)]
+                ("n_replays", C.c_int64), ("virial", vp), ("order", vp)]
 
 
 class ReplicaDesc(C.Structure):

@@ -32,7 +32,7 @@ using namespace nnp;
     return NNP_OK;
 
 extern "C" const char* nnp_last_error(void) { return g_err.c_str(); }
-extern "C" int32_t nnp_abi_version(void) { return 3; }
+extern "C" int32_t nnp_abi_version(void) { return 4; }
 
 // ===================================================================== model
 namespace nnp {
@@ -495,11 +495,15 @@ MpGeom make_geom(const Model* m, const nnp_system& sys, const RepGeom& geom, con
 }
 
 // With `vir`, also the per-atom shares of the virial -sum_i F_i . q_i.
+// With `perm`, sys and nl are in a working row order and row i's outputs
+// (forces, atomic energies, virial shares) go to the caller's index perm[i].
 void cons_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const SysTables& t, const nnp_nlist& nl,
-               ModelBuf& b, double* energy, float* forces, hipStream_t s, float* vir = nullptr) {
+               ModelBuf& b, double* energy, float* forces, hipStream_t s, float* vir = nullptr,
+               const int* perm = nullptr) {
     const int n = int(sys.n_atoms);
     const int F = m->desc.width;
     MpGeom mg = make_geom(m, sys, geom, nl);
+    mg.perm = perm;
     if (b.ecnt && message_mx_active(F, m->desc.n_rbf, 0)) {
         // the edges within the cutoff, prepared once for all six message launches
         launch_edge_prep(mg, b.ecnt, b.erec, b.ehalf, s);
@@ -511,7 +515,7 @@ void cons_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const
     const int L = m->n_layers();
     gemm_xwt(n, F, F, b.s[L], F, m->p(m->off_Wo), m->p(m->off_bo), b.zo, F, EPI_SILU, b.ao, F, false, s, m->bf16(),
              m->px(m->off_Wo), m->wx_stride());
-    launch_readout(n, F, m->desc.n_species, b.zo, m->p(m->off_wo), m->p(m->off_beta), sys.species, b.Ei, s);
+    launch_readout(n, F, m->desc.n_species, b.zo, m->p(m->off_wo), m->p(m->off_beta), sys.species, b.Ei, s, perm);
     if (energy) launch_rep_sum(sys.n_rep, t.rep_start, b.Ei, energy, s);
     if (!forces) return;
     launch_readout_bwd(n, F, b.ao, m->p(m->off_wo), b.gs2, s);
@@ -521,12 +525,15 @@ void cons_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const
 
 // With vir_set / vir_add, also the per-atom shares of the NPT virial proxy
 // sum_i sum_j F_ij . r_ij, written / added to.
+// `perm` as in cons_eval.
 void nc_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const nnp_nlist& nl, ModelBuf& b,
-             float* forces, hipStream_t s, float* vir_set = nullptr, float* vir_add = nullptr) {
+             float* forces, hipStream_t s, float* vir_set = nullptr, float* vir_add = nullptr,
+             const int* perm = nullptr) {
     const int n = int(sys.n_atoms);
     const int F = m->desc.width;
     const int HC = 2 * (m->desc.n_s + m->desc.n_l) * m->desc.n_c;
     MpGeom mg = make_geom(m, sys, geom, nl);
+    mg.perm = perm;
     if (F <= 32) {
         // inference: species-table perceptron, message, then one fused kernel
         // for the update block and the projections (no intermediates kept)
@@ -600,6 +607,8 @@ struct CallScratch {
     double* inner_energy = nullptr;
     double* disagree = nullptr;
     double* ke_part = nullptr;
+    double* pos_rows = nullptr;  // [3][n] positions in the evaluations' row order
+    int* species_rows = nullptr;  // [n] species in that order
 };
 
 // One layout serves every entry point: tables, neighbour scratch, the
@@ -623,6 +632,8 @@ void carve_all(Arena& a, const Model* cons, const Model* nc, int64_t n, int32_t 
     c.inner_energy = a.take<double>(n_rep);
     c.disagree = a.take<double>(int64_t(n_rep) * (cdiv(n, kDisChunk) + 1));
     c.ke_part = a.take<double>(int64_t(n_rep) * cdiv(n, kKeChunk));
+    c.pos_rows = a.take<double>(3 * n);
+    c.species_rows = a.take<int>(n);
     if (cons) carve_model(a, cons, n, E, false, c.cons);
     if (nc) carve_model(a, nc, n, E, wgrad, c.nc);
 }
@@ -1125,12 +1136,25 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     NNP_HIP(hipMemsetAsync(c.t.rebuilds, 0, sizeof(long long), s));
 
     nnp_nlist lc = st->nl_cons, ln = st->nl_nc;
+    // With state->order the force evaluations keep their rows in the cell
+    // order of the last build (row_of: caller index -> row; perm: back) and
+    // read positions and species from row-ordered copies, which the builds
+    // and every B A O A update keep current.
+    const bool rows = st->order != nullptr;
+    const int* perm = rows ? st->order : nullptr;
+    const int* row_of = rows ? st->order + n : nullptr;
+    nnp_system sys_ev = st->sys;
+    if (rows) {
+        sys_ev.pos = c.pos_rows;
+        sys_ev.species = c.species_rows;
+    }
     auto rebuild_if_flagged = [&]() {
         launch_build(n, st->pos, g, plan, c.nb, trig, rc_cons, lc.capacity, lc.offsets, lc.nbr, lc.rev, st->pos_ref,
-                     s);
+                     s, rows);
         if (mts)
-            launch_filter(n, st->pos, g, c.nb, trig, lc.offsets, lc.nbr, rc_nc, ln.capacity, ln.offsets, ln.nbr,
-                          nullptr, nc_status, s);
+            launch_filter(n, rows ? c.nb.cell_pos : st->pos, g, c.nb, trig, lc.offsets, lc.nbr, rc_nc, ln.capacity,
+                          ln.offsets, ln.nbr, nullptr, nc_status, s, rows ? c.nb.cell_atoms : nullptr);
+        if (rows) launch_commit_order(n, c.nb, trig, st->sys.species, st->order, c.pos_rows, c.species_rows, s);
         launch_finish_rebuild(trig, c.t.rebuilds, maxd2, s);
     };
     const double disp_thr = 0.5 * p->skin;
@@ -1153,20 +1177,23 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     ba.maxd2 = maxd2;
     ba.step_offset = 0;
     ba.step_dev = c.t.o_step;
+    ba.pos_rows = rows ? c.pos_rows : nullptr;
+    ba.row = row_of;
 
     // NPT virial estimator (state->virial): per-atom shares of W_cons in
     // c.cons.vir, of the fast force's W_S in c.nc.vir (last evaluation) and
     // c.nc.vir_sum (summed over the inner loop of the current outer step)
     const bool want_vir = st->virial != nullptr;
     auto eval_cons = [&]() {
-        cons_eval(cons, st->sys, g, c.t, lc, c.cons, st->energy, st->f_cons, s, want_vir ? c.cons.vir : nullptr);
+        cons_eval(cons, sys_ev, g, c.t, lc, c.cons, st->energy, st->f_cons, s, want_vir ? c.cons.vir : nullptr,
+                  perm);
     };
     auto eval_inner = [&]() {
         if (inner_nc) {
-            nc_eval(nc, st->sys, g, ln, c.nc, st->f_nc, s, want_vir ? c.nc.vir : nullptr,
-                    want_vir ? c.nc.vir_sum : nullptr);
+            nc_eval(nc, sys_ev, g, ln, c.nc, st->f_nc, s, want_vir ? c.nc.vir : nullptr,
+                    want_vir ? c.nc.vir_sum : nullptr, perm);
         } else {
-            cons_eval(nc, st->sys, g, c.t, ln, c.nc, inner_energy, st->f_nc, s, want_vir ? c.nc.vir : nullptr);
+            cons_eval(nc, sys_ev, g, c.t, ln, c.nc, inner_energy, st->f_nc, s, want_vir ? c.nc.vir : nullptr, perm);
             if (want_vir) launch_add(n, c.nc.vir, c.nc.vir_sum, s);
         }
     };
@@ -1193,6 +1220,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
             cp(st->pos, dst_buf.pos, d3); cp(st->vel, dst_buf.vel, d3); cp(st->pos_ref, dst_buf.pos_ref, d3);
             cp(st->f_cons, dst_buf.f_cons, f3); if (mts) cp(st->f_nc, dst_buf.f_nc, f3);
             cp(st->energy, dst_buf.energy, sizeof(double) * R);
+            if (rows) launch_gather_rows(n, perm, st->pos, nullptr, c.pos_rows, nullptr, s);
         }
     };
     long long rebuilds_seen = 0;
@@ -1241,9 +1269,13 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     // cached forces goes straight on
     bool entry_work = false;
     const bool built_at_entry = !st->lists_valid;
+    // valid lists from an earlier call: their order, with the caller's
+    // current positions
+    if (rows && st->lists_valid) launch_gather_rows(n, perm, st->pos, st->sys.species, c.pos_rows, c.species_rows, s);
     if (!st->lists_valid) {
         // empty rows until the first build succeeds, so a failed build never
-        // leaves uninitialised offsets behind
+        // leaves uninitialised offsets behind (and the identity order)
+        if (rows) launch_reset_rows(n, st->order, st->pos, st->sys.species, c.pos_rows, c.species_rows, s);
         NNP_HIP(hipMemsetAsync(lc.offsets, 0, sizeof(int) * (size_t(n) + 1), s));
         if (mts) NNP_HIP(hipMemsetAsync(ln.offsets, 0, sizeof(int) * (size_t(n) + 1), s));
         launch_set_flag(trig, 1, s);

@@ -110,14 +110,15 @@ __global__ void k_norm_bwd(int n, int F, const float* __restrict__ gs, const flo
 
 // E_i = wo . z_i + beta[t_i] (z = silu(Wo s + bo) from the GEMM epilogue)
 __global__ void k_readout(int n, int F, int S, const float* __restrict__ z, const float* __restrict__ wo,
-                          const float* __restrict__ beta, const int* __restrict__ species, float* __restrict__ Ei) {
+                          const float* __restrict__ beta, const int* __restrict__ species, float* __restrict__ Ei,
+                          const int* __restrict__ perm) {
     int lane = threadIdx.x & 63;
     int i = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     if (i >= n) return;
     float acc = 0.f;
     for (int f = lane; f < F; f += 64) acc = fmaf(wo[f], z[int64_t(i) * F + f], acc);
     acc = wave_sum(acc);
-    if (lane == 0) Ei[i] = acc + beta[min(max(species[i], 0), S - 1)];
+    if (lane == 0) Ei[perm ? min(max(perm[i], 0), n - 1) : i] = acc + beta[min(max(species[i], 0), S - 1)];
 }
 
 // g_ao = wo * silu'(a_o)  (dE/dE_i = 1)
@@ -328,14 +329,15 @@ __global__ void __launch_bounds__(256) k_head_fwd(MpGeom mg, const float* __rest
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
     if (active && l == 0) {
+        const int io = mg.perm ? min(max(mg.perm[i], 0), n - 1) : i;
         if (accum) {
-            Fout[i] += fx; Fout[n + i] += fy; Fout[2 * n + i] += fz;
+            Fout[io] += fx; Fout[n + io] += fy; Fout[2 * n + io] += fz;
         } else {
-            Fout[i] = fx; Fout[n + i] = fy; Fout[2 * n + i] = fz;
+            Fout[io] = fx; Fout[n + io] = fy; Fout[2 * n + io] = fz;
         }
         if constexpr (VIR) {
-            if (vir_set) vir_set[i] = vr;
-            if (vir_add) vir_add[i] += vr;
+            if (vir_set) vir_set[io] = vr;
+            if (vir_add) vir_add[io] += vr;
         }
     }
 }
@@ -358,7 +360,7 @@ __global__ void __launch_bounds__(256) k_head_fwd_rec(int n, const int* __restri
                                                       const int* __restrict__ cnt_in, const NcEdge* __restrict__ rec,
                                                       const float* __restrict__ QK, const float* __restrict__ Vh,
                                                       float* __restrict__ Fout, int accum, float* __restrict__ vir_set,
-                                                      float* __restrict__ vir_add) {
+                                                      float* __restrict__ vir_add, const int* __restrict__ perm) {
     constexpr int HC = 2 * kH * kNc;
     const int lane = threadIdx.x & 63;
     const int e = lane >> 4, h = lane & 15;
@@ -484,14 +486,15 @@ __global__ void __launch_bounds__(256) k_head_fwd_rec(int n, const int* __restri
         }
     }
     if (own && h == kNs) {
+        const int io = perm ? min(max(perm[i], 0), n - 1) : i;  // outputs under the caller's index
         if (accum) {
-            Fout[i] += fx; Fout[n + i] += fy; Fout[2 * n + i] += fz;
+            Fout[io] += fx; Fout[n + io] += fy; Fout[2 * n + io] += fz;
         } else {
-            Fout[i] = fx; Fout[n + i] = fy; Fout[2 * n + i] = fz;
+            Fout[io] = fx; Fout[n + io] = fy; Fout[2 * n + io] = fz;
         }
         if constexpr (VIR) {
-            if (vir_set) vir_set[i] = vr;
-            if (vir_add) vir_add[i] += vr;
+            if (vir_set) vir_set[io] = vr;
+            if (vir_add) vir_add[io] += vr;
         }
     }
 }
@@ -951,8 +954,8 @@ void launch_norm_bwd(int n, int F, const float* gs, const float* gX, const float
     NNP_LAUNCH_CHECK();
 }
 void launch_readout(int n, int F, int S, const float* z, const float* wo, const float* beta, const int* species, float* Ei,
-                    hipStream_t st) {
-    k_readout<<<cdiv(n, 4), 256, 0, st>>>(n, F, S, z, wo, beta, species, Ei);
+                    hipStream_t st, const int* perm) {
+    k_readout<<<cdiv(n, 4), 256, 0, st>>>(n, F, S, z, wo, beta, species, Ei, perm);
     NNP_LAUNCH_CHECK();
 }
 void launch_readout_bwd(int n, int F, const float* ao, const float* wo, float* gao, hipStream_t st) {
@@ -980,12 +983,13 @@ void launch_head_fwd_rec(const MpGeom& mg, const int* cnt, const NcEdge* rec, co
                          float* F, bool accum, hipStream_t st, float* vir_set, float* vir_add) {
     if (mg.n <= 0) return;
     ScopedTimer timer("head_fwd", st);
-    // one wavefront per owner atom
+    // four owner atoms per wavefront
     if (vir_set || vir_add)
-        k_head_fwd_rec<true><<<cdiv(mg.n, 16), 256, 0, st>>>(mg.n, mg.off, cnt, rec, QK, Vh, F, accum, vir_set, vir_add);
+        k_head_fwd_rec<true><<<cdiv(mg.n, 16), 256, 0, st>>>(mg.n, mg.off, cnt, rec, QK, Vh, F, accum, vir_set, vir_add,
+                                                             mg.perm);
     else
         k_head_fwd_rec<false><<<cdiv(mg.n, 16), 256, 0, st>>>(mg.n, mg.off, cnt, rec, QK, Vh, F, accum, nullptr,
-                                                              nullptr);
+                                                              nullptr, mg.perm);
     NNP_LAUNCH_CHECK();
 }
 void launch_head_bwd(const MpGeom& mg, const float* QK, const float* Vh, const float* gF, float* gQK, float* gVh,

@@ -103,10 +103,12 @@ __global__ void k_baoa(BaoaArgs a) {
             }
         }
         double d2 = 0.0;
+        const int ri = a.pos_rows ? min(max(a.row[i], 0), n - 1) : 0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             x[c] += hd * nv[c];
             a.pos[c * n + i] = x[c];
+            if (a.pos_rows) a.pos_rows[c * n + ri] = x[c];
             a.vel[c * n + i] = nv[c];
             if (a.pos_ref) {
                 const double d = x[c] - a.pos_ref[c * n + i];

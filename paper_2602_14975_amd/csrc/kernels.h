@@ -42,12 +42,28 @@ CellPlan plan_cells(const nnp_system& sys, double radius);
 int64_t max_cells(int64_t n_atoms, int32_t n_rep);
 void carve_nbr_scratch(Arena& a, int64_t n, int32_t n_rep, NbrScratch& s);
 void upload_cell_plan(const CellPlan& plan, NbrScratch& s, hipStream_t stream);
+// cell_rows: rows and entries in the cell order of this build (s.cell_atoms
+// maps them to the caller's indices, s.cell_pos holds the positions in that
+// order); each row still ascending in caller index.
 void launch_build(int n, const double* pos, const RepGeom& geom, const CellPlan& plan, NbrScratch& s, const int* run,
                   double radius, int64_t capacity, int* offsets, int* nbr, int* rev, double* pos_ref,
-                  hipStream_t stream);
+                  hipStream_t stream, bool cell_rows = false);
+// pos: the positions in the order of the input list's rows; key (or
+// nullptr): caller's index of a row, for the reverse entries
 void launch_filter(int n, const double* pos, const RepGeom& geom, NbrScratch& s, const int* run, const int* off_in,
                    const int* nbr_in, double radius, int64_t capacity, int* offsets, int* nbr, int* rev, int* status,
-                   hipStream_t stream);
+                   hipStream_t stream, const int* key = nullptr);
+// After a cell-order build that succeeded: the permutation into order[2n]
+// (row -> caller index, then caller index -> row), positions and species in
+// row order.
+void launch_commit_order(int n, const NbrScratch& s, const int* run, const int* species, int* order, double* pos_m,
+                         int* species_m, hipStream_t stream);
+// pos_m / species_m (or nullptr) in row order from the caller's arrays
+void launch_gather_rows(int n, const int* order, const double* pos, const int* species, double* pos_m,
+                        int* species_m, hipStream_t stream);
+// The identity order into order[2n], with pos_m and species_m copied.
+void launch_reset_rows(int n, int* order, const double* pos, const int* species, double* pos_m, int* species_m,
+                       hipStream_t stream);
 void launch_set_flag(int* flag, int value, hipStream_t stream);
 void launch_disp_check(int n, const double* pos, const double* ref, double thr, int* flag, hipStream_t stream);
 // Ends a (possibly skipped) rebuild: counts it, clears the trigger and, with
@@ -125,8 +141,9 @@ void launch_update_combine_bwd(int n, int F, const float* UV, const float* pqo, 
                                float* gpqo, float* gUV, hipStream_t st);
 void launch_norm_bwd(int n, int F, const float* gs, const float* gX, const float* X, const float* UV, float* gsmid,
                      float* gUV, hipStream_t st);
+// perm (or nullptr): E_i of row i stored at Ei[perm[i]]
 void launch_readout(int n, int F, int S, const float* z, const float* wo, const float* beta, const int* species, float* Ei,
-                    hipStream_t st);
+                    hipStream_t st, const int* perm = nullptr);
 void launch_readout_bwd(int n, int F, const float* ao, const float* wo, float* gao, hipStream_t st);
 void launch_rep_sum(int n_rep, const int64_t* rep_start, const float* x, double* out, hipStream_t st);
 void launch_emb_grad(int n, int F, int S, const int* species, const float* gs0, float* gemb, hipStream_t st);
@@ -180,6 +197,10 @@ struct BaoaArgs {
     // 1: the opening kick is B(dt) instead of B(dt/2), standing for the
     // closing B(dt/2) of the previous step with the same force as well
     int full_kick;
+    // optional: the new positions also into pos_rows[c * n + row[i]] (the
+    // force evaluations' copy in their working row order)
+    double* pos_rows;
+    const int* row;
 };
 
 // v += half_dt * ACC * (Fa - Fb) / m; with `bump`, also advances that O-step

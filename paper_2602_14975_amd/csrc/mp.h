@@ -42,6 +42,10 @@ struct MpGeom {
     const int* ecnt;
     const EdgeRec* erec;
     const uint4* ehalf;
+    // Rows in a working order (or nullptr: the caller's): the caller's index
+    // of row i, under which the per-atom outputs (forces, energies, virial
+    // shares) are stored.
+    const int* perm;
 };
 
 struct MpFwd {

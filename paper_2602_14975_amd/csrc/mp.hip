@@ -465,14 +465,15 @@ k_message_bwd(MpGeom mg, MpBwd a) {
             }
         }
         if (active && l == 0 && w % WPA == 0) {
+            const int io = mg.perm ? min(max(mg.perm[i], 0), n - 1) : i;
             if (a.accum_force) {
-                a.force[i] += fx; a.force[n + i] += fy; a.force[2 * n + i] += fz;
+                a.force[io] += fx; a.force[n + io] += fy; a.force[2 * n + io] += fz;
             } else {
-                a.force[i] = fx; a.force[n + i] = fy; a.force[2 * n + i] = fz;
+                a.force[io] = fx; a.force[n + io] = fy; a.force[2 * n + io] = fz;
             }
             if (a.vir) {  // each pair is seen by both of its atoms
-                if (a.accum_force) a.vir[i] += 0.5f * vr;
-                else a.vir[i] = 0.5f * vr;
+                if (a.accum_force) a.vir[io] += 0.5f * vr;
+                else a.vir[io] = 0.5f * vr;
             }
         }
     }

@@ -675,7 +675,8 @@ __global__ void __launch_bounds__(64 * kMxWaves, 3) k_message_bwd_mx(MpGeom mg, 
             float sum = 0.f;
             for (int k = 0; k < kMxWaves; ++k) sum += fpart[ai][k][c];
             sum *= isc;
-            float* fo = c < 3 ? a.force + int64_t(c) * n + i : a.vir + i;
+            const int io = mg.perm ? min(max(mg.perm[i], 0), n - 1) : i;
+            float* fo = c < 3 ? a.force + int64_t(c) * n + io : a.vir + io;
             if (c == 3) sum *= 0.5f;  // each pair is seen by both of its atoms
             if (a.accum_force) *fo += sum;
             else *fo = sum;

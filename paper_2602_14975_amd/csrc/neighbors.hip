@@ -16,6 +16,13 @@
 //   nbr_reverse  rev[e] for e = (i, j): position of i in row j (binary search)
 // A second list at a smaller radius is filtered from the first row by row
 // (filter_count / scan / filter_fill), which keeps row order.
+//
+// In cell order (the working order of the force evaluations inside the
+// integrator) row p belongs to the atom at position p of the cell-sorted
+// array and an entry names its neighbour by that position too; rows still
+// list the neighbours in ascending caller index, so each atom's sums keep
+// their order.  commit_order then records the permutation with the
+// positions and species in that order, once both lists are built.
 #include "common.h"
 #include "kernels.h"
 #include "model.h"
@@ -207,13 +214,15 @@ __device__ __forceinline__ void for_candidates(const Stencil& st, int i, int r, 
     }
 }
 
+// cell_rows: row p is the atom at cell position p (else row i is atom i)
 __global__ void __launch_bounds__(64 * kWaves)
 k_nbr_count(int n, const double* __restrict__ pos, RepGeom geom, Stencil st, double rc2,
-            const int* __restrict__ run, int* __restrict__ counts, int* __restrict__ status) {
+            const int* __restrict__ run, int* __restrict__ counts, int* __restrict__ status, int cell_rows) {
     if (*run == 0) return;
     int lane = threadIdx.x & 63;
-    int i = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
-    if (i >= n) return;  // whole wavefront exits together
+    const int row_i = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
+    if (row_i >= n) return;  // whole wavefront exits together
+    const int i = cell_rows ? st.cell_atoms[row_i] : row_i;
     int r = geom.rep_of_atom ? geom.rep_of_atom[i] : 0;
     double L, inv;
     geom.get(i, L, inv);
@@ -231,31 +240,34 @@ k_nbr_count(int n, const double* __restrict__ pos, RepGeom geom, Stencil st, dou
     float tot = wave_sum(float(cnt));
     if (lane == 0) {
         const int c = int(tot + 0.5f);
-        counts[i] = c;
+        counts[row_i] = c;
         if (c > kMaxRow) status[2] = 1;  // the fill kernel cannot sort this row: build nothing
     }
 }
 
-// Rank sort of `cnt` distinct values in LDS row[] into out[] (global).
-__device__ __forceinline__ void rank_sort_store(const int* row, int cnt, int lane, int* out) {
+// Rank sort of `cnt` distinct keys in LDS key[] into out[] (global): the
+// entry of rank k is val[t] of the key of rank k (val = nullptr: the key).
+__device__ __forceinline__ void rank_sort_store(const int* key, const int* val, int cnt, int lane, int* out) {
     for (int t = lane; t < cnt; t += 64) {
-        int v = row[t];
+        int v = key[t];
         int rank = 0;
-        for (int u = 0; u < cnt; ++u) rank += row[u] < v;
-        out[rank] = v;
+        for (int u = 0; u < cnt; ++u) rank += key[u] < v;
+        out[rank] = val ? val[t] : v;
     }
 }
 
 __global__ void __launch_bounds__(64 * kWaves)
 k_nbr_fill(int n, const double* __restrict__ pos, RepGeom geom, Stencil st, double rc2,
            const int* __restrict__ run, const int* __restrict__ tmp_off, int64_t capacity,
-           int* __restrict__ offsets, int* __restrict__ nbr, int* __restrict__ status) {
+           int* __restrict__ offsets, int* __restrict__ nbr, int* __restrict__ status, int cell_rows) {
     if (*run == 0) return;
     __shared__ int rows[kWaves][kMaxRow];
+    __shared__ int cpos[kWaves][kMaxRow];  // cell positions of the entries (cell_rows)
     int lane = threadIdx.x & 63;
     int w = threadIdx.x >> 6;
-    int i = xcd_block(blockIdx.x, gridDim.x) * kWaves + w;
-    if (i >= n) return;
+    const int row_i = xcd_block(blockIdx.x, gridDim.x) * kWaves + w;
+    if (row_i >= n) return;
+    const int i = cell_rows ? st.cell_atoms[row_i] : row_i;
     int total = tmp_off[n];
     if (status[2] != 0) return;  // a row is longer than kMaxRow: keep the previous list intact
     if (int64_t(total) > capacity) {
@@ -271,6 +283,7 @@ k_nbr_fill(int n, const double* __restrict__ pos, RepGeom geom, Stencil st, doub
     double xi = pos[i], yi = pos[n + i], zi = pos[2 * n + i];
     int fill = 0;
     int* row = rows[w];
+    int* crow = cpos[w];
     for_candidates(st, i, r, lane, [&](int t) {
         const int j = t >= 0 ? st.cell_atoms[t] : -1;
         bool ok = false;
@@ -281,22 +294,26 @@ k_nbr_fill(int n, const double* __restrict__ pos, RepGeom geom, Stencil st, doub
         }
         uint64_t bal = __ballot(ok);
         int pre = __popcll(bal & ((1ull << lane) - 1ull));
-        if (ok && fill + pre < kMaxRow) row[fill + pre] = j;
+        if (ok && fill + pre < kMaxRow) {
+            row[fill + pre] = j;
+            crow[fill + pre] = t;
+        }
         fill += __popcll(bal);
     });
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    int start = tmp_off[i];
-    if (fill != tmp_off[i + 1] - start) {
+    int start = tmp_off[row_i];
+    if (fill != tmp_off[row_i + 1] - start) {
         if (lane == 0) status[3] = 1;  // count and fill disagree (not expected)
     }
-    fill = min(fill, tmp_off[i + 1] - start);
+    fill = min(fill, tmp_off[row_i + 1] - start);
     if (lane == 0) {
-        offsets[i] = start;
-        if (i == n - 1) offsets[n] = total;
+        offsets[row_i] = start;
+        if (row_i == n - 1) offsets[n] = total;
     }
-    rank_sort_store(row, fill, lane, nbr + start);
+    // ascending caller index; stored as cell positions in cell order
+    rank_sort_store(row, cell_rows ? crow : nullptr, fill, lane, nbr + start);
 }
 
 // Second list at a smaller radius, filtered from a first list row by row.
@@ -363,22 +380,66 @@ k_filter_fill(int n, const double* __restrict__ pos, RepGeom geom, const int* __
     }
 }
 
+// key (or nullptr): the caller's index of a row (rows in cell order list
+// their entries in ascending key)
 __global__ void __launch_bounds__(64 * kWaves)
 k_nbr_reverse(int n, const int* __restrict__ run, const int* __restrict__ status,
-              const int* __restrict__ offsets, const int* __restrict__ nbr, int* __restrict__ rev) {
+              const int* __restrict__ offsets, const int* __restrict__ nbr, int* __restrict__ rev,
+              const int* __restrict__ key) {
     if (*run == 0 || status[0] != 0 || status[2] != 0) return;
     int lane = threadIdx.x & 63;
     int i = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
     if (i >= n) return;
+    const int ki = key ? key[i] : i;
     for (int e = offsets[i] + lane; e < offsets[i + 1]; e += 64) {
         int j = nbr[e];
-        int lo = offsets[j], hi = offsets[j + 1];  // search i in row j (ascending)
+        int lo = offsets[j], hi = offsets[j + 1];  // search i in row j (ascending key)
         while (lo < hi) {
             int mid = (lo + hi) >> 1;
-            if (nbr[mid] < i) lo = mid + 1; else hi = mid;
+            if ((key ? key[nbr[mid]] : nbr[mid]) < ki) lo = mid + 1; else hi = mid;
         }
         rev[e] = (lo < offsets[j + 1] && nbr[lo] == i) ? lo : e;
     }
+}
+
+// After a successful build in cell order: order[p] = caller's index of row
+// p, order[n + i] = row of atom i, and the positions and species in row
+// order for the evaluations (a failed build keeps the previous order with
+// the previous lists).
+__global__ void k_commit_order(int n, const int* __restrict__ run, const int* __restrict__ status,
+                               const int* __restrict__ cell_atoms, const double* __restrict__ cell_pos,
+                               const int* __restrict__ species, int* __restrict__ order, double* __restrict__ pos_m,
+                               int* __restrict__ species_m) {
+    if (*run == 0 || status[0] != 0 || status[2] != 0) return;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int i = cell_atoms[p];
+    order[p] = i;
+    order[n + i] = p;
+    pos_m[p] = cell_pos[p];
+    pos_m[n + p] = cell_pos[n + p];
+    pos_m[2 * n + p] = cell_pos[2 * n + p];
+    species_m[p] = species[i];
+}
+
+// Positions and species in row order from the caller's arrays (order ==
+// nullptr: the identity, also written to `reset`).  Indices read from
+// `order` are clamped to [0, n): a buffer that no build has written yet
+// still leads to no access out of bounds.
+__global__ void k_gather_rows(int n, const int* __restrict__ order, const double* __restrict__ pos,
+                              const int* __restrict__ species, double* __restrict__ pos_m,
+                              int* __restrict__ species_m, int* __restrict__ reset) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int i = order ? min(max(order[p], 0), n - 1) : p;
+    if (reset) {
+        reset[p] = p;
+        reset[n + p] = p;
+    }
+    pos_m[p] = pos[i];
+    pos_m[n + p] = pos[n + i];
+    pos_m[2 * n + p] = pos[2 * n + i];
+    if (species_m) species_m[p] = species[i];
 }
 
 __global__ void k_disp_check(int n, const double* __restrict__ pos, const double* __restrict__ ref,
@@ -467,7 +528,7 @@ void upload_cell_plan(const CellPlan& plan, NbrScratch& s, hipStream_t stream) {
 
 void launch_build(int n, const double* pos, const RepGeom& geom, const CellPlan& plan, NbrScratch& s,
                   const int* run, double radius, int64_t capacity, int* offsets, int* nbr, int* rev,
-                  double* pos_ref, hipStream_t stream) {
+                  double* pos_ref, hipStream_t stream, bool cell_rows) {
     launch_zero(s.cell_count, plan.n_cells + 1, run, stream);
     k_cell_assign<<<cdiv(n, 256), 256, 0, stream>>>(n, pos, geom, s.grid_m, s.grid_base, run, s.cell_of_atom,
                                                     s.slot_of_atom, s.cell_count, pos_ref);
@@ -476,26 +537,49 @@ void launch_build(int n, const double* pos, const RepGeom& geom, const CellPlan&
                                                   s.cell_atoms, pos, s.cell_pos);
     Stencil st{s.grid_m, s.grid_base, s.cell_of_atom, s.cell_start, s.cell_atoms, s.cell_pos};
     double rc2 = radius * radius;
-    k_nbr_count<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, pos, geom, st, rc2, run, s.counts, s.status);
+    const int cr = cell_rows ? 1 : 0;
+    k_nbr_count<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, pos, geom, st, rc2, run, s.counts, s.status, cr);
     k_scan<<<1, 1024, 0, stream>>>(n, s.counts, s.tmp_off, run);
     ScopedTimer timer("nbr_fill", stream);
     k_nbr_fill<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, pos, geom, st, rc2, run, s.tmp_off, capacity,
-                                                            offsets, nbr, s.status);
+                                                            offsets, nbr, s.status, cr);
     if (rev)
-        k_nbr_reverse<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, run, s.status, offsets, nbr, rev);
+        k_nbr_reverse<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, run, s.status, offsets, nbr, rev,
+                                                                   cell_rows ? s.cell_atoms : nullptr);
+    NNP_LAUNCH_CHECK();
+}
+
+void launch_commit_order(int n, const NbrScratch& s, const int* run, const int* species, int* order,
+                         double* pos_m, int* species_m, hipStream_t stream) {
+    k_commit_order<<<cdiv(n, 256), 256, 0, stream>>>(n, run, s.status, s.cell_atoms, s.cell_pos, species, order,
+                                                     pos_m, species_m);
+    NNP_LAUNCH_CHECK();
+}
+
+void launch_gather_rows(int n, const int* order, const double* pos, const int* species, double* pos_m,
+                        int* species_m, hipStream_t stream) {
+    if (n <= 0) return;
+    k_gather_rows<<<cdiv(n, 256), 256, 0, stream>>>(n, order, pos, species, pos_m, species_m, nullptr);
+    NNP_LAUNCH_CHECK();
+}
+
+void launch_reset_rows(int n, int* order, const double* pos, const int* species, double* pos_m, int* species_m,
+                       hipStream_t stream) {
+    if (n <= 0) return;
+    k_gather_rows<<<cdiv(n, 256), 256, 0, stream>>>(n, nullptr, pos, species, pos_m, species_m, order);
     NNP_LAUNCH_CHECK();
 }
 
 void launch_filter(int n, const double* pos, const RepGeom& geom, NbrScratch& s, const int* run,
                    const int* off_in, const int* nbr_in, double radius, int64_t capacity, int* offsets,
-                   int* nbr, int* rev, int* status, hipStream_t stream) {
+                   int* nbr, int* rev, int* status, hipStream_t stream, const int* key) {
     double rc2 = radius * radius;
     k_filter_count<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, pos, geom, off_in, nbr_in, rc2, run, s.counts);
     k_scan<<<1, 1024, 0, stream>>>(n, s.counts, s.tmp_off, run);
     k_filter_fill<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, pos, geom, off_in, nbr_in, rc2, run, s.tmp_off,
                                                                capacity, offsets, nbr, status);
     if (rev)
-        k_nbr_reverse<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, run, status, offsets, nbr, rev);
+        k_nbr_reverse<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, run, status, offsets, nbr, rev, key);
     NNP_LAUNCH_CHECK();
 }
 
@@ -524,7 +608,7 @@ void launch_predict_rebuild(unsigned* maxd2, double thr, int* flag, hipStream_t 
 namespace nnp {
 void launch_reverse(int n, const int* run, const int* status, const int* offsets, const int* nbr, int* rev,
                     hipStream_t s) {
-    k_nbr_reverse<<<cdiv(n, kWaves), 64 * kWaves, 0, s>>>(n, run, status, offsets, nbr, rev);
+    k_nbr_reverse<<<cdiv(n, kWaves), 64 * kWaves, 0, s>>>(n, run, status, offsets, nbr, rev, nullptr);
     NNP_LAUNCH_CHECK();
 }
 }  // namespace nnp

@@ -235,7 +235,10 @@ class Trajectory:
     """Device-resident respa_state plus its list buffers and workspace."""
 
     def __init__(self, cons, nc, system, vel, masses, gamma, params, skin=1.0, capacity_factor=1.4,
-                 virial=False):
+                 virial=False, cell_order=True):
+        """cell_order: the force evaluations keep their rows in the cell order
+        of each list build (respa_state.order); the results are the same bits
+        either way."""
         self.cons, self.nc, self.sys = cons, nc, system
         n = system.n
         self.params = params
@@ -249,6 +252,7 @@ class Trajectory:
         self.pos_ref = torch.zeros(3, n, dtype=torch.float64, device=DEV)
         # NPT virial estimator of the last outer step, per replica (respa_step)
         self.virial = torch.zeros(system.n_rep, dtype=torch.float64, device=DEV) if virial else None
+        self.order = torch.zeros(2 * n, dtype=torch.int32, device=DEV) if cell_order else None
         # initial capacity from a list build at the Verlet radius
         ws0 = workspace(None, None, n, system.n_rep, 1)
         rc_c = cons.cutoff + params.skin
@@ -276,7 +280,8 @@ class Trajectory:
                                self.energy.data_ptr(), self.pos_ref.data_ptr(), self.nl_cons.c(), self.nl_nc.c(),
                                self.step_count, self.first_step, self.lists_valid,
                                ke.data_ptr() if ke is not None else None, self.n_rebuilds, self.n_rewinds,
-                               self.n_replays, self.virial.data_ptr() if self.virial is not None else None)
+                               self.n_replays, self.virial.data_ptr() if self.virial is not None else None,
+                               self.order.data_ptr() if self.order is not None else None)
 
     def respa_step(self, n_outer, ke=None):
         """Advances by n_outer outer steps, growing the list buffers on

@@ -76,7 +76,7 @@ def test_structure_layouts_match_the_header(tmp_path):
 
 
 def test_abi_version_and_error_string(lib):
-    assert lib.nnp_abi_version() == 3
+    assert lib.nnp_abi_version() == 4
     assert isinstance(lib.nnp_last_error(), bytes)
 
 

@@ -279,3 +279,39 @@ def test_rewind_gives_up_when_the_fast_force_always_disagrees(gpu_lib):
         traj.respa_step(4)
     assert traj.n_rewinds == 16
     assert np.all(np.isfinite(traj.positions()))
+
+@pytest.mark.parametrize("width", [32, 128])
+def test_cell_order_gives_the_same_bits(gpu_lib, width):
+    """Force evaluations that keep their rows in the cell order of each list
+    build (respa_state.order) give the trajectory, forces, energies, virial
+    and kinetic energies of evaluations in the caller's order, bit for bit:
+    each atom's sums run over the same neighbours in the same order.  Width
+    32: the 192-atom box (one cell, vector message kernels); width 128: the
+    1,536-atom box (4 x 4 x 4 cells, matrix-core message kernels, NC pair
+    head over edge records); a small skin rebuilds the lists mid-run."""
+    if width == 32:
+        s = synth.water_config(0)
+        cons, _, nc, _ = _models_cfg0(gpu_lib)
+        dt, n_in = 2.0, 4
+    else:
+        s = synth.water_config(3)
+        cons = gpu_lib.Model.from_spec(synth.CONS_CFG1, synth.random_weights(synth.CONS_CFG1, 2001))
+        nc = gpu_lib.Model.from_spec(synth.NC_CFG1, synth.random_weights(synth.NC_CFG1, 3001))
+        dt, n_in = 4.0, 8
+    m = s.standard_masses()
+    v0 = synth.maxwell_boltzmann(m, 300.0, 5000)
+    runs = []
+    for cell_order in (False, True):
+        system = gpu_lib.DeviceSystem(s.pos, s.species, s.box)
+        prm = gpu_lib.respa_params(dt, n_in, 300.0, seed=4000, mode="dmts_nc", skin=0.3, check_every=2)
+        t = gpu_lib.Trajectory(cons, nc, system, v0, m, np.ones(s.n), prm, virial=True, cell_order=cell_order)
+        ke = torch.zeros(6, 1, dtype=torch.float64, device="cuda")
+        t.respa_step(6, ke)
+        runs.append((t, ke))
+    (a, ka), (b, kb) = runs
+    assert a.order is None and b.n_rebuilds >= 2
+    if width == 128:
+        assert not torch.equal(b.order[:s.n], torch.arange(s.n, dtype=torch.int32, device="cuda"))
+    assert np.array_equal(a.positions(), b.positions()) and np.array_equal(a.velocities(), b.velocities())
+    assert torch.equal(a.f_cons, b.f_cons) and torch.equal(a.f_nc, b.f_nc)
+    assert torch.equal(a.energy, b.energy) and torch.equal(a.virial, b.virial) and torch.equal(ka, kb)
