@@ -107,7 +107,7 @@ def run_gpu(args):
     def timed(prec, mode, dt, n_inner, steps, warmup, sites=(), **kw):
         cons, nc = models[prec]
         system = nnp.DeviceSystem(s.pos, s.species, s.box)
-        prm = nnp.respa_params(dt, n_inner, 300.0, seed=4001, mode=mode, skin=1.0,
+        prm = nnp.respa_params(dt, n_inner, 300.0, seed=4001, mode=mode, skin=args.skin,
                                check_every=kw.pop("check_every", args.check_every), **kw)
         traj = nnp.Trajectory(cons, nc if mode == "dmts_nc" else None, system, v0, m, gamma, prm)
         traj.respa_step(max(1, warmup))
@@ -460,6 +460,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--skin", type=float, default=1.0, help="Verlet skin of both lists (A) in the 12,288-atom legs")
     ap.add_argument("--kernel-steps", type=int, default=20, help="outer steps of the kernel-timing region")
     ap.add_argument("--no-oracle", action="store_true", help="skip the host oracle leg")
     ap.add_argument("--workload", default="water",
