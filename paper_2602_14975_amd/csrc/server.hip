@@ -148,6 +148,7 @@ static void carve_fixed(Server& sv, int64_t n_cap, Arena& a) {
 
 struct Dynamic {
     int *off_c, *nbr_c, *off_n, *nbr_n;
+    int* order;  // [2N]: the cell order of the evaluations' rows (respa_state.order)
     char* ws;
     size_t ws_bytes;
 };
@@ -168,6 +169,7 @@ static size_t carve_dynamic(Server& sv, const std::vector<Replica*>& set, char* 
     D.nbr_c = a.take<int>(Ec);
     D.off_n = a.take<int>(N + 1);
     D.nbr_n = a.take<int>(En);
+    D.order = a.take<int>(2 * std::max<int64_t>(N, 1));
     const size_t wsb = call_scratch_bytes(sv.cons, sv.nc, std::max<int64_t>(N, 1), std::max(R, 1),
                                           std::max<int64_t>(std::max(Ec, En), 1));
     D.ws = a.take<char>(wsb);
@@ -241,6 +243,7 @@ static void point_state(Server& sv, const Bank& b, const Dynamic& D, int64_t Ec,
     st.pos_ref = sv.pos_ref;
     st.nl_cons = nnp_nlist{N, Ec, 0, D.off_c, D.nbr_c, nullptr, sv.cons->desc.cutoff + sv.p.skin};
     st.nl_nc = nnp_nlist{N, En, 0, D.off_n, D.nbr_n, nullptr, sv.nc->desc.cutoff + sv.p.skin};
+    st.order = D.order;  // rebuilt with the lists (lists_valid = 0)
     st.lists_valid = 0;
     st.first_step = 0;
     sv.ws = D.ws;
