@@ -30,11 +30,17 @@ struct CellPlan {
     std::vector<int> m;     // cells per side per replica (1 = whole replica)
     std::vector<int> base;  // first global cell of each replica
     int n_cells = 0;
+    // Cell numbering: the cell at lexicographic position l ((cx m + cy) m + cz)
+    // of replica r is number code[base_r + l]; lex is the inverse.  Within a
+    // replica the numbers follow the Morton (bit-interleaved) order of the
+    // cell coordinates, so consecutive cells, and the atoms the cell order
+    // puts together, form compact blocks of space.
+    std::vector<int> code, lex;
 };
 
 struct NbrScratch {
-    int *grid_m, *grid_base, *cell_of_atom, *slot_of_atom, *cell_count, *cell_start, *cell_atoms, *counts,
-        *tmp_off, *status;
+    int *grid_m, *grid_base, *cell_code, *cell_lex, *cell_of_atom, *slot_of_atom, *cell_count, *cell_start,
+        *cell_atoms, *counts, *tmp_off, *status;
     double* cell_pos;  // [3][n] positions in cell order
 };
 

@@ -4,7 +4,8 @@
 // a no-op when the device flag `run` is zero, so a rebuild can be decided on
 // the device without a host round trip):
 //   cell_assign  atom -> cell (per-replica grid of m^3 cells of edge >= rc,
-//                or a single cell holding the whole replica when m < 3),
+//                numbered in the Morton order of their coordinates, or a
+//                single cell holding the whole replica when m < 3),
 //                counting-sort slot by atomic increment, and a copy of the
 //                positions as the reference for the displacement trigger
 //   scan         exclusive prefix sums of the cell counts
@@ -23,6 +24,9 @@
 // list the neighbours in ascending caller index, so each atom's sums keep
 // their order.  commit_order then records the permutation with the
 // positions and species in that order, once both lists are built.
+#include <algorithm>
+#include <utility>
+
 #include "common.h"
 #include "kernels.h"
 #include "model.h"
@@ -38,6 +42,7 @@ __global__ void k_set_flag(int* flag, int value) {
 
 __global__ void k_cell_assign(int n, const double* __restrict__ pos, RepGeom geom,
                               const int* __restrict__ grid_m, const int* __restrict__ grid_base,
+                              const int* __restrict__ cell_code,
                               const int* __restrict__ run, int* __restrict__ cell_of_atom,
                               int* __restrict__ slot_of_atom, int* __restrict__ cell_count,
                               double* __restrict__ pos_ref) {
@@ -64,7 +69,7 @@ __global__ void k_cell_assign(int n, const double* __restrict__ pos, RepGeom geo
             int ci = int(w * inv * double(m));
             c[a] = ci < 0 ? 0 : (ci >= m ? m - 1 : ci);
         }
-        cell += (c[0] * m + c[1]) * m + c[2];
+        cell = cell_code[cell + (c[0] * m + c[1]) * m + c[2]];
     }
     cell_of_atom[i] = cell;
     slot_of_atom[i] = atomicAdd(&cell_count[cell], 1);
@@ -160,6 +165,8 @@ __global__ void k_cell_fill(int n, const int* __restrict__ run, const int* __res
 struct Stencil {
     const int* grid_m;
     const int* grid_base;
+    const int* cell_code;  // lexicographic position -> cell number (CellPlan)
+    const int* cell_lex;   // and back
     const int* cell_of_atom;
     const int* cell_start;
     const int* cell_atoms;
@@ -180,13 +187,13 @@ __device__ __forceinline__ void for_candidates(const Stencil& st, int i, int r, 
         }
         return;
     }
-    const int local = cell - base;
+    const int local = st.cell_lex[cell] - base;
     const int cx = local / (m * m), cy = (local / m) % m, cz = local % m;
     int start = 0, count = 0;
     if (lane < 27) {
         const int dx = lane / 9 - 1, dy = (lane / 3) % 3 - 1, dz = lane % 3 - 1;
         const int ax = (cx + dx + m) % m, ay = (cy + dy + m) % m, az = (cz + dz + m) % m;
-        const int c = base + (ax * m + ay) * m + az;
+        const int c = st.cell_code[base + (ax * m + ay) * m + az];
         start = st.cell_start[c];
         count = st.cell_start[c + 1] - start;
     }
@@ -482,6 +489,24 @@ __global__ void k_predict_rebuild(unsigned* maxd2, double thr, int* flag) {
 
 // ------------------------------------------------------------------- host --
 
+// Morton rank of each lexicographic cell position of an m^3 grid: the cells
+// sorted by their bit-interleaved coordinates (x, y, z bits in turn).
+static std::vector<int> morton_ranks(int m) {
+    const int n = m * m * m;
+    std::vector<std::pair<uint64_t, int>> key(n);
+    for (int l = 0; l < n; ++l) {
+        const int c[3] = {l / (m * m), (l / m) % m, l % m};
+        uint64_t code = 0;
+        for (int b = 0; b < 20; ++b)
+            for (int d = 0; d < 3; ++d) code |= uint64_t((c[d] >> b) & 1) << (3 * b + (2 - d));
+        key[l] = {code, l};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int> rank(n);
+    for (int k = 0; k < n; ++k) rank[key[k].second] = k;
+    return rank;
+}
+
 CellPlan plan_cells(const nnp_system& sys, double radius) {
     CellPlan p;
     p.m.resize(sys.n_rep);
@@ -500,6 +525,21 @@ CellPlan plan_cells(const nnp_system& sys, double radius) {
         total += m * m * m;
     }
     p.n_cells = total;
+    p.code.resize(total);
+    p.lex.resize(total);
+    std::vector<int> rank;
+    int rank_m = 0;
+    for (int r = 0; r < sys.n_rep; ++r) {
+        const int m = p.m[r], b = p.base[r], nc = m * m * m;
+        if (m != rank_m) {
+            rank = morton_ranks(m);
+            rank_m = m;
+        }
+        for (int l = 0; l < nc; ++l) {
+            p.code[b + l] = b + rank[l];
+            p.lex[b + rank[l]] = b + l;
+        }
+    }
     return p;
 }
 
@@ -509,6 +549,8 @@ void carve_nbr_scratch(Arena& a, int64_t n, int32_t n_rep, NbrScratch& s) {
     int64_t C = max_cells(n, n_rep);
     s.grid_m = a.take<int>(n_rep);
     s.grid_base = a.take<int>(n_rep);
+    s.cell_code = a.take<int>(C + 1);
+    s.cell_lex = a.take<int>(C + 1);
     s.cell_of_atom = a.take<int>(n);
     s.slot_of_atom = a.take<int>(n);
     s.cell_count = a.take<int>(C + 1);
@@ -521,6 +563,10 @@ void carve_nbr_scratch(Arena& a, int64_t n, int32_t n_rep, NbrScratch& s) {
 }
 
 void upload_cell_plan(const CellPlan& plan, NbrScratch& s, hipStream_t stream) {
+    NNP_HIP(hipMemcpyAsync(s.cell_code, plan.code.data(), plan.code.size() * sizeof(int), hipMemcpyHostToDevice,
+                           stream));
+    NNP_HIP(hipMemcpyAsync(s.cell_lex, plan.lex.data(), plan.lex.size() * sizeof(int), hipMemcpyHostToDevice,
+                           stream));
     NNP_HIP(hipMemcpyAsync(s.grid_m, plan.m.data(), plan.m.size() * sizeof(int), hipMemcpyHostToDevice, stream));
     NNP_HIP(hipMemcpyAsync(s.grid_base, plan.base.data(), plan.base.size() * sizeof(int),
                            hipMemcpyHostToDevice, stream));
@@ -530,12 +576,12 @@ void launch_build(int n, const double* pos, const RepGeom& geom, const CellPlan&
                   const int* run, double radius, int64_t capacity, int* offsets, int* nbr, int* rev,
                   double* pos_ref, hipStream_t stream, bool cell_rows) {
     launch_zero(s.cell_count, plan.n_cells + 1, run, stream);
-    k_cell_assign<<<cdiv(n, 256), 256, 0, stream>>>(n, pos, geom, s.grid_m, s.grid_base, run, s.cell_of_atom,
-                                                    s.slot_of_atom, s.cell_count, pos_ref);
+    k_cell_assign<<<cdiv(n, 256), 256, 0, stream>>>(n, pos, geom, s.grid_m, s.grid_base, s.cell_code, run,
+                                                    s.cell_of_atom, s.slot_of_atom, s.cell_count, pos_ref);
     k_scan<<<1, 1024, 0, stream>>>(plan.n_cells, s.cell_count, s.cell_start, run);
     k_cell_fill<<<cdiv(n, 256), 256, 0, stream>>>(n, run, s.cell_of_atom, s.slot_of_atom, s.cell_start,
                                                   s.cell_atoms, pos, s.cell_pos);
-    Stencil st{s.grid_m, s.grid_base, s.cell_of_atom, s.cell_start, s.cell_atoms, s.cell_pos};
+    Stencil st{s.grid_m, s.grid_base, s.cell_code, s.cell_lex, s.cell_of_atom, s.cell_start, s.cell_atoms, s.cell_pos};
     double rc2 = radius * radius;
     const int cr = cell_rows ? 1 : 0;
     k_nbr_count<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, pos, geom, st, rc2, run, s.counts, s.status, cr);
