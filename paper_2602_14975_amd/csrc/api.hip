@@ -609,6 +609,10 @@ struct CallScratch {
     double* ke_part = nullptr;
     double* pos_rows = nullptr;  // [3][n] positions in the evaluations' row order
     int* species_rows = nullptr;  // [n] species in that order
+    // the next outer step's conservative list, built beside the current
+    // step's conservative evaluation, with its order and row-ordered copies
+    int *spare_off = nullptr, *spare_nbr = nullptr, *spare_order = nullptr, *spare_species = nullptr;
+    double* spare_pos = nullptr;
 };
 
 // One layout serves every entry point: tables, neighbour scratch, the
@@ -634,6 +638,11 @@ void carve_all(Arena& a, const Model* cons, const Model* nc, int64_t n, int32_t 
     c.ke_part = a.take<double>(int64_t(n_rep) * cdiv(n, kKeChunk));
     c.pos_rows = a.take<double>(3 * n);
     c.species_rows = a.take<int>(n);
+    c.spare_off = a.take<int>(n + 1);
+    c.spare_nbr = a.take<int>(E);
+    c.spare_order = a.take<int>(2 * n);
+    c.spare_pos = a.take<double>(3 * n);
+    c.spare_species = a.take<int>(n);
     if (cons) carve_model(a, cons, n, E, false, c.cons);
     if (nc) carve_model(a, nc, n, E, wgrad, c.nc);
 }
@@ -1134,8 +1143,10 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
     NNP_HIP(hipMemsetAsync(c.t.rep_bad, 0, sizeof(int) * R, s));
     NNP_HIP(hipMemsetAsync(c.nb.status, 0, sizeof(int) * 8, s));
     NNP_HIP(hipMemsetAsync(c.t.rebuilds, 0, sizeof(long long), s));
+    NNP_HIP(hipMemsetAsync(c.spare_off, 0, sizeof(int) * (size_t(n) + 1), s));  // empty rows until a spare build
 
     nnp_nlist lc = st->nl_cons, ln = st->nl_nc;
+    const double disp_thr = 0.5 * p->skin;
     // With state->order the force evaluations keep their rows in the cell
     // order of the last build (row_of: caller index -> row; perm: back) and
     // read positions and species from row-ordered copies, which the builds
@@ -1157,7 +1168,30 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         if (rows) launch_commit_order(n, c.nb, trig, st->sys.species, st->order, c.pos_rows, c.species_rows, s);
         launch_finish_rebuild(trig, c.t.rebuilds, maxd2, s);
     };
-    const double disp_thr = 0.5 * p->skin;
+    // Predictive outer steps decide on the next step's rebuild right after
+    // their last B A O A (the positions the next step starts from) and build
+    // the conservative list into spare buffers beside the conservative
+    // evaluation that still reads the one in use; the fast-force list, read
+    // only by the inner evaluations before it, is filtered in place.  The
+    // spare list is adopted once that evaluation is done.  Needs the side
+    // stream and no reverse index.
+    const bool overlap_build = mts && lc.rev == nullptr && lc.capacity <= E;
+    auto build_spare_if_predicted = [&]() {
+        launch_predict_rebuild(maxd2, disp_thr, trig, s);
+        launch_build(n, st->pos, g, plan, c.nb, trig, rc_cons, lc.capacity, c.spare_off, c.spare_nbr, nullptr,
+                     st->pos_ref, s, rows);
+        launch_filter(n, rows ? c.nb.cell_pos : st->pos, g, c.nb, trig, c.spare_off, c.spare_nbr, rc_nc,
+                      ln.capacity, ln.offsets, ln.nbr, nullptr, nc_status, s, rows ? c.nb.cell_atoms : nullptr,
+                      c.nb.status);
+        if (rows)
+            launch_commit_order(n, c.nb, trig, st->sys.species, c.spare_order, c.spare_pos, c.spare_species, s);
+    };
+    auto adopt_spare = [&]() {
+        launch_adopt_lists(n, trig, c.nb, c.spare_off, c.spare_nbr, lc.capacity, lc.offsets, lc.nbr,
+                           rows ? c.spare_order : nullptr, st->order, c.spare_pos, c.pos_rows, c.spare_species,
+                           c.species_rows, s);
+        launch_finish_rebuild(trig, c.t.rebuilds, maxd2, s);
+    };
     BaoaArgs ba{};
     ba.n = n;
     ba.pos = st->pos;
@@ -1339,8 +1373,11 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         eval_cons();
         NNP_HIP(hipEventRecord(side->join, side->s));
     };
+    // With the spare build (ov), the step's own rebuild was decided and made
+    // by the previous step, or by mts_step just before it.
     auto mts_launches = [&](bool strict) {
-        if (!strict) {
+        const bool ov = !strict && overlap_build && side;
+        if (!strict && !ov) {
             launch_predict_rebuild(maxd2, disp_thr, trig, s);
             rebuild_if_flagged();
         }
@@ -1361,9 +1398,11 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
             if (side && k == n_in - 1) eval_cons_beside();
             eval_inner();
         }
+        if (ov) build_spare_if_predicted();
         launch_kick(n, st->vel, st->mass, st->f_nc, nullptr, 0.5 * d, s, c.t.o_step, uint64_t(n_in));
         if (side) NNP_HIP(hipStreamWaitEvent(s, side->join, 0));
         else eval_cons();
+        if (ov) adopt_spare();
         if (want_vir) {
             launch_virial_combine(n, c.cons.vir, c.nc.vir, c.nc.vir_sum, float(1.0 / n_in), c.cons.vir_sum, s);
             launch_rep_sum(R, c.t.rep_start, c.cons.vir_sum, st->virial, s);
@@ -1394,7 +1433,13 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
             if (cs) (void)hipStreamDestroy(cs);
         }
     } outer_graph;
+    bool prebuilt = false;  // this step's rebuild was decided by the previous (spare-building) step
     auto mts_step = [&](bool strict, bool allow_graph) {
+        const bool ov = !strict && overlap_build && side;
+        if (ov && !prebuilt) {
+            launch_predict_rebuild(maxd2, disp_thr, trig, s);
+            rebuild_if_flagged();
+        }
         if (!strict && allow_graph && !outer_graph.failed) {
             if (!outer_graph.x) {
                 // record on a private stream that first waits for the work
@@ -1430,6 +1475,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
         } else {
             mts_launches(strict);
         }
+        prebuilt = ov;
         offset += n_in;
         st->step += n_in;
     };
@@ -1496,6 +1542,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
                     st->n_replays += 1;
                 }
                 launch_set_u64(c.t.o_step, offset, s);
+                prebuilt = false;
                 NNP_HIP(hipMemsetAsync(c.t.flags + 4, 0, sizeof(int) * 12, s));  // stale, record, lists, trip
                 NNP_HIP(hipMemsetAsync(c.nb.status, 0, sizeof(int) * 8, s));
                 NNP_HIP(hipMemsetAsync(c.t.rep_bad, 0, sizeof(int) * R, s));

@@ -56,9 +56,17 @@ void launch_build(int n, const double* pos, const RepGeom& geom, const CellPlan&
                   hipStream_t stream, bool cell_rows = false);
 // pos: the positions in the order of the input list's rows; key (or
 // nullptr): caller's index of a row, for the reverse entries
+// src_status (or nullptr): the input list's build status; a failed build
+// leaves this list untouched
 void launch_filter(int n, const double* pos, const RepGeom& geom, NbrScratch& s, const int* run, const int* off_in,
                    const int* nbr_in, double radius, int64_t capacity, int* offsets, int* nbr, int* rev, int* status,
-                   hipStream_t stream, const int* key = nullptr);
+                   hipStream_t stream, const int* key = nullptr, const int* src_status = nullptr);
+// After a build into spare buffers that ran and succeeded (s.status): the
+// spare list (and, with order_src, the order and row-ordered positions and
+// species) copied over the ones in use.
+void launch_adopt_lists(int n, const int* run, const NbrScratch& s, const int* off_src, const int* nbr_src,
+                        int64_t capacity, int* off_dst, int* nbr_dst, const int* order_src, int* order_dst,
+                        const double* pos_src, double* pos_dst, const int* sp_src, int* sp_dst, hipStream_t stream);
 // After a cell-order build that succeeded: the permutation into order[2n]
 // (row -> caller index, then caller index -> row), positions and species in
 // row order.

@@ -327,8 +327,8 @@ k_nbr_fill(int n, const double* __restrict__ pos, RepGeom geom, Stencil st, doub
 __global__ void __launch_bounds__(64 * kWaves)
 k_filter_count(int n, const double* __restrict__ pos, RepGeom geom, const int* __restrict__ off_in,
                const int* __restrict__ nbr_in, double rc2, const int* __restrict__ run,
-               int* __restrict__ counts) {
-    if (*run == 0) return;
+               int* __restrict__ counts, const int* __restrict__ src_status) {
+    if (*run == 0 || (src_status && (src_status[0] | src_status[2]) != 0)) return;
     int lane = threadIdx.x & 63;
     int i = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
     if (i >= n) return;
@@ -349,8 +349,8 @@ __global__ void __launch_bounds__(64 * kWaves)
 k_filter_fill(int n, const double* __restrict__ pos, RepGeom geom, const int* __restrict__ off_in,
               const int* __restrict__ nbr_in, double rc2, const int* __restrict__ run,
               const int* __restrict__ tmp_off, int64_t capacity, int* __restrict__ offsets,
-              int* __restrict__ nbr, int* __restrict__ status) {
-    if (*run == 0) return;
+              int* __restrict__ nbr, int* __restrict__ status, const int* __restrict__ src_status) {
+    if (*run == 0 || (src_status && (src_status[0] | src_status[2]) != 0)) return;
     int lane = threadIdx.x & 63;
     int i = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
     if (i >= n) return;
@@ -427,6 +427,31 @@ __global__ void k_commit_order(int n, const int* __restrict__ run, const int* __
     pos_m[n + p] = cell_pos[n + p];
     pos_m[2 * n + p] = cell_pos[2 * n + p];
     species_m[p] = species[i];
+}
+
+// A list built into spare buffers (with its order and row-ordered copies)
+// replaces the one in use, once nothing reads the latter any more; only
+// after a build that ran and succeeded.
+__global__ void k_adopt_lists(int n, const int* __restrict__ run, const int* __restrict__ status,
+                              const int* __restrict__ off_src, const int* __restrict__ nbr_src, int64_t capacity,
+                              int* __restrict__ off_dst, int* __restrict__ nbr_dst, const int* __restrict__ order_src,
+                              int* __restrict__ order_dst, const double* __restrict__ pos_src,
+                              double* __restrict__ pos_dst, const int* __restrict__ sp_src, int* __restrict__ sp_dst) {
+    if (*run == 0 || status[0] != 0 || status[2] != 0) return;
+    const int64_t total = min(int64_t(off_src[n]), capacity);
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += stride) nbr_dst[t] = nbr_src[t];
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t <= n; t += stride) {
+        off_dst[t] = off_src[t];
+        if (t < n && order_src) {
+            order_dst[t] = order_src[t];
+            order_dst[n + t] = order_src[n + t];
+            pos_dst[t] = pos_src[t];
+            pos_dst[n + t] = pos_src[n + t];
+            pos_dst[2 * n + t] = pos_src[2 * n + t];
+            sp_dst[t] = sp_src[t];
+        }
+    }
 }
 
 // Positions and species in row order from the caller's arrays (order ==
@@ -609,6 +634,15 @@ void launch_gather_rows(int n, const int* order, const double* pos, const int* s
     NNP_LAUNCH_CHECK();
 }
 
+void launch_adopt_lists(int n, const int* run, const NbrScratch& s, const int* off_src, const int* nbr_src,
+                        int64_t capacity, int* off_dst, int* nbr_dst, const int* order_src, int* order_dst,
+                        const double* pos_src, double* pos_dst, const int* sp_src, int* sp_dst, hipStream_t stream) {
+    if (n <= 0) return;
+    k_adopt_lists<<<1024, 256, 0, stream>>>(n, run, s.status, off_src, nbr_src, capacity, off_dst, nbr_dst, order_src,
+                                            order_dst, pos_src, pos_dst, sp_src, sp_dst);
+    NNP_LAUNCH_CHECK();
+}
+
 void launch_reset_rows(int n, int* order, const double* pos, const int* species, double* pos_m, int* species_m,
                        hipStream_t stream) {
     if (n <= 0) return;
@@ -618,12 +652,13 @@ void launch_reset_rows(int n, int* order, const double* pos, const int* species,
 
 void launch_filter(int n, const double* pos, const RepGeom& geom, NbrScratch& s, const int* run,
                    const int* off_in, const int* nbr_in, double radius, int64_t capacity, int* offsets,
-                   int* nbr, int* rev, int* status, hipStream_t stream, const int* key) {
+                   int* nbr, int* rev, int* status, hipStream_t stream, const int* key, const int* src_status) {
     double rc2 = radius * radius;
-    k_filter_count<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, pos, geom, off_in, nbr_in, rc2, run, s.counts);
+    k_filter_count<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, pos, geom, off_in, nbr_in, rc2, run, s.counts,
+                                                                src_status);
     k_scan<<<1, 1024, 0, stream>>>(n, s.counts, s.tmp_off, run);
     k_filter_fill<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, pos, geom, off_in, nbr_in, rc2, run, s.tmp_off,
-                                                               capacity, offsets, nbr, status);
+                                                               capacity, offsets, nbr, status, src_status);
     if (rev)
         k_nbr_reverse<<<cdiv(n, kWaves), 64 * kWaves, 0, stream>>>(n, run, status, offsets, nbr, rev, key);
     NNP_LAUNCH_CHECK();
