@@ -1164,7 +1164,7 @@ nnp_status respa_run(const Model* cons, const Model* nc, respa_state* st, const 
                      s, rows);
         if (mts)
             launch_filter(n, rows ? c.nb.cell_pos : st->pos, g, c.nb, trig, lc.offsets, lc.nbr, rc_nc, ln.capacity,
-                          ln.offsets, ln.nbr, nullptr, nc_status, s, rows ? c.nb.cell_atoms : nullptr);
+                          ln.offsets, ln.nbr, nullptr, nc_status, s, rows ? c.nb.cell_atoms : nullptr, c.nb.status);
         if (rows) launch_commit_order(n, c.nb, trig, st->sys.species, st->order, c.pos_rows, c.species_rows, s);
         launch_finish_rebuild(trig, c.t.rebuilds, maxd2, s);
     };

@@ -527,15 +527,14 @@ __device__ __forceinline__ void bwd_batch(const MpBwd& a, const float* ptab, con
                 acc.GV[1] = fmaf(w1, g1v, acc.GV[1]);
                 acc.GV[2] = fmaf(w1, g2v, acc.GV[2]);
             }
-            // g_u . u of the unit-vector adjoints, from the projections above
-            const float cA = d.pc[g] * w2;
-            const float ud = fmaf(cA, gvo_u, -((o.ph[2] * w2) * gvn_u));
-            const float sv = fmaf(-ud, ir, dr);
+            // g_u . u of the unit-vector adjoints is w2 C (the projections
+            // above), so its share of the radial term is C w2 / r
+            const float w2ir = w2 * ir;
+            const float sv = fmaf(-C, w2ir, dr);
             acc.S1[0] = fmaf(sv, u0, acc.S1[0]);
             acc.S1[1] = fmaf(sv, u1, acc.S1[1]);
             acc.S1[2] = fmaf(sv, u2, acc.S1[2]);
-            acc.T1 = fmaf(cA, ir, acc.T1);
-            const float w2ir = w2 * ir;
+            acc.T1 = fmaf(d.pc[g], w2ir, acc.T1);
             acc.T2[0] = fmaf(w2ir, g0v, acc.T2[0]);
             acc.T2[1] = fmaf(w2ir, g1v, acc.T2[1]);
             acc.T2[2] = fmaf(w2ir, g2v, acc.T2[2]);
