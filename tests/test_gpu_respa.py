@@ -315,3 +315,34 @@ def test_cell_order_gives_the_same_bits(gpu_lib, width):
     assert np.array_equal(a.positions(), b.positions()) and np.array_equal(a.velocities(), b.velocities())
     assert torch.equal(a.f_cons, b.f_cons) and torch.equal(a.f_nc, b.f_nc)
     assert torch.equal(a.energy, b.energy) and torch.equal(a.virial, b.virial) and torch.equal(ka, kb)
+
+
+def test_list_overflow_mid_run_resumes_exactly(gpu_lib):
+    """A fast-force list buffer sized to the first build overflows when a
+    later rebuild (made beside the conservative evaluation) needs more room:
+    the call restores the last checked state and reports NNP_ECAPACITY, the
+    binding grows the buffer and resumes at that step, and the trajectory
+    equals, bit for bit, one whose buffers never overflowed."""
+    s = synth.water_config(3)
+    cons, _, nc, _ = _models_cfg0(gpu_lib)
+    m = s.standard_masses()
+    v0 = synth.maxwell_boltzmann(m, 300.0, 5000)
+    skin = 0.3
+    runs = []
+    for tight in (False, True):
+        system = gpu_lib.DeviceSystem(s.pos, s.species, s.box)
+        prm = gpu_lib.respa_params(2.0, 4, 300.0, seed=4000, mode="dmts_nc", skin=skin, check_every=2)
+        t = gpu_lib.Trajectory(cons, nc, system, v0, m, np.ones(s.n), prm)
+        cap0 = t.nl_nc.capacity
+        if tight:
+            probe = gpu_lib.NeighborList(s.n, nc.cutoff + skin, 1 << 22, with_rev=False)
+            gpu_lib.nnp_neighbors(system, probe, gpu_lib.workspace(None, None, s.n, 1, 1))
+            cap0 = int(probe.n_edges)  # exactly the first build's entries
+            t.nl_nc = gpu_lib.NeighborList(s.n, nc.cutoff + skin, cap0, with_rev=False)
+        t.respa_step(16)
+        runs.append((t, cap0))
+    (a, _), (b, cap_b) = runs
+    assert b.nl_nc.capacity > cap_b  # at least one rebuild overflowed and was retried
+    assert a.step_count == b.step_count == 64
+    assert np.array_equal(a.positions(), b.positions()) and np.array_equal(a.velocities(), b.velocities())
+    assert torch.equal(a.f_cons, b.f_cons) and torch.equal(a.f_nc, b.f_nc)
