@@ -472,7 +472,7 @@ def main():
     ap.add_argument("--chain-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+        print("bench.py measures one GPU only: this implementation has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
 

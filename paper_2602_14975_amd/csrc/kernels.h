@@ -48,7 +48,7 @@ CellPlan plan_cells(const nnp_system& sys, double radius);
 int64_t max_cells(int64_t n_atoms, int32_t n_rep);
 void carve_nbr_scratch(Arena& a, int64_t n, int32_t n_rep, NbrScratch& s);
 void upload_cell_plan(const CellPlan& plan, NbrScratch& s, hipStream_t stream);
-// cell_rows: rows and entries in the cell order of this build (s.cell_atoms
+// cell_rows: rows and entries in the cell order of this list build (s.cell_atoms
 // maps them to the caller's indices, s.cell_pos holds the positions in that
 // order); each row still ascending in caller index.
 void launch_build(int n, const double* pos, const RepGeom& geom, const CellPlan& plan, NbrScratch& s, const int* run,
