@@ -73,7 +73,8 @@ def message_counts(F, K, n_atoms, n_edges, reverse):
 # launch-timer groups, one timed region each: a site's launches are timed
 # while the other launches of the step run untimed, so that the host keeps
 # ahead of the device as in production (the dominant kernel alone first)
-TIMER_GROUPS = (("message_bwd",), ("message_fwd",), ("nc_message_fwd", "nc_update", "head_fwd", "baoa"), ("gemm",))
+TIMER_GROUPS = (("message_bwd",), ("message_fwd",), ("message_fwd_first", "message_bwd_first"),
+                ("nc_message_fwd", "nc_update", "head_fwd", "baoa"), ("gemm",))
 
 
 def run_gpu(args):
@@ -512,13 +513,14 @@ def main():
     roof, kernels = None, {}
     if kt.get("message_bwd", (0, 0))[1] > 0:
         flops, nbytes = message_counts(F, K, s.n, g["n_edges5"], reverse=True)
-        roof = roofline_entry("k_message_bwd_mx (conservative message reverse, F=128, K=16, cosine cutoff)",
+        roof = roofline_entry("k_message_bwd_mx (conservative message reverse, layers 2-3, F=128, K=16, "
+                              "cosine cutoff)",
                               *kt["message_bwd"], flops, nbytes, measured_traffic())
     if kt.get("message_fwd", (0, 0))[1] > 0:
         flops, nbytes = message_counts(F, K, s.n, g["n_edges5"], reverse=False)
-        kernels["message_fwd"] = roofline_entry("k_message_fwd_mx (conservative message forward)",
+        kernels["message_fwd"] = roofline_entry("k_message_fwd_mx (conservative message forward, layers 2-3)",
                                                 *kt["message_fwd"], flops, nbytes)
-    for site in ("nc_message_fwd", "nc_update", "head_fwd", "baoa", "gemm"):
+    for site in ("message_fwd_first", "message_bwd_first", "nc_message_fwd", "nc_update", "head_fwd", "baoa", "gemm"):
         if kt.get(site, (0, 0))[1] > 0:
             tot, cnt = kt[site]
             kernels[site] = {"avg_launch_us": round(tot / cnt * 1e3, 2), "launches": cnt,

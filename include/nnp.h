@@ -490,12 +490,20 @@ nnp_status nnp_timer_read(const char* site, double* total_ms, int64_t* launches,
  *   NNP_MP_AUTO (0): the matrix-core kernels for the shapes they cover
  *     (width 128, 16 Bessel functions, cosine cutoff, force evaluation);
  *     the radial filter runs there as split FP16 products at FP32-equivalent
- *     precision; the vector kernels elsewhere.
+ *     precision; the vector kernels elsewhere.  In that shape, with at most
+ *     8 species, the first layer (whose neighbour features depend on the
+ *     species alone and whose vector input is zero) is evaluated from
+ *     per-atom sums of the radial basis by neighbour species and four dense
+ *     products instead of per-edge feature work (the same function: the
+ *     filter is linear in the basis); its reverse, for forces, likewise.
  *   NNP_MP_VECTOR (1): the vector kernels (plain FP32 filter) everywhere.
- * Both give results within FP32 rounding of each other; this is for
- * measuring one against the other.  Other values: NNP_EINVAL. */
+ *   NNP_MP_EDGE (2): as NNP_MP_AUTO, but the first layer per edge on the
+ *     matrix-core kernels too.
+ * All give results within FP32 rounding of each other; this is for
+ * measuring one against another.  Other values: NNP_EINVAL. */
 #define NNP_MP_AUTO 0
 #define NNP_MP_VECTOR 1
+#define NNP_MP_EDGE 2
 nnp_status nnp_set_message_kernels(int32_t mode);
 
 /* Kernel selection for the per-atom perceptrons and linear maps of FP32

@@ -12,6 +12,7 @@ NNP_MODEL_CONS, NNP_MODEL_NC = 0, 1
 NNP_FP32, NNP_BF16 = 0, 1
 NNP_MODE_DMTS_NC, NNP_MODE_STS, NNP_MODE_DMTS = 0, 1, 2
 NNP_THERMO_LANGEVIN, NNP_THERMO_FFL = 0, 1
+NNP_MP_AUTO, NNP_MP_VECTOR, NNP_MP_EDGE = 0, 1, 2
 REPLICA_QUEUED, REPLICA_RUNNING, REPLICA_DONE, REPLICA_FAILED = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "NNP_OK", -1: "NNP_EINVAL", -2: "NNP_ENOMEM", -3: "NNP_ECAPACITY", -4: "NNP_EDEVICE",

@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libnnp.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = [
     "api.hip", "neighbors.hip", "gemm.hip", "mp.hip", "mp_mx.hip", "blocks.hip", "integrator.hip", "server.hip",
-    "timers.hip",
+    "timers.hip", "mp_species.hip",
 ]
 ARCH = "gfx950"
 

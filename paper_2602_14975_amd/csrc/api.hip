@@ -119,6 +119,11 @@ extern "C" nnp_status nnp_model_create(const nnp_model_desc* desc, nnp_model** o
         e = hipMalloc(&m->ncw, sizeof(float) * nc_image_count(d.width));
     if (e == hipSuccess) e = hipMalloc(&m->wT, sizeof(float) * m->n_weights);
     if (e == hipSuccess) e = hipMalloc(&m->mxs, sizeof(float) * 2 * kMaxLayers);
+    if (e == hipSuccess && d.kind == NNP_MODEL_CONS && species_sum_shape(d.width, d.n_rbf, 0, d.n_species)) {
+        species_sum_pitches(d.n_species, m->sp_pp, m->sp_ep);
+        e = hipMalloc(&m->sp, sizeof(float) * m->sp_count());
+        if (e == hipSuccess) e = hipMalloc(&m->sp_x, sizeof(uint16_t) * 3 * m->sp_xs());
+    }
     if (e == hipSuccess) e = hipMalloc(&m->wx, sizeof(uint16_t) * 6 * m->wx_stride());
     if (e != hipSuccess) {
         (void)hipFree(m->w);
@@ -127,6 +132,8 @@ extern "C" nnp_status nnp_model_create(const nnp_model_desc* desc, nnp_model** o
         if (m->wT) (void)hipFree(m->wT);
         if (m->mxs) (void)hipFree(m->mxs);
         if (m->wx) (void)hipFree(m->wx);
+        if (m->sp) (void)hipFree(m->sp);
+        if (m->sp_x) (void)hipFree(m->sp_x);
         delete m;
         set_error(std::string("model set-up: ") + hipGetErrorString(e));
         return NNP_EDEVICE;
@@ -141,6 +148,8 @@ extern "C" nnp_status nnp_model_create(const nnp_model_desc* desc, nnp_model** o
         (void)hipFree(m->wT);
         (void)hipFree(m->mxs);
         if (m->wx) (void)hipFree(m->wx);
+        if (m->sp) (void)hipFree(m->sp);
+        if (m->sp_x) (void)hipFree(m->sp_x);
         delete m;
         throw;
     }
@@ -157,6 +166,8 @@ extern "C" void nnp_model_destroy(nnp_model* model) {
     if (m->wT) (void)hipFree(m->wT);
     if (m->mxs) (void)hipFree(m->mxs);
     if (m->wx) (void)hipFree(m->wx);
+    if (m->sp) (void)hipFree(m->sp);
+    if (m->sp_x) (void)hipFree(m->sp_x);
     delete m;
 }
 
@@ -276,6 +287,7 @@ void carve_model(Arena& a, const Model* m, int64_t n, int64_t E, bool for_wgrad,
             b.erec = a.take<EdgeRec>(E);
             b.ehalf = a.take<uint4>(8 * E);
             for (int l = 1; l < L; ++l) b.layer[l].pv = a.take<float>(n * 3 * F);
+            if (m->sp) b.sp = a.take<float>(n * 4 * std::max(m->sp_pp, m->sp_ep));
         }
     } else {
         const int64_t HC = 2 * int64_t(m->desc.n_s + m->desc.n_l) * m->desc.n_c;
@@ -317,6 +329,10 @@ void Model::refresh_tables(hipStream_t s) {
     gemm_xwt(S, F, F, p(off_emb), F, p(lo.W1), p(lo.b1), z_tab(), F, EPI_SILU, h1_tab(), F, false, s, bf16());
     gemm_xwt(S, 3 * F, F, z_tab(), F, p(lo.W2), p(lo.b2), phi_tab(), 3 * F, EPI_NONE, nullptr, 0, false, s, bf16());
     if (ncw) pack_nc_weights(F, p(lo.U), p(lo.M1), p(lo.M2), p(off_Wq), p(off_WV), bf16(), ncw, s);
+    if (sp) {
+        launch_sp_tables(F, S, p(lo.Wr), p(lo.br), phi_tab(), p(off_emb), sp, sp + 2 * int64_t(F) * sp_ep, s);
+        launch_split3(sp, sp_count(), sp_x, sp_xs(), s);
+    }
     // transposed mirror of the matrices used as G W; both mirrors split into
     // bfloat16 pieces
     auto tr = [&](int64_t off, int rows, int cols) {
@@ -351,6 +367,13 @@ static void gemm_gwt(const Model* m, int64_t off, int M, int N, int K, const flo
              m->pxT(off), m->wx_stride());
 }
 
+// The first layer of a conservative model by neighbour species (its edge
+// sums and two dense products in place of the per-edge message kernels),
+// where the model has the tables and the edges are prepared.
+static bool species_sum_on(const Model* m, const MpGeom& mg, const ModelBuf& b) {
+    return m->sp && b.sp && mg.ecnt && message_mx_active(m->desc.width, m->desc.n_rbf, 0) && species_sum_active();
+}
+
 void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, ModelBuf& b, hipStream_t s) {
     const int n = int(sys.n_atoms);
     const int F = m->desc.width, K = m->desc.n_rbf, S = m->desc.n_species;
@@ -378,7 +401,27 @@ void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, Mode
             a.phi = lb.phi;
             a.pv = lb.pv;
         }
-        launch_message_fwd(F, K, cut, mg, a, s);
+        if (l == 0 && species_sum_on(m, mg, b)) {
+            // s = [E | species indicator] T_0^T (T_0 holds the embedding in
+            // the indicator slots), v = U T_2^T: one launch over the rows
+            // [s; v] where they are adjacent (FP32-equivalent split-bfloat16
+            // products, else float32 ones)
+            const int ep = m->sp_ep;
+            float* Ev = b.sp + int64_t(n) * ep;
+            launch_sp_fwd(mg, S, b.sp, Ev, s);
+            const bool adj = lb.vmid == lb.smid + int64_t(n) * F;
+            if (!(adj && n % 128 == 0 &&
+                  gemm_x3_split(4 * n, F, ep, b.sp, ep, m->sp_Tx(0), m->sp_Tx(1), m->sp_xs(), n, lb.smid, F, s))) {
+                if (adj && n % 32 == 0) {
+                    gemm_xwt_f32_split(4 * n, F, ep, b.sp, ep, m->sp_T(0), m->sp_T(1), n, lb.smid, F, s);
+                } else {
+                    gemm_xwt(n, F, ep, b.sp, ep, m->sp_T(0), nullptr, lb.smid, F, EPI_NONE, nullptr, 0, false, s);
+                    gemm_xwt(3 * n, F, ep, Ev, ep, m->sp_T(1), nullptr, lb.vmid, F, EPI_NONE, nullptr, 0, false, s);
+                }
+            }
+        } else {
+            launch_message_fwd(F, K, cut, mg, a, s);
+        }
         gemm_xwt(3 * n, 2 * F, F, lb.vmid, F, m->p(lo.U), nullptr, lb.UV, 2 * F, EPI_NONE, nullptr, 0, false, s,
                  m->bf16(), m->px(lo.U), m->wx_stride());
         launch_build_x(n, F, lb.smid, lb.UV, lb.X, s);
@@ -438,6 +481,25 @@ void layer_backward(const Model* m, int l, const MpGeom& mg, ModelBuf& b, float*
         a.phi = lb.phi;
         a.pv = lb.pv;
         a.want_gphi = 1;
+    }
+    if (l == 0 && !wg && force && species_sum_on(m, mg, b)) {
+        // P_0 = g_smid T_0, P_2 = g_vmid T_2 (float32 products), then the
+        // per-edge force shares
+        // (one launch over the rows [g_smid; g_vmid] where they are adjacent)
+        const int pp = m->sp_pp;
+        float* P2 = b.sp + int64_t(n) * pp;
+        const bool adj = b.gv == b.gs2 + int64_t(n) * F;
+        if (!(adj && n % 128 == 0 &&
+              gemm_x3_split(4 * n, pp, F, b.gs2, F, m->sp_TTx(0), m->sp_TTx(1), m->sp_xs(), n, b.sp, pp, s))) {
+            if (adj && n % 32 == 0) {
+                gemm_xwt_f32_split(4 * n, pp, F, b.gs2, F, m->sp_TT(0), m->sp_TT(1), n, b.sp, pp, s);
+            } else {
+                gemm_xwt(n, pp, F, b.gs2, F, m->sp_TT(0), nullptr, b.sp, pp, EPI_NONE, nullptr, 0, false, s);
+                gemm_xwt(3 * n, pp, F, b.gv, F, m->sp_TT(1), nullptr, P2, pp, EPI_NONE, nullptr, 0, false, s);
+            }
+        }
+        launch_sp_bwd(mg, m->desc.n_species, b.sp, P2, force, accum_force, vir, s);
+        return;
     }
     launch_message_bwd(F, K, cut, mg, a, force != nullptr, wg, s);
     if (wg) {

@@ -160,10 +160,12 @@ __global__ void __launch_bounds__(64 * S) k_gemm_rk(GemmArgs g) {
     const float* arow = g.A + (mok ? int64_t(m0 + r) * g.sam : 0);
     const float* brow[T];
     bool nok[T];
+    // rows from b_split on take the second operand (b_split a multiple of 32)
+    const float* B = (g.B2 && m0 >= g.b_split) ? g.B2 : g.B;
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         nok[t] = n0 + 32 * t + r < g.N;
-        brow[t] = g.B + (nok[t] ? int64_t(n0 + 32 * t + r) * g.sbn : 0);
+        brow[t] = B + (nok[t] ? int64_t(n0 + 32 * t + r) * g.sbn : 0);
     }
     floatx16 acc[T];
 #pragma unroll
@@ -389,6 +391,8 @@ __global__ void __launch_bounds__(256) k_gemm_x3(GemmArgs g) {
     // rows past M read row M - 1 (unconditional loads keep the waits exact)
     // and are never stored
     const float* arow = g.A + int64_t(min(m0 + r, g.M - 1)) * g.sam + 16 * h;
+    // row tiles from b_split on take the second set of pieces
+    const uint16_t* Bx = (g.Bx2 && (L / NT) * 128 >= g.b_split) ? g.Bx2 : g.Bx;
 
 #define NNP_X3_LOAD_A(DST, C) \
     _Pragma("unroll") for (int q = 0; q < 4; ++q) DST[q] = *reinterpret_cast<const f32x4_t*>(arow + (C) * 32 + 4 * q);
@@ -403,7 +407,7 @@ __global__ void __launch_bounds__(256) k_gemm_x3(GemmArgs g) {
         for (int u = 0; u < UPT; ++u) {
             const int idx = u * 256 + tid;
             const int p = idx / (BN * RU), col = (idx / RU) % BN, q = idx % RU;
-            tmp[u] = *reinterpret_cast<const u32x4_v*>(g.Bx + p * g.bxs + int64_t(n0 + col) * KK + 8 * q);
+            tmp[u] = *reinterpret_cast<const u32x4_v*>(Bx + p * g.bxs + int64_t(n0 + col) * KK + 8 * q);
         }
 #pragma unroll
         for (int u = 0; u < UPT; ++u) {
@@ -559,6 +563,49 @@ void gemm_xwt(int M, int N, int K, const float* X, int ldx, const float* W, cons
     g.bf16 = bf16;
     g.Bx = Wx; g.bxs = wx_stride;
     launch_gemm(g, s);
+}
+
+bool gemm_x3_split(int M, int N, int K, const float* X, int ldx, const uint16_t* Wx, const uint16_t* Wx2,
+                   int64_t wx_stride, int m_split, float* out, int ldo, hipStream_t s) {
+    GemmArgs g{};
+    g.M = M; g.N = N; g.K = K;
+    g.A = X; g.sam = ldx; g.sak = 1;
+    g.sbk = 1; g.sbn = K;
+    g.C = out; g.ldc = ldo; g.epi = EPI_NONE;
+    g.Bx = Wx; g.bxs = wx_stride;
+    g.Bx2 = Wx2; g.b_split = m_split;
+    if (g_dense_mode.load() != 0 || m_split % 128 != 0 || !Wx2 || (reinterpret_cast<uintptr_t>(Wx2) & 15) != 0 ||
+        !x3_ok(g))
+        return false;
+    if (M <= 0) return true;
+    ScopedTimer timer("gemm", s);
+    x3_launch(g, s);
+    NNP_LAUNCH_CHECK();
+    return true;
+}
+
+void gemm_xwt_f32_split(int M, int N, int K, const float* X, int ldx, const float* W, const float* W2, int m_split,
+                        float* out, int ldo, hipStream_t s) {
+    GemmArgs g{};
+    g.M = M; g.N = N; g.K = K;
+    g.A = X; g.sam = ldx; g.sak = 1;
+    g.B = W; g.sbk = 1; g.sbn = K;
+    g.B2 = W2; g.b_split = m_split;
+    g.C = out; g.ldc = ldo; g.epi = EPI_NONE;
+    if (M <= 0 || N <= 0) return;
+    if (m_split % 32 != 0 || !rk_ok(g) || N > 160) {
+        set_error("gemm_xwt_f32_split: unsupported shape");
+        throw Fail{NNP_EINVAL};
+    }
+    ScopedTimer timer("gemm", s);
+    const int T = cdiv(N, 32);
+    const int S = K >= 128 ? 4 : 1;
+    if (T == 4 && S == 1) rk_launch<4, 1>(g, s);
+    else if (T <= 2 && S == 4) rk_launch<2, 4>(g, s);
+    else if (T == 3 && S == 4) rk_launch<3, 4>(g, s);
+    else if (S == 4) rk_launch<5, 4>(g, s);
+    else rk_launch<1, 1>(g, s);
+    NNP_LAUNCH_CHECK();
 }
 
 // out = G W (G [M][N] row-major, W [N][K]) -> [M][K]; optional silu'(pre) factor.

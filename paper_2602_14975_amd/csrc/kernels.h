@@ -113,12 +113,30 @@ struct GemmArgs {
     // same [N][K] layout; lets FP32 products run on bfloat16 matrix cores
     const uint16_t* Bx;
     int64_t bxs;
+    // float32 register-direct kernel only: rows from b_split on multiply by
+    // B2 instead of B (same layout)
+    const float* B2;
+    int64_t b_split;
+    // split-bfloat16 kernel: row tiles from b_split on (a multiple of 128)
+    // take the pieces at Bx2 instead of Bx
+    const uint16_t* Bx2;
 };
 
 void launch_gemm(const GemmArgs& g, hipStream_t s);
 void gemm_xwt(int M, int N, int K, const float* X, int ldx, const float* W, const float* b, float* out, int ldo,
               int epi, float* pre, int ldp, bool accum, hipStream_t s, bool bf16 = false,
               const uint16_t* Wx = nullptr, int64_t wx_stride = 0);
+// out = X W^T with float32 operands on the matrix cores, rows m >= m_split
+// taking W2 (same [N][K] layout) instead of W; m_split a multiple of 32,
+// N <= 160, K and the strides multiples of 4.
+// The same on the split-bfloat16 kernel (FP32-equivalent): pieces Wx and Wx2
+// (piece stride wx_stride), m_split a multiple of 128; false (nothing
+// launched) where the kernel cannot take the shapes or the float32 kernels
+// are selected.
+bool gemm_x3_split(int M, int N, int K, const float* X, int ldx, const uint16_t* Wx, const uint16_t* Wx2,
+                   int64_t wx_stride, int m_split, float* out, int ldo, hipStream_t s);
+void gemm_xwt_f32_split(int M, int N, int K, const float* X, int ldx, const float* W, const float* W2, int m_split,
+                        float* out, int ldo, hipStream_t s);
 // dst[p * piece_stride + e] = piece p (hi, mid, lo) of src[e] as bfloat16
 void launch_split3(const float* src, int64_t count, uint16_t* dst, int64_t piece_stride, hipStream_t s);
 // 0: FP32 products on split-bfloat16 matrix cores where the shapes allow
@@ -138,7 +156,21 @@ int mp_blocks(int n, int F);
 // matrix-core message kernels (F = 128, K = 16, cosine cutoff; forces, no weight adjoints)
 bool message_mx_shape(int F, int K, int cut);
 bool message_mx_active(int F, int K, int cut);  // shape covered and not switched off
+bool species_sum_active();                       // first layer by neighbour species not switched off
 void launch_edge_prep(const MpGeom& mg, int* ecnt, EdgeRec* erec, uint4* ehalf, hipStream_t s);
+// First layer of the conservative message step summed by neighbour species
+// (mp_species.hip): row pitches (pp of the per-atom tables P, a multiple of
+// 32; ep of the edge sums, 128 or 256), shapes covered, the weight tables
+// T [2][F][ep] and TT [2][pp][F] (refreshed with the weights), the forward
+// edge sums (rows Es [n][ep], Ev [3n][ep]) and the reverse edge kernel from
+// P0 [n][pp], P2 [3n][pp].
+void species_sum_pitches(int n_species, int& pp, int& ep);
+bool species_sum_shape(int F, int K, int cut, int n_species);
+void launch_sp_tables(int F, int S, const float* Wr, const float* br, const float* phi, const float* emb, float* T,
+                      float* TT, hipStream_t s);
+void launch_sp_fwd(const MpGeom& mg, int S, float* Es, float* Ev, hipStream_t s);
+void launch_sp_bwd(const MpGeom& mg, int S, const float* P0, const float* P2, float* force, bool accum, float* vir,
+                   hipStream_t s);
 void launch_message_fwd_mx(const MpGeom& mg, const MpFwd& a, hipStream_t s, const ScopedTimer& t);
 void launch_message_bwd_mx(const MpGeom& mg, const MpBwd& a, hipStream_t s, const ScopedTimer& t);
 void launch_filter_scale(int count, const float* Wr, float* out, hipStream_t s);

@@ -56,6 +56,22 @@ struct Model {
     // matrix-core message kernels, and its inverse.
     float* mxs = nullptr;
     const float* mx_scale(int l) const { return mxs + 2 * l; }
+    // Conservative models of the matrix-core message shape: the first
+    // layer's tables by neighbour species (launch_sp_tables), T [2][F][ep]
+    // then TT [2][pp][F] (species_sum_pitches), and the same split into
+    // three bfloat16 pieces (piece stride sp_xs()) for the matrix-core
+    // products.
+    float* sp = nullptr;
+    uint16_t* sp_x = nullptr;
+    int sp_pp = 0, sp_ep = 0;
+    int64_t sp_count() const { return 2 * int64_t(desc.width) * (sp_ep + sp_pp); }
+    int64_t sp_xs() const { return (sp_count() + 7) / 8 * 8; }
+    const float* sp_T(int c) const { return sp + int64_t(c) * desc.width * sp_ep; }
+    const float* sp_TT(int c) const { return sp + 2 * int64_t(desc.width) * sp_ep + int64_t(c) * sp_pp * desc.width; }
+    const uint16_t* sp_Tx(int c) const { return sp_x + int64_t(c) * desc.width * sp_ep; }
+    const uint16_t* sp_TTx(int c) const {
+        return sp_x + 2 * int64_t(desc.width) * sp_ep + int64_t(c) * sp_pp * desc.width;
+    }
     void refresh_tables(hipStream_t s);
 };
 
@@ -75,6 +91,9 @@ struct ModelBuf {
     float *chunk_part = nullptr, *mp_part = nullptr, *filt_sum = nullptr;
     // per-atom virial shares: of the last evaluation, and a running sum
     float *vir = nullptr, *vir_sum = nullptr;
+    // first layer by neighbour species: the edge sums (forward) or the P
+    // tables (reverse), [n][NS] then [3n][NS]; null when not carved
+    float* sp = nullptr;
     // NC models: the edges within the cutoff as records for the pair head
     // (list capacity E), and their count per atom; null when not carved
     NcEdge* nc_edges = nullptr;

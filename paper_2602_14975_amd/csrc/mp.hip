@@ -566,8 +566,9 @@ int mp_blocks(int n, int F) {
 // The matrix-core kernels serve the shapes they cover unless the vector
 // kernels were selected (nnp_set_message_kernels).
 static std::atomic<int> g_mp_mode{NNP_MP_AUTO};
-static bool mx_enabled() { return g_mp_mode.load(std::memory_order_relaxed) == NNP_MP_AUTO; }
+static bool mx_enabled() { return g_mp_mode.load(std::memory_order_relaxed) != NNP_MP_VECTOR; }
 bool message_mx_active(int F, int K, int cut) { return message_mx_shape(F, K, cut) && mx_enabled(); }
+bool species_sum_active() { return g_mp_mode.load(std::memory_order_relaxed) == NNP_MP_AUTO; }
 
 #define NNP_DISPATCH_MP(F_, K_, CUT_, CALL)                                          \
     if (F == F_ && K == K_ && cut == CUT_) { CALL; NNP_LAUNCH_CHECK(); return; }
@@ -619,7 +620,7 @@ void launch_message_bwd(int F, int K, int cut, const MpGeom& mg, const MpBwd& a,
 }  // namespace nnp
 
 extern "C" nnp_status nnp_set_message_kernels(int32_t mode) {
-    if (mode != NNP_MP_AUTO && mode != NNP_MP_VECTOR) return NNP_EINVAL;
+    if (mode != NNP_MP_AUTO && mode != NNP_MP_VECTOR && mode != NNP_MP_EDGE) return NNP_EINVAL;
     nnp::g_mp_mode.store(mode, std::memory_order_relaxed);
     return NNP_OK;
 }

@@ -122,3 +122,18 @@ def test_model_create_rejects_wrong_weight_count(lib):
     assert b"manifest needs" in lib.nnp_last_error()
     n_ok = synth.manifest_size(synth.CONS_CFG0)
     assert str(n_ok).encode() in lib.nnp_last_error()
+
+
+def test_message_kernel_modes(lib):
+    """The kernel choice is a host-side setting: the three modes of the
+    header are accepted, anything else is NNP_EINVAL."""
+    from paper_2602_14975_amd import _abi
+    header = open(os.path.join(os.path.dirname(__file__), "..", "include", "nnp.h")).read()
+    for name in ("NNP_MP_AUTO", "NNP_MP_VECTOR", "NNP_MP_EDGE"):
+        assert re.search(rf"#define {name} {getattr(_abi, name)}\b", header)
+    try:
+        for mode in (_abi.NNP_MP_VECTOR, _abi.NNP_MP_EDGE, _abi.NNP_MP_AUTO):
+            assert lib.nnp_set_message_kernels(mode) == _abi.NNP_OK
+        assert lib.nnp_set_message_kernels(3) == _abi.NNP_EINVAL
+    finally:
+        lib.nnp_set_message_kernels(_abi.NNP_MP_AUTO)

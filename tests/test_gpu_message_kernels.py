@@ -69,6 +69,32 @@ def test_matrix_core_and_vector_kernels_agree(gpu_lib):
     assert abs(em - ev) <= 1e-6 * abs(E) + 1e-4
 
 
+@pytest.mark.parametrize("which", [0, 3])
+def test_species_sums_match_per_edge_first_layer(gpu_lib, which):
+    """The first layer from per-species sums of the radial basis (default)
+    and per edge on the matrix-core kernels (NNP_MP_EDGE) compute the same
+    function: forces within FP32 rounding of each other and of the oracle.
+    The 192-atom box runs its dense products over [s; v] as float32 ones
+    (192 rows are not a multiple of 128), the 1,536-atom box as split
+    bfloat16 ones."""
+    from paper_2602_14975_amd import _abi
+    s = synth.water_config(which)
+    spec = synth.CONS_CFG1
+    w = synth.random_weights(spec, 4150)
+    print(f"case water{which} n={s.n}", flush=True)
+    try:
+        _set_kernels(gpu_lib, _abi.NNP_MP_EDGE)
+        ee, fe = _forces(gpu_lib, spec, w, s.pos, s.species, s.box, 5.0)
+        _set_kernels(gpu_lib, _abi.NNP_MP_AUTO)
+        es, fs = _forces(gpu_lib, spec, w, s.pos, s.species, s.box, 5.0)
+    finally:
+        _set_kernels(gpu_lib, _abi.NNP_MP_AUTO)
+    E, F = _oracle(spec, w, s.pos, s.species, s.box)
+    assert rel_rmse(fs, F) <= FP32_TOL and rel_rmse(fe, F) <= FP32_TOL
+    assert rel_rmse(fs, fe) <= 2e-6
+    assert abs(es - ee) <= 1e-6 * abs(E) + 1e-4
+
+
 def test_kernel_mode_rejects_unknown_value(gpu_lib):
     assert gpu_lib.lib().nnp_set_message_kernels(7) != 0
 
