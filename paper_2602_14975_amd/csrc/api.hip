@@ -408,7 +408,7 @@ void embed_forward(const Model* m, const nnp_system& sys, const MpGeom& mg, Mode
             // products, else float32 ones)
             const int ep = m->sp_ep;
             float* Ev = b.sp + int64_t(n) * ep;
-            launch_sp_fwd(mg, S, b.sp, Ev, s);
+            // (the edge sums E, U come with the edge preparation)
             const bool adj = lb.vmid == lb.smid + int64_t(n) * F;
             if (!(adj && n % 128 == 0 &&
                   gemm_x3_split(4 * n, F, ep, b.sp, ep, m->sp_Tx(0), m->sp_Tx(1), m->sp_xs(), n, lb.smid, F, s))) {
@@ -568,7 +568,12 @@ void cons_eval(const Model* m, const nnp_system& sys, const RepGeom& geom, const
     mg.perm = perm;
     if (b.ecnt && message_mx_active(F, m->desc.n_rbf, 0)) {
         // the edges within the cutoff, prepared once for all six message launches
-        launch_edge_prep(mg, b.ecnt, b.erec, b.ehalf, s);
+        // (with the first layer by neighbour species, its edge sums in the same pass)
+        if (m->sp && b.sp && species_sum_active())
+            launch_edge_prep(mg, b.ecnt, b.erec, b.ehalf, s, b.sp, b.sp + int64_t(n) * m->sp_ep, m->desc.n_species,
+                             m->sp_ep);
+        else
+            launch_edge_prep(mg, b.ecnt, b.erec, b.ehalf, s);
         mg.ecnt = b.ecnt;
         mg.erec = b.erec;
         mg.ehalf = b.ehalf;

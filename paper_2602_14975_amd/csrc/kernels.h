@@ -157,18 +157,20 @@ int mp_blocks(int n, int F);
 bool message_mx_shape(int F, int K, int cut);
 bool message_mx_active(int F, int K, int cut);  // shape covered and not switched off
 bool species_sum_active();                       // first layer by neighbour species not switched off
-void launch_edge_prep(const MpGeom& mg, int* ecnt, EdgeRec* erec, uint4* ehalf, hipStream_t s);
+// With Es, also the first conservative layer's edge sums by neighbour species
+// (rows Es [n][ep], Ev [3n][ep]; S species, S <= 8; mp_species.hip).
+void launch_edge_prep(const MpGeom& mg, int* ecnt, EdgeRec* erec, uint4* ehalf, hipStream_t s, float* Es = nullptr,
+                      float* Ev = nullptr, int S = 0, int ep = 0);
 // First layer of the conservative message step summed by neighbour species
 // (mp_species.hip): row pitches (pp of the per-atom tables P, a multiple of
 // 32; ep of the edge sums, 128 or 256), shapes covered, the weight tables
-// T [2][F][ep] and TT [2][pp][F] (refreshed with the weights), the forward
-// edge sums (rows Es [n][ep], Ev [3n][ep]) and the reverse edge kernel from
+// T [2][F][ep] and TT [2][pp][F] (refreshed with the weights; the forward
+// edge sums come from launch_edge_prep) and the reverse edge kernel from
 // P0 [n][pp], P2 [3n][pp].
 void species_sum_pitches(int n_species, int& pp, int& ep);
 bool species_sum_shape(int F, int K, int cut, int n_species);
 void launch_sp_tables(int F, int S, const float* Wr, const float* br, const float* phi, const float* emb, float* T,
                       float* TT, hipStream_t s);
-void launch_sp_fwd(const MpGeom& mg, int S, float* Es, float* Ev, hipStream_t s);
 void launch_sp_bwd(const MpGeom& mg, int S, const float* P0, const float* P2, float* force, bool accum, float* vir,
                    hipStream_t s);
 void launch_message_fwd_mx(const MpGeom& mg, const MpFwd& a, hipStream_t s, const ScopedTimer& t);

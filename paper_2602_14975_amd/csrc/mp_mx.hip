@@ -139,11 +139,27 @@ __device__ __forceinline__ float ld_off(const float* base, uint32_t byte_off) {
 
 // ---------------------------------------------------------- edge preparation
 
+// With SM > 0 the same pass also forms the first conservative layer's edge
+// sums by neighbour species (see mp_species.hip): the edges of each
+// iteration are staged in LDS grouped by species, and lane (c, k) =
+// (lane / 16, lane % 16) adds w_c e_k f (w_0 = 1, w_{1+a} = u_a) and w_c f
+// over each species' segment; rows Es[i][ep] (c = 0) and Ev[3 i + a][ep],
+// 20 slots per species (16 basis values, the cutoff, the species
+// indicator, two zeros), zero past S species.
+constexpr int kSpKP = kMxK + 4;
+
+template <int SM>
 __global__ void __launch_bounds__(256, 3) k_edge_prep(MpGeom mg, int* __restrict__ ecnt, EdgeRec* __restrict__ erec,
-                                                   uint4* __restrict__ ehalf) {
+                                                   uint4* __restrict__ ehalf, float* __restrict__ Es,
+                                                   float* __restrict__ Ev, int S, int ep) {
+    constexpr int SP_PITCH = kMxK + 5;  // staged edge: e_k f, 1, u[3], f
+    __shared__ float stage[SM > 0 ? 4 : 1][SM > 0 ? 64 : 1][SP_PITCH];
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= mg.n) return;  // whole wavefronts
+    const int c = lane >> 4, kk = lane & 15;
+    float acc[SM > 0 ? SM : 1] = {}, accf[SM > 0 ? SM : 1] = {};
+    float(*st)[SP_PITCH] = stage[SM > 0 ? (threadIdx.x >> 6) : 0];
     const int n = mg.n;
     const int start = mg.off[i], end = mg.off[i + 1];
     double L, inv;
@@ -160,6 +176,21 @@ __global__ void __launch_bounds__(256, 3) k_edge_prep(MpGeom mg, int* __restrict
             ok = pair_rule(xi, yi, zi, mg.pos[j], mg.pos[n + j], mg.pos[2 * n + j], L, inv, mg.rc2, dx, dy, dz);
         }
         const uint64_t bal = __ballot(ok);
+        const int tj = ok && mg.species ? min(max(mg.species[j], 0), mg.n_species - 1) : 0;
+        // this iteration's edges grouped by neighbour species (list order
+        // within a species)
+        int seg[SM + 1];
+        seg[0] = 0;
+        int slot = 0;  // staging row of this lane's edge
+        if constexpr (SM > 0) {
+            const int t = ok ? min(tj, S - 1) : SM;
+#pragma unroll
+            for (int sp = 0; sp < SM; ++sp) {
+                const uint64_t m = __ballot(t == sp);
+                if (t == sp) slot = seg[sp] + __popcll(m & ((1ull << lane) - 1ull));
+                seg[sp + 1] = seg[sp] + __popcll(m);
+            }
+        }
         if (ok) {
             const int p = start + cnt + __popcll(bal & ((1ull << lane) - 1ull));
             const double r = sqrt((dx * dx + dy * dy) + dz * dz);
@@ -168,7 +199,7 @@ __global__ void __launch_bounds__(256, 3) k_edge_prep(MpGeom mg, int* __restrict
             radial_cos_f32<kMxK>(float(r), mg, ef, def, fc, dfc);
             EdgeRec rec;
             rec.j = j;
-            rec.t = mg.species ? min(max(mg.species[j], 0), mg.n_species - 1) : 0;
+            rec.t = tj;
             rec.fc = fc;
             rec.dfc = dfc;
             rec.u[0] = float(dx * ir);
@@ -187,10 +218,47 @@ __global__ void __launch_bounds__(256, 3) k_edge_prep(MpGeom mg, int* __restrict
                 dst[4 + q] = __builtin_bit_cast(uint4, hi);
                 dst[6 + q] = __builtin_bit_cast(uint4, lo);
             }
+            if constexpr (SM > 0) {
+#pragma unroll
+                for (int q = 0; q < kMxK; ++q) st[slot][q] = ef[q];
+                st[slot][kMxK] = 1.f;
+                st[slot][kMxK + 1] = rec.u[0];
+                st[slot][kMxK + 2] = rec.u[1];
+                st[slot][kMxK + 3] = rec.u[2];
+                st[slot][kMxK + 4] = fc;
+            }
         }
         cnt += __popcll(bal);
+        if constexpr (SM > 0) {
+            wave_sync_lds();
+            // each edge added to the running sums in list order (within its
+            // species), so that the sums do not depend on where the list
+            // rows split into iterations (list radius, replica packing)
+#pragma unroll
+            for (int sp = 0; sp < SM; ++sp) {
+                for (int q = seg[sp]; q < seg[sp + 1]; ++q) {
+                    const float wc = st[q][kMxK + c];
+                    acc[sp] = fmaf(wc, st[q][kk], acc[sp]);
+                    accf[sp] = fmaf(wc, st[q][kMxK + 4], accf[sp]);
+                }
+            }
+            wave_sync_lds();  // the next iteration overwrites the staged edges
+        }
     }
     if (lane == 0) ecnt[i] = cnt;
+    if constexpr (SM > 0) {
+        float* row = c == 0 ? Es + int64_t(i) * ep : Ev + (int64_t(i) * 3 + (c - 1)) * ep;
+        const int ti = min(max(mg.species[i], 0), S - 1);
+#pragma unroll
+        for (int sp = 0; sp < SM; ++sp) {
+            if (sp >= S) break;
+            row[sp * kSpKP + kk] = acc[sp];
+            if (kk == 0) row[sp * kSpKP + kMxK] = accf[sp];
+            if (kk == 1) row[sp * kSpKP + kMxK + 1] = (c == 0 && sp == ti) ? 1.f : 0.f;
+            if (kk >= 2 && kk < kSpKP - kMxK) row[sp * kSpKP + kMxK + kk] = 0.f;
+        }
+        for (int z = S * kSpKP + kk; z < ep; z += 16) row[z] = 0.f;
+    }
 }
 
 // A batch's prepared edges are loaded once per block: thread t holds one
@@ -762,9 +830,14 @@ void launch_message_bwd_mx(const MpGeom& mg, const MpBwd& a, hipStream_t s, cons
     }
 }
 
-void launch_edge_prep(const MpGeom& mg, int* ecnt, EdgeRec* erec, uint4* ehalf, hipStream_t s) {
+void launch_edge_prep(const MpGeom& mg, int* ecnt, EdgeRec* erec, uint4* ehalf, hipStream_t s, float* Es, float* Ev,
+                      int S, int ep) {
     if (mg.n <= 0) return;
-    k_edge_prep<<<cdiv(mg.n, 4), 256, 0, s>>>(mg, ecnt, erec, ehalf);
+    const dim3 grid(cdiv(mg.n, 4));
+    if (!Es) k_edge_prep<0><<<grid, 256, 0, s>>>(mg, ecnt, erec, ehalf, nullptr, nullptr, 0, 0);
+    else if (S <= 2) k_edge_prep<2><<<grid, 256, 0, s>>>(mg, ecnt, erec, ehalf, Es, Ev, S, ep);
+    else if (S <= 4) k_edge_prep<4><<<grid, 256, 0, s>>>(mg, ecnt, erec, ehalf, Es, Ev, S, ep);
+    else k_edge_prep<8><<<grid, 256, 0, s>>>(mg, ecnt, erec, ehalf, Es, Ev, S, ep);
     NNP_LAUNCH_CHECK();
 }
 

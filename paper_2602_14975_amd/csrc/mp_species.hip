@@ -21,8 +21,9 @@
 //   F_o += dr u + (Q - (Q . u) u) / r.
 // Per edge this reads 4 (K + 1) numbers of the neighbour instead of 4 F
 // feature values, and the per-feature work moves into four dense products
-// per evaluation (float32 operands).  The edges are those of the edge
-// preparation (records and split radial values, see mp_mx.hip).
+// per evaluation.  The edges are those of the edge preparation (records and
+// split radial values, see mp_mx.hip), which also forms the forward sums E
+// and U in the same pass; this file holds the tables and the reverse.
 //
 // Slot layout of a species: KP = K + 4 numbers, k < K the basis, K the
 // cutoff (bias column), K + 1 the species indicator (forward: T_0 holds the
@@ -91,83 +92,6 @@ __global__ void k_sp_tables(int F, int S, int pp, int ep, const float* __restric
         const int rem = int(t % (int64_t(pp) * F));
         TT[t] = sp_entry(F, S, c, rem % F, rem / F, false, Wr, br, phi, emb);
     }
-}
-
-// Forward edge sums: one wavefront per atom, lane (c, k) = (lane / 16,
-// lane % 16) sums w_c B_k over the atom's edges by neighbour species
-// (w_0 = 1, w_{1+a} = u_a), and w_c f in the cutoff slot; the edges are
-// staged in LDS 64 at a time (one lane each), grouped by species, so that
-// each species' sums run over one contiguous segment.  Rows: Es[i][NS]
-// (c = 0), Ev[3 i + a][ep].
-template <int SM>
-__global__ void __launch_bounds__(64 * kSpWaves) k_sp_fwd(MpGeom mg, int S, int ep, float* __restrict__ Es,
-                                                        float* __restrict__ Ev) {
-    constexpr int K = kSpK, KP = kSpKP, PITCH = 21;  // staged edge: B[16], 1, u[3], f
-    __shared__ float eds[kSpWaves][64][PITCH];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int i = xcd_block(blockIdx.x, gridDim.x) * kSpWaves + w;
-    if (i >= mg.n) return;  // whole wavefronts; no block barriers below
-    const int c = lane >> 4, k = lane & 15;
-    const int start = mg.off[i], cnt = mg.ecnt[i];
-    float acc[SM] = {}, accf[SM] = {};
-    float(*ed)[PITCH] = eds[w];
-    for (int base = 0; base < cnt; base += 64) {
-        const int nb = min(64, cnt - base);
-        // the batch's edges staged grouped by neighbour species (list order
-        // within a species): lane q of the batch goes to its species'
-        // segment, at its rank among the lanes before it
-        const bool valid = lane < nb;
-        const int p = start + base + (valid ? lane : 0);
-        const EdgeRec rec = mg.erec[p];
-        const int t = valid ? min(max(rec.t, 0), S - 1) : SM;
-        int seg[SM + 1];
-        seg[0] = 0;
-        int dst = 0;
-#pragma unroll
-        for (int s = 0; s < SM; ++s) {
-            const uint64_t m = __ballot(t == s);
-            if (t == s) dst = seg[s] + __popcll(m & ((1ull << lane) - 1ull));
-            seg[s + 1] = seg[s] + __popcll(m);
-        }
-        if (valid) {
-            const uint4* hp = mg.ehalf + int64_t(p) * 8;
-            const uint4 hi[2] = {hp[0], hp[1]}, lo[2] = {hp[2], hp[3]};
-            float b[K];
-            unsplit16(hi, lo, b);
-#pragma unroll
-            for (int q = 0; q < K; ++q) ed[dst][q] = b[q];
-            ed[dst][K] = 1.f;
-            ed[dst][K + 1] = rec.u[0];
-            ed[dst][K + 2] = rec.u[1];
-            ed[dst][K + 3] = rec.u[2];
-            ed[dst][K + 4] = rec.fc;
-        }
-        wave_sync_lds();
-#pragma unroll
-        for (int s = 0; s < SM; ++s) {
-            float a = 0.f, af = 0.f;
-#pragma unroll 4
-            for (int e = seg[s]; e < seg[s + 1]; ++e) {
-                const float wc = ed[e][K + c];
-                a = fmaf(wc, ed[e][k], a);
-                af = fmaf(wc, ed[e][K + 4], af);
-            }
-            acc[s] += a;
-            accf[s] += af;
-        }
-        wave_sync_lds();  // the next batch overwrites the staged edges
-    }
-    float* row = c == 0 ? Es + int64_t(i) * ep : Ev + (int64_t(i) * 3 + (c - 1)) * ep;
-    const int ti = min(max(mg.species[i], 0), S - 1);
-#pragma unroll
-    for (int s = 0; s < SM; ++s) {
-        if (s >= S) break;
-        row[s * KP + k] = acc[s];
-        if (k == 0) row[s * KP + K] = accf[s];
-        if (k == 1) row[s * KP + K + 1] = (c == 0 && s == ti) ? 1.f : 0.f;
-        if (k >= 2 && k < KP - K) row[s * KP + K + k] = 0.f;
-    }
-    for (int z = S * KP + k; z < ep; z += 16) row[z] = 0.f;
 }
 
 // Reverse: one wavefront per owner atom, one lane per edge (64 at a time);
@@ -320,22 +244,6 @@ void launch_sp_tables(int F, int S, const float* Wr, const float* br, const floa
     species_sum_pitches(S, pp, ep);
     const int64_t total = int64_t(2) * F * std::max(pp, ep);
     k_sp_tables<<<cdiv(total, 256), 256, 0, s>>>(F, S, pp, ep, Wr, br, phi, emb, T, TT);
-    NNP_LAUNCH_CHECK();
-}
-
-void launch_sp_fwd(const MpGeom& mg, int S, float* Es, float* Ev, hipStream_t s) {
-    if (mg.n <= 0) return;
-    int pp, ep;
-    species_sum_pitches(S, pp, ep);
-    ScopedTimer t("message_fwd_first", s, true);
-    const dim3 grid(cdiv(mg.n, kSpWaves)), block(64 * kSpWaves);
-    auto go = [&](auto kern) {
-        if (t.active && t.by_launch) hipExtLaunchKernelGGL(kern, grid, block, 0, s, t.a, t.b, 0, mg, S, ep, Es, Ev);
-        else kern<<<grid, block, 0, s>>>(mg, S, ep, Es, Ev);
-    };
-    if (S <= 2) go(k_sp_fwd<2>);
-    else if (S <= 4) go(k_sp_fwd<4>);
-    else go(k_sp_fwd<8>);
     NNP_LAUNCH_CHECK();
 }
 
