@@ -598,12 +598,14 @@ void gemm_xwt_f32_split(int M, int N, int K, const float* X, int ldx, const floa
         throw Fail{NNP_EINVAL};
     }
     ScopedTimer timer("gemm", s);
+    // one block per 32 rows and all N columns (N = 128: one wavefront over
+    // all of K; N <= 160 with K >= 128: K split over four wavefronts);
+    // otherwise one 32-column strip per block
     const int T = cdiv(N, 32);
-    const int S = K >= 128 ? 4 : 1;
-    if (T == 4 && S == 1) rk_launch<4, 1>(g, s);
-    else if (T <= 2 && S == 4) rk_launch<2, 4>(g, s);
-    else if (T == 3 && S == 4) rk_launch<3, 4>(g, s);
-    else if (S == 4) rk_launch<5, 4>(g, s);
+    if (T == 4) rk_launch<4, 1>(g, s);
+    else if (K >= 128 && T <= 2) rk_launch<2, 4>(g, s);
+    else if (K >= 128 && T == 3) rk_launch<3, 4>(g, s);
+    else if (K >= 128) rk_launch<5, 4>(g, s);
     else rk_launch<1, 1>(g, s);
     NNP_LAUNCH_CHECK();
 }
