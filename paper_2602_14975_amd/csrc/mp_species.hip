@@ -21,7 +21,8 @@
 //   F_o += dr u + (Q - (Q . u) u) / r.
 // Per edge this reads 4 (K + 1) numbers of the neighbour instead of 4 F
 // feature values, and the per-feature work moves into four dense products
-// per evaluation.  The edges are those of the edge preparation (records and
+// per evaluation (two launches: [s; v] and [P_0; P_2] each take one, the
+// row tiles past n multiplying by the second table).  The edges are those of the edge preparation (records and
 // split radial values, see mp_mx.hip), which also forms the forward sums E
 // and U in the same pass; this file holds the tables and the reverse.
 //
