@@ -95,6 +95,32 @@ def test_species_sums_match_per_edge_first_layer(gpu_lib, which):
     assert abs(es - ee) <= 1e-6 * abs(E) + 1e-4
 
 
+@pytest.mark.parametrize("n_species", [1, 6, 8])
+def test_species_sums_any_species_count(gpu_lib, n_species):
+    """One species (the smallest tables: 32-slot rows of P), six and eight
+    (the eight-species kernels; 128 and 160 slots, the latter with 256-deep
+    edge-sum rows), on a random box of 256 atoms (a multiple of 128: the
+    split-bfloat16 products over [s; v]): forces within FP32 rounding of the
+    per-edge path and of the oracle."""
+    from paper_2602_14975_amd import _abi
+    spec = ModelSpec("cons", 128, 2, 16, 5.0, n_species=n_species)
+    w = synth.random_weights(spec, 4400 + n_species)
+    pos, _, box = small_box(80 + n_species, n=256, box=13.5)
+    species = np.random.default_rng(n_species).integers(0, n_species, size=256).astype(np.int32)
+    print(f"case species={n_species}", flush=True)
+    try:
+        _set_kernels(gpu_lib, _abi.NNP_MP_EDGE)
+        ee, fe = _forces(gpu_lib, spec, w, pos, species, box, 5.0)
+        _set_kernels(gpu_lib, _abi.NNP_MP_AUTO)
+        es, fs = _forces(gpu_lib, spec, w, pos, species, box, 5.0)
+    finally:
+        _set_kernels(gpu_lib, _abi.NNP_MP_AUTO)
+    E, F = _oracle(spec, w, pos, species, box)
+    assert rel_rmse(fs, F) <= FP32_TOL and rel_rmse(fe, F) <= FP32_TOL
+    assert rel_rmse(fs, fe) <= 2e-6
+    assert abs(es - ee) <= 1e-6 * abs(E) + 1e-4
+
+
 def test_kernel_mode_rejects_unknown_value(gpu_lib):
     assert gpu_lib.lib().nnp_set_message_kernels(7) != 0
 
